@@ -1,0 +1,694 @@
+/*
+ * Serial reference model (oracle) of the per-cycle step of a bufferless
+ * deflection-routed 2D-mesh chip multicore with a statically homed L2.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  It shares no code
+ * with the HIP library.  Plain C, one thread, written to be read against the
+ * paper (Kumar & Sahu, arXiv 1508.03235):
+ *
+ *   - the cycle loop and its three phases over every router: Sec. 7.1 (serial
+ *     version; phase one = memory access, phase two = arbitration, phase three
+ *     = traversal, ejection, injection);
+ *   - bufferless deflection routing, oldest first, X-then-Y productive
+ *     preference kept after deflection, injection only into a free input:
+ *     Sec. 4.2-4.3 and Sec. 6.2.1;
+ *   - private L1 and a logically shared, physically distributed L2 with one
+ *     copy of each line: Sec. 3.1; request policy (no miss under a miss):
+ *     Sec. 3.5; statistics (requests made/received, replies sent/received,
+ *     hits and misses): Sec. 6.2.2.
+ *
+ * Where the paper is silent or ambiguous the oracle follows the readings listed
+ * in the design notes (static home = line mod N, injection-time age, one eject
+ * per cycle, per-home reply queues as intrusive lists, Philox4x32-10 draws keyed
+ * by (seed; cycle, tile, stream)).  Every function below names the passage it
+ * follows.
+ *
+ * Parity pins: the Philox generator is pinned to published known-answer
+ * vectors; routing to closed-form zero-load latencies and hand traces; the
+ * arbitration to brute-force rule checks; the caches to a textbook LRU list and
+ * to Mattson stack distances; conservation and drain to the equalities the
+ * paper's statistics table shows (requests made = received, replies sent =
+ * received).  The full-system counts themselves are not printed in the paper.
+ */
+#include "nocsim_oracle.h"
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- fixed encodings --------------------------------------------------------------- */
+enum { K_REQ = 0, K_REPLY = 1, K_BG = 2 };                              /* flit kinds */
+enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4 }; /* core states */
+enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
+/* per-tile core record (16 words) */
+enum {
+  C_STATE = 0, C_WAKE = 1, C_LINE = 2, C_ISSUE = 3, C_L2Q = 4, C_L2Q_LINE = 5,
+  C_HIT_H = 6, C_HIT_T = 7, C_MISS_H = 8, C_MISS_T = 9, C_BG = 10,
+  C_NEXT = 11, C_READY = 12, C_NLINE = 13, C_FLINE = 14, C_FDST = 15, C_WORDS = 16
+};
+/* flit record (4 words) */
+enum { F_DST = 0, F_INJ = 1, F_SRC = 2, F_INFO = 3, F_WORDS = 4 };
+#define LINE_MASK 0x3FFFFFFF
+#define DUMP_MAGIC 0x4E4F4353
+#define DUMP_HEADER 16
+
+struct oracle_sim {
+  oracle_config cfg;
+  int32_t W, H, N;
+  int64_t cycle;
+  int32_t zk;
+  uint32_t* zs;          /* shared-region quantile table, zk+1 entries */
+  uint32_t* zp;          /* private-region quantile table */
+  int32_t* link[2];      /* [N][4 ports][4 words]: input slots, double buffered by cycle parity */
+  int32_t* core;         /* [N][C_WORDS] */
+  int32_t* l1;           /* [N][S1][W1], most recently used first, -1 = invalid */
+  int32_t* l2;           /* [N][S2][W2] */
+  int64_t stats[OS_COUNT];
+  /* scratch of one cycle */
+  uint32_t* rnd;         /* [N][4] the tile's main draw of this cycle */
+  int32_t* outp;         /* [N][4 ports][4 words] flits routed out this cycle */
+  int32_t* ej;           /* [N][4 words] flit ejected this cycle (dst < 0: none) */
+  int32_t* oldest_ok;    /* [N] 1 if the router's oldest flit was ejected or moved productively */
+  int32_t check;
+  int32_t bad;
+  char msg[256];
+};
+
+/* ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from that paper ------ */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u; /* round multipliers */
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u; /* key schedule (Weyl) increments */
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { k0 += W0; k1 += W1; }
+    uint64_t p0 = (uint64_t)M0 * c0;
+    uint64_t p1 = (uint64_t)M1 * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(const oracle_sim* s, int64_t cycle, int32_t tile, uint32_t stream, uint32_t out[4]) {
+  uint32_t ctr[4] = {(uint32_t)cycle, (uint32_t)tile, stream, 0u};
+  uint32_t key[2] = {s->cfg.seed_lo, s->cfg.seed_hi};
+  oracle_philox4x32_10(ctr, key, out);
+}
+
+/* Zipf rank from a quantile table: bucket = high 16 bits, linear position inside it from
+   the low 16 bits. */
+static int32_t zipf_rank(const uint32_t* q, uint32_t u) {
+  uint32_t b = u >> 16, f = u & 0xFFFFu;
+  uint32_t lo = q[b], hi = q[b + 1];
+  return (int32_t)(lo + (uint32_t)(((uint64_t)f * (uint64_t)(hi - lo)) >> 16));
+}
+
+void oracle_zipf_ranks(const uint32_t* table, const uint32_t* u, int64_t n, int32_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = zipf_rank(table, u[i]);
+}
+
+/* ---- geometry (Sec. 6.2.1: Input[0..3] = north, south, east, west) ---------------- */
+static int port_valid(const oracle_sim* s, int32_t t, int p) {
+  int32_t x = t % s->W, y = t / s->W;
+  switch (p) {
+    case PN: return y > 0;
+    case PS: return y < s->H - 1;
+    case PE: return x < s->W - 1;
+    default: return x > 0;
+  }
+}
+static int32_t neighbour(const oracle_sim* s, int32_t t, int p) {
+  switch (p) {
+    case PN: return t - s->W;
+    case PS: return t + s->W;
+    case PE: return t + 1;
+    default: return t - 1;
+  }
+}
+static int opposite(int p) { return p ^ 1; } /* N<->S, E<->W */
+
+/* ---- caches: a set is a list of line tags, most recently used first --------------- */
+/* Touch `line` in a set of `ways` tags: on a hit move it to the front; on a miss insert it at
+   the front when `insert`, dropping the last entry (an invalid way if one exists, else the
+   least recently used one).  Returns 1 on a hit.  Local victim selection: Sec. 3.4. */
+static int cache_touch(int32_t* set, int ways, int32_t line, int insert) {
+  for (int i = 0; i < ways; ++i) {
+    if (set[i] == line) {
+      for (int j = i; j > 0; --j) set[j] = set[j - 1];
+      set[0] = line;
+      return 1;
+    }
+  }
+  if (insert) {
+    for (int j = ways - 1; j > 0; --j) set[j] = set[j - 1];
+    set[0] = line;
+  }
+  return 0;
+}
+
+static void check_set(oracle_sim* s, const int32_t* set, int ways, const char* what, int32_t tile) {
+  for (int i = 0; i < ways; ++i) {
+    if (set[i] < 0) {
+      for (int j = i + 1; j < ways; ++j)
+        if (set[j] >= 0 && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "%s tile %d: valid way after invalid", what, tile); }
+      continue;
+    }
+    for (int j = i + 1; j < ways; ++j)
+      if (set[j] == set[i] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "%s tile %d: duplicate tag %d", what, tile, set[i]); }
+  }
+}
+
+static int32_t* l1_set(oracle_sim* s, int32_t t, int32_t line) {
+  int32_t set = line & (s->cfg.l1_sets - 1);
+  return s->l1 + ((size_t)t * s->cfg.l1_sets + set) * s->cfg.l1_ways;
+}
+static int32_t* l2_set(oracle_sim* s, int32_t t, int32_t line) {
+  int32_t set = (line / s->N) & (s->cfg.l2_sets - 1);
+  return s->l2 + ((size_t)t * s->cfg.l2_sets + set) * s->cfg.l2_ways;
+}
+
+/* L2 lookup at home slice t: install on a miss (the block arrives from memory after
+   mem_lat cycles; one copy per line, Sec. 3.1).  Returns 1 on a hit. */
+static int l2_lookup(oracle_sim* s, int32_t t, int32_t line) {
+  int32_t* set = l2_set(s, t, line);
+  int hit = cache_touch(set, s->cfg.l2_ways, line, 1);
+  if (hit) s->stats[OS_L2_HIT]++; else s->stats[OS_L2_MISS]++;
+  if (s->check) {
+    check_set(s, set, s->cfg.l2_ways, "L2", t);
+    if (line % s->N != t && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "L2 slice %d got line %d", t, line); }
+  }
+  return hit;
+}
+
+/* ---- per-home reply queues: FIFOs threaded through the requesters' node words ------ */
+static void list_append(oracle_sim* s, int32_t home, int head_w, int tail_w, int32_t rq, int32_t ready, int32_t line) {
+  int32_t* h = s->core + (size_t)home * C_WORDS;
+  int32_t* n = s->core + (size_t)rq * C_WORDS;
+  n[C_NEXT] = -1;
+  n[C_READY] = ready;
+  n[C_NLINE] = line;
+  if (h[tail_w] >= 0) s->core[(size_t)h[tail_w] * C_WORDS + C_NEXT] = rq;
+  else h[head_w] = rq;
+  h[tail_w] = rq;
+}
+static int32_t list_pop(oracle_sim* s, int32_t home, int head_w, int tail_w) {
+  int32_t* h = s->core + (size_t)home * C_WORDS;
+  int32_t rq = h[head_w];
+  h[head_w] = s->core[(size_t)rq * C_WORDS + C_NEXT];
+  if (h[head_w] < 0) h[tail_w] = -1;
+  return rq;
+}
+
+/* ---- phase one: memory access (Sec. 7.1, work in phase one; Sec. 3.5) -------------- */
+static void phase_memory(oracle_sim* s, int32_t t) {
+  const int64_t c = s->cycle;
+  int32_t* k = s->core + (size_t)t * C_WORDS;
+  const uint32_t* r = s->rnd + (size_t)t * 4;
+
+  /* home L2 slice serves the request that was ejected here in the previous cycle */
+  if (k[C_L2Q] >= 0) {
+    int32_t rq = k[C_L2Q], line = k[C_L2Q_LINE];
+    if (l2_lookup(s, t, line)) list_append(s, t, C_HIT_H, C_HIT_T, rq, (int32_t)c, line);
+    else list_append(s, t, C_MISS_H, C_MISS_T, rq, (int32_t)(c + s->cfg.mem_lat), line);
+    k[C_L2Q] = -1;
+    k[C_L2Q_LINE] = -1;
+  }
+
+  switch (k[C_STATE]) {
+    case ST_FILL:
+      if (k[C_WAKE] == (int32_t)c) {            /* block arrives: L1 fill, op complete */
+        int32_t* set = l1_set(s, t, k[C_LINE]);
+        cache_touch(set, s->cfg.l1_ways, k[C_LINE], 1);
+        if (s->check) check_set(s, set, s->cfg.l1_ways, "L1", t);
+        int64_t lat = c - k[C_ISSUE];
+        s->stats[OS_OPS_DONE]++;
+        s->stats[OS_OP_LAT] += lat;
+        if (lat > s->stats[OS_OP_LAT_MAX]) s->stats[OS_OP_LAT_MAX] = lat;
+        k[C_STATE] = ST_IDLE;
+      }
+      break;
+    case ST_L1MISS:
+      if (k[C_WAKE] == (int32_t)c) {            /* L1 miss penalty over: go to the home slice */
+        int32_t line = k[C_LINE];
+        if (line % s->N == t) {
+          int hit = l2_lookup(s, t, line);
+          k[C_STATE] = ST_FILL;
+          k[C_WAKE] = (int32_t)(hit ? c + 1 : c + s->cfg.mem_lat);
+        } else {
+          k[C_STATE] = ST_SEND;                 /* request flit waits for an injection slot */
+          s->stats[OS_REQ_MADE]++;
+        }
+      }
+      break;
+    case ST_IDLE: {
+      int issue = 0;
+      int32_t line = 0;
+      if (k[C_FLINE] >= 0) {
+        line = k[C_FLINE];
+        k[C_FLINE] = -1;
+        issue = 1;
+      } else if (r[0] < s->cfg.op_thr) {
+        issue = 1;
+        if (s->cfg.private_lines > 0 && r[1] >= s->cfg.shared_thr)
+          line = s->cfg.shared_lines + t * s->cfg.private_lines + zipf_rank(s->zp, r[2]);
+        else
+          line = zipf_rank(s->zs, r[2]);
+      }
+      if (issue) {
+        s->stats[OS_OPS_ISSUED]++;
+        k[C_LINE] = line;
+        k[C_ISSUE] = (int32_t)c;
+        int32_t* set = l1_set(s, t, line);
+        if (cache_touch(set, s->cfg.l1_ways, line, 0)) {
+          s->stats[OS_L1_HIT]++;
+          s->stats[OS_OPS_DONE]++;
+        } else {
+          s->stats[OS_L1_MISS]++;
+          k[C_STATE] = ST_L1MISS;
+          k[C_WAKE] = (int32_t)(c + s->cfg.l1_lat);
+        }
+      }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+/* ---- phase two: oldest-first deflection arbitration (Sec. 4.3, Sec. 6.2.1) ---------- */
+/* Flits are considered oldest first (key: injection cycle, then source tile).  Each takes
+   the eject link if it is destined here and the link is still free, else its first free
+   productive port (X before Y), else the lowest-numbered free port (a deflection). */
+static int arbitrate_router(int32_t W, int32_t H, int32_t t, int n, const int32_t* dst, const int32_t* inj,
+                            const int32_t* src, int32_t* port, int32_t* defl) {
+  int order[8];
+  for (int i = 0; i < n; ++i) order[i] = i;
+  for (int i = 1; i < n; ++i) {                 /* insertion sort by (inj, src) */
+    int v = order[i], j = i - 1;
+    while (j >= 0 && (inj[order[j]] > inj[v] || (inj[order[j]] == inj[v] && src[order[j]] > src[v]))) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  int32_t x = t % W, y = t / W;
+  int valid[4] = {y > 0, y < H - 1, x < W - 1, x > 0};
+  int used[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < n; ++k) {
+    int i = order[k];
+    port[i] = -1;
+    defl[i] = 0;
+    if (dst[i] == t && !used[PX]) {
+      port[i] = PX;
+      used[PX] = 1;
+      continue;
+    }
+    int32_t dx = dst[i] % W - x, dy = dst[i] / W - y;
+    int pref[2], np = 0;
+    if (dx > 0) pref[np++] = PE;
+    else if (dx < 0) pref[np++] = PW;
+    if (dy > 0) pref[np++] = PS;
+    else if (dy < 0) pref[np++] = PN;
+    for (int q = 0; q < np && port[i] < 0; ++q)
+      if (!used[pref[q]]) port[i] = pref[q];
+    if (port[i] < 0) {
+      for (int p = 0; p < 4 && port[i] < 0; ++p)
+        if (valid[p] && !used[p]) port[i] = p;
+      defl[i] = 1;
+    }
+    if (port[i] < 0) return ORACLE_EINVAL;   /* more flits than ports */
+    used[port[i]] = 1;
+  }
+  return ORACLE_OK;
+}
+
+int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, const int32_t* dst, const int32_t* inj,
+                     const int32_t* src, int32_t* port, int32_t* deflected) {
+  if (width < 1 || height < 1 || tile < 0 || tile >= width * height || n < 0 || n > 5) return ORACLE_EINVAL;
+  return arbitrate_router(width, height, tile, n, dst, inj, src, port, deflected);
+}
+
+/* Phase two of tile t: gather arrivals, add at most one injected flit when an input is
+   free (Sec. 4.2: a node injects whenever it finds a free input port), arbitrate. */
+static void phase_route(oracle_sim* s, int32_t t) {
+  const int64_t c = s->cycle;
+  int32_t* k = s->core + (size_t)t * C_WORDS;
+  const int32_t* in = s->link[c & 1] + (size_t)t * 16;
+  int32_t fl[5][F_WORDS];
+  int n = 0, deg = 0;
+  for (int p = 0; p < 4; ++p) {
+    if (port_valid(s, t, p)) deg++;
+    if (in[p * 4 + F_DST] >= 0) {
+      memcpy(fl[n], in + p * 4, sizeof fl[n]);
+      n++;
+    }
+  }
+  int arrivals = n;
+
+  /* injection candidate: ready miss reply, hit reply, own request, test flit, background */
+  int cls = -1;
+  if (k[C_MISS_H] >= 0 && s->core[(size_t)k[C_MISS_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 0;
+  else if (k[C_HIT_H] >= 0) cls = 1;
+  else if (k[C_STATE] == ST_SEND) cls = 2;
+  else if (k[C_FDST] >= 0) cls = 3;
+  else if (k[C_BG] > 0) cls = 4;
+  if (cls >= 0 && arrivals >= deg) {
+    s->stats[OS_INJ_BLOCKED]++;
+    cls = -1;
+  }
+  if (cls >= 0) {
+    int32_t* f = fl[n++];
+    f[F_INJ] = (int32_t)c;
+    f[F_SRC] = t;
+    if (cls == 0 || cls == 1) {
+      int32_t rq = cls == 0 ? list_pop(s, t, C_MISS_H, C_MISS_T) : list_pop(s, t, C_HIT_H, C_HIT_T);
+      f[F_DST] = rq;
+      f[F_INFO] = (K_REPLY << 30) | s->core[(size_t)rq * C_WORDS + C_NLINE];
+      s->stats[OS_REPLY_SENT]++;
+      s->stats[OS_INJ_REPLY]++;
+    } else if (cls == 2) {
+      f[F_DST] = k[C_LINE] % s->N;
+      f[F_INFO] = (K_REQ << 30) | k[C_LINE];
+      k[C_STATE] = ST_WAIT;
+      s->stats[OS_INJ_REQ]++;
+    } else {
+      if (cls == 3) {
+        f[F_DST] = k[C_FDST];
+        k[C_FDST] = -1;
+      } else {
+        uint32_t r2[4];
+        draw(s, c, t, 1u, r2);
+        int32_t d = (int32_t)(((uint64_t)r2[0] * (uint64_t)(s->N - 1)) >> 32);
+        if (d >= t) d++;
+        f[F_DST] = d;
+        k[C_BG]--;
+      }
+      f[F_INFO] = K_BG << 30;
+      s->stats[OS_INJ_BG]++;
+    }
+  }
+
+  int32_t dst[5], inj[5], src[5], port[5], defl[5];
+  for (int i = 0; i < n; ++i) { dst[i] = fl[i][F_DST]; inj[i] = fl[i][F_INJ]; src[i] = fl[i][F_SRC]; }
+  int rc = arbitrate_router(s->W, s->H, t, n, dst, inj, src, port, defl);
+  if (rc != ORACLE_OK && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "router %d: no port", t); }
+
+  int32_t* out = s->outp + (size_t)t * 16;
+  int32_t* ej = s->ej + (size_t)t * 4;
+  for (int i = 0; i < 16; ++i) out[i] = -1;
+  for (int i = 0; i < 4; ++i) ej[i] = -1;
+  int oldest = -1;
+  for (int i = 0; i < n; ++i) {
+    if (oldest < 0 || inj[i] < inj[oldest] || (inj[i] == inj[oldest] && src[i] < src[oldest])) oldest = i;
+    if (port[i] == PX) {
+      memcpy(ej, fl[i], sizeof fl[i]);
+    } else if (port[i] >= 0) {
+      memcpy(out + port[i] * 4, fl[i], sizeof fl[i]);
+      s->stats[OS_TRAVERSALS]++;
+      if (defl[i]) s->stats[OS_DEFLECTIONS]++;
+    }
+  }
+  s->oldest_ok[t] = oldest < 0 || !defl[oldest];
+}
+
+/* ---- phase three: traversal, ejection, generation (Sec. 7.1, work in phase three) --- */
+static void phase_move(oracle_sim* s, int32_t t) {
+  const int64_t c = s->cycle;
+  int32_t* k = s->core + (size_t)t * C_WORDS;
+  int32_t* nxt = s->link[(c + 1) & 1];
+  const int32_t* out = s->outp + (size_t)t * 16;
+  for (int p = 0; p < 4; ++p) {
+    if (!port_valid(s, t, p)) continue;
+    int32_t nb = neighbour(s, t, p);
+    memcpy(nxt + (size_t)nb * 16 + opposite(p) * 4, out + p * 4, 4 * sizeof(int32_t));
+  }
+  const int32_t* ej = s->ej + (size_t)t * 4;
+  if (ej[F_DST] >= 0) {
+    int kind = (int)((uint32_t)ej[F_INFO] >> 30);
+    int64_t lat = c - ej[F_INJ];
+    s->stats[OS_EJ_REQ + kind]++;
+    s->stats[OS_LAT_REQ + kind] += lat;
+    if (lat > s->stats[OS_LAT_MAX]) s->stats[OS_LAT_MAX] = lat;
+    int bin = 0;
+    while (bin < 15 && (lat >> (bin + 1)) > 0) bin++;
+    s->stats[OS_HIST + bin]++;
+    if (s->check) {
+      int32_t sx = ej[F_SRC] % s->W, sy = ej[F_SRC] / s->W, x = t % s->W, y = t / s->W;
+      int64_t man = labs((long)(sx - x)) + labs((long)(sy - y));
+      if (lat < man && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit faster than Manhattan at %d", t); }
+    }
+    if (kind == K_REQ) {                       /* request reaches its home slice */
+      s->stats[OS_REQ_RECV]++;
+      k[C_L2Q] = ej[F_SRC];
+      k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
+    } else if (kind == K_REPLY) {              /* block reaches the requester */
+      s->stats[OS_REPLY_RECV]++;
+      if (k[C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "reply at idle tile %d", t); }
+      k[C_STATE] = ST_FILL;
+      k[C_WAKE] = (int32_t)(c + 1);
+    }
+  }
+  if (s->N > 1 && s->rnd[(size_t)t * 4 + 3] < s->cfg.bg_thr) {
+    k[C_BG]++;
+    s->stats[OS_BG_GEN]++;
+  }
+}
+
+/* ---- per-cycle state digest --------------------------------------------------------- */
+static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 2014) */
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
+  int32_t w[32];
+  memcpy(w, s->link[(c + 1) & 1] + (size_t)t * 16, 16 * sizeof(int32_t));
+  memcpy(w + 16, s->core + (size_t)t * C_WORDS, 16 * sizeof(int32_t));
+  uint64_t h = mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)t);
+  for (int i = 0; i < 16; ++i) h = mix64(h ^ (((uint64_t)(uint32_t)w[2 * i] << 32) | (uint32_t)w[2 * i + 1]));
+  return h;
+}
+
+/* ---- invariants --------------------------------------------------------------------- */
+static void check_cycle(oracle_sim* s) {
+  const int64_t c = s->cycle;
+  const int32_t* nxt = s->link[(c + 1) & 1];
+  int64_t occupied = 0, req_fl = 0, rep_fl = 0;
+  for (int32_t t = 0; t < s->N; ++t) {
+    for (int p = 0; p < 4; ++p) {
+      const int32_t* f = nxt + (size_t)t * 16 + p * 4;
+      if (f[F_DST] < 0) continue;
+      occupied++;
+      int kind = (int)((uint32_t)f[F_INFO] >> 30);
+      if (kind == K_REQ) req_fl++;
+      if (kind == K_REPLY) rep_fl++;
+      if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
+    }
+    if (!s->oldest_ok[t] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "oldest flit deflected at %d", t); }
+  }
+  int64_t inj = s->stats[OS_INJ_REQ] + s->stats[OS_INJ_REPLY] + s->stats[OS_INJ_BG];
+  int64_t ejc = s->stats[OS_EJ_REQ] + s->stats[OS_EJ_REPLY] + s->stats[OS_EJ_BG];
+  if (inj - ejc != occupied && !s->bad) {
+    s->bad = 1;
+    snprintf(s->msg, sizeof s->msg, "conservation: injected-ejected=%lld occupied=%lld", (long long)(inj - ejc), (long long)occupied);
+  }
+  /* every waiting requester is accounted for exactly once: request or reply in flight,
+     request at its home slice's input, or queued at its home */
+  int64_t waiting = 0, queued = 0, at_home = 0;
+  for (int32_t t = 0; t < s->N; ++t) {
+    const int32_t* k = s->core + (size_t)t * C_WORDS;
+    if (k[C_STATE] == ST_WAIT) waiting++;
+    if (k[C_L2Q] >= 0) at_home++;
+    for (int which = 0; which < 2; ++which) {
+      int32_t r = k[which ? C_MISS_H : C_HIT_H], last = -1;
+      int64_t len = 0;
+      while (r >= 0) {
+        if (s->core[(size_t)r * C_WORDS + C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "queued tile %d not waiting", r); }
+        last = r;
+        r = s->core[(size_t)r * C_WORDS + C_NEXT];
+        if (++len > s->N) { if (!s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "cyclic reply list at %d", t); } break; }
+      }
+      if (last != k[which ? C_MISS_T : C_HIT_T] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "bad list tail at %d", t); }
+      queued += len;
+    }
+  }
+  if (waiting != req_fl + rep_fl + queued + at_home && !s->bad) {
+    s->bad = 1;
+    snprintf(s->msg, sizeof s->msg, "requester accounting: waiting=%lld req=%lld reply=%lld queued=%lld at_home=%lld",
+             (long long)waiting, (long long)req_fl, (long long)rep_fl, (long long)queued, (long long)at_home);
+  }
+}
+
+/* ---- driver (Sec. 7.1: the serial main loop) ----------------------------------------- */
+int oracle_step(oracle_sim* s, int64_t n, uint64_t* digests, int32_t check) {
+  if (!s || n < 0) return ORACLE_EINVAL;
+  s->check = check;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t c = s->cycle;
+    for (int32_t t = 0; t < s->N; ++t) draw(s, c, t, 0u, s->rnd + (size_t)t * 4);
+    for (int32_t t = 0; t < s->N; ++t) phase_memory(s, t);
+    for (int32_t t = 0; t < s->N; ++t) phase_route(s, t);
+    for (int32_t t = 0; t < s->N; ++t) phase_move(s, t);
+    if (digests) {
+      uint64_t d = 0;
+      for (int32_t t = 0; t < s->N; ++t) d += tile_digest(s, c, t);
+      digests[i] = d;
+    }
+    if (check) check_cycle(s);
+    s->stats[OS_CYCLES]++;
+    s->cycle++;
+    if (s->bad) return ORACLE_EINVARIANT;
+  }
+  return ORACLE_OK;
+}
+
+/* ---- creation, dump, hooks ------------------------------------------------------------ */
+static int is_pow2(int32_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* zp, int32_t zk, oracle_sim** out) {
+  if (!cfg || !out || !zs) return ORACLE_EINVAL;
+  *out = NULL;
+  int64_t N = (int64_t)cfg->width * cfg->height;
+  if (cfg->width < 1 || cfg->height < 1 || N > (1 << 20)) return ORACLE_EINVAL;
+  if (!is_pow2(cfg->l1_sets) || !is_pow2(cfg->l1_ways) || cfg->l1_ways > 8) return ORACLE_EINVAL;
+  if (!is_pow2(cfg->l2_sets) || !is_pow2(cfg->l2_ways) || cfg->l2_ways > 8) return ORACLE_EINVAL;
+  if (cfg->l1_lat < 1 || cfg->mem_lat < 1 || cfg->shared_lines < 1 || cfg->private_lines < 0) return ORACLE_EINVAL;
+  if ((int64_t)cfg->shared_lines + N * cfg->private_lines > (int64_t)LINE_MASK + 1) return ORACLE_EINVAL;
+  if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
+  oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
+  if (!s) return ORACLE_ENOMEM;
+  s->cfg = *cfg;
+  s->W = cfg->width;
+  s->H = cfg->height;
+  s->N = (int32_t)N;
+  s->zk = zk;
+  s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
+  s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
+  s->link[0] = (int32_t*)malloc((size_t)N * 16 * 4);
+  s->link[1] = (int32_t*)malloc((size_t)N * 16 * 4);
+  s->core = (int32_t*)malloc((size_t)N * C_WORDS * 4);
+  s->l1 = (int32_t*)malloc((size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
+  s->l2 = (int32_t*)malloc((size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
+  s->rnd = (uint32_t*)malloc((size_t)N * 4 * 4);
+  s->outp = (int32_t*)malloc((size_t)N * 16 * 4);
+  s->ej = (int32_t*)malloc((size_t)N * 4 * 4);
+  s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
+  if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej || !s->oldest_ok) {
+    oracle_destroy(s);
+    return ORACLE_ENOMEM;
+  }
+  memcpy(s->zs, zs, (size_t)(zk + 1) * 4);
+  if (zp) memcpy(s->zp, zp, (size_t)(zk + 1) * 4);
+  else memcpy(s->zp, zs, (size_t)(zk + 1) * 4);
+  memset(s->link[0], 0xFF, (size_t)N * 16 * 4);
+  memset(s->link[1], 0xFF, (size_t)N * 16 * 4);
+  memset(s->core, 0xFF, (size_t)N * C_WORDS * 4);
+  for (int64_t t = 0; t < N; ++t) {
+    s->core[t * C_WORDS + C_STATE] = ST_IDLE;
+    s->core[t * C_WORDS + C_BG] = 0;
+  }
+  memset(s->l1, 0xFF, (size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
+  memset(s->l2, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
+  *out = s;
+  return ORACLE_OK;
+}
+
+void oracle_destroy(oracle_sim* s) {
+  if (!s) return;
+  free(s->zs); free(s->zp); free(s->link[0]); free(s->link[1]); free(s->core); free(s->l1); free(s->l2);
+  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok);
+  free(s);
+}
+
+int oracle_stats(const oracle_sim* s, int64_t* out) {
+  if (!s || !out) return ORACLE_EINVAL;
+  memcpy(out, s->stats, sizeof s->stats);
+  return ORACLE_OK;
+}
+
+int64_t oracle_cycle(const oracle_sim* s) { return s ? s->cycle : -1; }
+
+size_t oracle_dump_words(const oracle_sim* s) {
+  size_t N = (size_t)s->N;
+  return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways + 2 * OS_COUNT;
+}
+
+/* Canonical state: header, input slots of the next cycle, core records, L1 and L2 tags
+   (most recently used first), statistics as (low, high) word pairs. */
+int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
+  if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
+  size_t N = (size_t)s->N, o = 0;
+  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 1, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
+                              s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, 0, 0, 0, 0, 0, 0};
+  memcpy(buf, hdr, sizeof hdr);
+  o += DUMP_HEADER;
+  memcpy(buf + o, s->link[s->cycle & 1], N * 16 * 4); o += N * 16;
+  memcpy(buf + o, s->core, N * C_WORDS * 4); o += N * C_WORDS;
+  size_t n1 = N * s->cfg.l1_sets * s->cfg.l1_ways, n2 = N * s->cfg.l2_sets * s->cfg.l2_ways;
+  memcpy(buf + o, s->l1, n1 * 4); o += n1;
+  memcpy(buf + o, s->l2, n2 * 4); o += n2;
+  for (int i = 0; i < OS_COUNT; ++i) {
+    buf[o++] = (int32_t)(uint32_t)(uint64_t)s->stats[i];
+    buf[o++] = (int32_t)((uint64_t)s->stats[i] >> 32);
+  }
+  return ORACLE_OK;
+}
+
+int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
+  if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
+  if (buf[0] != DUMP_MAGIC || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets || buf[7] != s->cfg.l1_ways ||
+      buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways)
+    return ORACLE_EINVAL;
+  size_t N = (size_t)s->N, o = DUMP_HEADER;
+  s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
+  memcpy(s->link[s->cycle & 1], buf + o, N * 16 * 4); o += N * 16;
+  memset(s->link[(s->cycle + 1) & 1], 0xFF, N * 16 * 4);
+  memcpy(s->core, buf + o, N * C_WORDS * 4); o += N * C_WORDS;
+  size_t n1 = N * s->cfg.l1_sets * s->cfg.l1_ways, n2 = N * s->cfg.l2_sets * s->cfg.l2_ways;
+  memcpy(s->l1, buf + o, n1 * 4); o += n1;
+  memcpy(s->l2, buf + o, n2 * 4); o += n2;
+  for (int i = 0; i < OS_COUNT; ++i) {
+    s->stats[i] = (int64_t)(((uint64_t)(uint32_t)buf[o + 1] << 32) | (uint32_t)buf[o]);
+    o += 2;
+  }
+  return ORACLE_OK;
+}
+
+int oracle_force_op(oracle_sim* s, int32_t tile, int32_t line) {
+  if (!s || tile < 0 || tile >= s->N || line < 0 || line > LINE_MASK) return ORACLE_EINVAL;
+  s->core[(size_t)tile * C_WORDS + C_FLINE] = line;
+  return ORACLE_OK;
+}
+
+int oracle_force_bg(oracle_sim* s, int32_t tile, int32_t dst) {
+  if (!s || tile < 0 || tile >= s->N || dst < 0 || dst >= s->N || dst == tile) return ORACLE_EINVAL;
+  s->core[(size_t)tile * C_WORDS + C_FDST] = dst;
+  return ORACLE_OK;
+}
+
+int oracle_set_rates(oracle_sim* s, uint32_t op_thr, uint32_t bg_thr) {
+  if (!s) return ORACLE_EINVAL;
+  s->cfg.op_thr = op_thr;
+  s->cfg.bg_thr = bg_thr;
+  return ORACLE_OK;
+}
+
+int oracle_quiescent(const oracle_sim* s) {
+  const int32_t* cur = s->link[s->cycle & 1];
+  for (int32_t t = 0; t < s->N; ++t) {
+    for (int p = 0; p < 4; ++p)
+      if (cur[(size_t)t * 16 + p * 4] >= 0) return 0;
+    const int32_t* k = s->core + (size_t)t * C_WORDS;
+    if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0)
+      return 0;
+  }
+  return 1;
+}
+
+const char* oracle_invariant_msg(const oracle_sim* s) { return s ? s->msg : ""; }

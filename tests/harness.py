@@ -1,0 +1,120 @@
+"""Helpers shared by the tests: canonical-dump views and the hand-trace runner.
+
+The runner drives any simulator object with the common surface (step, dump, stats,
+force_op, force_bg, cycle), so the same golden traces check the oracle on the CPU and
+the HIP library on the GPU.
+"""
+import json
+import os
+
+import numpy as np
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+STAT = {
+    "cycles": 0, "inj_req": 1, "inj_reply": 2, "inj_bg": 3, "ej_req": 4, "ej_reply": 5,
+    "ej_bg": 6, "lat_req": 7, "lat_reply": 8, "lat_bg": 9, "lat_max": 10,
+    "traversals": 11, "deflections": 12, "ops_issued": 13, "ops_done": 14, "op_lat": 15,
+    "l1_hit": 16, "l1_miss": 17, "l2_hit": 18, "l2_miss": 19, "req_made": 20,
+    "req_received": 21, "reply_sent": 22, "reply_received": 23, "inj_blocked": 24,
+    "bg_generated": 25, "op_lat_max": 26,
+}
+CORE = {"state": 0, "wake": 1, "line": 2, "issue": 3, "l2q": 4, "l2q_line": 5, "hit_head": 6,
+        "hit_tail": 7, "miss_head": 8, "miss_tail": 9, "bg_pending": 10, "node_next": 11,
+        "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15}
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def split_dump(buf, params):
+    N = params.width * params.height
+    o = 16
+    out = {"header": buf[:16]}
+    out["links"] = buf[o:o + N * 16].reshape(N, 4, 4); o += N * 16
+    out["core"] = buf[o:o + N * 16].reshape(N, 16); o += N * 16
+    n1 = N * params.l1_sets * params.l1_ways
+    out["l1"] = buf[o:o + n1].reshape(N, params.l1_sets, params.l1_ways); o += n1
+    n2 = N * params.l2_sets * params.l2_ways
+    out["l2"] = buf[o:o + n2].reshape(N, params.l2_sets, params.l2_ways); o += n2
+    out["stats"] = buf[o:o + 96].copy().view(np.int64)
+    return out
+
+
+def quiet_params(width, height, **kw):
+    """A chip with no random traffic: flits and ops come only from the test hooks."""
+    from paper_1508_03235_amd.workload import SimParams
+    base = dict(width=width, height=height, seed=1, op_thr=0, bg_thr=0, shared_lines=2**20,
+                private_lines=0)
+    base.update(kw)
+    return SimParams(**base)
+
+
+def run_flit_trace(make_sim, tr):
+    p = quiet_params(tr["width"], tr["height"])
+    sim = make_sim(p)
+    slots = {}
+    for s in tr["slots"]:
+        slots.setdefault(s["after"], []).append(s)
+    injects = {}
+    for i in tr["inject"]:
+        injects.setdefault(i["at"], []).append(i)
+    for c in range(tr["run"]):
+        for i in injects.get(c, []):
+            sim.force_bg(i["src"], i["dst"])
+        sim.step(1)
+        for s in slots.get(c + 1, []):
+            d = split_dump(sim.dump(), p)
+            got = d["links"][s["tile"], s["port"]].tolist()
+            assert got == s["flit"], (tr["name"], s, got)
+    st = sim.stats()
+    for k, v in tr["stats"].items():
+        assert st[STAT[k]] == v, (tr["name"], k, int(st[STAT[k]]), v)
+    d = split_dump(sim.dump(), p)
+    assert (d["links"][:, :, 0] < 0).all(), "network must be empty at the end"
+
+
+def run_op_trace(make_sim, tr, max_cycles=1000):
+    p = quiet_params(tr["width"], tr["height"], l1_sets=tr["l1_sets"], l1_ways=tr["l1_ways"],
+                     l2_sets=tr["l2_sets"], l2_ways=tr["l2_ways"], l1_lat=tr["l1_lat"],
+                     mem_lat=tr["mem_lat"])
+    sim = make_sim(p)
+    for op in tr["ops"]:
+        start = sim.cycle
+        st0 = sim.stats()
+        sim.force_op(op["tile"], op["line"])
+        checks = {}
+        for s in op.get("slots", []):
+            checks.setdefault(start + s["after"], []).append(("slot", s))
+        for s in op.get("core", []):
+            checks.setdefault(start + s["after"], []).append(("core", s))
+        for _ in range(max_cycles):
+            sim.step(1)
+            for kind, s in checks.get(sim.cycle, []):
+                d = split_dump(sim.dump(), p)
+                if kind == "slot":
+                    got = d["links"][s["tile"], s["port"]].tolist()
+                    assert got == s["flit"], (tr["name"], s, got)
+                else:
+                    for k, v in s.items():
+                        if k in ("after", "tile"):
+                            continue
+                        assert d["core"][s["tile"], CORE[k]] == v, (tr["name"], s, k, d["core"][s["tile"]].tolist())
+            st = sim.stats()
+            if st[STAT["ops_done"]] > st0[STAT["ops_done"]]:
+                break
+        else:
+            raise AssertionError(f"{tr['name']}: op {op} did not finish")
+        lat = int(st[STAT["op_lat"]] - st0[STAT["op_lat"]])
+        assert lat == op["latency"], (tr["name"], op, lat)
+    st = sim.stats()
+    for k, v in tr["stats"].items():
+        assert st[STAT[k]] == v, (tr["name"], k, int(st[STAT[k]]), v)
+    if "final_sets" in tr:
+        d = split_dump(sim.dump(), p)
+        for s, ways in tr["final_sets"].get("l1", {}).items():
+            assert d["l1"][0, int(s)].tolist() == ways
+        for s, ways in tr["final_sets"].get("l2", {}).items():
+            assert d["l2"][0, int(s)].tolist() == ways
