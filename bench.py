@@ -1,0 +1,233 @@
+"""Benchmark: simulated tile-cycles per second of the 208x208 (43,264-tile) chip.
+
+One step = 1,000 simulated cycles of the whole per-cycle path (memory access at L1 and the
+home L2 slice, oldest-first deflection arbitration, traversal/ejection/injection) over every
+tile, running the config-1 cache model plus uniform background traffic at 0.05 flits per
+tile per cycle (a saturated point of the paper-style sweep).  Inputs are synthetic and seeded
+(workload module); all state is resident in HBM before the timed region starts.
+
+Besides the headline line the JSON carries:
+  roofline     - algorithmic bytes per launch of the step kernel / its measured duration,
+                 against the 8 TB/s HBM peak;
+  cpu_baseline - the serial oracle on the host, on a bounded prefix of the same workload;
+  parity       - per-cycle state digests of the GPU run compared with the oracle on that
+                 prefix;
+  sweep        - per-rate throughput and the sweep's outputs (deflection rate, average
+                 latency, L2 hit rate) when --sweep is given;
+  batched      - the 256-chip batch in one launch vs the same chips one at a time (--batched).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+CYCLES_PER_STEP = 1000
+
+
+def algorithmic_bytes(p, st_delta, cycles):
+    """Bytes a cycle sweep must move, from the event counts of the run:
+    every directed link's destination word read and written; 12 payload bytes written and
+    read per flit hop; the 13-word core record read; a 16-byte core word written per
+    injection, ejection and op event; the L1 set (16 B) read and written per op issue and
+    fill; the L2 set (32 B) read and written per lookup; queue nodes (12 B per append, 8 B per
+    pop)."""
+    W, H = p.width, p.height
+    N = W * H
+    links = 4 * N - 2 * W - 2 * H
+    from paper_1508_03235_amd.nocsim import STAT
+    g = lambda k: int(st_delta[STAT[k]])
+    inj = g("inj_req") + g("inj_reply") + g("inj_bg")
+    ej = g("ej_req") + g("ej_reply") + g("ej_bg")
+    b = cycles * (links * 8 + N * 52)
+    b += g("traversals") * 24
+    b += (inj + ej + g("ops_issued") + g("ops_done")) * 16
+    b += (g("ops_issued") + g("ops_done")) * 2 * 16 // 1
+    b += (g("l2_hit") + g("l2_miss")) * 2 * 32
+    b += g("req_received") * 12 + g("reply_sent") * 8
+    return b
+
+
+def kernel_events_ms(sim, n_cycles, torch):
+    """Average duration of one step-kernel launch, timed with events on the chip's stream."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    sim.step(n_cycles, sync=False)
+    e1.record(s)
+    e1.synchronize()
+    _, _, _, chunk = sim.get_launch()
+    launches = -(-n_cycles // chunk)
+    return e0.elapsed_time(e1) / launches, launches
+
+
+def cpu_baseline(p, budget_s=12.0):
+    from oracle import oracle as O
+    o = O.OracleSim(p)
+    t0 = time.perf_counter()
+    n = 0
+    digests = []
+    while time.perf_counter() - t0 < budget_s:
+        digests.append(o.step(50, digests=True))
+        n += 50
+    dt = time.perf_counter() - t0
+    return {"value": p.tiles * n / dt, "unit": "tile-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{p.width}x{p.height} chip, first {n} cycles of the benchmark workload, "
+                      f"serial C oracle (gcc -O2), one host thread, {dt:.1f} s"}, np.concatenate(digests)
+
+
+def run_sweep(nocsim, W, torch, cycles):
+    out = []
+    for rate in W.CONFIG2_RATES:
+        p = W.config2(rate)
+        sim = nocsim.Sim(p)
+        sim.step(200)
+        st0 = sim.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(cycles)
+        dt = time.perf_counter() - t0
+        st = sim.stats() - st0
+        S = nocsim.STAT
+        ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
+        lat = st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]
+        out.append({"rate": rate, "tile_cycles_per_s": p.tiles * cycles / dt,
+                    "deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
+                    "avg_latency": float(lat / max(1, ej)),
+                    "l2_hit_rate": float(st[S["l2_hit"]] / max(1, st[S["l2_hit"]] + st[S["l2_miss"]]))})
+        del sim
+    return out
+
+
+def run_batched(nocsim, W, torch, cycles, plain_chips):
+    params = W.config3()
+    sims = [nocsim.Sim(p) for p in params]
+    for s in sims:
+        s.set_launch(block=256)
+    b = nocsim.Batch(sims, block=256)
+    b.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(cycles)
+    dt = time.perf_counter() - t0
+    tiles = sum(p.tiles for p in params)
+    batched = tiles * cycles / dt
+    # one at a time: the first `plain_chips` chips, each alone with its own best single launch
+    t_plain, tiles_plain = 0.0, 0
+    for s, p in list(zip(sims, params))[:plain_chips]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(cycles)
+        t_plain += time.perf_counter() - t0
+        tiles_plain += p.tiles
+    plain = tiles_plain * cycles / t_plain
+    return {"chips": len(params), "tiles": tiles, "cycles": cycles,
+            "batched_tile_cycles_per_s": batched, "plain_tile_cycles_per_s": plain,
+            "plain_sample_chips": plain_chips, "speedup": batched / plain}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rate", type=float, default=0.05)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--launch", type=str, default="", help="patch_w,patch_h,block,chunk")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: every box in this setup has one GPU, and the simulator "
+              "shards a chip across GPUs only by design (see DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1508_03235_amd import nocsim, workload as W
+
+    torch.cuda.set_device(0)
+    p = W.config2(args.rate)
+    sim = nocsim.Sim(p)
+    if args.launch:
+        sim.set_launch(*[int(v) for v in args.launch.split(",")])
+    pw, ph, block, chunk = sim.get_launch()
+    print(f"# {p.width}x{p.height} chip, launch patch={pw}x{ph} block={block} chunk={chunk}", file=sys.stderr, flush=True)
+
+    # parity on the benchmark configuration: digests of the first cycles vs the oracle
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        cpu, odig = cpu_baseline(p, args.cpu_budget)
+        n_par = len(odig)
+        chk = nocsim.Sim(p)
+        chk.set_launch(pw, ph, block, chunk)
+        gdig = chk.step(n_par, digests=True)
+        parity = {"cycles": n_par, "digests_equal": bool((gdig == odig).all())}
+        del chk
+        print(f"# parity over {n_par} cycles: {parity['digests_equal']}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        sim.step(CYCLES_PER_STEP)
+    torch.cuda.synchronize()
+    st0 = sim.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sim.step(CYCLES_PER_STEP, sync=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.sync()
+    st = sim.stats() - st0
+    cycles = args.steps * CYCLES_PER_STEP
+    value = p.tiles * cycles / dt
+
+    # roofline of the step kernel: event-timed launches on the chip's stream
+    ms_launch, launches = kernel_events_ms(sim, 2 * chunk, torch)
+    abytes_per_launch = algorithmic_bytes(p, st, cycles) / cycles * chunk
+    achieved = abytes_per_launch / (ms_launch * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "step_kernel<true>", "launch_ms": ms_launch, "cycles_per_launch": chunk,
+            "algorithmic_bytes_per_tile_cycle": abytes_per_launch / chunk / p.tiles}
+
+    S = nocsim.STAT
+    ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
+    out = {
+        "metric": "simulated tile-cycles/sec at ~43k-tile mesh, bit-exact vs oracle; batched vs plain",
+        "value": value, "unit": "tile-cycles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"208x208 bufferless mesh (43,264 tiles), config-1 cache model + "
+                               f"uniform background {args.rate} flits/tile/cycle, seed 7, "
+                               f"{CYCLES_PER_STEP} cycles per step",
+                   "tiles": p.tiles, "cycles_per_step": CYCLES_PER_STEP,
+                   "launch": {"patch": [pw, ph], "block": block, "chunk": chunk}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "run": {"deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
+                "avg_latency": float((st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]) / max(1, ej)),
+                "l2_hit_rate": float(st[S["l2_hit"]] / max(1, st[S["l2_hit"]] + st[S["l2_miss"]]))},
+    }
+    if cpu:
+        out["gpu_over_oracle"] = value / cpu["value"]
+    if args.sweep:
+        out["sweep"] = run_sweep(nocsim, W, torch, 5000)
+    if args.batched:
+        out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * nocsim.h -- C ABI of the MI355X (gfx950) simulator of a bufferless deflection-routed
+ * 2D-mesh chip multicore with a logically shared, physically distributed L2.
+ *
+ * Method: Kumar & Sahu, "Bufferless NOC Simulation of Large Multicore System on GPU
+ * Hardware" (arXiv 1508.03235).  One call of the step advances every tile of every
+ * simulated chip by whole cycles; each cycle runs the paper's three phases per router
+ * (Sec. 7.1): the memory access (private L1, then the line's home L2 slice, Sec. 3.1-3.5),
+ * oldest-first bufferless deflection arbitration with X-then-Y productive preference and
+ * injection only into a free input (Sec. 4.2-4.3, Sec. 6.2.1), and link traversal,
+ * ejection and injection.
+ *
+ * Conventions
+ *  - Every function returns an int32 status: SIM_OK (0) or a negative SIM_E* code; nothing
+ *    throws.  sim_strerror() names a code.
+ *  - Device memory is owned by the caller: sim_state_bytes() sizes one buffer, which the
+ *    caller allocates (e.g. torch.empty(bytes, dtype=torch.uint8, device="cuda")) and passes
+ *    as `dev_mem` together with a hipStream_t (`stream`, NULL = default stream).  The
+ *    library allocates no device memory; it keeps the pointer and never frees it.  The
+ *    buffer must stay alive until sim_destroy()/simb_destroy().
+ *  - Steps are asynchronous on the stream.  sim_stats, sim_dump, sim_load and the test hooks
+ *    synchronise the stream.
+ *  - A handle is bound to one stream and is not thread safe.  Two handles may share nothing.
+ *  - Host pointers are plain host memory; `dev_*` pointers are device memory.
+ *  - Tile numbering: tile = y * width + x, x = column, y = row; ports 0..3 = north (y-1),
+ *    south (y+1), east (x+1), west (x-1).
+ */
+#ifndef NOCSIM_H
+#define NOCSIM_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SIM_OK = 0,
+  SIM_EINVAL = -1,     /* bad argument or shape (see sim_state_bytes) */
+  SIM_ENOMEM = -2,     /* device buffer too small */
+  SIM_EHIP = -3,       /* a HIP runtime call failed; sim_last_hip_error() has the code */
+  SIM_EINVARIANT = -4, /* a state index out of range was caught on the device */
+  SIM_EBUSY = -5,      /* slot in use / no free slot */
+  SIM_EHANG = -6       /* a bounded cross-workgroup wait ran out; results are invalid */
+};
+
+/* Model parameters of one simulated chip.  Bernoulli draws are u32 and succeed when
+   draw < threshold (threshold = floor(p * 2^32)). */
+typedef struct {
+  int32_t width, height;      /* 1..2048 each, width*height <= 2^20 */
+  uint32_t seed_lo, seed_hi;  /* Philox4x32-10 key */
+  int32_t l1_sets, l1_ways;   /* private L1 per tile: sets a power of two, ways in {1,2,4,8} */
+  int32_t l2_sets, l2_ways;   /* L2 slice per tile, same constraints */
+  int32_t l1_lat;             /* cycles from an L1 miss to its follow-up, >= 1 */
+  int32_t mem_lat;            /* latency of an L2 miss (off-chip memory), >= 1 */
+  uint32_t op_thr;            /* a memory op is issued by an idle core when draw < op_thr */
+  uint32_t shared_thr;        /* the op goes to the shared region when draw < shared_thr */
+  uint32_t bg_thr;            /* a background flit is generated when draw < bg_thr */
+  int32_t shared_lines;       /* shared region = lines [0, shared_lines) */
+  int32_t private_lines;      /* per-tile private region (0 = none); shared_lines +
+                                 width*height*private_lines must be <= 2^30 */
+  int32_t flags;              /* 0 */
+} sim_config;
+
+/* Statistics: 48 int64 counters (index = position in `v`).  Latencies are in cycles from
+   injection to ejection; op latency from issue to L1 fill. */
+enum {
+  SIM_ST_CYCLES = 0,
+  SIM_ST_INJ_REQ = 1, SIM_ST_INJ_REPLY = 2, SIM_ST_INJ_BG = 3,
+  SIM_ST_EJ_REQ = 4, SIM_ST_EJ_REPLY = 5, SIM_ST_EJ_BG = 6,
+  SIM_ST_LAT_REQ = 7, SIM_ST_LAT_REPLY = 8, SIM_ST_LAT_BG = 9,
+  SIM_ST_LAT_MAX = 10,
+  SIM_ST_TRAVERSALS = 11,   /* flits sent over a link */
+  SIM_ST_DEFLECTIONS = 12,  /* flits sent over a non-productive link */
+  SIM_ST_OPS_ISSUED = 13, SIM_ST_OPS_DONE = 14, SIM_ST_OP_LAT = 15,
+  SIM_ST_L1_HIT = 16, SIM_ST_L1_MISS = 17, SIM_ST_L2_HIT = 18, SIM_ST_L2_MISS = 19,
+  SIM_ST_REQ_MADE = 20, SIM_ST_REQ_RECV = 21, SIM_ST_REPLY_SENT = 22, SIM_ST_REPLY_RECV = 23,
+  SIM_ST_INJ_BLOCKED = 24,  /* tile-cycles with a flit to inject but no free input */
+  SIM_ST_BG_GEN = 25, SIM_ST_OP_LAT_MAX = 26,
+  SIM_ST_HIST = 32,         /* 16 bins of floor(log2(latency)); the last bin is open */
+  SIM_ST_COUNT = 48
+};
+typedef struct { int64_t v[SIM_ST_COUNT]; } sim_stats_t;
+
+typedef struct sim_chip sim_t;    /* one chip */
+typedef struct sim_group simb_t;  /* many chips advanced by one launch */
+
+/* Bytes of device state for one chip; 0 if the config is invalid.  Zipf tables are
+   included. */
+size_t sim_state_bytes(const sim_config* cfg);
+
+/* Creates one chip in `dev_mem` and initialises it (all links empty, cores idle, caches
+   invalid, cycle 0).  zipf_shared / zipf_private: host arrays of zipf_k + 1 (= 65537)
+   uint32 quantile boundaries (entry b = first rank whose CDF exceeds b/zipf_k; entry
+   zipf_k = region size); zipf_private may be NULL when private_lines == 0.  Copied. */
+int sim_create(const sim_config* cfg, const uint32_t* zipf_shared, const uint32_t* zipf_private,
+               int32_t zipf_k, void* dev_mem, size_t bytes, void* stream, sim_t** out);
+
+/* Advances the chip by n_cycles whole cycles (Sec. 7.1 main loop; each cycle = phase one
+   memory access, phase two arbitration, phase three traversal/ejection/injection for all
+   tiles).  dev_digests: NULL, or a device array of n_cycles uint64 that receives the state
+   digest of each cycle (sum over tiles of a SplitMix64 chain over the tile's input slots and
+   core words); asks for a slower checking launch.  Asynchronous. */
+int sim_step(sim_t* h, int64_t n_cycles, uint64_t* dev_digests);
+
+/* Waits for the chip's stream and reports SIM_EHANG if a cross-workgroup wait timed out. */
+int sim_sync(sim_t* h);
+
+/* Cycles run so far (counting steps already enqueued). */
+int64_t sim_cycle(const sim_t* h);
+
+/* Statistics of the chip (synchronises). */
+int sim_stats(sim_t* h, sim_stats_t* out);
+
+/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 1, width,
+   height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, 0...}, then per tile the 4
+   input slots of the next cycle ({dst (-1 = empty), inject cycle, source, kind<<30 | line}),
+   then per tile 16 core words {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail,
+   miss_head, miss_tail, bg_pending, node_next, node_ready, node_line, force_line,
+   force_dst}, then L1 and L2 tags per tile per set (most recently used first, -1 invalid),
+   then the 48 statistics as (low, high) word pairs.  sim_dump_words() gives the size in
+   int32 words. */
+size_t sim_dump_words(const sim_t* h);
+int sim_dump(sim_t* h, int32_t* host_buf, size_t words);
+/* Restores a canonical state produced by sim_dump (checkpoint / resume). */
+int sim_load(sim_t* h, const int32_t* host_buf, size_t words);
+
+/* Test hooks (synchronise): make `tile` issue a memory op on `line` at its next idle cycle;
+   make `tile` inject a background flit to `dst` (priority just above random background). */
+int sim_force_op(sim_t* h, int32_t tile, int32_t line);
+int sim_force_bg(sim_t* h, int32_t tile, int32_t dst);
+/* Changes the op-issue and background thresholds from the next step on (0, 0 = drain). */
+int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr);
+
+/* Launch mapping: patch_w x patch_h tiles per workgroup (the chip is cut into patches that
+   exchange boundary links through per-patch cycle flags), `block` threads per workgroup (64..256, a multiple of 64),
+   `chunk` cycles per launch.  0 keeps the current value.  EINVAL if the patch grid cannot
+   be resident on the device at once. */
+int sim_set_launch(sim_t* h, int32_t patch_w, int32_t patch_h, int32_t block, int32_t chunk);
+int sim_get_launch(const sim_t* h, int32_t* patch_w, int32_t* patch_h, int32_t* block, int32_t* chunk);
+
+int sim_destroy(sim_t* h);
+const char* sim_strerror(int code);
+int sim_last_hip_error(void);
+
+/* ---- batches: many independent chips advanced by one persistent launch ---------------- */
+/* A batch groups chips created with sim_create (each in its own buffer) so that one launch
+   advances all of them: workgroup w runs one patch of one chip, and chips never wait on each
+   other.  The launch table lives in a caller-owned device buffer of simb_state_bytes().  The
+   batch launches on its own stream; the caller orders any per-chip call with it.  Chips keep
+   their own launch mapping, except the workgroup size, which is the batch's `block` (0 =
+   largest of the chips').  A chip cut into several patches needs all of its workgroups
+   resident at once: simb_create returns SIM_EINVAL when the batch grid cannot be. */
+size_t simb_state_bytes(int32_t n_chips, int64_t n_patches);
+int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, size_t bytes,
+                void* stream, simb_t** out);
+/* Advances chip i by cycles[i] >= 0 cycles (host array of n), all in one persistent launch
+   per `chunk` cycles; chips that need fewer cycles stop early.  Asynchronous. */
+int simb_step(simb_t* b, const int64_t* cycles);
+int simb_destroy(simb_t* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

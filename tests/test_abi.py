@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every symbol include/nocsim.h declares; host-only
+calls (sizing, validation, error strings) work without a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1508_03235_amd import nocsim, workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nocsim.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_\w+|simb_\w+)\s*\(", src)))
+
+
+def test_header_declares_binding_surface():
+    assert sorted(nocsim.exported_symbols()) == declared_functions()
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(nocsim.LIB_PATH), "build the library first (__graft_entry__.build())"
+    out = subprocess.check_output(["nm", "-D", "--defined-only", nocsim.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    lib = nocsim._lib()
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_state_bytes_and_validation():
+    p = W.config2(0.05)
+    n = nocsim.state_bytes(p)
+    N = 208 * 208
+    assert n >= N * (128 * 4 * 4 + 512 * 8 * 4)       # L1 + L2 tags
+    assert n < N * 22_000
+    lib = nocsim._lib()
+    bad = [p.with_(l1_sets=100), p.with_(l2_ways=3), p.with_(width=0), p.with_(mem_lat=0),
+           p.with_(width=2048, height=1024), p.with_(private_lines=2**20)]
+    for b in bad:
+        cfg = nocsim.SimConfig.from_params(b)
+        assert lib.sim_state_bytes(C.byref(cfg)) == 0, b
+    assert lib.sim_strerror(-6) == b"cross-workgroup wait timed out"
+    assert lib.simb_state_bytes(4, 3) == 0
+
+
+def test_null_handles_rejected():
+    lib = nocsim._lib()
+    assert lib.sim_step(None, 1, None) == -1
+    assert lib.sim_stats(None, None) == -1
+    assert lib.simb_step(None, None) == -1

@@ -1,0 +1,142 @@
+"""Parity of the HIP path (through the C ABI) with the serial oracle.
+
+Bar: bit-exact.  Every per-cycle state digest and the final canonical dump (link slots,
+core words, queue nodes, every L1/L2 tag in LRU order, all statistics) must be identical.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1508_03235_amd import workload as W
+from tests.harness import STAT, load_golden, run_flit_trace, run_op_trace, split_dump
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_sim(p, launch=None):
+    from paper_1508_03235_amd import nocsim
+    s = nocsim.Sim(p)
+    if launch:
+        s.set_launch(*launch)
+    return s
+
+
+def assert_same_run(p, cycles, launch=None, step_sizes=None):
+    g = gpu_sim(p, launch)
+    o = O.OracleSim(p)
+    steps = step_sizes or [cycles]
+    for n in steps:
+        dg = g.step(n, digests=True)
+        do = o.step(n, digests=True)
+        bad = np.nonzero(dg != do)[0]
+        assert len(bad) == 0, f"{p.width}x{p.height} launch={launch}: digest differs at cycle {g.cycle - n + bad[0]}"
+    a, b = g.dump(), o.dump()
+    if not (a == b).all():
+        da, db = split_dump(a, p), split_dump(b, p)
+        for k in ("links", "core", "l1", "l2", "stats"):
+            if not np.array_equal(da[k], db[k]):
+                idx = np.argwhere(da[k] != db[k])[:5]
+                raise AssertionError(f"dump section {k} differs at {idx.tolist()}")
+    return g, o
+
+
+GOLD = load_golden("hand_traces.json")
+
+
+@pytest.mark.parametrize("tr", GOLD["flit_traces"], ids=lambda t: t["name"])
+def test_gpu_hand_flit_trace(tr):
+    run_flit_trace(gpu_sim, tr)
+
+
+@pytest.mark.parametrize("tr", GOLD["op_traces"], ids=lambda t: t["name"])
+def test_gpu_hand_op_trace(tr):
+    run_op_trace(gpu_sim, tr)
+
+
+def test_config0_full_run():
+    """4x4, 10,000 cycles, background 0.05 + Zipf(0.8) cache traffic, seed 1."""
+    assert_same_run(W.config0(), 10_000, step_sizes=[1, 999, 4000, 5000])
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (9, 1), (2, 3), (5, 5), (13, 7)])
+def test_small_shapes(w, h):
+    p = W.config0().with_(width=w, height=h, seed=w * 100 + h, bg_thr=W.thr(0.2) if w * h > 1 else 0,
+                          op_thr=W.thr(0.5))
+    assert_same_run(p, 3000)
+
+
+@pytest.mark.parametrize("launch", [(4, 4, 64, 0), (3, 5, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (1, 13, 64, 0),
+                                    (5, 5, 64, 37)])
+def test_patch_mappings_are_exact(launch):
+    """The chip cut into patches (edges exchanged through cycle flags) gives the same run as
+    the oracle for patch shapes that do and do not divide the mesh, and odd chunk lengths."""
+    p = W.config0().with_(width=20, height=13, seed=5, bg_thr=W.thr(0.15), op_thr=W.thr(0.5))
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+
+
+def test_config1_prefix():
+    """64x64, the cache-only model (30% shared Zipf(0.9) over 2^24 lines, 70% private)."""
+    assert_same_run(W.config1(), 1500, step_sizes=[500, 1000])
+
+
+@pytest.mark.parametrize("rate", [0.01, 0.3])
+def test_config2_full_size_prefix(rate):
+    """208x208 (43,264 tiles) in the launch configuration the benchmark times: a prefix of
+    the run, every cycle compared."""
+    assert_same_run(W.config2(rate), 120)
+
+
+def test_repeatable_and_mapping_independent():
+    p = W.config0().with_(width=16, height=16, seed=3, bg_thr=W.thr(0.1), op_thr=W.thr(0.4))
+    runs = []
+    for launch in [None, (4, 4, 64, 0), (16, 1, 64, 0), (8, 8, 64, 100)]:
+        g = gpu_sim(p, launch)
+        runs.append(g.step(800, digests=True))
+    for r in runs[1:]:
+        assert (r == runs[0]).all()
+
+
+def test_checkpoint_resume_on_gpu():
+    p = W.config0().with_(width=8, height=8, seed=11, bg_thr=W.thr(0.1))
+    a = gpu_sim(p)
+    da = a.step(1000, digests=True)
+    b = gpu_sim(p)
+    b.step(400)
+    snap = b.dump()
+    c = gpu_sim(p)
+    c.load(snap)
+    dc = c.step(600, digests=True)
+    assert (dc == da[400:]).all()
+    assert (c.dump() == a.dump()).all()
+
+
+def test_drain_on_gpu_matches_oracle():
+    p = W.config0().with_(width=6, height=6, seed=21, bg_thr=W.thr(0.2), op_thr=W.thr(0.5))
+    g, o = gpu_sim(p), O.OracleSim(p)
+    g.step(1500)
+    o.step(1500)
+    g.set_rates(0, 0)
+    o.set_rates(0, 0)
+    g.step(1500)
+    o.step(1500)
+    assert (g.dump() == o.dump()).all()
+    assert o.quiescent()
+    st = g.stats()
+    assert st[STAT["req_made"]] == st[STAT["req_received"]] == st[STAT["reply_sent"]] == st[STAT["reply_received"]]
+
+
+def test_batch_each_chip_matches_its_own_run():
+    """Chips of uneven sizes, seeds and rates advanced by one launch equal their oracle runs."""
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=1000 + i, bg_thr=W.thr(r))
+              for i, (s, r) in enumerate([(8, 0.01), (16, 0.3), (24, 0.1), (8, 0.2), (32, 0.05)])]
+    sims = [gpu_sim(p) for p in params]
+    b = nocsim.Batch(sims)
+    cycles = [300, 250, 300, 123, 0]
+    b.step(cycles)
+    b.step([200, 250, 0, 77, 100])
+    for p, s, c0, c1 in zip(params, sims, cycles, [200, 250, 0, 77, 100]):
+        o = O.OracleSim(p)
+        o.step(c0 + c1)
+        assert s.cycle == c0 + c1
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} seed {p.seed}"
