@@ -13,8 +13,8 @@ Besides the headline line the JSON carries:
   parity       - per-cycle state digests of the GPU run compared with the oracle on that
                  prefix;
   sweep        - per-rate throughput and the sweep's outputs (deflection rate, average
-                 latency, L2 hit rate) when --sweep is given;
-  batched      - the 256-chip batch in one launch vs the same chips one at a time (--batched).
+                 latency, L2 hit rate) (skip with --no-sweep);
+  batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched).
 """
 from __future__ import annotations
 
@@ -111,8 +111,8 @@ def run_sweep(nocsim, W, torch, cycles):
 def run_batched(nocsim, W, torch, cycles, plain_chips):
     params = W.config3()
     sims = [nocsim.Sim(p) for p in params]
-    for s in sims:
-        s.set_launch(block=256)
+    for s, p in zip(sims, params):
+        s.set_launch(p.width, p.height, 256, 0)  # one workgroup per chip
     b = nocsim.Batch(sims, block=256)
     b.step(10)
     torch.cuda.synchronize()
@@ -121,14 +121,19 @@ def run_batched(nocsim, W, torch, cycles, plain_chips):
     dt = time.perf_counter() - t0
     tiles = sum(p.tiles for p in params)
     batched = tiles * cycles / dt
-    # one at a time: the first `plain_chips` chips, each alone with its own best single launch
+    del b, sims
+    # one at a time: the first `plain_chips` chips, each alone with the default single-chip
+    # mapping (patches spread over the device for the larger chips)
     t_plain, tiles_plain = 0.0, 0
-    for s, p in list(zip(sims, params))[:plain_chips]:
+    for p in params[:plain_chips]:
+        s = nocsim.Sim(p)
+        s.step(10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(cycles)
         t_plain += time.perf_counter() - t0
         tiles_plain += p.tiles
+        del s
     plain = tiles_plain * cycles / t_plain
     return {"chips": len(params), "tiles": tiles, "cycles": cycles,
             "batched_tile_cycles_per_s": batched, "plain_tile_cycles_per_s": plain,
@@ -143,10 +148,23 @@ def main():
     ap.add_argument("--rate", type=float, default=0.05)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sweep", action="store_true")
-    ap.add_argument("--batched", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--launch", type=str, default="", help="patch_w,patch_h,block,chunk")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (scales the "
+                         "profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 3}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: every box in this setup has one GPU, and the simulator "
               "shards a chip across GPUs only by design (see DESIGN.md); run with --gpus 1.",
@@ -222,10 +240,16 @@ def main():
     }
     if cpu:
         out["gpu_over_oracle"] = value / cpu["value"]
-    if args.sweep:
-        out["sweep"] = run_sweep(nocsim, W, torch, 5000)
-    if args.batched:
-        out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
+    if not args.no_sweep:
+        try:
+            out["sweep"] = run_sweep(nocsim, W, torch, 5000)
+        except Exception as e:  # an optional leg must not hide the headline number
+            out["sweep"] = {"error": repr(e)}
+    if not args.no_batched:
+        try:
+            out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
+        except Exception as e:
+            out["batched"] = {"error": repr(e)}
     print(json.dumps(out))
 
 

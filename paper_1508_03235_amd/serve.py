@@ -1,0 +1,221 @@
+"""Serving loop: simulation jobs admitted as they arrive, run with continuous batching.
+
+Each job is one chip (its own device buffer).  A job is admitted when its buffer fits the
+HBM state budget and a slot is free; every scheduler tick advances all resident jobs
+together by one persistent launch (`simb_step`: one workgroup per chip, each chip with its
+own remaining cycle count), retires the jobs that finished, reads their statistics, frees
+their memory and admits new arrivals.  Requests that arrive while others run join at the
+next tick, so their work overlaps on the device.  Because every chip's randomness is keyed
+by its own (seed; cycle, tile), a job's result does not depend on what it ran beside.
+
+The scheduler is written against a small backend interface so that its admission, memory
+accounting and completion logic can be tested on the CPU with the oracle behind it.
+"""
+from __future__ import annotations
+
+import heapq
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+import numpy as np
+
+
+@dataclass
+class JobResult:
+    index: int
+    arrival_s: float
+    admit_s: float
+    finish_s: float
+    cycles: int
+    tiles: int
+    stats: np.ndarray
+    digest: Optional[np.ndarray] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.finish_s - self.arrival_s
+
+
+class Backend:
+    """What the scheduler needs from a simulator."""
+
+    def state_bytes(self, params) -> int: ...
+    def create(self, params): ...
+    def step(self, chips: list, cycles: list[int]) -> None: ...
+    def stats(self, chip) -> np.ndarray: ...
+    def release(self, chip) -> None: ...
+
+
+class GpuBackend(Backend):
+    """Chips on the GPU through the C ABI; one batched launch per tick."""
+
+    def __init__(self, block: int = 256, chunk: int = 1000):
+        from paper_1508_03235_amd import nocsim
+        self.nocsim = nocsim
+        self.block = block
+        self.chunk = chunk
+
+    def state_bytes(self, params) -> int:
+        return self.nocsim.state_bytes(params) + 256
+
+    def create(self, params):
+        s = self.nocsim.Sim(params)
+        s.set_launch(params.width, params.height, self.block, self.chunk)
+        return s
+
+    def step(self, chips, cycles):
+        b = self.nocsim.Batch(chips, block=self.block)
+        b.step(cycles)
+        b.close()
+
+    def stats(self, chip):
+        return chip.stats()
+
+    def release(self, chip):
+        chip.close()
+        del chip.mem
+
+
+class OracleBackend(Backend):
+    """The serial oracle behind the same interface (test double for the scheduler)."""
+
+    def __init__(self):
+        from oracle import oracle as O
+        self.O = O
+
+    def state_bytes(self, params) -> int:
+        N = params.tiles
+        return N * (128 + 64 + 16 + 4 * (params.l1_sets * params.l1_ways + params.l2_sets * params.l2_ways))
+
+    def create(self, params):
+        return self.O.OracleSim(params)
+
+    def step(self, chips, cycles):
+        for c, n in zip(chips, cycles):
+            if n:
+                c.step(int(n))
+
+    def stats(self, chip):
+        return chip.stats()
+
+    def release(self, chip):
+        chip.close()
+
+
+@dataclass
+class _Live:
+    job: object
+    chip: object
+    remaining: int
+    admit_s: float
+    nbytes: int
+
+
+@dataclass
+class ServeReport:
+    results: list
+    wall_s: float
+    tile_cycles: int
+    peak_bytes: int
+    ticks: int
+
+    def latency_percentiles(self):
+        lat = np.array([r.latency_s for r in self.results])
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    @property
+    def tile_cycles_per_s(self) -> float:
+        return self.tile_cycles / self.wall_s if self.wall_s > 0 else 0.0
+
+
+class Server:
+    """Continuous-batching scheduler over a Backend.
+
+    budget_bytes: device-state budget across resident jobs.  max_slots: resident jobs at once.
+    tick_cycles: cycles each resident job advances per tick (or fewer if it finishes).
+    clock: time source; `realtime=False` replays arrivals on a virtual clock that advances by
+    the measured duration of each tick (so a run does not sleep through idle gaps).
+    """
+
+    def __init__(self, backend: Backend, budget_bytes: int, max_slots: int = 512,
+                 tick_cycles: int = 2000, realtime: bool = False,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.backend = backend
+        self.budget = budget_bytes
+        self.max_slots = max_slots
+        self.tick_cycles = tick_cycles
+        self.realtime = realtime
+        self.clock = clock
+
+    def run(self, jobs, on_finish=None) -> ServeReport:
+        pending = sorted(jobs, key=lambda j: j.arrival_s)
+        for j in pending:
+            if self.backend.state_bytes(j.params) > self.budget:
+                raise ValueError(f"job {j.index} needs more than the whole budget")
+        arrivals = list(pending)
+        arrivals.reverse()           # pop() gives the earliest
+        waiting: list = []           # arrived, not admitted (FIFO)
+        live: list[_Live] = []
+        used = 0
+        peak = 0
+        results = []
+        tile_cycles = 0
+        ticks = 0
+        t_start = self.clock()
+        vnow = 0.0                   # virtual time since start
+
+        def now():
+            return self.clock() - t_start if self.realtime else vnow
+
+        while arrivals or waiting or live:
+            t = now()
+            while arrivals and arrivals[-1].arrival_s <= t:
+                waiting.append(arrivals.pop())
+            if not live and not waiting and arrivals:
+                # idle: jump (or sleep) to the next arrival
+                nxt = arrivals[-1].arrival_s
+                if self.realtime:
+                    time.sleep(max(0.0, nxt - t))
+                else:
+                    vnow = nxt
+                continue
+            # admit in arrival order while memory and slots allow (no overtaking)
+            while waiting and len(live) < self.max_slots:
+                j = waiting[0]
+                nb = self.backend.state_bytes(j.params)
+                if used + nb > self.budget:
+                    break
+                waiting.pop(0)
+                chip = self.backend.create(j.params)
+                used += nb
+                peak = max(peak, used)
+                live.append(_Live(j, chip, j.cycles, now(), nb))
+            # one tick: every resident job advances together
+            steps = [min(self.tick_cycles, lv.remaining) for lv in live]
+            t0 = self.clock()
+            self.backend.step([lv.chip for lv in live], steps)
+            dt = self.clock() - t0
+            if not self.realtime:
+                vnow += dt
+            ticks += 1
+            for lv, n in zip(live, steps):
+                lv.remaining -= n
+                tile_cycles += n * lv.job.params.tiles
+            still = []
+            for lv in live:
+                if lv.remaining == 0:
+                    st = self.backend.stats(lv.chip)
+                    r = JobResult(lv.job.index, lv.job.arrival_s, lv.admit_s, now(), lv.job.cycles,
+                                  lv.job.params.tiles, st)
+                    if on_finish:
+                        on_finish(r, lv.chip)
+                    results.append(r)
+                    self.backend.release(lv.chip)
+                    used -= lv.nbytes
+                else:
+                    still.append(lv)
+            live = still
+        wall = now()
+        results.sort(key=lambda r: r.index)
+        return ServeReport(results, wall, tile_cycles, peak, ticks)
