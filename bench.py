@@ -14,7 +14,9 @@ Besides the headline line the JSON carries:
                  prefix;
   sweep        - per-rate throughput and the sweep's outputs (deflection rate, average
                  latency, L2 hit rate) (skip with --no-sweep);
-  batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched).
+  batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
+  serving      - Poisson-arriving simulation jobs under continuous batching: p50/p99 job
+                 latency and aggregate throughput, against one job at a time (--no-serving).
 """
 from __future__ import annotations
 
@@ -70,6 +72,24 @@ def kernel_events_ms(sim, n_cycles, torch):
     return e0.elapsed_time(e1) / launches, launches
 
 
+def profiled_traffic(kernel_tag):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a copy
+    calibration) for this exact kernel source, or None when the source changed since."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1508_03235_amd", "csrc", "nocsim.hip")
+    prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_208x208_bg0.05_counters.md")
+    if not os.path.exists(prof):
+        return None
+    text = open(prof).read()
+    m_sha = re.search(r"kernel source sha256 \(first 16 hex\): ([0-9a-f]{16})", text)
+    m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if not m_sha or not m_b or m_sha.group(1) != sha:
+        return None
+    return int(m_b.group(1))
+
+
 def cpu_baseline(p, budget_s=12.0):
     from oracle import oracle as O
     o = O.OracleSim(p)
@@ -112,7 +132,8 @@ def run_batched(nocsim, W, torch, cycles, plain_chips):
     params = W.config3()
     sims = [nocsim.Sim(p) for p in params]
     for s, p in zip(sims, params):
-        s.set_launch(p.width, p.height, 256, 0)  # one workgroup per chip
+        side = min(16, p.width)
+        s.set_launch(side, side, 256, 0)  # patches of <= 256 tiles: one tile per thread
     b = nocsim.Batch(sims, block=256)
     b.step(10)
     torch.cuda.synchronize()
@@ -140,6 +161,32 @@ def run_batched(nocsim, W, torch, cycles, plain_chips):
             "plain_sample_chips": plain_chips, "speedup": batched / plain}
 
 
+def run_serving(W, n_jobs, one_at_a_time_jobs):
+    """Config 4: Poisson arrivals (50 jobs/s) of jobs with side U[4,128] and cycles
+    log-U[1e4, 2e5], admitted under a 200 GB state budget, continuous batching; against the
+    same arrival stream served one job at a time."""
+    from paper_1508_03235_amd.serve import GpuBackend, Server
+    jobs = W.config4(n_jobs)
+    be = GpuBackend(block=256, chunk=1000)
+    rep = Server(be, budget_bytes=200 << 30, tick_cycles=2000, realtime=True).run(jobs)
+    p50, p99 = rep.latency_percentiles()
+    out = {"jobs": n_jobs, "arrival_rate_per_s": 50.0, "budget_gb": 200,
+           "tile_cycles_per_s": rep.tile_cycles_per_s, "p50_latency_s": p50, "p99_latency_s": p99,
+           "wall_s": rep.wall_s, "ticks": rep.ticks, "peak_state_gb": rep.peak_bytes / 2**30}
+    if one_at_a_time_jobs:
+        sub = jobs[:one_at_a_time_jobs]
+        rep1 = Server(be, budget_bytes=200 << 30, max_slots=1, tick_cycles=2000, realtime=True).run(sub)
+        q50, q99 = rep1.latency_percentiles()
+        rep2 = Server(be, budget_bytes=200 << 30, tick_cycles=2000, realtime=True).run(sub)
+        r50, r99 = rep2.latency_percentiles()
+        out["same_jobs"] = {"jobs": len(sub),
+                            "one_at_a_time": {"tile_cycles_per_s": rep1.tile_cycles_per_s, "p50_latency_s": q50,
+                                              "p99_latency_s": q99, "wall_s": rep1.wall_s},
+                            "continuous_batching": {"tile_cycles_per_s": rep2.tile_cycles_per_s,
+                                                    "p50_latency_s": r50, "p99_latency_s": r99, "wall_s": rep2.wall_s}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +197,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=60)
     ap.add_argument("--launch", type=str, default="", help="patch_w,patch_h,block,chunk")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (scales the "
@@ -214,10 +263,15 @@ def main():
     ms_launch, launches = kernel_events_ms(sim, 2 * chunk, torch)
     abytes_per_launch = algorithmic_bytes(p, st, cycles) / cycles * chunk
     achieved = abytes_per_launch / (ms_launch * 1e-3) / 1e9
+    fast = pw * ph <= block
+    kernel = "step_fast<true>" if fast else "step_kernel<true>"
+    traffic = profiled_traffic("step_fast" if fast else "step_kernel") if (args.rate == 0.05 and not args.launch) else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "step_kernel<true>", "launch_ms": ms_launch, "cycles_per_launch": chunk,
-            "algorithmic_bytes_per_tile_cycle": abytes_per_launch / chunk / p.tiles}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": kernel, "launch_ms": ms_launch, "cycles_per_launch": chunk,
+            "algorithmic_bytes_per_tile_cycle": abytes_per_launch / chunk / p.tiles,
+            "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 "
+                            "(profiles/, same kernel source hash), null if the source changed"}
 
     S = nocsim.STAT
     ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
@@ -250,6 +304,11 @@ def main():
             out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
         except Exception as e:
             out["batched"] = {"error": repr(e)}
+    if not args.no_serving:
+        try:
+            out["serving"] = run_serving(W, args.serving_jobs, one_at_a_time_jobs=12)
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
     print(json.dumps(out))
 
 

@@ -47,7 +47,7 @@ enum {
 /* Model parameters of one simulated chip.  Bernoulli draws are u32 and succeed when
    draw < threshold (threshold = floor(p * 2^32)). */
 typedef struct {
-  int32_t width, height;      /* 1..2048 each, width*height <= 2^20 */
+  int32_t width, height;      /* 1..2048 each, width*height < 2^20 */
   uint32_t seed_lo, seed_hi;  /* Philox4x32-10 key */
   int32_t l1_sets, l1_ways;   /* private L1 per tile: sets a power of two, ways in {1,2,4,8} */
   int32_t l2_sets, l2_ways;   /* L2 slice per tile, same constraints */
@@ -138,6 +138,10 @@ int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr);
    be resident on the device at once. */
 int sim_set_launch(sim_t* h, int32_t patch_w, int32_t patch_h, int32_t block, int32_t chunk);
 int sim_get_launch(const sim_t* h, int32_t* patch_w, int32_t* patch_h, int32_t* block, int32_t* chunk);
+/* Kernel choice: when every patch has at most `block` tiles the library runs a kernel that keeps
+   one tile per thread in registers and interior links in LDS; generic_only = 1 forces the
+   general kernel (several tiles per thread, all state in HBM).  Both give identical results. */
+int sim_set_kernel(sim_t* h, int32_t generic_only);
 
 int sim_destroy(sim_t* h);
 const char* sim_strerror(int code);

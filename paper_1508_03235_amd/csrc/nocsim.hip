@@ -43,6 +43,8 @@ struct ChipDev {
   int32_t W, H, N, n_patches;
   uint32_t key0, key1, op_thr, shared_thr;
   uint32_t bg_thr, w_magic;  // w_magic = ceil(2^32 / W) (W > 1): tile / W = umulhi(tile, w_magic)
+  uint32_t n_magic, n_shift; // line / N = umulhi(line, n_magic) >> n_shift for line < 2^30, N >= 2
+  int32_t w1_shift, w2_shift; // log2 of the way counts
   int32_t s1, w1, s2, w2;
   int32_t l1_lat, mem_lat, shared_lines, private_lines;
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
@@ -66,31 +68,84 @@ struct LaunchEntry {
   int32_t stop;
 };
 
+// All chip state is in device global memory; pointers are cast to the global address space so
+// accesses compile to global (not flat) instructions with a scalar base.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gp(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int4 gload4(const int4* p) {
+  const v4i v = *(const __attribute__((address_space(1))) v4i*)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore4(int4* p, const int4& a) {
+  v4i v;
+  v.x = a.x; v.y = a.y; v.z = a.z; v.w = a.w;
+  *(__attribute__((address_space(1))) v4i*)p = v;
+}
+__device__ __forceinline__ int2 gload2(const int2* p) {
+  const v2i v = *(const __attribute__((address_space(1))) v2i*)p;
+  return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore2(int2* p, const int2& a) {
+  v2i v;
+  v.x = a.x; v.y = a.y;
+  *(__attribute__((address_space(1))) v2i*)p = v;
+}
+
 // ---- coherent access for state that crosses workgroups -------------------------------------
 // Link slots on a patch edge and reply-queue nodes of a multi-patch chip are read and written
 // by different workgroups, possibly on different XCDs; they use device-scope relaxed atomics,
 // and stores are ordered before the cycle flag with s_waitcnt.
 __device__ __forceinline__ int ld_coh(const int* p) {
-  return __hip_atomic_load(const_cast<int*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(const_cast<int*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh(int* p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int4 ld_slot(const int4* p, bool coh) {
-  if (!coh) return *p;
-  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
-  unsigned long long a = __hip_atomic_load(const_cast<unsigned long long*>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  unsigned long long b = __hip_atomic_load(const_cast<unsigned long long*>(q + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!coh) return gload4(p);
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<int4*>(p));
+  unsigned long long a = __hip_atomic_load(gp(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long b = __hip_atomic_load(gp(q + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return make_int4((int)(uint32_t)a, (int)(uint32_t)(a >> 32), (int)(uint32_t)b, (int)(uint32_t)(b >> 32));
 }
 __device__ __forceinline__ void st_slot(int4* p, int4 v, bool coh) {
-  if (!coh) { *p = v; return; }
+  if (!coh) { gstore4(p, v); return; }
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-  __hip_atomic_store(q, (unsigned long long)(uint32_t)v.x | ((unsigned long long)(uint32_t)v.y << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(q + 1, (unsigned long long)(uint32_t)v.z | ((unsigned long long)(uint32_t)v.w << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(q), (unsigned long long)(uint32_t)v.x | ((unsigned long long)(uint32_t)v.y << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(q + 1), (unsigned long long)(uint32_t)v.z | ((unsigned long long)(uint32_t)v.w << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <bool COH> __device__ __forceinline__ int ld_i(const int* p) { return COH ? ld_coh(p) : *p; }
-template <bool COH> __device__ __forceinline__ void st_i(int* p, int v) { if (COH) st_coh(p, v); else *p = v; }
+template <bool COH> __device__ __forceinline__ int ld_i(const int* p) { return COH ? ld_coh(p) : *gp(p); }
+template <bool COH> __device__ __forceinline__ void st_i(int* p, int v) { if (COH) st_coh(p, v); else *gp(p) = v; }
+
+// ---- link-slot encoding -------------------------------------------------------------------------
+// A slot holds a flit {dst, inject cycle, src, kind<<30 | line} for the cycle it is an input of.
+// Tile indices take 20 bits; the top 12 bits of the dst and src words carry that cycle
+// (mod 4096), so each 64-bit half of a slot says by itself which cycle it belongs to.  A tile on
+// a patch edge polls its neighbour's slot until both halves carry the cycle it needs: the data
+// and the "ready" signal arrive together, with no separate flag and no store drain.  An empty
+// slot has dst = src = 0xFFFFF.
+constexpr uint32_t TILE_BITS_MASK = 0xFFFFFu;
+constexpr int STAMP_SHIFT = 20;
+constexpr uint32_t STAMP_MASK = 0xFFFu;
+
+__device__ __forceinline__ int4 slot_encode(const int4& f, uint32_t stamp) {
+  const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
+  if (f.x < 0) return make_int4((int)(TILE_BITS_MASK | s), -1, (int)(TILE_BITS_MASK | s), -1);
+  return make_int4((int)((uint32_t)f.x | s), f.y, (int)((uint32_t)f.z | s), f.w);
+}
+__device__ __forceinline__ int4 slot_decode(const int4& w) {
+  const uint32_t d = (uint32_t)w.x & TILE_BITS_MASK;
+  if (d == TILE_BITS_MASK) return make_int4(-1, -1, -1, -1);
+  return make_int4((int)d, w.y, (int)((uint32_t)w.z & TILE_BITS_MASK), w.w);
+}
+__device__ __forceinline__ bool slot_has_stamp(const int4& w, uint32_t stamp) {
+  return ((uint32_t)w.x >> STAMP_SHIFT) == (stamp & STAMP_MASK) && ((uint32_t)w.z >> STAMP_SHIFT) == (stamp & STAMP_MASK);
+}
 
 // ---- counter-based randomness: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) -----------
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
@@ -105,68 +160,74 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   return make_uint4(c0, c1, c2, c3);
 }
 
+// Exact line / N and line mod N for lines < 2^30 without a divide: n_magic = ceil(2^(32+k) / N),
+// k = floor(log2 N) - 1 (so n_magic < 2^32 and the rounding error stays below 1/N).
+__device__ __forceinline__ uint32_t div_n(const ChipDev& C, uint32_t v) {
+  return C.N > 1 ? __umulhi(v, C.n_magic) >> C.n_shift : v;
+}
+__device__ __forceinline__ uint32_t mod_n(const ChipDev& C, uint32_t v) { return v - div_n(C, v) * (uint32_t)C.N; }
+
 // Zipf rank through a quantile table: bucket from the high half of u, linear position inside
 // the bucket from the low half.
 __device__ __forceinline__ int zipf_rank(const uint32_t* __restrict__ q, uint32_t u) {
   const uint32_t b = u >> 16, f = u & 0xFFFFu;
-  const uint32_t lo = q[b], hi = q[b + 1];
+  const uint32_t lo = *gp(q + b), hi = *gp(q + b + 1);
   return (int)(lo + (uint32_t)(((unsigned long long)f * (hi - lo)) >> 16));
 }
 
 // ---- set-associative LRU sets: tags most recently used first -------------------------------
-// touch: on a hit move the line to the front; on a miss insert it at the front if `insert`,
-// dropping the last way (an invalid one if any, else the least recently used).
-template <int WAYS> struct SetIO;
-template <> struct SetIO<1> {
-  __device__ static void ld(const int* p, int* v) { v[0] = p[0]; }
-  __device__ static void st(int* p, const int* v) { p[0] = v[0]; }
-};
-template <> struct SetIO<2> {
-  __device__ static void ld(const int* p, int* v) { int2 a = *reinterpret_cast<const int2*>(p); v[0] = a.x; v[1] = a.y; }
-  __device__ static void st(int* p, const int* v) { *reinterpret_cast<int2*>(p) = make_int2(v[0], v[1]); }
-};
-template <> struct SetIO<4> {
-  __device__ static void ld(const int* p, int* v) { int4 a = *reinterpret_cast<const int4*>(p); v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; }
-  __device__ static void st(int* p, const int* v) { *reinterpret_cast<int4*>(p) = make_int4(v[0], v[1], v[2], v[3]); }
-};
-template <> struct SetIO<8> {
-  __device__ static void ld(const int* p, int* v) {
-    int4 a = reinterpret_cast<const int4*>(p)[0], b = reinterpret_cast<const int4*>(p)[1];
+// Register copies of a set: load `ways` tags (positions >= ways read as -2, which no line
+// matches), update in registers, store `ways` tags back.
+__device__ __forceinline__ void set_load(const int* p, int ways, int (&v)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = -2;
+  if (ways == 8) {
+    const int4 a = gload4(reinterpret_cast<const int4*>(p)), b = gload4(reinterpret_cast<const int4*>(p) + 1);
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else if (ways == 4) {
+    const int4 a = gload4(reinterpret_cast<const int4*>(p));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  } else if (ways == 2) {
+    const int2 a = gload2(reinterpret_cast<const int2*>(p));
+    v[0] = a.x; v[1] = a.y;
+  } else {
+    v[0] = *gp(p);
   }
-  __device__ static void st(int* p, const int* v) {
-    reinterpret_cast<int4*>(p)[0] = make_int4(v[0], v[1], v[2], v[3]);
-    reinterpret_cast<int4*>(p)[1] = make_int4(v[4], v[5], v[6], v[7]);
+}
+__device__ __forceinline__ void set_store(int* p, int ways, const int (&v)[8]) {
+  if (ways == 8) {
+    gstore4(reinterpret_cast<int4*>(p), make_int4(v[0], v[1], v[2], v[3]));
+    gstore4(reinterpret_cast<int4*>(p) + 1, make_int4(v[4], v[5], v[6], v[7]));
+  } else if (ways == 4) {
+    gstore4(reinterpret_cast<int4*>(p), make_int4(v[0], v[1], v[2], v[3]));
+  } else if (ways == 2) {
+    gstore2(reinterpret_cast<int2*>(p), make_int2(v[0], v[1]));
+  } else {
+    *gp(p) = v[0];
   }
-};
-
-template <int WAYS>
-__device__ __forceinline__ bool touch_w(int* p, int line, bool insert) {
-  int v[WAYS];
-  SetIO<WAYS>::ld(p, v);
-  int pos = WAYS;
+}
+// Touch `line`: a hit moves it to the front; a miss inserts it at the front when `insert`,
+// dropping the last way.  `changed` tells whether the set must be written back.
+__device__ __forceinline__ bool set_touch(int (&v)[8], int ways, int line, bool insert, bool& changed) {
+  int pos = 8;
 #pragma unroll
-  for (int i = WAYS - 1; i >= 0; --i)
-    if (v[i] == line) pos = i;
-  if (pos == 0) return true;
-  if (pos == WAYS && !insert) return false;
-  const int lim = pos == WAYS ? WAYS - 1 : pos;
+  for (int i = 7; i >= 0; --i)
+    if (i < ways && v[i] == line) pos = i;
+  const bool hit = pos < 8;
+  changed = false;
+  if (pos == 0 || (!hit && !insert)) return hit;
+  const int lim = hit ? pos : ways - 1;
 #pragma unroll
-  for (int i = WAYS - 1; i >= 1; --i)
+  for (int i = 7; i >= 1; --i)
     if (i <= lim) v[i] = v[i - 1];
   v[0] = line;
-  SetIO<WAYS>::st(p, v);
-  return pos != WAYS;
+  changed = true;
+  return hit;
 }
 
-__device__ __forceinline__ bool touch(int* p, int ways, int line, bool insert) {
-  switch (ways) {
-    case 8: return touch_w<8>(p, line, insert);
-    case 4: return touch_w<4>(p, line, insert);
-    case 2: return touch_w<2>(p, line, insert);
-    default: return touch_w<1>(p, line, insert);
-  }
-}
+// Queue nodes {next, ready, line, 0}: device-scope atomics when several workgroups share a chip.
+template <bool COH> __device__ __forceinline__ int4 ld_node(const int4* p) { return ld_slot(p, COH); }
+template <bool COH> __device__ __forceinline__ void st_node(int4* p, int4 v) { st_slot(p, v, COH); }
 
 // Per-workgroup counters in LDS (rare events) and per-thread counters in registers (every
 // cycle: link traversals, deflections, injections, ejections, latency sums).
@@ -175,8 +236,12 @@ struct LdsStats {
 };
 struct Acc {
   int trav, defl;
-  int inj[3], ej[3];
-  unsigned long long lat[3];
+  int inj_req, inj_reply, inj_bg, ej_req, ej_reply, ej_bg;
+  unsigned long long lat_req, lat_reply, lat_bg;
+  // events counted in registers by the one-tile-per-thread kernel
+  int l2_hit, l2_miss, ops_done, ops_issued, l1_hit, l1_miss, req_made, inj_blocked, reply_sent, req_recv,
+      reply_recv, bg_gen, lat_max, op_lat_max;
+  unsigned long long op_lat;
 };
 __device__ __forceinline__ void lds_add(LdsStats& L, int i, unsigned long long d) { atomicAdd(&L.v[i], d); }
 
@@ -185,53 +250,148 @@ __device__ __forceinline__ void lds_add(LdsStats& L, int i, unsigned long long d
 // ejection, injection) of tile t in cycle c.  Reads the input slots of parity c, writes the
 // neighbours' slots of parity c+1; every other word it writes is owned by t, except the
 // queue nodes of requesters queued at t (t is their home while they wait).
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {  // SplitMix64 finalizer
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ unsigned long long mix_pair(unsigned long long h, int a, int b) {
+  return mix64(h ^ (((unsigned long long)(uint32_t)a << 32) | (uint32_t)b));
+}
+
 template <bool MULTI>
-__device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y, int c, const bool cross[4],
-                                          Acc& acc, LdsStats& L) {
+__device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y, int c, const bool cross[4], bool step,
+                                          bool digest, unsigned long long& dsum, Acc& acc, LdsStats& L) {
   const int N = C.N;
   const int cur = c & 1, nxt = cur ^ 1;
   const bool v0 = y > 0, v1 = y < C.H - 1, v2 = x < C.W - 1, v3 = x > 0;
   const int4 EMPTY = make_int4(-1, -1, -1, -1);
 
-  int4 f0 = v0 ? ld_slot(&C.link[(cur * 4 + 0) * N + t], cross[0]) : EMPTY;
-  int4 f1 = v1 ? ld_slot(&C.link[(cur * 4 + 1) * N + t], cross[1]) : EMPTY;
-  int4 f2 = v2 ? ld_slot(&C.link[(cur * 4 + 2) * N + t], cross[2]) : EMPTY;
-  int4 f3 = v3 ? ld_slot(&C.link[(cur * 4 + 3) * N + t], cross[3]) : EMPTY;
-  int4 k0 = C.core[t];          // state, wake, line, issue
-  int4 k1 = C.core[N + t];      // l2q, l2q_line, hit_head, hit_tail
-  int4 k2 = C.core[2 * N + t];  // miss_head, miss_tail, bg_pending, force_line
-  int fdst = C.core[3 * N + t].x;
+  // inputs of cycle c: interior slots were written by this workgroup before its last barrier;
+  // edge slots are polled until both halves carry cycle c
+  const int4* in0 = &C.link[(cur * 4 + 0) * N + t];
+  const int4* in1 = &C.link[(cur * 4 + 1) * N + t];
+  const int4* in2 = &C.link[(cur * 4 + 2) * N + t];
+  const int4* in3 = &C.link[(cur * 4 + 3) * N + t];
+  const bool e0 = MULTI && cross[0] && v0, e1 = MULTI && cross[1] && v1, e2 = MULTI && cross[2] && v2,
+             e3 = MULTI && cross[3] && v3;
+  int4 w0 = v0 ? ld_slot(in0, e0) : EMPTY;
+  int4 w1 = v1 ? ld_slot(in1, e1) : EMPTY;
+  int4 w2 = v2 ? ld_slot(in2, e2) : EMPTY;
+  int4 w3 = v3 ? ld_slot(in3, e3) : EMPTY;
+  if (MULTI) {
+    int spins = 0;
+    for (;;) {
+      const bool p0 = e0 && !slot_has_stamp(w0, (uint32_t)c), p1 = e1 && !slot_has_stamp(w1, (uint32_t)c);
+      const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
+      if (!(p0 | p1 | p2 | p3)) break;
+      if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
+        st_coh(C.err, 1);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if (p0) w0 = ld_slot(in0, true);
+      if (p1) w1 = ld_slot(in1, true);
+      if (p2) w2 = ld_slot(in2, true);
+      if (p3) w3 = ld_slot(in3, true);
+    }
+  }
+  if ((v0 && !e0 && !slot_has_stamp(w0, (uint32_t)c)) || (v1 && !e1 && !slot_has_stamp(w1, (uint32_t)c)) ||
+      (v2 && !e2 && !slot_has_stamp(w2, (uint32_t)c)) || (v3 && !e3 && !slot_has_stamp(w3, (uint32_t)c))) {
+    st_coh(C.err, 3);  // an interior slot from the wrong cycle: a synchronisation bug
+    return false;
+  }
+  int4 f0 = v0 ? slot_decode(w0) : EMPTY;
+  int4 f1 = v1 ? slot_decode(w1) : EMPTY;
+  int4 f2 = v2 ? slot_decode(w2) : EMPTY;
+  int4 f3 = v3 ? slot_decode(w3) : EMPTY;
+  int4 k0 = gload4(&C.core[t]);          // state, wake, line, issue
+  int4 k1 = gload4(&C.core[N + t]);      // l2q, l2q_line, hit_head, hit_tail
+  int4 k2 = gload4(&C.core[2 * N + t]);  // miss_head, miss_tail, bg_pending, force_line
+  int fdst = *gp(reinterpret_cast<const int*>(&C.core[3 * N + t]));
+
+  if (digest) {  // state owned by t after cycle c-1: its inputs of cycle c and its core words
+    unsigned long long h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
+    h = mix_pair(h, f0.x, f0.y); h = mix_pair(h, f0.z, f0.w);
+    h = mix_pair(h, f1.x, f1.y); h = mix_pair(h, f1.z, f1.w);
+    h = mix_pair(h, f2.x, f2.y); h = mix_pair(h, f2.z, f2.w);
+    h = mix_pair(h, f3.x, f3.y); h = mix_pair(h, f3.z, f3.w);
+    h = mix_pair(h, k0.x, k0.y); h = mix_pair(h, k0.z, k0.w);
+    h = mix_pair(h, k1.x, k1.y); h = mix_pair(h, k1.z, k1.w);
+    h = mix_pair(h, k2.x, k2.y);
+    h = mix_pair(h, k2.z, 0);   // bg_pending; the queue-node words are written by the home
+    h = mix_pair(h, 0, 0);
+    h = mix_pair(h, k2.w, fdst);
+    dsum += h;
+  }
+  if (!step) return true;
   bool d0 = false, d1 = false, d2 = false, d3 = false;
   const uint4 r = philox((uint32_t)c, (uint32_t)t, 0u, 0u, C.key0, C.key1);
 
-  // ---- phase one: home L2 service, then the core --------------------------------------------
+  // ---- every load of the cycle is issued before any store -----------------------------------
   // Indices read from state are checked before they address memory: a corrupt index sets the
-  // chip's error word (reported as SIM_EHANG's sibling, SIM_EINVARIANT) instead of faulting.
+  // chip's error word (reported as SIM_EINVARIANT) instead of faulting.
 #define GUARD(i)                                                   \
   if ((unsigned)(i) >= (unsigned)N) {                              \
     st_coh(C.err, 2);                                              \
-    return;                                                        \
+    return false;                                                  \
   }
-  if (k1.x >= 0) {  // a request ejected here last cycle: look up the home slice
+  const bool svc = k1.x >= 0;  // a request was ejected here last cycle: home-slice lookup
+  if (svc) { GUARD(k1.x) }
+  if (k1.z >= 0) { GUARD(k1.z) }
+  if (k1.w >= 0) { GUARD(k1.w) }
+  if (k2.x >= 0) { GUARD(k2.x) }
+  if (k2.y >= 0) { GUARD(k2.y) }
+  const bool wake = k0.y == c;
+  const bool fill = k0.x == CORE_FILL && wake;
+  const bool missed = k0.x == CORE_L1MISS && wake;
+  const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  const bool forced = k0.x == CORE_IDLE && k2.w >= 0;
+  const bool drawn = k0.x == CORE_IDLE && !forced && r.x < C.op_thr;
+  int* setR = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1))) * C.w2;
+  int* setL = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1))) * C.w2;
+  int vR[8], vL[8], u[8];
+  if (svc) set_load(setR, C.w2, vR);
+  if (local) set_load(setL, C.w2, vL);
+  int4 nh = EMPTY, nm = EMPTY;  // nodes at the hit-queue and miss-queue heads: next, ready, line
+  if (k1.z >= 0) nh = ld_node<MULTI>(&C.node[k1.z]);
+  if (k2.x >= 0) nm = ld_node<MULTI>(&C.node[k2.x]);
+  int line_op = k0.z;  // the line of the op that touches L1 this cycle (fill or issue)
+  if (forced) line_op = k2.w;
+  else if (drawn)
+    line_op = (C.private_lines > 0 && r.y >= C.shared_thr) ? C.shared_lines + t * C.private_lines + zipf_rank(C.zp, r.z)
+                                                           : zipf_rank(C.zs, r.z);
+  int* set1 = C.l1 + ((size_t)t * C.s1 + (line_op & (C.s1 - 1))) * C.w1;
+  if (fill || forced || drawn) set_load(set1, C.w1, u);
+
+  // ---- phase one: home L2 service, then the core (Sec. 7.1, phase one; Sec. 3.5) ----------
+  bool dirtyR = false, dirtyL = false, dirty1 = false;
+  int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
+  if (svc) {
     const int rq = k1.x, line = k1.y;
-    GUARD(rq)
-    if (k1.w >= 0) { GUARD(k1.w) }
-    if (k2.y >= 0) { GUARD(k2.y) }
-    int* set = C.l2 + ((size_t)t * C.s2 + ((uint32_t)line / (uint32_t)N & (uint32_t)(C.s2 - 1))) * C.w2;
-    const bool hit = touch(set, C.w2, line, true);
+    const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
     lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
-    const int ready = hit ? c : c + C.mem_lat;
-    int* nd = reinterpret_cast<int*>(&C.node[rq]);
-    st_i<MULTI>(nd + 0, -1);
-    st_i<MULTI>(nd + 1, ready);
-    st_i<MULTI>(nd + 2, line);
+    node_rq = rq;
+    node_ready = hit ? c : c + C.mem_lat;
+    node_line = line;
+    const int4 fresh = make_int4(-1, node_ready, line, 0);
     if (hit) {
-      if (k1.w >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[k1.w]), rq);
-      else k1.z = rq;
+      if (k1.w >= 0) {
+        node_tail = k1.w;
+        if (k1.w == k1.z) nh.x = rq;
+      } else {
+        k1.z = rq;
+        nh = fresh;
+      }
       k1.w = rq;
     } else {
-      if (k2.y >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[k2.y]), rq);
-      else k2.x = rq;
+      if (k2.y >= 0) {
+        node_tail = k2.y;
+        if (k2.y == k2.x) nm.x = rq;
+      } else {
+        k2.x = rq;
+        nm = fresh;
+      }
       k2.y = rq;
     }
     k1.x = -1;
@@ -239,60 +399,45 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
     d1 = true;
     d2 = true;
   }
-  if (k0.x == CORE_FILL) {
-    if (k0.y == c) {  // the block arrived: fill L1, the op completes
-      const int line = k0.z;
-      touch(C.l1 + ((size_t)t * C.s1 + (line & (C.s1 - 1))) * C.w1, C.w1, line, true);
-      const unsigned long long lat = (unsigned long long)(c - k0.w);
-      lds_add(L, SIM_ST_OPS_DONE, 1);
-      lds_add(L, SIM_ST_OP_LAT, lat);
-      atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
-      k0.x = CORE_IDLE;
-      d0 = true;
-    }
-  } else if (k0.x == CORE_L1MISS) {
-    if (k0.y == c) {  // L1 miss penalty over: local home slice, or a request flit
-      const int line = k0.z;
-      if ((uint32_t)line % (uint32_t)N == (uint32_t)t) {
-        int* set = C.l2 + ((size_t)t * C.s2 + ((uint32_t)line / (uint32_t)N & (uint32_t)(C.s2 - 1))) * C.w2;
-        const bool hit = touch(set, C.w2, line, true);
-        lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
-        k0.x = CORE_FILL;
-        k0.y = hit ? c + 1 : c + C.mem_lat;
-      } else {
-        k0.x = CORE_SEND;
-        lds_add(L, SIM_ST_REQ_MADE, 1);
+  if (fill) {  // the block arrived: fill L1, the op completes
+    set_touch(u, C.w1, line_op, true, dirty1);
+    const unsigned long long lat = (unsigned long long)(c - k0.w);
+    lds_add(L, SIM_ST_OPS_DONE, 1);
+    lds_add(L, SIM_ST_OP_LAT, lat);
+    atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
+    k0.x = CORE_IDLE;
+    d0 = true;
+  } else if (missed) {  // L1 miss penalty over: local home slice, or a request flit
+    if (local) {
+      if (svc && setL == setR) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) vL[i] = vR[i];
       }
-      d0 = true;
+      const bool hit = set_touch(vL, C.w2, k0.z, true, dirtyL);
+      lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
+      k0.x = CORE_FILL;
+      k0.y = hit ? c + 1 : c + C.mem_lat;
+    } else {
+      k0.x = CORE_SEND;
+      lds_add(L, SIM_ST_REQ_MADE, 1);
     }
-  } else if (k0.x == CORE_IDLE) {
-    bool issue = false;
-    int line = 0;
-    if (k2.w >= 0) {
-      line = k2.w;
+    d0 = true;
+  } else if (forced || drawn) {
+    if (forced) {
       k2.w = -1;
       d2 = true;
-      issue = true;
-    } else if (r.x < C.op_thr) {
-      issue = true;
-      if (C.private_lines > 0 && r.y >= C.shared_thr)
-        line = C.shared_lines + t * C.private_lines + zipf_rank(C.zp, r.z);
-      else
-        line = zipf_rank(C.zs, r.z);
     }
-    if (issue) {
-      lds_add(L, SIM_ST_OPS_ISSUED, 1);
-      k0.z = line;
-      k0.w = c;
-      d0 = true;
-      if (touch(C.l1 + ((size_t)t * C.s1 + (line & (C.s1 - 1))) * C.w1, C.w1, line, false)) {
-        lds_add(L, SIM_ST_L1_HIT, 1);
-        lds_add(L, SIM_ST_OPS_DONE, 1);
-      } else {
-        lds_add(L, SIM_ST_L1_MISS, 1);
-        k0.x = CORE_L1MISS;
-        k0.y = c + C.l1_lat;
-      }
+    lds_add(L, SIM_ST_OPS_ISSUED, 1);
+    k0.z = line_op;
+    k0.w = c;
+    d0 = true;
+    if (set_touch(u, C.w1, line_op, false, dirty1)) {
+      lds_add(L, SIM_ST_L1_HIT, 1);
+      lds_add(L, SIM_ST_OPS_DONE, 1);
+    } else {
+      lds_add(L, SIM_ST_L1_MISS, 1);
+      k0.x = CORE_L1MISS;
+      k0.y = c + C.l1_lat;
     }
   }
 
@@ -300,9 +445,7 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
   const int arrivals = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0);
   const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
   int cls = -1;
-  if (k2.x >= 0) { GUARD(k2.x) }
-  if (k1.z >= 0) { GUARD(k1.z) }
-  if (k2.x >= 0 && ld_i<MULTI>(reinterpret_cast<const int*>(&C.node[k2.x]) + 1) <= c) cls = 0;
+  if (k2.x >= 0 && nm.y <= c) cls = 0;
   else if (k1.z >= 0) cls = 1;
   else if (k0.x == CORE_SEND) cls = 2;
   else if (fdst >= 0) cls = 3;
@@ -316,28 +459,27 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
     fi.y = c;
     fi.z = t;
     if (cls <= 1) {  // reply: pop the queue head
+      const int4 hd = cls == 0 ? nm : nh;
       const int rq = cls == 0 ? k2.x : k1.z;
-      const int* nd = reinterpret_cast<const int*>(&C.node[rq]);
-      const int next = ld_i<MULTI>(nd + 0);
       if (cls == 0) {
-        k2.x = next;
-        if (next < 0) k2.y = -1;
+        k2.x = hd.x;
+        if (hd.x < 0) k2.y = -1;
       } else {
-        k1.z = next;
-        if (next < 0) k1.w = -1;
+        k1.z = hd.x;
+        if (hd.x < 0) k1.w = -1;
       }
       fi.x = rq;
-      fi.w = (KIND_REPLY << 30) | ld_i<MULTI>(nd + 2);
+      fi.w = (KIND_REPLY << 30) | hd.z;
       lds_add(L, SIM_ST_REPLY_SENT, 1);
-      acc.inj[KIND_REPLY]++;
+      acc.inj_reply++;
       d1 = true;
       d2 = true;
     } else if (cls == 2) {
-      fi.x = (int)((uint32_t)k0.z % (uint32_t)N);
+      fi.x = (int)mod_n(C, (uint32_t)k0.z);
       fi.w = (KIND_REQ << 30) | k0.z;
       k0.x = CORE_WAIT;
       d0 = true;
-      acc.inj[KIND_REQ]++;
+      acc.inj_req++;
     } else {
       if (cls == 3) {
         fi.x = fdst;
@@ -351,7 +493,7 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
         d2 = true;
       }
       fi.w = (int)(KIND_BG << 30);
-      acc.inj[KIND_BG]++;
+      acc.inj_bg++;
     }
   }
 
@@ -405,15 +547,23 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
   assign(sd3, si3);
   assign(sd4, si4);
 
-  // ---- phase three: traversal to the neighbours' next-cycle inputs, ejection, generation ---
+  // ---- phase three: stores (caches, queue nodes, slots, core words) -------------------------
+  if (dirtyR) set_store(setR, C.w2, vR);
+  if (dirtyL) set_store(setL, C.w2, vL);
+  if (dirty1) set_store(set1, C.w1, u);
+  if (node_rq >= 0) {
+    st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
+    if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
+  }
   int4 oe = EMPTY;
+  const uint32_t ns = (uint32_t)(c + 1);
   auto send = [&](const int4& f, unsigned port) {
     if (port == 4) { oe = f; return; }
     if (port > 3) return;
     const int nbr = port == 0 ? t - C.W : port == 1 ? t + C.W : port == 2 ? t + 1 : t - 1;
     const int slot = (int)(port ^ 1u);
-    const bool cx = port == 0 ? cross[0] : port == 1 ? cross[1] : port == 2 ? cross[2] : cross[3];
-    st_slot(&C.link[(nxt * 4 + slot) * N + nbr], f, cx);
+    const bool cx = MULTI && (port == 0 ? cross[0] : port == 1 ? cross[1] : port == 2 ? cross[2] : cross[3]);
+    st_slot(&C.link[(nxt * 4 + slot) * N + nbr], slot_encode(f, ns), cx);
   };
   send(f0, ports & 7u);
   send(f1, (ports >> 3) & 7u);
@@ -421,16 +571,22 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
   send(f3, (ports >> 9) & 7u);
   send(fi, (ports >> 12) & 7u);
   const unsigned idle = valid & ~used;  // links that carry nothing next cycle
-  if (idle & 1u) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], EMPTY, cross[0]);
-  if (idle & 2u) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], EMPTY, cross[1]);
-  if (idle & 4u) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], EMPTY, cross[2]);
-  if (idle & 8u) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], EMPTY, cross[3]);
+  const int4 E = slot_encode(EMPTY, ns);
+  if (idle & 1u) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], E, MULTI && cross[0]);
+  if (idle & 2u) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], E, MULTI && cross[1]);
+  if (idle & 4u) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], E, MULTI && cross[2]);
+  if (idle & 8u) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], E, MULTI && cross[3]);
 
   if (oe.x >= 0) {
     const int kind = (int)((uint32_t)oe.w >> 30);
     const int lat = c - oe.y;
-    acc.ej[kind]++;
-    acc.lat[kind] += (unsigned long long)lat;
+    const unsigned long long ulat = (unsigned long long)lat;
+    acc.ej_req += kind == KIND_REQ;
+    acc.ej_reply += kind == KIND_REPLY;
+    acc.ej_bg += kind == KIND_BG;
+    acc.lat_req += kind == KIND_REQ ? ulat : 0ull;
+    acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
+    acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
     atomicMax(&L.v[SIM_ST_LAT_MAX], (unsigned long long)lat);
     lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
     if (kind == KIND_REQ) {
@@ -450,42 +606,12 @@ __device__ __forceinline__ void tile_step(const ChipDev& C, int t, int x, int y,
     d2 = true;
     lds_add(L, SIM_ST_BG_GEN, 1);
   }
-  if (d0) C.core[t] = k0;
-  if (d1) C.core[N + t] = k1;
-  if (d2) C.core[2 * N + t] = k2;
-  if (d3) C.core[3 * N + t] = make_int4(fdst, 0, 0, 0);
+  if (d0) gstore4(&C.core[t], k0);
+  if (d1) gstore4(&C.core[N + t], k1);
+  if (d2) gstore4(&C.core[2 * N + t], k2);
+  if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, 0, 0, 0));
 #undef GUARD
-}
-
-// ---- state digest of the words a tile owns after cycle c --------------------------------------
-__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {  // SplitMix64 finalizer
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-__device__ __forceinline__ unsigned long long mix_pair(unsigned long long h, int a, int b) {
-  return mix64(h ^ (((unsigned long long)(uint32_t)a << 32) | (uint32_t)b));
-}
-__device__ unsigned long long tile_digest(const ChipDev& C, int t, int x, int y, int c, const bool cross[4]) {
-  const int N = C.N, par = (c + 1) & 1;
-  const bool v[4] = {y > 0, y < C.H - 1, x < C.W - 1, x > 0};
-  unsigned long long h = mix64(((unsigned long long)(uint32_t)c << 32) | (uint32_t)t);
-#pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const int4 f = v[p] ? ld_slot(&C.link[(par * 4 + p) * N + t], cross[p]) : make_int4(-1, -1, -1, -1);
-    h = mix_pair(h, f.x, f.y);
-    h = mix_pair(h, f.z, f.w);
-  }
-  const int4 k0 = C.core[t], k1 = C.core[N + t], k2 = C.core[2 * N + t], k3 = C.core[3 * N + t];
-  h = mix_pair(h, k0.x, k0.y);
-  h = mix_pair(h, k0.z, k0.w);
-  h = mix_pair(h, k1.x, k1.y);
-  h = mix_pair(h, k1.z, k1.w);
-  h = mix_pair(h, k2.x, k2.y);
-  h = mix_pair(h, k2.z, 0);      // bg_pending, (node words are written by the home, not hashed)
-  h = mix_pair(h, 0, 0);
-  h = mix_pair(h, k2.w, k3.x);   // force_line, force_dst
-  return h;
+  return true;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -499,80 +625,10 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
-// ---- the persistent step kernel ----------------------------------------------------------------
-// Workgroup w runs patch table[w].patch of chip table[w].chip from the cycle its flag records
-// up to min(flag + chunk, stop).  digests (optional, single chip): digests[c - digest_base] +=
-// this patch's share of the digest of cycle c.
-template <bool MULTI>
-__global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict__ table, int chunk,
-                                                    unsigned long long* digests, int digest_base) {
-  __shared__ LdsStats L;
-  __shared__ int s_stop_flag;
-  const LaunchEntry e = table[blockIdx.x];
-  const ChipDev C = *e.chip;
-  const int patch = e.patch;
-  const int pxi = patch % C.pgx, pyi = patch / C.pgx;
-  const int x0 = pxi * C.pw, y0 = pyi * C.ph;
-  const int cols = min(C.pw, C.W - x0), rows = min(C.ph, C.H - y0);
-  const int ntiles = cols * rows;
-  // neighbouring patch watched by lane 0..3 of the first wave (N, S, E, W), -1 if none
-  const int lane = (int)threadIdx.x;
-  const int my_nb = lane == 0 ? (pyi > 0 ? patch - C.pgx : -1)
-                  : lane == 1 ? (pyi < C.pgy - 1 ? patch + C.pgx : -1)
-                  : lane == 2 ? (pxi < C.pgx - 1 ? patch + 1 : -1)
-                  : lane == 3 ? (pxi > 0 ? patch - 1 : -1) : -1;
-  for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
-  Acc acc = {};
-  const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
-  const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
-  __syncthreads();
-
-  for (int c = c0; c <= c_end; ++c) {
-    if (MULTI) {  // wait until every neighbouring patch has completed c cycles
-      if (threadIdx.x == 0) s_stop_flag = 0;
-      __syncthreads();
-      if (my_nb >= 0) {
-        const int* fl = &C.flags[my_nb * FLAG_STRIDE];
-        int spins = 0;
-        while (ld_coh(fl) < c) {
-          if (++spins > SPIN_LIMIT || ld_coh(C.err)) {
-            st_coh(C.err, 1);
-            s_stop_flag = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (s_stop_flag) break;
-    }
-    if (digests && c > c0) {  // digest of cycle c-1 (all writes into this patch's slots are done)
-      unsigned long long h = 0;
-      for (int j = threadIdx.x; j < ntiles; j += blockDim.x) {
-        const int lx = j % cols, ly = j / cols, x = x0 + lx, y = y0 + ly;
-        const bool cross[4] = {MULTI && ly == 0 && y > 0, MULTI && ly == rows - 1 && y < C.H - 1,
-                               MULTI && lx == cols - 1 && x < C.W - 1, MULTI && lx == 0 && x > 0};
-        h += tile_digest(C, y * C.W + x, x, y, c - 1, cross);
-      }
-      h = wave_sum(h);
-      if ((threadIdx.x & 63) == 0 && c - 1 - digest_base >= 0) atomicAdd(&digests[c - 1 - digest_base], h);
-    }
-    if (c == c_end) break;
-    for (int j = threadIdx.x; j < ntiles; j += blockDim.x) {
-      const int lx = j % cols, ly = j / cols, x = x0 + lx, y = y0 + ly;
-      const bool cross[4] = {MULTI && ly == 0 && y > 0, MULTI && ly == rows - 1 && y < C.H - 1,
-                             MULTI && lx == cols - 1 && x < C.W - 1, MULTI && lx == 0 && x > 0};
-      tile_step<MULTI>(C, y * C.W + x, x, y, c, cross, acc, L);
-    }
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's stores are complete before the flag moves
-    __syncthreads();
-    if (threadIdx.x == 0) st_coh(&C.flags[patch * FLAG_STRIDE], c + 1);
-  }
-
-  // ---- flush counters ----
+// Adds a workgroup's counters to the chip's statistics (once per launch).
+__device__ __forceinline__ void flush_counters(const Acc& acc, LdsStats& L, const ChipDev& C, int patch, int c0, int c_done) {
   {
-    int v[8] = {acc.trav, acc.defl, acc.inj[0], acc.inj[1], acc.inj[2], acc.ej[0], acc.ej[1], acc.ej[2]};
+    int v[8] = {acc.trav, acc.defl, acc.inj_req, acc.inj_reply, acc.inj_bg, acc.ej_req, acc.ej_reply, acc.ej_bg};
     const int idx[8] = {SIM_ST_TRAVERSALS, SIM_ST_DEFLECTIONS, SIM_ST_INJ_REQ, SIM_ST_INJ_REPLY, SIM_ST_INJ_BG,
                         SIM_ST_EJ_REQ, SIM_ST_EJ_REPLY, SIM_ST_EJ_BG};
 #pragma unroll
@@ -580,20 +636,507 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
       const int s = wave_sum_i(v[i]);
       if ((threadIdx.x & 63) == 0 && s) atomicAdd(&L.v[idx[i]], (unsigned long long)s);
     }
+    const unsigned long long lat[4] = {acc.lat_req, acc.lat_reply, acc.lat_bg, acc.op_lat};
+    const int lidx[4] = {SIM_ST_LAT_REQ, SIM_ST_LAT_REPLY, SIM_ST_LAT_BG, SIM_ST_OP_LAT};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const unsigned long long s = wave_sum(acc.lat[k]);
-      if ((threadIdx.x & 63) == 0 && s) atomicAdd(&L.v[SIM_ST_LAT_REQ + k], s);
+    for (int k = 0; k < 4; ++k) {
+      const unsigned long long s = wave_sum(lat[k]);
+      if ((threadIdx.x & 63) == 0 && s) atomicAdd(&L.v[lidx[k]], s);
     }
+    int w[12] = {acc.l2_hit, acc.l2_miss, acc.ops_done, acc.ops_issued, acc.l1_hit, acc.l1_miss, acc.req_made,
+                 acc.inj_blocked, acc.reply_sent, acc.req_recv, acc.reply_recv, acc.bg_gen};
+    const int widx[12] = {SIM_ST_L2_HIT, SIM_ST_L2_MISS, SIM_ST_OPS_DONE, SIM_ST_OPS_ISSUED, SIM_ST_L1_HIT,
+                          SIM_ST_L1_MISS, SIM_ST_REQ_MADE, SIM_ST_INJ_BLOCKED, SIM_ST_REPLY_SENT, SIM_ST_REQ_RECV,
+                          SIM_ST_REPLY_RECV, SIM_ST_BG_GEN};
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const int s = wave_sum_i(w[i]);
+      if ((threadIdx.x & 63) == 0 && s) atomicAdd(&L.v[widx[i]], (unsigned long long)s);
+    }
+    if (acc.lat_max) atomicMax(&L.v[SIM_ST_LAT_MAX], (unsigned long long)acc.lat_max);
+    if (acc.op_lat_max) atomicMax(&L.v[SIM_ST_OP_LAT_MAX], (unsigned long long)acc.op_lat_max);
   }
   __syncthreads();
-  if (patch == 0 && threadIdx.x == 0 && c_end > c0) L.v[SIM_ST_CYCLES] += (unsigned long long)(c_end - c0);
+  if (patch == 0 && threadIdx.x == 0 && c_done > c0) L.v[SIM_ST_CYCLES] += (unsigned long long)(c_done - c0);
   __syncthreads();
   for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) {
     if (!L.v[i]) continue;
     if (i == SIM_ST_LAT_MAX || i == SIM_ST_OP_LAT_MAX) atomicMax(&C.stats[i], L.v[i]);
     else atomicAdd(&C.stats[i], L.v[i]);
   }
+}
+
+// ---- the persistent step kernel ----------------------------------------------------------------
+// Workgroup w runs patch table[w].patch of chip table[w].chip from the cycle its flag records
+// up to min(flag + chunk, stop): one barrier per cycle inside the patch; patch edges are
+// synchronised through the stamped slots.  digests (optional, single chip): digests[c -
+// digest_base] += this patch's share of the digest of cycle c.
+template <bool MULTI>
+__global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict__ table, int chunk,
+                                                   unsigned long long* digests, int digest_base) {
+  __shared__ LdsStats L;
+  __shared__ int s_fail;
+  const LaunchEntry e = table[blockIdx.x];
+  const ChipDev C = *e.chip;
+  const int patch = e.patch;
+  const int pxi = patch % C.pgx, pyi = patch / C.pgx;
+  const int x0 = pxi * C.pw, y0 = pyi * C.ph;
+  const int cols = min(C.pw, C.W - x0), rows = min(C.ph, C.H - y0);
+  const int ntiles = cols * rows;
+  for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
+  if (threadIdx.x == 0) s_fail = 0;
+  Acc acc = {};
+  const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
+  const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
+  int c_done = c0;
+  __syncthreads();
+
+  for (int c = c0; c <= c_end; ++c) {
+    const bool step = c < c_end;
+    const bool dig = digests != nullptr && c > c0;
+    if (!step && !dig) break;
+    unsigned long long h = 0;
+    bool ok = true;
+    for (int j = threadIdx.x; j < ntiles; j += blockDim.x) {
+      const int lx = j % cols, ly = j / cols, x = x0 + lx, y = y0 + ly;
+      const bool cross[4] = {ly == 0 && y > 0, ly == rows - 1 && y < C.H - 1, lx == cols - 1 && x < C.W - 1,
+                             lx == 0 && x > 0};
+      ok = ok && tile_step<MULTI>(C, y * C.W + x, x, y, c, cross, step, dig, h, acc, L);
+    }
+    if (dig) {
+      h = wave_sum(h);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&digests[c - 1 - digest_base], h);
+    }
+    if (!ok) s_fail = 1;
+    // Every store of cycle c completes before the barrier: interior slots are read by other
+    // waves of this workgroup in cycle c+1, and a queue node written in cycle c must be
+    // performed before its next writer (another home, reached only through at least three
+    // more cycles of flit traffic) can touch it.
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (s_fail) break;
+    if (step) c_done = c + 1;
+  }
+  if (threadIdx.x == 0) st_coh(&C.flags[patch * FLAG_STRIDE], c_done);
+
+  flush_counters(acc, L, C, patch, c0, c_done);
+}
+
+// ---- the one-tile-per-thread step kernel --------------------------------------------------------
+// Used when a patch has no more tiles than its workgroup has threads (the mapping of large chips
+// and of small chips in a batch).  Same model and same results as step_kernel; organised for a
+// short cycle:
+//  - a thread owns one tile for the whole launch; the tile's core words stay in registers;
+//  - link slots between two tiles of the patch live in LDS; only patch-edge slots go through
+//    global memory (stamped, polled), and the per-cycle barrier waits on LDS only;
+//  - at the end of cycle c-1 the thread draws cycle c's random words and issues cycle c's loads
+//    that do not depend on link inputs (L2 sets, queue-head nodes, the Zipf table); the L1 set
+//    load follows right after the barrier, together with the edge polls;
+//  - every thread drains its global stores (s_waitcnt vmcnt(0)) once per cycle, after issuing
+//    that cycle's loads: a queue node stored in cycle c is therefore performed before the home
+//    finishes cycle c+1, while its next writer is at least three cycles of flit traffic away.
+constexpr int FAST_MAX = 256;
+
+// Port of one flit, oldest first: eject if destined here and free, else the first free
+// productive port (X before Y), else the lowest free port; packs it at bits 3*idx of `ports`.
+__device__ __forceinline__ void arb_assign(int dst, int idx, int t, int x, int y, const ChipDev& C, unsigned valid,
+                                           unsigned& used, uint32_t& ports, Acc& acc) {
+  if (dst < 0) return;
+  unsigned port;
+  if (dst == t && !(used & 16u)) {
+    port = 4;
+  } else {
+    const int drow = C.W > 1 ? (int)__umulhi((uint32_t)dst, C.w_magic) : dst;
+    const int dx = (dst - drow * C.W) - x, dy = drow - y;
+    const int px = dx > 0 ? 2 : (dx < 0 ? 3 : -1);
+    const int py = dy > 0 ? 1 : (dy < 0 ? 0 : -1);
+    if (px >= 0 && !(used & (1u << px))) port = (unsigned)px;
+    else if (py >= 0 && !(used & (1u << py))) port = (unsigned)py;
+    else {
+      port = (unsigned)__builtin_ctz(valid & ~used & 15u);
+      acc.defl++;
+    }
+    acc.trav++;
+  }
+  used |= 1u << port;
+  ports = (ports & ~(7u << (3 * idx))) | (port << (3 * idx));
+}
+
+// The flit leaving through port p (0..3, or 4 = eject), or an empty slot.
+__device__ __forceinline__ int4 flit_on_port(uint32_t ports, unsigned p, const int4& f0, const int4& f1, const int4& f2,
+                                             const int4& f3, const int4& f4) {
+  int4 o = make_int4(-1, -1, -1, -1);
+  if ((ports & 7u) == p) o = f0;
+  if (((ports >> 3) & 7u) == p) o = f1;
+  if (((ports >> 6) & 7u) == p) o = f2;
+  if (((ports >> 9) & 7u) == p) o = f3;
+  if (((ports >> 12) & 7u) == p) o = f4;
+  return o;
+}
+
+struct Prefetch {            // loads of one cycle issued ahead of it
+  uint4 r;                   // the tile's random words
+  bool svc, local, fill, forced, drawn;
+  int line_op;               // the op's line (fill or issue); drawn ops: known after zipf_lo/hi
+  uint32_t zipf_lo, zipf_hi, zipf_f;
+  int* setR;
+  int* setL;
+  int vR[8], vL[8];
+  int4 nh, nm;               // hit-queue and miss-queue head nodes
+};
+
+template <bool MULTI>
+__device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
+                                         int* l2_base, Prefetch& P) {
+  const int N = C.N;
+  P.r = philox((uint32_t)c, (uint32_t)t, 0u, 0u, C.key0, C.key1);
+  P.svc = k1.x >= 0;
+  const bool wake = k0.y == c;
+  P.fill = k0.x == CORE_FILL && wake;
+  const bool missed = k0.x == CORE_L1MISS && wake;
+  P.local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  P.forced = k0.x == CORE_IDLE && k2.w >= 0;
+  P.drawn = k0.x == CORE_IDLE && !P.forced && P.r.x < C.op_thr;
+  P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
+  P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
+  if (P.svc) set_load(P.setR, C.w2, P.vR);
+  if (P.local) set_load(P.setL, C.w2, P.vL);
+  P.nh = make_int4(-1, -1, -1, -1);
+  P.nm = make_int4(-1, -1, -1, -1);
+  if ((unsigned)k1.z < (unsigned)N) P.nh = ld_node<MULTI>(&C.node[k1.z]);
+  if ((unsigned)k2.x < (unsigned)N) P.nm = ld_node<MULTI>(&C.node[k2.x]);
+  P.line_op = P.forced ? k2.w : k0.z;
+  P.zipf_lo = P.zipf_hi = P.zipf_f = 0;
+  if (P.drawn) {
+    const bool priv = C.private_lines > 0 && P.r.y >= C.shared_thr;
+    const uint32_t* q = priv ? C.zp : C.zs;
+    const uint32_t b = P.r.z >> 16;
+    P.zipf_f = P.r.z & 0xFFFFu;
+    P.zipf_lo = *gp(q + b);
+    P.zipf_hi = *gp(q + b + 1);
+    P.line_op = priv ? C.shared_lines + t * C.private_lines : 0;  // + rank, once the table words arrive
+  }
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
+                                                      unsigned long long* digests, int digest_base) {
+  __shared__ LdsStats L;
+  __shared__ int s_fail;
+  __shared__ int4 s_link[2][4][FAST_MAX];  // interior input slots [parity][port][local tile]
+  const LaunchEntry e = table[blockIdx.x];
+  const ChipDev C = *e.chip;
+  const int N = C.N;
+  const int patch = e.patch;
+  const int pxi = patch % C.pgx, pyi = patch / C.pgx;
+  const int x0 = pxi * C.pw, y0 = pyi * C.ph;
+  const int cols = min(C.pw, C.W - x0), rows = min(C.ph, C.H - y0);
+  const int ntiles = cols * rows;
+  const int j = threadIdx.x;
+  const bool active = j < ntiles;
+  const int lx = active ? j % cols : 0, ly = active ? j / cols : 0;
+  const int x = x0 + lx, y = y0 + ly, t = y * C.W + x;
+  const bool v0 = active && y > 0, v1 = active && y < C.H - 1, v2 = active && x < C.W - 1, v3 = active && x > 0;
+  const bool i0 = v0 && ly > 0, i1 = v1 && ly < rows - 1, i2 = v2 && lx < cols - 1, i3 = v3 && lx > 0;  // in-patch
+  const bool e0 = v0 && !i0, e1 = v1 && !i1, e2 = v2 && !i2, e3 = v3 && !i3;                            // patch edge
+  const int4 EMPTY = make_int4(-1, -1, -1, -1);
+
+  for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
+  if (threadIdx.x == 0) s_fail = 0;
+  Acc acc = {};
+  const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
+  const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
+  int c_done = c0;
+
+  int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
+  int fdst = -1;
+  if (active) {
+    k0 = gload4(&C.core[t]);
+    k1 = gload4(&C.core[N + t]);
+    k2 = gload4(&C.core[2 * N + t]);
+    fdst = *gp(reinterpret_cast<const int*>(&C.core[3 * N + t]));
+    const int par = c0 & 1;
+    if (i0) s_link[par][0][j] = slot_decode(gload4(&C.link[(par * 4 + 0) * N + t]));
+    if (i1) s_link[par][1][j] = slot_decode(gload4(&C.link[(par * 4 + 1) * N + t]));
+    if (i2) s_link[par][2][j] = slot_decode(gload4(&C.link[(par * 4 + 2) * N + t]));
+    if (i3) s_link[par][3][j] = slot_decode(gload4(&C.link[(par * 4 + 3) * N + t]));
+  }
+  // this tile's cache arrays
+  int* const l1_base = C.l1 + (size_t)(active ? t : 0) * (size_t)C.s1 * (size_t)C.w1;
+  int* const l2_base = C.l2 + (size_t)(active ? t : 0) * (size_t)C.s2 * (size_t)C.w2;
+  Prefetch P;
+  if (active) prefetch<MULTI>(C, t, c0, k0, k1, k2, l2_base, P);
+  __syncthreads();
+
+  for (int c = c0; c <= c_end; ++c) {
+    const bool step = c < c_end;
+    const bool dig = digests != nullptr && c > c0;
+    if (!step && !dig) break;
+    const int cur = c & 1, nxt = cur ^ 1;
+    unsigned long long h = 0;
+    bool ok = true;
+    if (active) {
+      // ---- inputs of cycle c: interior from LDS, edges polled until stamped c ----------------
+      int4 w0 = e0 ? ld_slot(&C.link[(cur * 4 + 0) * N + t], MULTI) : EMPTY;
+      int4 w1 = e1 ? ld_slot(&C.link[(cur * 4 + 1) * N + t], MULTI) : EMPTY;
+      int4 w2 = e2 ? ld_slot(&C.link[(cur * 4 + 2) * N + t], MULTI) : EMPTY;
+      int4 w3 = e3 ? ld_slot(&C.link[(cur * 4 + 3) * N + t], MULTI) : EMPTY;
+      // the op's L1 set (its line may need the Zipf words loaded at the end of last cycle)
+      if (P.drawn)
+        P.line_op += (int)(P.zipf_lo + (uint32_t)(((unsigned long long)P.zipf_f * (P.zipf_hi - P.zipf_lo)) >> 16));
+      int* set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
+      int u[8];
+      if (P.fill || P.forced || P.drawn) set_load(set1, C.w1, u);
+      if (MULTI && (e0 | e1 | e2 | e3)) {
+        int spins = 0;
+        for (;;) {
+          const bool p0 = e0 && !slot_has_stamp(w0, (uint32_t)c), p1 = e1 && !slot_has_stamp(w1, (uint32_t)c);
+          const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
+          if (!(p0 | p1 | p2 | p3)) break;
+          if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
+            st_coh(C.err, 1);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          if (p0) w0 = ld_slot(&C.link[(cur * 4 + 0) * N + t], true);
+          if (p1) w1 = ld_slot(&C.link[(cur * 4 + 1) * N + t], true);
+          if (p2) w2 = ld_slot(&C.link[(cur * 4 + 2) * N + t], true);
+          if (p3) w3 = ld_slot(&C.link[(cur * 4 + 3) * N + t], true);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
+      int4 f0 = i0 ? s_link[cur][0][j] : (e0 ? slot_decode(w0) : EMPTY);
+      int4 f1 = i1 ? s_link[cur][1][j] : (e1 ? slot_decode(w1) : EMPTY);
+      int4 f2 = i2 ? s_link[cur][2][j] : (e2 ? slot_decode(w2) : EMPTY);
+      int4 f3 = i3 ? s_link[cur][3][j] : (e3 ? slot_decode(w3) : EMPTY);
+
+      if (dig) {  // state owned by t after cycle c-1
+        h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
+        h = mix_pair(h, f0.x, f0.y); h = mix_pair(h, f0.z, f0.w);
+        h = mix_pair(h, f1.x, f1.y); h = mix_pair(h, f1.z, f1.w);
+        h = mix_pair(h, f2.x, f2.y); h = mix_pair(h, f2.z, f2.w);
+        h = mix_pair(h, f3.x, f3.y); h = mix_pair(h, f3.z, f3.w);
+        h = mix_pair(h, k0.x, k0.y); h = mix_pair(h, k0.z, k0.w);
+        h = mix_pair(h, k1.x, k1.y); h = mix_pair(h, k1.z, k1.w);
+        h = mix_pair(h, k2.x, k2.y);
+        h = mix_pair(h, k2.z, 0);
+        h = mix_pair(h, 0, 0);
+        h = mix_pair(h, k2.w, fdst);
+      }
+      if (step && ok) {
+        if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
+            (k2.y >= 0 && (unsigned)k2.y >= (unsigned)N) || (k1.z >= 0 && (unsigned)k1.z >= (unsigned)N) ||
+            (k2.x >= 0 && (unsigned)k2.x >= (unsigned)N)) {
+          st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
+          ok = false;
+        }
+      }
+      if (step && ok) {
+        // ---- phase one: home L2 service, then the core (Sec. 7.1 phase one; Sec. 3.5) -------
+        bool dirtyR = false, dirtyL = false, dirty1 = false;
+        int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
+        int4 nh = P.nh, nm = P.nm;
+        if (P.svc) {
+          const int rq = k1.x, line = k1.y;
+          const bool hit = set_touch(P.vR, C.w2, line, true, dirtyR);
+          acc.l2_hit += hit;
+          acc.l2_miss += !hit;
+          node_rq = rq;
+          node_ready = hit ? c : c + C.mem_lat;
+          node_line = line;
+          const int4 fresh = make_int4(-1, node_ready, line, 0);
+          if (hit) {
+            if (k1.w >= 0) { node_tail = k1.w; if (k1.w == k1.z) nh.x = rq; }
+            else { k1.z = rq; nh = fresh; }
+            k1.w = rq;
+          } else {
+            if (k2.y >= 0) { node_tail = k2.y; if (k2.y == k2.x) nm.x = rq; }
+            else { k2.x = rq; nm = fresh; }
+            k2.y = rq;
+          }
+          k1.x = -1;
+          k1.y = -1;
+        }
+        if (P.fill) {
+          set_touch(u, C.w1, P.line_op, true, dirty1);
+          const int lat = c - k0.w;
+          acc.ops_done++;
+          acc.op_lat += (unsigned long long)lat;
+          acc.op_lat_max = max(acc.op_lat_max, lat);
+          k0.x = CORE_IDLE;
+        } else if (k0.x == CORE_L1MISS && k0.y == c) {
+          if (P.local) {
+            if (P.svc && P.setL == P.setR) {
+#pragma unroll
+              for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
+            }
+            const bool hit = set_touch(P.vL, C.w2, k0.z, true, dirtyL);
+            acc.l2_hit += hit;
+            acc.l2_miss += !hit;
+            k0.x = CORE_FILL;
+            k0.y = hit ? c + 1 : c + C.mem_lat;
+          } else {
+            k0.x = CORE_SEND;
+            acc.req_made++;
+          }
+        } else if (P.forced || P.drawn) {
+          if (P.forced) k2.w = -1;
+          acc.ops_issued++;
+          k0.z = P.line_op;
+          k0.w = c;
+          if (set_touch(u, C.w1, P.line_op, false, dirty1)) {
+            acc.l1_hit++;
+            acc.ops_done++;
+          } else {
+            acc.l1_miss++;
+            k0.x = CORE_L1MISS;
+            k0.y = c + C.l1_lat;
+          }
+        }
+
+        // ---- phase two: injection, then oldest-first arbitration ----------------------------
+        const int arrivals = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0);
+        const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
+        int cls = -1;
+        if (k2.x >= 0 && nm.y <= c) cls = 0;
+        else if (k1.z >= 0) cls = 1;
+        else if (k0.x == CORE_SEND) cls = 2;
+        else if (fdst >= 0) cls = 3;
+        else if (k2.z > 0) cls = 4;
+        if (cls >= 0 && arrivals >= deg) {
+          acc.inj_blocked++;
+          cls = -1;
+        }
+        int4 fi = EMPTY;
+        if (cls >= 0) {
+          fi.y = c;
+          fi.z = t;
+          if (cls <= 1) {
+            const int4 hd = cls == 0 ? nm : nh;
+            fi.x = cls == 0 ? k2.x : k1.z;
+            if (cls == 0) { k2.x = hd.x; if (hd.x < 0) k2.y = -1; }
+            else { k1.z = hd.x; if (hd.x < 0) k1.w = -1; }
+            fi.w = (KIND_REPLY << 30) | hd.z;
+            acc.reply_sent++;
+            acc.inj_reply++;
+          } else if (cls == 2) {
+            fi.x = (int)mod_n(C, (uint32_t)k0.z);
+            fi.w = (KIND_REQ << 30) | k0.z;
+            k0.x = CORE_WAIT;
+            acc.inj_req++;
+          } else {
+            if (cls == 3) {
+              fi.x = fdst;
+              fdst = -1;
+            } else {
+              const uint4 r2 = philox((uint32_t)c, (uint32_t)t, 1u, 0u, C.key0, C.key1);
+              const int d = (int)__umulhi(r2.x, (uint32_t)(N - 1));
+              fi.x = d + (d >= t);
+              k2.z -= 1;
+            }
+            fi.w = (int)(KIND_BG << 30);
+            acc.inj_bg++;
+          }
+        }
+        uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
+        uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
+        uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
+        uint32_t qh3 = f3.x < 0 ? ~0u : (uint32_t)f3.y, ql3 = f3.x < 0 ? ~0u : (uint32_t)f3.z;
+        uint32_t qh4 = fi.x < 0 ? ~0u : (uint32_t)fi.y, ql4 = fi.x < 0 ? ~0u : (uint32_t)fi.z;
+        int sd0 = f0.x, sd1 = f1.x, sd2 = f2.x, sd3 = f3.x, sd4 = fi.x;
+        int si0 = 0, si1 = 1, si2 = 2, si3 = 3, si4 = 4;
+#define CSWAP(a, b)                                                            \
+  if (qh##b < qh##a || (qh##b == qh##a && ql##b < ql##a)) {                    \
+    uint32_t th = qh##a; qh##a = qh##b; qh##b = th;                            \
+    uint32_t tl = ql##a; ql##a = ql##b; ql##b = tl;                            \
+    int td = sd##a; sd##a = sd##b; sd##b = td;                                 \
+    int ti = si##a; si##a = si##b; si##b = ti;                                 \
+  }
+        CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
+#undef CSWAP
+        const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
+        unsigned used = 0;
+        uint32_t ports = 0x7FFFu;
+        arb_assign(sd0, si0, t, x, y, C, valid, used, ports, acc);
+        arb_assign(sd1, si1, t, x, y, C, valid, used, ports, acc);
+        arb_assign(sd2, si2, t, x, y, C, valid, used, ports, acc);
+        arb_assign(sd3, si3, t, x, y, C, valid, used, ports, acc);
+        arb_assign(sd4, si4, t, x, y, C, valid, used, ports, acc);
+
+        // ---- phase three: stores -----------------------------------------------------------
+        if (dirtyR) set_store(P.setR, C.w2, P.vR);
+        if (dirtyL) set_store(P.setL, C.w2, P.vL);
+        if (dirty1) set_store(set1, C.w1, u);
+        if (node_rq >= 0) {
+          st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
+          if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
+        }
+        // output port p of this tile: the neighbour's input slot opp(p), in LDS inside the patch
+#define out_for(p) flit_on_port(ports, (p), f0, f1, f2, f3, fi)
+        const uint32_t ns = (uint32_t)(c + 1);
+        if (v0) { const int4 o = out_for(0); if (i0) s_link[nxt][1][j - cols] = o; else st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(o, ns), MULTI); }
+        if (v1) { const int4 o = out_for(1); if (i1) s_link[nxt][0][j + cols] = o; else st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(o, ns), MULTI); }
+        if (v2) { const int4 o = out_for(2); if (i2) s_link[nxt][3][j + 1] = o; else st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(o, ns), MULTI); }
+        if (v3) { const int4 o = out_for(3); if (i3) s_link[nxt][2][j - 1] = o; else st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(o, ns), MULTI); }
+        const int4 oe = out_for(4);
+#undef out_for
+        if (oe.x >= 0) {
+          const int kind = (int)((uint32_t)oe.w >> 30);
+          const int lat = c - oe.y;
+          const unsigned long long ulat = (unsigned long long)lat;
+          acc.ej_req += kind == KIND_REQ;
+          acc.ej_reply += kind == KIND_REPLY;
+          acc.ej_bg += kind == KIND_BG;
+          acc.lat_req += kind == KIND_REQ ? ulat : 0ull;
+          acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
+          acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
+          acc.lat_max = max(acc.lat_max, lat);
+          lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
+          if (kind == KIND_REQ) {
+            acc.req_recv++;
+            k1.x = oe.z;
+            k1.y = oe.w & LINE_MASK;
+          } else if (kind == KIND_REPLY) {
+            acc.reply_recv++;
+            k0.x = CORE_FILL;
+            k0.y = c + 1;
+          }
+        }
+        if (N > 1 && P.r.w < C.bg_thr) {
+          k2.z += 1;
+          acc.bg_gen++;
+        }
+        if (c + 1 < c_end) prefetch<MULTI>(C, t, c + 1, k0, k1, k2, l2_base, P);
+      }
+    }
+    if (dig) {
+      h = wave_sum(h);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&digests[c - 1 - digest_base], h);
+    }
+    if (!ok) s_fail = 1;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0) only: this wave's LDS slot writes are done
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (s_fail) break;
+    if (step) c_done = c + 1;
+  }
+
+  // ---- write back: core words, interior slots of cycle c_done (stamped), flag, counters ----
+  if (active) {
+    gstore4(&C.core[t], k0);
+    gstore4(&C.core[N + t], k1);
+    gstore4(&C.core[2 * N + t], k2);
+    gstore4(&C.core[3 * N + t], make_int4(fdst, 0, 0, 0));
+    const int par = c_done & 1;
+    if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
+    if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
+    if (i2) gstore4(&C.link[(par * 4 + 2) * N + t], slot_encode(s_link[par][2][j], (uint32_t)c_done));
+    if (i3) gstore4(&C.link[(par * 4 + 3) * N + t], slot_encode(s_link[par][3][j], (uint32_t)c_done));
+  }
+  if (threadIdx.x == 0) st_coh(&C.flags[patch * FLAG_STRIDE], c_done);
+  flush_counters(acc, L, C, patch, c0, c_done);
 }
 
 // ---- small utility kernels (no memsets: these also record safely into graphs) -----------------
@@ -604,6 +1147,14 @@ __global__ void fill_u64(unsigned long long* p, unsigned long long v, size_t n) 
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void set_stop(ChipDev* d, int stop) { d->stop = stop; }
+// link slots of a fresh (or reloaded) chip at cycle c: every slot empty; parity c&1 holds the
+// inputs of cycle c, the other parity is stamped c-1 so that it cannot pass for cycle c+1
+__global__ void init_links(int4* link, int N, int c) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 8 * N; i += gridDim.x * blockDim.x) {
+    const int par = i / (4 * N);
+    link[i] = slot_encode(make_int4(-1, -1, -1, -1), (uint32_t)(par == (c & 1) ? c : c - 1));
+  }
+}
 // core words of a fresh chip: state idle, bg 0, everything else -1
 __global__ void init_core(int4* core, int N) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N; t += gridDim.x * blockDim.x) {
@@ -628,15 +1179,27 @@ struct sim_chip {
   hipStream_t stream;
   int64_t cycle;
   int32_t block, chunk;
+  bool fast;               // every patch fits its workgroup: one tile per thread (step_fast)
+  bool use_fast;           // allow step_fast (tests compare both kernels)
   LaunchEntry* table_dev;  // MAX_PATCHES entries
   LaunchEntry* table_host; // pinned staging
+};
+
+// A launch group: consecutive chips whose workgroups are launched together.  Chips cut into
+// several patches wait on each other's edges, so a group that holds such a chip is kept within
+// the number of workgroups the device can hold at once; groups run one after the other.
+struct sim_launch_group {
+  int32_t first_chip, n_chips;
+  int64_t first_entry, n_entries;
+  bool multi;
 };
 
 struct sim_group {
   std::vector<sim_chip*> chips;
   std::vector<int32_t> first_entry;  // first table entry of chip i
+  std::vector<sim_launch_group> groups;
   int32_t block;
-  bool multi;
+  bool multi, fast;
   hipStream_t stream;
   LaunchEntry* table_dev;
   LaunchEntry* table_host;
@@ -661,7 +1224,7 @@ bool ways_ok(int32_t w) { return w == 1 || w == 2 || w == 4 || w == 8; }
 bool config_ok(const sim_config* c) {
   if (!c || c->width < 1 || c->height < 1 || c->width > 2048 || c->height > 2048) return false;
   const int64_t N = (int64_t)c->width * c->height;
-  if (N > (1 << 20)) return false;
+  if (N >= (1 << 20)) return false;  // tile indices take 20 bits in a slot word, all ones = empty
   if (!pow2(c->l1_sets) || !ways_ok(c->l1_ways) || !pow2(c->l2_sets) || !ways_ok(c->l2_ways)) return false;
   if (c->l1_lat < 1 || c->mem_lat < 1 || c->shared_lines < 1 || c->private_lines < 0) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
@@ -696,6 +1259,18 @@ Layout layout(const sim_config* c) {
   return L;
 }
 
+// host copies of the slot encoding (dump and load)
+void host_decode(const int4& w, int32_t* out) {
+  const uint32_t d = (uint32_t)w.x & TILE_BITS_MASK;
+  if (d == TILE_BITS_MASK) { out[0] = out[1] = out[2] = out[3] = -1; return; }
+  out[0] = (int32_t)d; out[1] = w.y; out[2] = (int32_t)((uint32_t)w.z & TILE_BITS_MASK); out[3] = w.w;
+}
+int4 host_encode(const int32_t* f, uint32_t stamp) {
+  const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
+  if (f[0] < 0) return make_int4((int)(TILE_BITS_MASK | s), -1, (int)(TILE_BITS_MASK | s), -1);
+  return make_int4((int)((uint32_t)f[0] | s), f[1], (int)((uint32_t)f[2] | s), f[3]);
+}
+
 int launch_grid_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
   if (!n) return SIM_OK;
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
@@ -723,11 +1298,13 @@ int device_cus() {
   return cus;
 }
 
+const void* multi_kernel(bool fast) {
+  return fast ? reinterpret_cast<const void*>(step_fast<true>) : reinterpret_cast<const void*>(step_kernel<true>);
+}
 // how many workgroups of `block` threads of the multi-patch kernel can be resident at once
-int resident_limit(int block) {
+int resident_limit(int block, bool fast) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(step_kernel<true>), block, 0) != hipSuccess)
-    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
   return per_cu * device_cus();
 }
 
@@ -763,13 +1340,14 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   const int pgx = (h->cfg.width + pw - 1) / pw, pgy = (h->cfg.height + ph - 1) / ph;
   const int np = pgx * pgy;
   if (np > h->hd.max_patches) return SIM_EINVAL;
-  if (np > 1 && np > resident_limit(block)) return SIM_EINVAL;
+  if (np > 1 && np > resident_limit(block, pw * ph <= block)) return SIM_EINVAL;
   h->hd.pw = pw;
   h->hd.ph = ph;
   h->hd.pgx = pgx;
   h->hd.pgy = pgy;
   h->hd.n_patches = np;
   h->block = block;
+  h->fast = pw * ph <= block;
   // every patch's flag records the chip's cycle
   int rc = launch_grid_fill_i32(h->hd.flags, (int32_t)h->cycle, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream);
   if (rc) return rc;
@@ -778,13 +1356,16 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   return upload_desc(h);
 }
 
-int launch_entries(const LaunchEntry* table, int64_t n, bool multi, int block, int chunk, unsigned long long* digests,
-                   int digest_base, hipStream_t s) {
+// fast: every patch has at most `block` tiles (one tile per thread: step_fast)
+int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
+                   unsigned long long* digests, int digest_base, hipStream_t s) {
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(step_kernel<true>), dim3((unsigned)n), dim3(block),
-                                        args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast), dim3((unsigned)n), dim3(block), args, 0, s));
+  } else if (fast) {
+    hipLaunchKernelGGL(step_fast<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    HIPCHECK(hipGetLastError());
   } else {
     hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
@@ -832,6 +1413,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
+  h->use_fast = true;
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -843,6 +1425,16 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.shared_thr = cfg->shared_thr;
   d.bg_thr = cfg->bg_thr;
   d.w_magic = cfg->width > 1 ? (uint32_t)((0x100000000ull + cfg->width - 1) / cfg->width) : 0u;
+  if (N > 1) {
+    const int k = 30 - __builtin_clz((unsigned)N);  // floor(log2 N) - 1
+    d.n_shift = (uint32_t)k;
+    d.n_magic = (uint32_t)(((1ull << (32 + k)) + (uint64_t)N - 1) / (uint64_t)N);
+  } else {
+    d.n_shift = 0;
+    d.n_magic = 0;
+  }
+  d.w1_shift = __builtin_ctz((unsigned)cfg->l1_ways);
+  d.w2_shift = __builtin_ctz((unsigned)cfg->l2_ways);
   d.s1 = cfg->l1_sets;
   d.w1 = cfg->l1_ways;
   d.s2 = cfg->l2_sets;
@@ -871,7 +1463,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   }
   int rc = SIM_OK;
   auto fail = [&](int code) { (void)hipHostFree(h->table_host); delete h; return code; };
-  if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.link), -1, 2 * 4 * (size_t)N * 4, h->stream))) return fail(rc);
+  hipLaunchKernelGGL(init_links, dim3(std::min((8 * N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.link, N, 0);
+  if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
   hipLaunchKernelGGL(init_core, dim3(std::min((N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.core, N);
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
   if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.node), -1, (size_t)N * 4, h->stream))) return fail(rc);
@@ -897,6 +1490,12 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
   if (chunk < 0) return SIM_EINVAL;
   if (chunk) h->chunk = chunk;
   return apply_mapping(h, pw ? pw : h->hd.pw, ph ? ph : h->hd.ph, block ? block : h->block);
+}
+
+int sim_set_kernel(sim_t* h, int32_t generic_only) {
+  if (!h) return SIM_EINVAL;
+  h->use_fast = !generic_only;
+  return SIM_OK;
 }
 
 int sim_get_launch(const sim_t* h, int32_t* pw, int32_t* ph, int32_t* block, int32_t* chunk) {
@@ -928,7 +1527,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   }
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
-    int rc = launch_entries(h->table_dev, np, np > 1, h->block, h->chunk, dig, (int)h->cycle, h->stream);
+    int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream);
     if (rc) return rc;
   }
   h->cycle += n;
@@ -973,11 +1572,7 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
                            h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, 0, 0, 0, 0, 0, 0};
   std::memcpy(buf, hdr, sizeof hdr);
   for (size_t t = 0; t < N; ++t)
-    for (int p = 0; p < 4; ++p) {
-      const int4 f = link[p * N + t];
-      int32_t* w = buf + o + t * 16 + p * 4;
-      w[0] = f.x; w[1] = f.y; w[2] = f.z; w[3] = f.w;
-    }
+    for (int p = 0; p < 4; ++p) host_decode(link[p * N + t], buf + o + t * 16 + p * 4);
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
     const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], nd = node[t];
@@ -1005,7 +1600,8 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) {
       const int32_t* w = buf + o + t * 16 + p * 4;
-      link[p * N + t] = make_int4(w[0], w[1], w[2], w[3]);
+      if (w[0] >= (int32_t)N || w[2] >= (int32_t)N || (w[0] >= 0 && w[2] < 0)) return SIM_EINVAL;
+      link[p * N + t] = host_encode(w, (uint32_t)cyc);
     }
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
@@ -1020,8 +1616,11 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
   const int par = (int)(cyc & 1);
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)par * 4 * N, link.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
-  int rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(h->hd.link + (size_t)(par ^ 1) * 4 * N), -1, 4 * N * 4, h->stream);
-  if (rc) return rc;
+  // the other parity: empty, stamped cyc-1 (it is rewritten during cycle cyc)
+  std::vector<int4> other(4 * N, host_encode(std::vector<int32_t>{-1, -1, -1, -1}.data(), (uint32_t)(cyc - 1)));
+  HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)(par ^ 1) * 4 * N, other.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  int rc = SIM_OK;
   HIPCHECK(hipMemcpyAsync(h->hd.core, core.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.node, node.data(), N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.l1, buf + o, n1 * 4, hipMemcpyHostToDevice, h->stream));
@@ -1082,23 +1681,48 @@ int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, si
   if (!out || !chips || n < 1 || !dev_mem || block < 0 || block > 256 || block % 64) return SIM_EINVAL;
   *out = nullptr;
   int64_t entries = 0;
-  int32_t bmax = 0;
-  bool multi = false;
+  int32_t bmax = 0, tmax = 0;
+  bool multi = false, use_fast = true;
   for (int i = 0; i < n; ++i) {
     if (!chips[i]) return SIM_EINVAL;
     entries += chips[i]->hd.n_patches;
     bmax = std::max(bmax, chips[i]->block);
+    tmax = std::max(tmax, chips[i]->hd.pw * chips[i]->hd.ph);
     multi = multi || chips[i]->hd.n_patches > 1;
+    use_fast = use_fast && chips[i]->use_fast;
   }
   if (bytes < simb_state_bytes(n, entries)) return SIM_ENOMEM;
   if (entries > 0x7FFFFFFF) return SIM_EINVAL;
   const int32_t blk = block ? block : bmax;
-  if (multi && entries > resident_limit(blk)) return SIM_EINVAL;
+  const bool fast = use_fast && tmax <= blk;
+  const int limit = multi ? resident_limit(blk, fast) : 0;
+  // split into launch groups: a group with a multi-patch chip stays within `limit` workgroups
+  std::vector<sim_launch_group> groups;
+  {
+    sim_launch_group cur{0, 0, 0, 0, false};
+    int64_t e = 0;
+    for (int i = 0; i < n; ++i) {
+      const int np = chips[i]->hd.n_patches;
+      if (np > 1 && np > limit) return SIM_EINVAL;  // this chip alone cannot be resident
+      const bool m = cur.multi || np > 1;
+      if (cur.n_chips > 0 && m && cur.n_entries + np > limit) {
+        groups.push_back(cur);
+        cur = sim_launch_group{i, 0, e, 0, false};
+      }
+      cur.n_chips++;
+      cur.n_entries += np;
+      cur.multi = cur.multi || np > 1;
+      e += np;
+    }
+    groups.push_back(cur);
+  }
   sim_group* g = new (std::nothrow) sim_group();
   if (!g) return SIM_ENOMEM;
   g->chips.assign(chips, chips + n);
   g->block = blk;
   g->multi = multi;
+  g->fast = fast;
+  g->groups = groups;
   g->stream = static_cast<hipStream_t>(stream);
   g->table_dev = static_cast<LaunchEntry*>(dev_mem);
   g->n_entries = entries;
@@ -1131,19 +1755,26 @@ int simb_step(simb_t* g, const int64_t* cycles) {
     for (int p = 0; p < h->hd.n_patches; ++p) g->table_host[g->first_entry[i] + p].stop = stop;
   }
   HIPCHECK(hipMemcpyAsync(g->table_dev, g->table_host, (size_t)g->n_entries * sizeof(LaunchEntry), hipMemcpyHostToDevice, g->stream));
-  const int launches = (int)((longest + chunk - 1) / chunk);
-  for (int i = 0; i < launches; ++i) {
-    int rc = launch_entries(g->table_dev, g->n_entries, g->multi, g->block, chunk, nullptr, 0, g->stream);
-    if (rc) return rc;
+  for (const sim_launch_group& lg : g->groups) {
+    int64_t lg_longest = 0;
+    for (int i = lg.first_chip; i < lg.first_chip + lg.n_chips; ++i) lg_longest = std::max(lg_longest, cycles[i]);
+    const int launches = (int)((lg_longest + chunk - 1) / chunk);
+    for (int k = 0; k < launches; ++k) {
+      int rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
+                              g->stream);
+      if (rc) return rc;
+    }
   }
   for (size_t i = 0; i < g->chips.size(); ++i) g->chips[i]->cycle += cycles[i];
   HIPCHECK(hipStreamSynchronize(g->stream));
+  int worst = SIM_OK;
   for (size_t i = 0; i < g->chips.size(); ++i) {
     int32_t err = 0;
     HIPCHECK(hipMemcpy(&err, g->chips[i]->hd.err, sizeof err, hipMemcpyDeviceToHost));
-    if (err) return SIM_EHANG;
+    if (err == 1) worst = SIM_EHANG;
+    else if (err && worst == SIM_OK) worst = SIM_EINVARIANT;
   }
-  return SIM_OK;
+  return worst;
 }
 
 int simb_destroy(simb_t* g) {

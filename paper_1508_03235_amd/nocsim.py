@@ -80,6 +80,7 @@ def _lib():
             "sim_set_rates": (i32, [p, u32, u32]),
             "sim_set_launch": (i32, [p, i32, i32, i32, i32]),
             "sim_get_launch": (i32, [p, p, p, p, p]),
+            "sim_set_kernel": (i32, [p, i32]),
             "sim_destroy": (i32, [p]),
             "sim_strerror": (C.c_char_p, [i32]),
             "sim_last_hip_error": (i32, []),
@@ -100,7 +101,7 @@ def exported_symbols():
     """Names of the functions the library must export (checked by the CPU tests)."""
     return ["sim_state_bytes", "sim_create", "sim_step", "sim_sync", "sim_cycle", "sim_stats",
             "sim_dump_words", "sim_dump", "sim_load", "sim_force_op", "sim_force_bg",
-            "sim_set_rates", "sim_set_launch", "sim_get_launch", "sim_destroy", "sim_strerror",
+            "sim_set_rates", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
             "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_step", "simb_destroy"]
 
 
@@ -214,6 +215,9 @@ class Sim:
 
     def set_launch(self, patch_w=0, patch_h=0, block=0, chunk=0):
         _check("sim_set_launch", _lib().sim_set_launch(self._h, patch_w, patch_h, block, chunk))
+
+    def set_kernel(self, generic_only: bool):
+        _check("sim_set_kernel", _lib().sim_set_kernel(self._h, 1 if generic_only else 0))
 
     def get_launch(self):
         v = [C.c_int32() for _ in range(4)]

@@ -61,7 +61,8 @@ class GpuBackend(Backend):
 
     def create(self, params):
         s = self.nocsim.Sim(params)
-        s.set_launch(params.width, params.height, self.block, self.chunk)
+        side = 16 if params.tiles > self.block else max(params.width, params.height)
+        s.set_launch(min(side, params.width), min(side, params.height), self.block, self.chunk)
         return s
 
     def step(self, chips, cycles):

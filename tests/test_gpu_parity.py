@@ -13,16 +13,18 @@ from tests.harness import STAT, load_golden, run_flit_trace, run_op_trace, split
 pytestmark = pytest.mark.gpu
 
 
-def gpu_sim(p, launch=None):
+def gpu_sim(p, launch=None, generic=False):
     from paper_1508_03235_amd import nocsim
     s = nocsim.Sim(p)
     if launch:
         s.set_launch(*launch)
+    if generic:
+        s.set_kernel(True)
     return s
 
 
-def assert_same_run(p, cycles, launch=None, step_sizes=None):
-    g = gpu_sim(p, launch)
+def assert_same_run(p, cycles, launch=None, step_sizes=None, generic=False):
+    g = gpu_sim(p, launch, generic)
     o = O.OracleSim(p)
     steps = step_sizes or [cycles]
     for n in steps:
@@ -65,13 +67,15 @@ def test_small_shapes(w, h):
     assert_same_run(p, 3000)
 
 
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (3, 5, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (1, 13, 64, 0),
-                                    (5, 5, 64, 37)])
-def test_patch_mappings_are_exact(launch):
-    """The chip cut into patches (edges exchanged through cycle flags) gives the same run as
-    the oracle for patch shapes that do and do not divide the mesh, and odd chunk lengths."""
+                                    (5, 5, 64, 37), (20, 13, 64, 0), (16, 8, 128, 0)])
+def test_patch_mappings_are_exact(launch, generic):
+    """The chip cut into patches (edges exchanged through stamped slots) gives the same run
+    as the oracle for patch shapes that do and do not divide the mesh, odd chunk lengths,
+    one tile per thread (fast kernel) and several tiles per thread (general kernel)."""
     p = W.config0().with_(width=20, height=13, seed=5, bg_thr=W.thr(0.15), op_thr=W.thr(0.5))
-    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800], generic=generic)
 
 
 def test_config1_prefix():
@@ -83,14 +87,19 @@ def test_config1_prefix():
 def test_config2_full_size_prefix(rate):
     """208x208 (43,264 tiles) in the launch configuration the benchmark times: a prefix of
     the run, every cycle compared."""
-    assert_same_run(W.config2(rate), 120)
+    assert_same_run(W.config2(rate), 120, step_sizes=[50, 70])
+
+
+def test_config2_general_kernel_prefix():
+    assert_same_run(W.config2(0.1), 60, generic=True)
 
 
 def test_repeatable_and_mapping_independent():
     p = W.config0().with_(width=16, height=16, seed=3, bg_thr=W.thr(0.1), op_thr=W.thr(0.4))
     runs = []
-    for launch in [None, (4, 4, 64, 0), (16, 1, 64, 0), (8, 8, 64, 100)]:
-        g = gpu_sim(p, launch)
+    for launch, generic in [(None, False), ((4, 4, 64, 0), False), ((16, 1, 64, 0), False), ((8, 8, 64, 100), False),
+                            ((4, 4, 64, 0), True), ((16, 16, 64, 0), True)]:
+        g = gpu_sim(p, launch, generic)
         runs.append(g.step(800, digests=True))
     for r in runs[1:]:
         assert (r == runs[0]).all()
@@ -140,3 +149,18 @@ def test_batch_each_chip_matches_its_own_run():
         o.step(c0 + c1)
         assert s.cycle == c0 + c1
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} seed {p.seed}"
+
+
+def test_batch_split_into_resident_groups():
+    """A batch with more workgroups than the device holds at once runs as several launch
+    groups; every chip still equals its own oracle run."""
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=32, height=32, seed=2000 + i, bg_thr=W.thr(0.05 + 0.01 * (i % 5)),
+                                l2_sets=64, l1_sets=32) for i in range(40)]
+    sims = [gpu_sim(p, launch=(4, 4, 64, 0)) for p in params]   # 64 patches per chip, 2,560 in all
+    b = nocsim.Batch(sims, block=64)
+    b.step([150] * len(sims))
+    for i in (0, 17, 39):
+        o = O.OracleSim(params[i])
+        o.step(150)
+        assert (sims[i].dump() == o.dump()).all(), f"chip {i}"
