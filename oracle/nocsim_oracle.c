@@ -465,10 +465,15 @@ static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
+/* Digest of the words tile t owns after cycle c: its 16 input-slot words for the next cycle
+   and its core record.  The queue-node words (next, ready, line) are written by the
+   requester's home, not by the tile, so they are left out (zeroed); they are compared through
+   the canonical dump instead. */
 static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
   int32_t w[32];
   memcpy(w, s->link[(c + 1) & 1] + (size_t)t * 16, 16 * sizeof(int32_t));
   memcpy(w + 16, s->core + (size_t)t * C_WORDS, 16 * sizeof(int32_t));
+  w[16 + C_NEXT] = w[16 + C_READY] = w[16 + C_NLINE] = 0;
   uint64_t h = mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)t);
   for (int i = 0; i < 16; ++i) h = mix64(h ^ (((uint64_t)(uint32_t)w[2 * i] << 32) | (uint32_t)w[2 * i + 1]));
   return h;
