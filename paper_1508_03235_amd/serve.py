@@ -2,9 +2,11 @@
 
 Each job is one chip (its own device buffer).  A job is admitted when its buffer fits the
 HBM state budget and a slot is free; every scheduler tick advances all resident jobs
-together by one persistent launch (`simb_step`: one workgroup per chip, each chip with its
-own remaining cycle count), retires the jobs that finished, reads their statistics, frees
-their memory and admits new arrivals.  Requests that arrive while others run join at the
+together (`simb_step`: the patches of all resident chips in one persistent launch, or a few
+launch groups when they do not fit the device at once, each chip with its own remaining
+cycle count), retires the jobs that finished, reads their statistics, frees their memory and
+admits new arrivals.  A job whose creation or step fails is retired with its error; the
+others keep running.  Requests that arrive while others run join at the
 next tick, so their work overlaps on the device.  Because every chip's randomness is keyed
 by its own (seed; cycle, tile), a job's result does not depend on what it ran beside.
 
@@ -13,9 +15,8 @@ accounting and completion logic can be tested on the CPU with the oracle behind 
 """
 from __future__ import annotations
 
-import heapq
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Callable, Optional
 
 import numpy as np
@@ -29,8 +30,8 @@ class JobResult:
     finish_s: float
     cycles: int
     tiles: int
-    stats: np.ndarray
-    digest: Optional[np.ndarray] = None
+    stats: Optional[np.ndarray]
+    error: Optional[str] = None
 
     @property
     def latency_s(self) -> float:
@@ -43,6 +44,9 @@ class Backend:
     def state_bytes(self, params) -> int: ...
     def create(self, params): ...
     def step(self, chips: list, cycles: list[int]) -> None: ...
+    def step_one(self, chip, cycles: int) -> None: ...
+    def cycle(self, chip) -> int: ...
+    def check(self, chip) -> None: ...
     def stats(self, chip) -> np.ndarray: ...
     def release(self, chip) -> None: ...
 
@@ -70,6 +74,15 @@ class GpuBackend(Backend):
         b.step(cycles)
         b.close()
 
+    def step_one(self, chip, cycles):
+        chip.step(int(cycles))
+
+    def cycle(self, chip):
+        return chip.cycle
+
+    def check(self, chip):
+        chip.sync()
+
     def stats(self, chip):
         return chip.stats()
 
@@ -94,8 +107,17 @@ class OracleBackend(Backend):
 
     def step(self, chips, cycles):
         for c, n in zip(chips, cycles):
-            if n:
-                c.step(int(n))
+            self.step_one(c, n)
+
+    def step_one(self, chip, cycles):
+        if cycles:
+            chip.step(int(cycles))
+
+    def cycle(self, chip):
+        return chip.cycle
+
+    def check(self, chip):
+        pass
 
     def stats(self, chip):
         return chip.stats()
@@ -122,7 +144,7 @@ class ServeReport:
     ticks: int
 
     def latency_percentiles(self):
-        lat = np.array([r.latency_s for r in self.results])
+        lat = np.array([r.latency_s for r in self.results if r.error is None])
         return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
 
     @property
@@ -188,24 +210,51 @@ class Server:
                 if used + nb > self.budget:
                     break
                 waiting.pop(0)
-                chip = self.backend.create(j.params)
+                try:
+                    chip = self.backend.create(j.params)
+                except Exception as e:  # the job fails alone
+                    results.append(JobResult(j.index, j.arrival_s, now(), now(), 0, j.params.tiles, None, repr(e)))
+                    continue
                 used += nb
                 peak = max(peak, used)
                 live.append(_Live(j, chip, j.cycles, now(), nb))
+            if not live:
+                continue
             # one tick: every resident job advances together
             steps = [min(self.tick_cycles, lv.remaining) for lv in live]
             t0 = self.clock()
-            self.backend.step([lv.chip for lv in live], steps)
+            failed = {}
+            before = [self.backend.cycle(lv.chip) for lv in live]
+            try:
+                self.backend.step([lv.chip for lv in live], steps)
+            except Exception:
+                # find the failing chips: finish each chip's share alone if the batch did not run
+                # it, then check the chip's own error status
+                for k, lv in enumerate(live):
+                    try:
+                        done = self.backend.cycle(lv.chip) - before[k]
+                        if done < steps[k]:
+                            self.backend.step_one(lv.chip, steps[k] - done)
+                        self.backend.check(lv.chip)
+                    except Exception as e:
+                        failed[k] = repr(e)
             dt = self.clock() - t0
             if not self.realtime:
                 vnow += dt
             ticks += 1
-            for lv, n in zip(live, steps):
+            for k, (lv, n) in enumerate(zip(live, steps)):
+                if k in failed:
+                    continue
                 lv.remaining -= n
                 tile_cycles += n * lv.job.params.tiles
             still = []
-            for lv in live:
-                if lv.remaining == 0:
+            for k, lv in enumerate(live):
+                if k in failed:
+                    results.append(JobResult(lv.job.index, lv.job.arrival_s, lv.admit_s, now(), lv.job.cycles - lv.remaining,
+                                             lv.job.params.tiles, None, failed[k]))
+                    self.backend.release(lv.chip)
+                    used -= lv.nbytes
+                elif lv.remaining == 0:
                     st = self.backend.stats(lv.chip)
                     r = JobResult(lv.job.index, lv.job.arrival_s, lv.admit_s, now(), lv.job.cycles,
                                   lv.job.params.tiles, st)

@@ -164,3 +164,28 @@ def test_batch_split_into_resident_groups():
         o = O.OracleSim(params[i])
         o.step(150)
         assert (sims[i].dump() == o.dump()).all(), f"chip {i}"
+
+
+@pytest.mark.parametrize("w,h", [(700, 3), (3, 700), (1, 1500), (300, 17)])
+def test_wide_and_tall_chips(w, h):
+    """Chips wider than 256 columns (square patches) and very tall or one-column chips."""
+    p = W.config0().with_(width=w, height=h, seed=w + 7 * h, bg_thr=W.thr(0.1), op_thr=W.thr(0.3),
+                          l1_sets=16, l2_sets=32)
+    assert_same_run(p, 150, step_sizes=[60, 90])
+
+
+def test_largest_line_numbers():
+    """252x256 tiles with 2^14 private lines each: the top private line is 2^30 - 1, the
+    largest line the flit format holds."""
+    p = W.config1().with_(width=252, height=256, l1_sets=16, l2_sets=16, op_thr=W.thr(0.9), shared_thr=0)
+    assert p.shared_lines + p.tiles * p.private_lines == 2**30
+    assert_same_run(p, 25)
+
+
+def test_autotuned_mapping_gives_the_same_run(tmp_path):
+    from paper_1508_03235_amd import autotune
+    p = W.config1().with_(width=40, height=24, seed=77, bg_thr=W.thr(0.1))
+    best = autotune.tune(p, cycles=100, warmup=20, cache_path=str(tmp_path / "tune.json"))
+    assert len(best) == 3
+    assert autotune.tune(p, cache_path=str(tmp_path / "tune.json")) == best   # cached
+    assert_same_run(p, 400, launch=(best[0], best[1], best[2], 0))

@@ -58,6 +58,47 @@ def test_job_larger_than_budget_is_rejected():
         Server(OracleBackend(), budget_bytes=10).run(jobs)
 
 
+class FlakyBackend(OracleBackend):
+    """The oracle backend with one job that cannot be created and one chip whose step fails."""
+
+    def __init__(self, bad_create, bad_step):
+        super().__init__()
+        self.bad_create, self.bad_step = bad_create, bad_step
+
+    def create(self, params):
+        if params.seed == self.bad_create:
+            raise RuntimeError("no memory for this job")
+        return super().create(params)
+
+    def step(self, chips, cycles):
+        if any(c.params.seed == self.bad_step for c in chips):
+            raise RuntimeError("batch step failed")
+        super().step(chips, cycles)
+
+    def step_one(self, chip, cycles):
+        if chip.params.seed == self.bad_step:
+            raise RuntimeError("chip fault")
+        super().step_one(chip, cycles)
+
+
+def test_failures_are_isolated_per_job():
+    jobs = small_jobs(12)
+    be = FlakyBackend(bad_create=jobs[3].params.seed, bad_step=jobs[7].params.seed)
+    budget = 4 * max(be.state_bytes(j.params) for j in jobs)
+    dumps = {}
+    rep = Server(be, budget, tick_cycles=50).run(jobs, on_finish=lambda r, chip: dumps.__setitem__(r.index, chip.dump()))
+    by = {r.index: r for r in rep.results}
+    assert len(by) == len(jobs)
+    assert by[3].error and "no memory" in by[3].error
+    assert by[7].error and "chip fault" in by[7].error
+    for j in jobs:
+        if j.index in (3, 7):
+            continue
+        assert by[j.index].error is None
+        d, st = alone(j)
+        assert (dumps[j.index] == d).all(), j.index   # neighbours of the failing chip are unaffected
+
+
 @pytest.mark.gpu
 def test_gpu_serving_results_equal_solo_runs():
     from paper_1508_03235_amd import nocsim
