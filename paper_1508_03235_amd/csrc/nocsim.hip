@@ -774,9 +774,11 @@ __device__ __forceinline__ int4 flit_on_port(uint32_t ports, unsigned p, const i
   return o;
 }
 
+constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;
+
 struct Prefetch {            // loads of one cycle issued ahead of it
   uint4 r;                   // the tile's random words
-  bool svc, local, fill, forced, drawn;
+  uint32_t flags;            // PF_*: which of the cycle's memory steps happen (bits, not lane masks)
   int line_op;               // the op's line (fill or issue); drawn ops: known after zipf_lo/hi
   uint32_t zipf_lo, zipf_hi, zipf_f;
   int* setR;
@@ -790,24 +792,26 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
                                          int* l2_base, Prefetch& P) {
   const int N = C.N;
   P.r = philox((uint32_t)c, (uint32_t)t, 0u, 0u, C.key0, C.key1);
-  P.svc = k1.x >= 0;
+  const bool svc = k1.x >= 0;
   const bool wake = k0.y == c;
-  P.fill = k0.x == CORE_FILL && wake;
+  const bool fill = k0.x == CORE_FILL && wake;
   const bool missed = k0.x == CORE_L1MISS && wake;
-  P.local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
-  P.forced = k0.x == CORE_IDLE && k2.w >= 0;
-  P.drawn = k0.x == CORE_IDLE && !P.forced && P.r.x < C.op_thr;
+  const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  const bool forced = k0.x == CORE_IDLE && k2.w >= 0;
+  const bool drawn = k0.x == CORE_IDLE && !forced && P.r.x < C.op_thr;
+  P.flags = (svc ? PF_SVC : 0u) | (local ? PF_LOCAL : 0u) | (fill ? PF_FILL : 0u) | (forced ? PF_FORCED : 0u) |
+            (drawn ? PF_DRAWN : 0u);
   P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
   P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
-  if (P.svc) set_load(P.setR, C.w2, P.vR);
-  if (P.local) set_load(P.setL, C.w2, P.vL);
+  if (svc) set_load(P.setR, C.w2, P.vR);
+  if (local) set_load(P.setL, C.w2, P.vL);
   P.nh = make_int4(-1, -1, -1, -1);
   P.nm = make_int4(-1, -1, -1, -1);
   if ((unsigned)k1.z < (unsigned)N) P.nh = ld_node<MULTI>(&C.node[k1.z]);
   if ((unsigned)k2.x < (unsigned)N) P.nm = ld_node<MULTI>(&C.node[k2.x]);
-  P.line_op = P.forced ? k2.w : k0.z;
+  P.line_op = forced ? k2.w : k0.z;
   P.zipf_lo = P.zipf_hi = P.zipf_f = 0;
-  if (P.drawn) {
+  if (drawn) {
     const bool priv = C.private_lines > 0 && P.r.y >= C.shared_thr;
     const uint32_t* q = priv ? C.zp : C.zs;
     const uint32_t b = P.r.z >> 16;
@@ -818,7 +822,7 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   }
 }
 
-template <bool MULTI>
+template <bool MULTI, bool DIGEST>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   __shared__ LdsStats L;
@@ -836,9 +840,18 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const bool active = j < ntiles;
   const int lx = active ? j % cols : 0, ly = active ? j / cols : 0;
   const int x = x0 + lx, y = y0 + ly, t = y * C.W + x;
-  const bool v0 = active && y > 0, v1 = active && y < C.H - 1, v2 = active && x < C.W - 1, v3 = active && x > 0;
-  const bool i0 = v0 && ly > 0, i1 = v1 && ly < rows - 1, i2 = v2 && lx < cols - 1, i3 = v3 && lx > 0;  // in-patch
-  const bool e0 = v0 && !i0, e1 = v1 && !i1, e2 = v2 && !i2, e3 = v3 && !i3;                            // patch edge
+  // geometry of the tile as bits of one vector register (bit p: link p exists; 4+p: the neighbour
+  // is in this patch; 8+p: it is across a patch edge); re-read each cycle so the compiler keeps
+  // these as bits instead of a dozen live scalar lane masks
+  uint32_t geo0;
+  {
+    const bool a0 = active && y > 0, a1 = active && y < C.H - 1, a2 = active && x < C.W - 1, a3 = active && x > 0;
+    const bool b0 = a0 && ly > 0, b1 = a1 && ly < rows - 1, b2 = a2 && lx < cols - 1, b3 = a3 && lx > 0;
+    geo0 = (a0 ? 1u : 0u) | (a1 ? 2u : 0u) | (a2 ? 4u : 0u) | (a3 ? 8u : 0u) | (b0 ? 16u : 0u) | (b1 ? 32u : 0u) |
+           (b2 ? 64u : 0u) | (b3 ? 128u : 0u) | ((a0 && !b0) ? 256u : 0u) | ((a1 && !b1) ? 512u : 0u) |
+           ((a2 && !b2) ? 1024u : 0u) | ((a3 && !b3) ? 2048u : 0u);
+  }
+#define GEO(bit) (((geo >> (bit)) & 1u) != 0u)
   const int4 EMPTY = make_int4(-1, -1, -1, -1);
 
   for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
@@ -850,6 +863,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 
   int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
   int fdst = -1;
+  uint32_t geo = geo0;
+  const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
   if (active) {
     k0 = gload4(&C.core[t]);
     k1 = gload4(&C.core[N + t]);
@@ -870,23 +885,32 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 
   for (int c = c0; c <= c_end; ++c) {
     const bool step = c < c_end;
-    const bool dig = digests != nullptr && c > c0;
+    const bool dig = DIGEST && c > c0;
     if (!step && !dig) break;
     const int cur = c & 1, nxt = cur ^ 1;
     unsigned long long h = 0;
     bool ok = true;
     if (active) {
+      uint32_t geo = geo0;
+      asm volatile("" : "+v"(geo));
+      const bool v0 = GEO(0), v1 = GEO(1), v2 = GEO(2), v3 = GEO(3);
+      const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
+      const bool e0 = GEO(8), e1 = GEO(9), e2 = GEO(10), e3 = GEO(11);
       // ---- inputs of cycle c: interior from LDS, edges polled until stamped c ----------------
       int4 w0 = e0 ? ld_slot(&C.link[(cur * 4 + 0) * N + t], MULTI) : EMPTY;
       int4 w1 = e1 ? ld_slot(&C.link[(cur * 4 + 1) * N + t], MULTI) : EMPTY;
       int4 w2 = e2 ? ld_slot(&C.link[(cur * 4 + 2) * N + t], MULTI) : EMPTY;
       int4 w3 = e3 ? ld_slot(&C.link[(cur * 4 + 3) * N + t], MULTI) : EMPTY;
+      uint32_t pf = P.flags;
+      asm volatile("" : "+v"(pf));
+      const bool p_svc = (pf & PF_SVC) != 0, p_local = (pf & PF_LOCAL) != 0, p_fill = (pf & PF_FILL) != 0;
+      const bool p_forced = (pf & PF_FORCED) != 0, p_drawn = (pf & PF_DRAWN) != 0;
       // the op's L1 set (its line may need the Zipf words loaded at the end of last cycle)
-      if (P.drawn)
+      if (p_drawn)
         P.line_op += (int)(P.zipf_lo + (uint32_t)(((unsigned long long)P.zipf_f * (P.zipf_hi - P.zipf_lo)) >> 16));
       int* set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
       int u[8];
-      if (P.fill || P.forced || P.drawn) set_load(set1, C.w1, u);
+      if (p_fill || p_forced || p_drawn) set_load(set1, C.w1, u);
       if (MULTI && (e0 | e1 | e2 | e3)) {
         int spins = 0;
         for (;;) {
@@ -937,7 +961,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         bool dirtyR = false, dirtyL = false, dirty1 = false;
         int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
         int4 nh = P.nh, nm = P.nm;
-        if (P.svc) {
+        if (p_svc) {
           const int rq = k1.x, line = k1.y;
           const bool hit = set_touch(P.vR, C.w2, line, true, dirtyR);
           acc.l2_hit += hit;
@@ -958,7 +982,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k1.x = -1;
           k1.y = -1;
         }
-        if (P.fill) {
+        if (p_fill) {
           set_touch(u, C.w1, P.line_op, true, dirty1);
           const int lat = c - k0.w;
           acc.ops_done++;
@@ -966,8 +990,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           acc.op_lat_max = max(acc.op_lat_max, lat);
           k0.x = CORE_IDLE;
         } else if (k0.x == CORE_L1MISS && k0.y == c) {
-          if (P.local) {
-            if (P.svc && P.setL == P.setR) {
+          if (p_local) {
+            if (p_svc && P.setL == P.setR) {
 #pragma unroll
               for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
             }
@@ -980,8 +1004,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             k0.x = CORE_SEND;
             acc.req_made++;
           }
-        } else if (P.forced || P.drawn) {
-          if (P.forced) k2.w = -1;
+        } else if (p_forced || p_drawn) {
+          if (p_forced) k2.w = -1;
           acc.ops_issued++;
           k0.z = P.line_op;
           k0.w = c;
@@ -1137,6 +1161,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   }
   if (threadIdx.x == 0) st_coh(&C.flags[patch * FLAG_STRIDE], c_done);
   flush_counters(acc, L, C, patch, c0, c_done);
+#undef GEO
 }
 
 // ---- small utility kernels (no memsets: these also record safely into graphs) -----------------
@@ -1298,8 +1323,9 @@ int device_cus() {
   return cus;
 }
 
-const void* multi_kernel(bool fast) {
-  return fast ? reinterpret_cast<const void*>(step_fast<true>) : reinterpret_cast<const void*>(step_kernel<true>);
+const void* multi_kernel(bool fast, bool digest = false) {
+  if (!fast) return reinterpret_cast<const void*>(step_kernel<true>);
+  return digest ? reinterpret_cast<const void*>(step_fast<true, true>) : reinterpret_cast<const void*>(step_fast<true, false>);
 }
 // how many workgroups of `block` threads of the multi-patch kernel can be resident at once
 int resident_limit(int block, bool fast) {
@@ -1314,8 +1340,8 @@ int upload_desc(sim_chip* h) {
   return SIM_OK;
 }
 
-// Default mapping: one workgroup for small chips; otherwise square-ish patches, about one per
-// compute unit.
+// Default mapping: one workgroup for small chips; strips of whole rows (up to 256 tiles) for
+// chips up to 256 columns wide; otherwise square-ish patches, about one per compute unit.
 void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* block) {
   const int N = c->width * c->height;
   if (N <= 1024) {
@@ -1324,12 +1350,17 @@ void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* blo
     *block = N <= 64 ? 64 : 256;
     return;
   }
-  const int target = device_cus();
-  int side = 1;
-  while ((int64_t)((c->width + side - 1) / side) * ((c->height + side - 1) / side) > target) side++;
-  *pw = std::min(side, c->width);
-  *ph = std::min(side, c->height);
-  const int tiles = (*pw) * (*ph);
+  if (c->width <= 256) {  // strips of whole rows, up to 256 tiles each (measured fastest)
+    *pw = c->width;
+    *ph = std::max(1, 256 / c->width);
+  } else {
+    const int target = device_cus();
+    int side = 1;
+    while ((int64_t)((c->width + side - 1) / side) * ((c->height + side - 1) / side) > target) side++;
+    *pw = std::min(side, c->width);
+    *ph = std::min(side, c->height);
+  }
+  const int tiles = (*pw) * std::min(*ph, c->height);
   *block = tiles <= 64 ? 64 : tiles <= 128 ? 128 : tiles <= 192 ? 192 : 256;
 }
 
@@ -1362,9 +1393,12 @@ int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, i
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast), dim3((unsigned)n), dim3(block), args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr), dim3((unsigned)n), dim3(block), args, 0, s));
   } else if (fast) {
-    hipLaunchKernelGGL(step_fast<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    if (digests)
+      hipLaunchKernelGGL((step_fast<false, true>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    else
+      hipLaunchKernelGGL((step_fast<false, false>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   } else {
     hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
