@@ -762,6 +762,29 @@ __device__ __forceinline__ void arb_assign(int dst, int idx, int t, int x, int y
   ports = (ports & ~(7u << (3 * idx))) | (port << (3 * idx));
 }
 
+// The same choice without branches, for the one-tile-per-thread kernel: `key` is the flit's
+// priority key (inject cycle, then source, then its input index in the low 3 bits; all ones for
+// an empty input), `dst` its destination (negative when empty).
+__device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, int t, int x, int y, const ChipDev& C,
+                                               unsigned valid, unsigned& used, uint32_t& ports, Acc& acc) {
+  const bool live = dst >= 0;
+  const unsigned idx = (unsigned)key & 7u;
+  const unsigned fr = ~used;
+  const bool ej = dst == t && (fr & 16u);
+  const int drow = C.W > 1 ? (int)__umulhi((uint32_t)dst, C.w_magic) : dst;
+  const int dx = (dst - drow * C.W) - x, dy = drow - y;
+  const unsigned px = dx > 0 ? 2u : 3u, py = dy > 0 ? 1u : 0u;
+  const bool okx = dx != 0 && ((fr >> px) & 1u);
+  const bool oky = dy != 0 && ((fr >> py) & 1u);
+  const unsigned dfl = (unsigned)__builtin_ctz((valid & fr & 15u) | 128u);  // 7 = none (cannot happen)
+  const unsigned port = ej ? 4u : (okx ? px : (oky ? py : dfl));
+  const bool moved = live && !ej;
+  acc.trav += moved;
+  acc.defl += moved && !okx && !oky;
+  used |= live ? (1u << port) : 0u;
+  ports = live ? ((ports & ~(7u << (3 * idx))) | (port << (3 * idx))) : ports;
+}
+
 // The flit leaving through port p (0..3, or 4 = eject), or an empty slot.
 __device__ __forceinline__ int4 flit_on_port(uint32_t ports, unsigned p, const int4& f0, const int4& f1, const int4& f2,
                                              const int4& f3, const int4& f4) {
@@ -1063,30 +1086,30 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             acc.inj_bg++;
           }
         }
-        uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
-        uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
-        uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
-        uint32_t qh3 = f3.x < 0 ? ~0u : (uint32_t)f3.y, ql3 = f3.x < 0 ? ~0u : (uint32_t)f3.z;
-        uint32_t qh4 = fi.x < 0 ? ~0u : (uint32_t)fi.y, ql4 = fi.x < 0 ? ~0u : (uint32_t)fi.z;
+        // sort keys: (inject cycle, source) with the input index in the low 3 bits (sources
+        // take 20 bits), all ones for an empty input; the destination rides along
+        typedef unsigned long long u64;
+#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)(uint32_t)(f).z << 3) | (i##ull)))
+        u64 q0 = SKEY(f0, 0), q1 = SKEY(f1, 1), q2 = SKEY(f2, 2), q3 = SKEY(f3, 3), q4 = SKEY(fi, 4);
+#undef SKEY
         int sd0 = f0.x, sd1 = f1.x, sd2 = f2.x, sd3 = f3.x, sd4 = fi.x;
-        int si0 = 0, si1 = 1, si2 = 2, si3 = 3, si4 = 4;
 #define CSWAP(a, b)                                                            \
-  if (qh##b < qh##a || (qh##b == qh##a && ql##b < ql##a)) {                    \
-    uint32_t th = qh##a; qh##a = qh##b; qh##b = th;                            \
-    uint32_t tl = ql##a; ql##a = ql##b; ql##b = tl;                            \
-    int td = sd##a; sd##a = sd##b; sd##b = td;                                 \
-    int ti = si##a; si##a = si##b; si##b = ti;                                 \
+  {                                                                            \
+    const bool sw = q##b < q##a;                                               \
+    const u64 qa = sw ? q##b : q##a, qb = sw ? q##a : q##b;                    \
+    const int da = sw ? sd##b : sd##a, db = sw ? sd##a : sd##b;                \
+    q##a = qa; q##b = qb; sd##a = da; sd##b = db;                              \
   }
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
 #undef CSWAP
         const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
         unsigned used = 0;
         uint32_t ports = 0x7FFFu;
-        arb_assign(sd0, si0, t, x, y, C, valid, used, ports, acc);
-        arb_assign(sd1, si1, t, x, y, C, valid, used, ports, acc);
-        arb_assign(sd2, si2, t, x, y, C, valid, used, ports, acc);
-        arb_assign(sd3, si3, t, x, y, C, valid, used, ports, acc);
-        arb_assign(sd4, si4, t, x, y, C, valid, used, ports, acc);
+        arb_assign_sel(q0, sd0, t, x, y, C, valid, used, ports, acc);
+        arb_assign_sel(q1, sd1, t, x, y, C, valid, used, ports, acc);
+        arb_assign_sel(q2, sd2, t, x, y, C, valid, used, ports, acc);
+        arb_assign_sel(q3, sd3, t, x, y, C, valid, used, ports, acc);
+        arb_assign_sel(q4, sd4, t, x, y, C, valid, used, ports, acc);
 
         // ---- phase three: stores -----------------------------------------------------------
         if (dirtyR) set_store(P.setR, C.w2, P.vR);
