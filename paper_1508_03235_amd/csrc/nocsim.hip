@@ -177,8 +177,11 @@ __device__ __forceinline__ int zipf_rank(const uint32_t* __restrict__ q, uint32_
 
 // ---- set-associative LRU sets: tags most recently used first -------------------------------
 // Register copies of a set: load `ways` tags (positions >= ways read as -2, which no line
-// matches), update in registers, store `ways` tags back.
+// matches), update in registers, store `ways` tags back.  `ways` is the same in every lane (one
+// chip per workgroup); reading it from the first lane keeps the branches on it scalar even
+// when the compiler has parked the value in a vector register.
 __device__ __forceinline__ void set_load(const int* p, int ways, int (&v)[8]) {
+  ways = __builtin_amdgcn_readfirstlane(ways);
 #pragma unroll
   for (int i = 0; i < 8; ++i) v[i] = -2;
   if (ways == 8) {
@@ -195,6 +198,7 @@ __device__ __forceinline__ void set_load(const int* p, int ways, int (&v)[8]) {
   }
 }
 __device__ __forceinline__ void set_store(int* p, int ways, const int (&v)[8]) {
+  ways = __builtin_amdgcn_readfirstlane(ways);
   if (ways == 8) {
     gstore4(reinterpret_cast<int4*>(p), make_int4(v[0], v[1], v[2], v[3]));
     gstore4(reinterpret_cast<int4*>(p) + 1, make_int4(v[4], v[5], v[6], v[7]));
@@ -209,6 +213,7 @@ __device__ __forceinline__ void set_store(int* p, int ways, const int (&v)[8]) {
 // Touch `line`: a hit moves it to the front; a miss inserts it at the front when `insert`,
 // dropping the last way.  `changed` tells whether the set must be written back.
 __device__ __forceinline__ bool set_touch(int (&v)[8], int ways, int line, bool insert, bool& changed) {
+  ways = __builtin_amdgcn_readfirstlane(ways);
   int pos = 8;
 #pragma unroll
   for (int i = 7; i >= 0; --i)
@@ -800,21 +805,35 @@ __device__ __forceinline__ int4 flit_on_port(uint32_t ports, unsigned p, const i
 constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;
 
 struct Prefetch {            // loads of one cycle issued ahead of it
-  uint4 r;                   // the tile's random words
+  uint4 r;                   // the tile's random words of the cycle
+  uint4 r1;                  // ... and of the cycle after it, with its Zipf table words:
+  uint32_t z_lo, z_hi;       // the op line a draw in that cycle would take is known a cycle early,
   uint32_t flags;            // PF_*: which of the cycle's memory steps happen (bits, not lane masks)
-  int line_op;               // the op's line (fill or issue); drawn ops: known after zipf_lo/hi
-  uint32_t zipf_lo, zipf_hi, zipf_f;
+  int line_op;               // the op's line (fill or issue)
+  int* set1;                 // its L1 set
   int* setR;
   int* setL;
-  int vR[8], vL[8];
+  int u[8], vR[8], vL[8];    // L1 set of the op; L2 sets of the served request and of a local miss
   int4 nh, nm;               // hit-queue and miss-queue head nodes
 };
 
+// Random words of cycle c and the Zipf table words their op draw would use (issued, not waited).
+__device__ __forceinline__ void draw_ahead(const ChipDev& C, int t, int c, Prefetch& P) {
+  P.r1 = philox((uint32_t)c, (uint32_t)t, 0u, 0u, C.key0, C.key1);
+  const bool priv = C.private_lines > 0 && P.r1.y >= C.shared_thr;
+  const uint32_t* q = priv ? C.zp : C.zs;
+  const uint32_t b = P.r1.z >> 16;
+  P.z_lo = *gp(q + b);
+  P.z_hi = *gp(q + b + 1);
+}
+
+// Issues every load of cycle c that does not depend on its link inputs.  The random words of c
+// and their Zipf words were drawn one cycle earlier (draw_ahead); this draws those of c+1.
 template <bool MULTI>
 __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
-                                         int* l2_base, Prefetch& P) {
+                                         int* l1_base, int* l2_base, Prefetch& P) {
   const int N = C.N;
-  P.r = philox((uint32_t)c, (uint32_t)t, 0u, 0u, C.key0, C.key1);
+  P.r = P.r1;
   const bool svc = k1.x >= 0;
   const bool wake = k0.y == c;
   const bool fill = k0.x == CORE_FILL && wake;
@@ -832,17 +851,15 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   P.nm = make_int4(-1, -1, -1, -1);
   if ((unsigned)k1.z < (unsigned)N) P.nh = ld_node<MULTI>(&C.node[k1.z]);
   if ((unsigned)k2.x < (unsigned)N) P.nm = ld_node<MULTI>(&C.node[k2.x]);
-  P.line_op = forced ? k2.w : k0.z;
-  P.zipf_lo = P.zipf_hi = P.zipf_f = 0;
-  if (drawn) {
-    const bool priv = C.private_lines > 0 && P.r.y >= C.shared_thr;
-    const uint32_t* q = priv ? C.zp : C.zs;
-    const uint32_t b = P.r.z >> 16;
-    P.zipf_f = P.r.z & 0xFFFFu;
-    P.zipf_lo = *gp(q + b);
-    P.zipf_hi = *gp(q + b + 1);
-    P.line_op = priv ? C.shared_lines + t * C.private_lines : 0;  // + rank, once the table words arrive
-  }
+  // a drawn op: Zipf rank from the table bucket of the high half of r.z, linear inside the
+  // bucket by the low half; private lines follow the shared ones, private_lines per tile
+  const bool priv = C.private_lines > 0 && P.r.y >= C.shared_thr;
+  const int rank = (int)(P.z_lo + (uint32_t)(((unsigned long long)(P.r.z & 0xFFFFu) * (P.z_hi - P.z_lo)) >> 16));
+  const int drawn_line = (priv ? C.shared_lines + t * C.private_lines : 0) + rank;
+  P.line_op = forced ? k2.w : (drawn ? drawn_line : k0.z);
+  P.set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
+  if (fill || forced || drawn) set_load(P.set1, C.w1, P.u);
+  draw_ahead(C, t, c + 1, P);
 }
 
 template <bool MULTI, bool DIGEST>
@@ -903,7 +920,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   int* const l1_base = C.l1 + (size_t)(active ? t : 0) * (size_t)C.s1 * (size_t)C.w1;
   int* const l2_base = C.l2 + (size_t)(active ? t : 0) * (size_t)C.s2 * (size_t)C.w2;
   Prefetch P;
-  if (active) prefetch<MULTI>(C, t, c0, k0, k1, k2, l2_base, P);
+  if (active) {
+    draw_ahead(C, t, c0, P);
+    prefetch<MULTI>(C, t, c0, k0, k1, k2, l1_base, l2_base, P);
+  }
   __syncthreads();
 
   for (int c = c0; c <= c_end; ++c) {
@@ -920,20 +940,97 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
       const bool e0 = GEO(8), e1 = GEO(9), e2 = GEO(10), e3 = GEO(11);
       // ---- inputs of cycle c: interior from LDS, edges polled until stamped c ----------------
-      int4 w0 = e0 ? ld_slot(&C.link[(cur * 4 + 0) * N + t], MULTI) : EMPTY;
-      int4 w1 = e1 ? ld_slot(&C.link[(cur * 4 + 1) * N + t], MULTI) : EMPTY;
-      int4 w2 = e2 ? ld_slot(&C.link[(cur * 4 + 2) * N + t], MULTI) : EMPTY;
-      int4 w3 = e3 ? ld_slot(&C.link[(cur * 4 + 3) * N + t], MULTI) : EMPTY;
+      // First read of the patch-edge slots, issued by every lane of the wave (a lane without
+      // an edge on port p reads one shared slot instead): a fixed number of loads lets the
+      // compiler wait for the prefetched words in phase one without waiting for these.
+      int4 w0 = EMPTY, w1 = EMPTY, w2 = EMPTY, w3 = EMPTY;
+      if (MULTI) {
+        const int4* shared_slot = C.link;
+        w0 = ld_slot(e0 ? &C.link[(cur * 4 + 0) * N + t] : shared_slot, true);
+        w1 = ld_slot(e1 ? &C.link[(cur * 4 + 1) * N + t] : shared_slot, true);
+        w2 = ld_slot(e2 ? &C.link[(cur * 4 + 2) * N + t] : shared_slot, true);
+        w3 = ld_slot(e3 ? &C.link[(cur * 4 + 3) * N + t] : shared_slot, true);
+      }
       uint32_t pf = P.flags;
       asm volatile("" : "+v"(pf));
       const bool p_svc = (pf & PF_SVC) != 0, p_local = (pf & PF_LOCAL) != 0, p_fill = (pf & PF_FILL) != 0;
       const bool p_forced = (pf & PF_FORCED) != 0, p_drawn = (pf & PF_DRAWN) != 0;
-      // the op's L1 set (its line may need the Zipf words loaded at the end of last cycle)
-      if (p_drawn)
-        P.line_op += (int)(P.zipf_lo + (uint32_t)(((unsigned long long)P.zipf_f * (P.zipf_hi - P.zipf_lo)) >> 16));
-      int* set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
-      int u[8];
-      if (p_fill || p_forced || p_drawn) set_load(set1, C.w1, u);
+      // the core words as they stand after cycle c-1 (the digest hashes them after the links)
+      const int4 d0 = k0, d1 = k1, d2 = k2;
+      const int dfd = fdst;
+      if (step) {
+        if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
+            (k2.y >= 0 && (unsigned)k2.y >= (unsigned)N) || (k1.z >= 0 && (unsigned)k1.z >= (unsigned)N) ||
+            (k2.x >= 0 && (unsigned)k2.x >= (unsigned)N)) {
+          st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
+          ok = false;
+        }
+      }
+      bool dirtyR = false, dirtyL = false, dirty1 = false;
+      int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
+      int4 nh = P.nh, nm = P.nm;
+      if (step && ok) {
+        // phase one reads no link input: it runs while this cycle's patch-edge reads are in flight
+        // ---- phase one: home L2 service, then the core (Sec. 7.1 phase one; Sec. 3.5) -------
+        if (p_svc) {
+          const int rq = k1.x, line = k1.y;
+          const bool hit = set_touch(P.vR, C.w2, line, true, dirtyR);
+          acc.l2_hit += hit;
+          acc.l2_miss += !hit;
+          node_rq = rq;
+          node_ready = hit ? c : c + C.mem_lat;
+          node_line = line;
+          const int4 fresh = make_int4(-1, node_ready, line, 0);
+          if (hit) {
+            if (k1.w >= 0) { node_tail = k1.w; if (k1.w == k1.z) nh.x = rq; }
+            else { k1.z = rq; nh = fresh; }
+            k1.w = rq;
+          } else {
+            if (k2.y >= 0) { node_tail = k2.y; if (k2.y == k2.x) nm.x = rq; }
+            else { k2.x = rq; nm = fresh; }
+            k2.y = rq;
+          }
+          k1.x = -1;
+          k1.y = -1;
+        }
+        if (p_fill) {
+          set_touch(P.u, C.w1, P.line_op, true, dirty1);
+          const int lat = c - k0.w;
+          acc.ops_done++;
+          acc.op_lat += (unsigned long long)lat;
+          acc.op_lat_max = max(acc.op_lat_max, lat);
+          k0.x = CORE_IDLE;
+        } else if (k0.x == CORE_L1MISS && k0.y == c) {
+          if (p_local) {
+            if (p_svc && P.setL == P.setR) {
+#pragma unroll
+              for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
+            }
+            const bool hit = set_touch(P.vL, C.w2, k0.z, true, dirtyL);
+            acc.l2_hit += hit;
+            acc.l2_miss += !hit;
+            k0.x = CORE_FILL;
+            k0.y = hit ? c + 1 : c + C.mem_lat;
+          } else {
+            k0.x = CORE_SEND;
+            acc.req_made++;
+          }
+        } else if (p_forced || p_drawn) {
+          if (p_forced) k2.w = -1;
+          acc.ops_issued++;
+          k0.z = P.line_op;
+          k0.w = c;
+          if (set_touch(P.u, C.w1, P.line_op, false, dirty1)) {
+            acc.l1_hit++;
+            acc.ops_done++;
+          } else {
+            acc.l1_miss++;
+            k0.x = CORE_L1MISS;
+            k0.y = c + C.l1_lat;
+          }
+        }
+
+      }
       if (MULTI && (e0 | e1 | e2 | e3)) {
         int spins = 0;
         for (;;) {
@@ -964,84 +1061,14 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, f1.x, f1.y); h = mix_pair(h, f1.z, f1.w);
         h = mix_pair(h, f2.x, f2.y); h = mix_pair(h, f2.z, f2.w);
         h = mix_pair(h, f3.x, f3.y); h = mix_pair(h, f3.z, f3.w);
-        h = mix_pair(h, k0.x, k0.y); h = mix_pair(h, k0.z, k0.w);
-        h = mix_pair(h, k1.x, k1.y); h = mix_pair(h, k1.z, k1.w);
-        h = mix_pair(h, k2.x, k2.y);
-        h = mix_pair(h, k2.z, 0);
+        h = mix_pair(h, d0.x, d0.y); h = mix_pair(h, d0.z, d0.w);
+        h = mix_pair(h, d1.x, d1.y); h = mix_pair(h, d1.z, d1.w);
+        h = mix_pair(h, d2.x, d2.y);
+        h = mix_pair(h, d2.z, 0);
         h = mix_pair(h, 0, 0);
-        h = mix_pair(h, k2.w, fdst);
+        h = mix_pair(h, d2.w, dfd);
       }
       if (step && ok) {
-        if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
-            (k2.y >= 0 && (unsigned)k2.y >= (unsigned)N) || (k1.z >= 0 && (unsigned)k1.z >= (unsigned)N) ||
-            (k2.x >= 0 && (unsigned)k2.x >= (unsigned)N)) {
-          st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
-          ok = false;
-        }
-      }
-      if (step && ok) {
-        // ---- phase one: home L2 service, then the core (Sec. 7.1 phase one; Sec. 3.5) -------
-        bool dirtyR = false, dirtyL = false, dirty1 = false;
-        int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
-        int4 nh = P.nh, nm = P.nm;
-        if (p_svc) {
-          const int rq = k1.x, line = k1.y;
-          const bool hit = set_touch(P.vR, C.w2, line, true, dirtyR);
-          acc.l2_hit += hit;
-          acc.l2_miss += !hit;
-          node_rq = rq;
-          node_ready = hit ? c : c + C.mem_lat;
-          node_line = line;
-          const int4 fresh = make_int4(-1, node_ready, line, 0);
-          if (hit) {
-            if (k1.w >= 0) { node_tail = k1.w; if (k1.w == k1.z) nh.x = rq; }
-            else { k1.z = rq; nh = fresh; }
-            k1.w = rq;
-          } else {
-            if (k2.y >= 0) { node_tail = k2.y; if (k2.y == k2.x) nm.x = rq; }
-            else { k2.x = rq; nm = fresh; }
-            k2.y = rq;
-          }
-          k1.x = -1;
-          k1.y = -1;
-        }
-        if (p_fill) {
-          set_touch(u, C.w1, P.line_op, true, dirty1);
-          const int lat = c - k0.w;
-          acc.ops_done++;
-          acc.op_lat += (unsigned long long)lat;
-          acc.op_lat_max = max(acc.op_lat_max, lat);
-          k0.x = CORE_IDLE;
-        } else if (k0.x == CORE_L1MISS && k0.y == c) {
-          if (p_local) {
-            if (p_svc && P.setL == P.setR) {
-#pragma unroll
-              for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
-            }
-            const bool hit = set_touch(P.vL, C.w2, k0.z, true, dirtyL);
-            acc.l2_hit += hit;
-            acc.l2_miss += !hit;
-            k0.x = CORE_FILL;
-            k0.y = hit ? c + 1 : c + C.mem_lat;
-          } else {
-            k0.x = CORE_SEND;
-            acc.req_made++;
-          }
-        } else if (p_forced || p_drawn) {
-          if (p_forced) k2.w = -1;
-          acc.ops_issued++;
-          k0.z = P.line_op;
-          k0.w = c;
-          if (set_touch(u, C.w1, P.line_op, false, dirty1)) {
-            acc.l1_hit++;
-            acc.ops_done++;
-          } else {
-            acc.l1_miss++;
-            k0.x = CORE_L1MISS;
-            k0.y = c + C.l1_lat;
-          }
-        }
-
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
         const int arrivals = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0);
         const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
@@ -1111,23 +1138,28 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         arb_assign_sel(q3, sd3, t, x, y, C, valid, used, ports, acc);
         arb_assign_sel(q4, sd4, t, x, y, C, valid, used, ports, acc);
 
-        // ---- phase three: stores -----------------------------------------------------------
+        // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
+        // then the next cycle's loads
+#define out_for(p) flit_on_port(ports, (p), f0, f1, f2, f3, fi)
+        const uint32_t ns = (uint32_t)(c + 1);
+        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(out_for(0), ns), MULTI);
+        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(out_for(1), ns), MULTI);
+        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(out_for(2), ns), MULTI);
+        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(out_for(3), ns), MULTI);
+        // inside the patch: the neighbour's input slot opp(p) in LDS
+        if (i0) s_link[nxt][1][j - cols] = out_for(0);
+        if (i1) s_link[nxt][0][j + cols] = out_for(1);
+        if (i2) s_link[nxt][3][j + 1] = out_for(2);
+        if (i3) s_link[nxt][2][j - 1] = out_for(3);
+        // phase one's stores: issued before the next cycle's loads of the same sets and nodes
         if (dirtyR) set_store(P.setR, C.w2, P.vR);
         if (dirtyL) set_store(P.setL, C.w2, P.vL);
-        if (dirty1) set_store(set1, C.w1, u);
+        if (dirty1) set_store(P.set1, C.w1, P.u);
         if (node_rq >= 0) {
           st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
           if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
         }
-        // output port p of this tile: the neighbour's input slot opp(p), in LDS inside the patch
-#define out_for(p) flit_on_port(ports, (p), f0, f1, f2, f3, fi)
-        const uint32_t ns = (uint32_t)(c + 1);
-        if (v0) { const int4 o = out_for(0); if (i0) s_link[nxt][1][j - cols] = o; else st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(o, ns), MULTI); }
-        if (v1) { const int4 o = out_for(1); if (i1) s_link[nxt][0][j + cols] = o; else st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(o, ns), MULTI); }
-        if (v2) { const int4 o = out_for(2); if (i2) s_link[nxt][3][j + 1] = o; else st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(o, ns), MULTI); }
-        if (v3) { const int4 o = out_for(3); if (i3) s_link[nxt][2][j - 1] = o; else st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(o, ns), MULTI); }
         const int4 oe = out_for(4);
-#undef out_for
         if (oe.x >= 0) {
           const int kind = (int)((uint32_t)oe.w >> 30);
           const int lat = c - oe.y;
@@ -1154,7 +1186,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k2.z += 1;
           acc.bg_gen++;
         }
-        if (c + 1 < c_end) prefetch<MULTI>(C, t, c + 1, k0, k1, k2, l2_base, P);
+        if (c + 1 < c_end) prefetch<MULTI>(C, t, c + 1, k0, k1, k2, l1_base, l2_base, P);
+#undef out_for
       }
     }
     if (dig) {
