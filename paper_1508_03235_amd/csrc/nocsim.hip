@@ -769,9 +769,10 @@ __device__ __forceinline__ void arb_assign(int dst, int idx, int t, int x, int y
 
 // The same choice without branches, for the one-tile-per-thread kernel: `key` is the flit's
 // priority key (inject cycle, then source, then its input index in the low 3 bits; all ones for
-// an empty input), `dst` its destination (negative when empty).
+// an empty input), `dst` its destination (negative when empty).  Records the flit's input index
+// at bits 3*port of `inv` (the flit each output port carries; 7 = none).
 __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, int t, int x, int y, const ChipDev& C,
-                                               unsigned valid, unsigned& used, uint32_t& ports, Acc& acc) {
+                                               unsigned valid, unsigned& used, uint32_t& inv, Acc& acc) {
   const bool live = dst >= 0;
   const unsigned idx = (unsigned)key & 7u;
   const unsigned fr = ~used;
@@ -787,7 +788,7 @@ __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, 
   acc.trav += moved;
   acc.defl += moved && !okx && !oky;
   used |= live ? (1u << port) : 0u;
-  ports = live ? ((ports & ~(7u << (3 * idx))) | (port << (3 * idx))) : ports;
+  inv = live ? ((inv & ~(7u << (3 * port))) | (idx << (3 * port))) : inv;
 }
 
 // The flit leaving through port p (0..3, or 4 = eject), or an empty slot.
@@ -867,7 +868,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
                                                       unsigned long long* digests, int digest_base) {
   __shared__ LdsStats L;
   __shared__ int s_fail;
-  __shared__ int4 s_link[2][4][FAST_MAX];  // interior input slots [parity][port][local tile]
+  // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
+  // neighbour inside the patch, or by the tile itself from a patch-edge slot), row 4 the flit
+  // the tile injects, row 5 an empty flit; each output port copies the row of the flit it carries
+  __shared__ int4 s_link[2][6][FAST_MAX];
   const LaunchEntry e = table[blockIdx.x];
   const ChipDev C = *e.chip;
   const int N = C.N;
@@ -896,6 +900,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 
   for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
   if (threadIdx.x == 0) s_fail = 0;
+  s_link[0][5][j] = EMPTY;
+  s_link[1][5][j] = EMPTY;
   Acc acc = {};
   const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
   const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
@@ -1054,6 +1060,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       int4 f1 = i1 ? s_link[cur][1][j] : (e1 ? slot_decode(w1) : EMPTY);
       int4 f2 = i2 ? s_link[cur][2][j] : (e2 ? slot_decode(w2) : EMPTY);
       int4 f3 = i3 ? s_link[cur][3][j] : (e3 ? slot_decode(w3) : EMPTY);
+      if (e0) s_link[cur][0][j] = f0;
+      if (e1) s_link[cur][1][j] = f1;
+      if (e2) s_link[cur][2][j] = f2;
+      if (e3) s_link[cur][3][j] = f3;
 
       if (dig) {  // state owned by t after cycle c-1
         h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
@@ -1129,18 +1139,19 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   }
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
 #undef CSWAP
+        s_link[cur][4][j] = fi;
         const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
         unsigned used = 0;
-        uint32_t ports = 0x7FFFu;
-        arb_assign_sel(q0, sd0, t, x, y, C, valid, used, ports, acc);
-        arb_assign_sel(q1, sd1, t, x, y, C, valid, used, ports, acc);
-        arb_assign_sel(q2, sd2, t, x, y, C, valid, used, ports, acc);
-        arb_assign_sel(q3, sd3, t, x, y, C, valid, used, ports, acc);
-        arb_assign_sel(q4, sd4, t, x, y, C, valid, used, ports, acc);
+        uint32_t inv = 0x7FFFu;
+        arb_assign_sel(q0, sd0, t, x, y, C, valid, used, inv, acc);
+        arb_assign_sel(q1, sd1, t, x, y, C, valid, used, inv, acc);
+        arb_assign_sel(q2, sd2, t, x, y, C, valid, used, inv, acc);
+        arb_assign_sel(q3, sd3, t, x, y, C, valid, used, inv, acc);
+        arb_assign_sel(q4, sd4, t, x, y, C, valid, used, inv, acc);
 
         // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
         // then the next cycle's loads
-#define out_for(p) flit_on_port(ports, (p), f0, f1, f2, f3, fi)
+#define out_for(p) s_link[cur][min((inv >> (3 * (p))) & 7u, 5u)][j]
         const uint32_t ns = (uint32_t)(c + 1);
         if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(out_for(0), ns), MULTI);
         if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(out_for(1), ns), MULTI);
