@@ -135,13 +135,17 @@ constexpr uint32_t STAMP_MASK = 0xFFFu;
 
 __device__ __forceinline__ int4 slot_encode(const int4& f, uint32_t stamp) {
   const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
-  if (f.x < 0) return make_int4((int)(TILE_BITS_MASK | s), -1, (int)(TILE_BITS_MASK | s), -1);
-  return make_int4((int)((uint32_t)f.x | s), f.y, (int)((uint32_t)f.z | s), f.w);
+  const bool empty = f.x < 0;  // selects, not a branch: every word of f is read either way
+  return make_int4((int)((empty ? TILE_BITS_MASK : (uint32_t)f.x) | s), empty ? -1 : f.y,
+                   (int)((empty ? TILE_BITS_MASK : (uint32_t)f.z) | s), empty ? -1 : f.w);
 }
 __device__ __forceinline__ int4 slot_decode(const int4& w) {
   const uint32_t d = (uint32_t)w.x & TILE_BITS_MASK;
   if (d == TILE_BITS_MASK) return make_int4(-1, -1, -1, -1);
   return make_int4((int)d, w.y, (int)((uint32_t)w.z & TILE_BITS_MASK), w.w);
+}
+__device__ __forceinline__ int4 sel4(bool p, const int4& a, const int4& b) {  // p ? a : b, per word
+  return make_int4(p ? a.x : b.x, p ? a.y : b.y, p ? a.z : b.z, p ? a.w : b.w);
 }
 __device__ __forceinline__ bool slot_has_stamp(const int4& w, uint32_t stamp) {
   return ((uint32_t)w.x >> STAMP_SHIFT) == (stamp & STAMP_MASK) && ((uint32_t)w.z >> STAMP_SHIFT) == (stamp & STAMP_MASK);
@@ -152,8 +156,10 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    // one 32x32->64 product per multiplier (a single instruction for both halves)
+    const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0, p1 = (unsigned long long)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
   }
@@ -778,7 +784,7 @@ __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, 
   const unsigned fr = ~used;
   const bool ej = dst == t && (fr & 16u);
   const int drow = C.W > 1 ? (int)__umulhi((uint32_t)dst, C.w_magic) : dst;
-  const int dx = (dst - drow * C.W) - x, dy = drow - y;
+  const int dx = (dst - (int)__umul24((uint32_t)drow, (uint32_t)C.W)) - x, dy = drow - y;  // both < 2^20
   const unsigned px = dx > 0 ? 2u : 3u, py = dy > 0 ? 1u : 0u;
   const bool okx = dx != 0 && ((fr >> px) & 1u);
   const bool oky = dy != 0 && ((fr >> py) & 1u);
@@ -957,6 +963,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         w2 = ld_slot(e2 ? &C.link[(cur * 4 + 2) * N + t] : shared_slot, true);
         w3 = ld_slot(e3 ? &C.link[(cur * 4 + 3) * N + t] : shared_slot, true);
       }
+      // the four input rows of this tile, read by every lane (rows of ports without an
+      // in-patch neighbour hold stale words, replaced below); their wait hides behind phase one
+      const int4 l0 = s_link[cur][0][j], l1 = s_link[cur][1][j], l2 = s_link[cur][2][j], l3 = s_link[cur][3][j];
       uint32_t pf = P.flags;
       asm volatile("" : "+v"(pf));
       const bool p_svc = (pf & PF_SVC) != 0, p_local = (pf & PF_LOCAL) != 0, p_fill = (pf & PF_FILL) != 0;
@@ -1056,14 +1065,16 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
-      int4 f0 = i0 ? s_link[cur][0][j] : (e0 ? slot_decode(w0) : EMPTY);
-      int4 f1 = i1 ? s_link[cur][1][j] : (e1 ? slot_decode(w1) : EMPTY);
-      int4 f2 = i2 ? s_link[cur][2][j] : (e2 ? slot_decode(w2) : EMPTY);
-      int4 f3 = i3 ? s_link[cur][3][j] : (e3 ? slot_decode(w3) : EMPTY);
-      if (e0) s_link[cur][0][j] = f0;
-      if (e1) s_link[cur][1][j] = f1;
-      if (e2) s_link[cur][2][j] = f2;
-      if (e3) s_link[cur][3][j] = f3;
+      const int4 f0 = sel4(i0, l0, e0 ? slot_decode(w0) : EMPTY);
+      const int4 f1 = sel4(i1, l1, e1 ? slot_decode(w1) : EMPTY);
+      const int4 f2 = sel4(i2, l2, e2 ? slot_decode(w2) : EMPTY);
+      const int4 f3 = sel4(i3, l3, e3 ? slot_decode(w3) : EMPTY);
+      // every input row now holds this cycle's input (a patch-edge flit, or empty where there
+      // is no link; an in-patch row is rewritten with what it held)
+      s_link[cur][0][j] = f0;
+      s_link[cur][1][j] = f1;
+      s_link[cur][2][j] = f2;
+      s_link[cur][3][j] = f3;
 
       if (dig) {  // state owned by t after cycle c-1
         h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
@@ -1152,16 +1163,18 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
         // then the next cycle's loads
 #define out_for(p) s_link[cur][min((inv >> (3 * (p))) & 7u, 5u)][j]
+        // the five gathers first (one LDS round trip), then the stores
+        const int4 o0 = out_for(0), o1 = out_for(1), o2 = out_for(2), o3 = out_for(3), oe = out_for(4);
         const uint32_t ns = (uint32_t)(c + 1);
-        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(out_for(0), ns), MULTI);
-        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(out_for(1), ns), MULTI);
-        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(out_for(2), ns), MULTI);
-        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(out_for(3), ns), MULTI);
+        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(o0, ns), MULTI);
+        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(o1, ns), MULTI);
+        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(o2, ns), MULTI);
+        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(o3, ns), MULTI);
         // inside the patch: the neighbour's input slot opp(p) in LDS
-        if (i0) s_link[nxt][1][j - cols] = out_for(0);
-        if (i1) s_link[nxt][0][j + cols] = out_for(1);
-        if (i2) s_link[nxt][3][j + 1] = out_for(2);
-        if (i3) s_link[nxt][2][j - 1] = out_for(3);
+        if (i0) s_link[nxt][1][j - cols] = o0;
+        if (i1) s_link[nxt][0][j + cols] = o1;
+        if (i2) s_link[nxt][3][j + 1] = o2;
+        if (i3) s_link[nxt][2][j - 1] = o3;
         // phase one's stores: issued before the next cycle's loads of the same sets and nodes
         if (dirtyR) set_store(P.setR, C.w2, P.vR);
         if (dirtyL) set_store(P.setL, C.w2, P.vL);
@@ -1170,7 +1183,6 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
           if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
         }
-        const int4 oe = out_for(4);
         if (oe.x >= 0) {
           const int kind = (int)((uint32_t)oe.w >> 30);
           const int lat = c - oe.y;
