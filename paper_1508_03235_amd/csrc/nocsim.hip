@@ -220,10 +220,10 @@ __device__ __forceinline__ void set_store(int* p, int ways, const int (&v)[8]) {
 // dropping the last way.  `changed` tells whether the set must be written back.
 __device__ __forceinline__ bool set_touch(int (&v)[8], int ways, int line, bool insert, bool& changed) {
   ways = __builtin_amdgcn_readfirstlane(ways);
-  int pos = 8;
+  int pos = 8;  // positions >= ways hold -2 and empty ways -1: neither matches a line (>= 0)
 #pragma unroll
   for (int i = 7; i >= 0; --i)
-    if (i < ways && v[i] == line) pos = i;
+    if (v[i] == line) pos = i;
   const bool hit = pos < 8;
   changed = false;
   if (pos == 0 || (!hit && !insert)) return hit;
