@@ -740,9 +740,13 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
 //  - a thread owns one tile for the whole launch; the tile's core words stay in registers;
 //  - link slots between two tiles of the patch live in LDS; only patch-edge slots go through
 //    global memory (stamped, polled), and the per-cycle barrier waits on LDS only;
-//  - at the end of cycle c-1 the thread draws cycle c's random words and issues cycle c's loads
-//    that do not depend on link inputs (L2 sets, queue-head nodes, the Zipf table); the L1 set
-//    load follows right after the barrier, together with the edge polls;
+//  - in cycle c-1 the thread issues cycle c's loads that do not depend on link inputs (L2 sets
+//    of a home lookup and of a local miss, the op's L1 set, queue-head nodes); the random words
+//    of a cycle and their Zipf table words are drawn one cycle before that, so the op's line
+//    is known when its L1 set is loaded;
+//  - a cycle issues its first read of the patch-edge slots, then runs phase one (which reads no
+//    link input) while those reads are in flight, then polls; the patch-edge outputs go out
+//    right after arbitration, before the rest of the cycle's stores;
 //  - every thread drains its global stores (s_waitcnt vmcnt(0)) once per cycle, after issuing
 //    that cycle's loads: a queue node stored in cycle c is therefore performed before the home
 //    finishes cycle c+1, while its next writer is at least three cycles of flit traffic away.
