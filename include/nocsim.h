@@ -60,6 +60,8 @@ typedef struct {
   int32_t private_lines;      /* per-tile private region (0 = none); shared_lines +
                                  width*height*private_lines must be <= 2^30 */
   int32_t flags;              /* 0 */
+  int32_t reply_flits;        /* flits of a reply packet, 1..16 (0 counts as 1); requests and
+                                 background flits are one flit */
 } sim_config;
 
 /* Statistics: 48 int64 counters (index = position in `v`).  Latencies are in cycles from

@@ -41,11 +41,15 @@
 enum { K_REQ = 0, K_REPLY = 1, K_BG = 2 };                              /* flit kinds */
 enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4 }; /* core states */
 enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
-/* per-tile core record (16 words) */
+/* per-tile core record (18 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
+   node as a requester, written by its home while it waits there */
 enum {
   C_STATE = 0, C_WAKE = 1, C_LINE = 2, C_ISSUE = 3, C_L2Q = 4, C_L2Q_LINE = 5,
   C_HIT_H = 6, C_HIT_T = 7, C_MISS_H = 8, C_MISS_T = 9, C_BG = 10,
-  C_NEXT = 11, C_READY = 12, C_NLINE = 13, C_FLINE = 14, C_FDST = 15, C_WORDS = 16
+  C_NEXT = 11, C_READY = 12, C_NLINE = 13, C_FLINE = 14, C_FDST = 15,
+  C_RCV = 16,   /* flits of the awaited reply received so far */
+  C_NSENT = 17, /* flits of this tile's reply already injected by its home */
+  C_WORDS = 18
 };
 /* flit record (4 words) */
 enum { F_DST = 0, F_INJ = 1, F_SRC = 2, F_INFO = 3, F_WORDS = 4 };
@@ -56,6 +60,8 @@ enum { F_DST = 0, F_INJ = 1, F_SRC = 2, F_INFO = 3, F_WORDS = 4 };
 struct oracle_sim {
   oracle_config cfg;
   int32_t W, H, N;
+  int32_t reply_flits;   /* flits per reply packet */
+  int32_t* scratch;      /* [2N], invariant checks */
   int64_t cycle;
   int32_t zk;
   uint32_t* zs;          /* shared-region quantile table, zk+1 entries */
@@ -192,6 +198,7 @@ static void list_append(oracle_sim* s, int32_t home, int head_w, int tail_w, int
   n[C_NEXT] = -1;
   n[C_READY] = ready;
   n[C_NLINE] = line;
+  n[C_NSENT] = 0;
   if (h[tail_w] >= 0) s->core[(size_t)h[tail_w] * C_WORDS + C_NEXT] = rq;
   else h[head_w] = rq;
   h[tail_w] = rq;
@@ -334,7 +341,11 @@ int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, con
 }
 
 /* Phase two of tile t: gather arrivals, add at most one injected flit when an input is
-   free (Sec. 4.2: a node injects whenever it finds a free input port), arbitrate. */
+   free (Sec. 4.2: a node injects whenever it finds a free input port), arbitrate.
+   A reply is a packet of reply_flits flits (Sec. 3.6, Table 1: a remote L2 access moves a
+   block as several flits); the home injects them one per injection, and the queue head is
+   popped with its last flit.  The queue is chosen anew each cycle, so flits of a miss reply
+   and of a hit reply can interleave. */
 static void phase_route(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
   int32_t* k = s->core + (size_t)t * C_WORDS;
@@ -366,11 +377,17 @@ static void phase_route(oracle_sim* s, int32_t t) {
     f[F_INJ] = (int32_t)c;
     f[F_SRC] = t;
     if (cls == 0 || cls == 1) {
-      int32_t rq = cls == 0 ? list_pop(s, t, C_MISS_H, C_MISS_T) : list_pop(s, t, C_HIT_H, C_HIT_T);
+      int32_t rq = k[cls == 0 ? C_MISS_H : C_HIT_H];
+      int32_t* node = s->core + (size_t)rq * C_WORDS;
       f[F_DST] = rq;
-      f[F_INFO] = (K_REPLY << 30) | s->core[(size_t)rq * C_WORDS + C_NLINE];
-      s->stats[OS_REPLY_SENT]++;
+      f[F_INFO] = (K_REPLY << 30) | node[C_NLINE];
       s->stats[OS_INJ_REPLY]++;
+      if (++node[C_NSENT] == s->reply_flits) {  /* the packet's last flit */
+        node[C_NSENT] = 0;
+        if (cls == 0) list_pop(s, t, C_MISS_H, C_MISS_T);
+        else list_pop(s, t, C_HIT_H, C_HIT_T);
+        s->stats[OS_REPLY_SENT]++;
+      }
     } else if (cls == 2) {
       f[F_DST] = k[C_LINE] % s->N;
       f[F_INFO] = (K_REQ << 30) | k[C_LINE];
@@ -446,11 +463,14 @@ static void phase_move(oracle_sim* s, int32_t t) {
       s->stats[OS_REQ_RECV]++;
       k[C_L2Q] = ej[F_SRC];
       k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
-    } else if (kind == K_REPLY) {              /* block reaches the requester */
-      s->stats[OS_REPLY_RECV]++;
+    } else if (kind == K_REPLY) {              /* a flit of the block reaches the requester */
       if (k[C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "reply at idle tile %d", t); }
-      k[C_STATE] = ST_FILL;
-      k[C_WAKE] = (int32_t)(c + 1);
+      if (++k[C_RCV] == s->reply_flits) {      /* all flits in: the block is complete */
+        k[C_RCV] = 0;
+        s->stats[OS_REPLY_RECV]++;
+        k[C_STATE] = ST_FILL;
+        k[C_WAKE] = (int32_t)(c + 1);
+      }
     }
   }
   if (s->N > 1 && s->rnd[(size_t)t * 4 + 3] < s->cfg.bg_thr) {
@@ -466,16 +486,17 @@ static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 
   return z ^ (z >> 31);
 }
 /* Digest of the words tile t owns after cycle c: its 16 input-slot words for the next cycle
-   and its core record.  The queue-node words (next, ready, line) are written by the
-   requester's home, not by the tile, so they are left out (zeroed); they are compared through
-   the canonical dump instead. */
+   and its core record.  The queue-node words (next, ready, line, flits sent) are written by
+   the requester's home, not by the tile, so they are left out (zeroed); they are compared
+   through the canonical dump instead. */
 static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
-  int32_t w[32];
+  int32_t w[16 + C_WORDS];
   memcpy(w, s->link[(c + 1) & 1] + (size_t)t * 16, 16 * sizeof(int32_t));
-  memcpy(w + 16, s->core + (size_t)t * C_WORDS, 16 * sizeof(int32_t));
-  w[16 + C_NEXT] = w[16 + C_READY] = w[16 + C_NLINE] = 0;
+  memcpy(w + 16, s->core + (size_t)t * C_WORDS, C_WORDS * sizeof(int32_t));
+  w[16 + C_NEXT] = w[16 + C_READY] = w[16 + C_NLINE] = w[16 + C_NSENT] = 0;
   uint64_t h = mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)t);
-  for (int i = 0; i < 16; ++i) h = mix64(h ^ (((uint64_t)(uint32_t)w[2 * i] << 32) | (uint32_t)w[2 * i + 1]));
+  for (int i = 0; i < (16 + C_WORDS) / 2; ++i)
+    h = mix64(h ^ (((uint64_t)(uint32_t)w[2 * i] << 32) | (uint32_t)w[2 * i + 1]));
   return h;
 }
 
@@ -483,7 +504,10 @@ static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
 static void check_cycle(oracle_sim* s) {
   const int64_t c = s->cycle;
   const int32_t* nxt = s->link[(c + 1) & 1];
-  int64_t occupied = 0, req_fl = 0, rep_fl = 0;
+  int64_t occupied = 0, req_fl = 0;
+  int32_t* rep_to = s->scratch;              /* reply flits in flight, per requester */
+  int32_t* queued_at = s->scratch + s->N;    /* 1 while the requester sits in a home's queue */
+  memset(s->scratch, 0, (size_t)s->N * 2 * sizeof(int32_t));
   for (int32_t t = 0; t < s->N; ++t) {
     for (int p = 0; p < 4; ++p) {
       const int32_t* f = nxt + (size_t)t * 16 + p * 4;
@@ -491,7 +515,7 @@ static void check_cycle(oracle_sim* s) {
       occupied++;
       int kind = (int)((uint32_t)f[F_INFO] >> 30);
       if (kind == K_REQ) req_fl++;
-      if (kind == K_REPLY) rep_fl++;
+      if (kind == K_REPLY) rep_to[f[F_DST]]++;
       if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
     }
     if (!s->oldest_ok[t] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "oldest flit deflected at %d", t); }
@@ -514,6 +538,7 @@ static void check_cycle(oracle_sim* s) {
       int64_t len = 0;
       while (r >= 0) {
         if (s->core[(size_t)r * C_WORDS + C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "queued tile %d not waiting", r); }
+        queued_at[r] = 1;
         last = r;
         r = s->core[(size_t)r * C_WORDS + C_NEXT];
         if (++len > s->N) { if (!s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "cyclic reply list at %d", t); } break; }
@@ -522,10 +547,27 @@ static void check_cycle(oracle_sim* s) {
       queued += len;
     }
   }
-  if (waiting != req_fl + rep_fl + queued + at_home && !s->bad) {
+  /* a waiting requester is in exactly one place: its request in flight, at its home's input,
+     queued at the home (some of its reply's flits possibly sent), or its whole reply sent with
+     flits still in flight; the flits in flight are those sent and not yet received */
+  int64_t rep_pk = 0;
+  for (int32_t r = 0; r < s->N; ++r) {
+    const int32_t* k = s->core + (size_t)r * C_WORDS;
+    const int32_t in_flight = rep_to[r];
+    if (queued_at[r]) {
+      if (in_flight != k[C_NSENT] - k[C_RCV] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "reply flits of queued tile %d", r); }
+    } else if (in_flight > 0) {
+      rep_pk++;
+      if ((k[C_STATE] != ST_WAIT || in_flight != s->reply_flits - k[C_RCV]) && !s->bad) {
+        s->bad = 1;
+        snprintf(s->msg, sizeof s->msg, "reply flits in flight to tile %d", r);
+      }
+    }
+  }
+  if (waiting != req_fl + rep_pk + queued + at_home && !s->bad) {
     s->bad = 1;
     snprintf(s->msg, sizeof s->msg, "requester accounting: waiting=%lld req=%lld reply=%lld queued=%lld at_home=%lld",
-             (long long)waiting, (long long)req_fl, (long long)rep_fl, (long long)queued, (long long)at_home);
+             (long long)waiting, (long long)req_fl, (long long)rep_pk, (long long)queued, (long long)at_home);
   }
 }
 
@@ -565,12 +607,14 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   if (cfg->l1_lat < 1 || cfg->mem_lat < 1 || cfg->shared_lines < 1 || cfg->private_lines < 0) return ORACLE_EINVAL;
   if ((int64_t)cfg->shared_lines + N * cfg->private_lines > (int64_t)LINE_MASK + 1) return ORACLE_EINVAL;
   if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
+  if (cfg->reply_flits < 0 || cfg->reply_flits > 16) return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
   s->cfg = *cfg;
   s->W = cfg->width;
   s->H = cfg->height;
   s->N = (int32_t)N;
+  s->reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
   s->zk = zk;
   s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
   s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
@@ -583,7 +627,9 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->outp = (int32_t*)malloc((size_t)N * 16 * 4);
   s->ej = (int32_t*)malloc((size_t)N * 4 * 4);
   s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
-  if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej || !s->oldest_ok) {
+  s->scratch = (int32_t*)malloc((size_t)N * 2 * 4);
+  if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
+      !s->oldest_ok || !s->scratch) {
     oracle_destroy(s);
     return ORACLE_ENOMEM;
   }
@@ -596,6 +642,8 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   for (int64_t t = 0; t < N; ++t) {
     s->core[t * C_WORDS + C_STATE] = ST_IDLE;
     s->core[t * C_WORDS + C_BG] = 0;
+    s->core[t * C_WORDS + C_RCV] = 0;
+    s->core[t * C_WORDS + C_NSENT] = 0;
   }
   memset(s->l1, 0xFF, (size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
   memset(s->l2, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
@@ -606,7 +654,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
 void oracle_destroy(oracle_sim* s) {
   if (!s) return;
   free(s->zs); free(s->zp); free(s->link[0]); free(s->link[1]); free(s->core); free(s->l1); free(s->l2);
-  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok);
+  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch);
   free(s);
 }
 
@@ -623,13 +671,15 @@ size_t oracle_dump_words(const oracle_sim* s) {
   return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways + 2 * OS_COUNT;
 }
 
-/* Canonical state: header, input slots of the next cycle, core records, L1 and L2 tags
-   (most recently used first), statistics as (low, high) word pairs. */
+/* Canonical state: header {magic, version 2, W, H, cycle (low, high), L1 sets, L1 ways, L2 sets,
+   L2 ways, reply flits, core-record words, 0...}, input slots of the next cycle, core records,
+   L1 and L2 tags (most recently used first), statistics as (low, high) word pairs. */
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
-  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 1, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
-                              s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, 0, 0, 0, 0, 0, 0};
+  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 2, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
+                              s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
+                              C_WORDS, 0, 0, 0, 0};
   memcpy(buf, hdr, sizeof hdr);
   o += DUMP_HEADER;
   memcpy(buf + o, s->link[s->cycle & 1], N * 16 * 4); o += N * 16;
@@ -646,8 +696,9 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
 
 int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
-  if (buf[0] != DUMP_MAGIC || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets || buf[7] != s->cfg.l1_ways ||
-      buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways)
+  if (buf[0] != DUMP_MAGIC || buf[1] != 2 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
+      buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
+      buf[11] != C_WORDS)
     return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = DUMP_HEADER;
   s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
@@ -690,7 +741,7 @@ int oracle_quiescent(const oracle_sim* s) {
       if (cur[(size_t)t * 16 + p * 4] >= 0) return 0;
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
-        k[C_FLINE] >= 0 || k[C_FDST] >= 0)
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0)
       return 0;
   }
   return 1;

@@ -35,6 +35,7 @@ typedef struct {
   int32_t shared_lines;        /* lines [0, shared_lines) form the shared region */
   int32_t private_lines;       /* per-tile private region size (0 = no private region) */
   int32_t flags;               /* reserved, 0 */
+  int32_t reply_flits;         /* flits of a reply packet, 1..16 (0 counts as 1) */
 } oracle_config;
 
 enum {

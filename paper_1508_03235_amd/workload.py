@@ -25,7 +25,7 @@ ZIPF_K = 65536
 FIELDS = (
     "width", "height", "seed", "l1_sets", "l1_ways", "l2_sets", "l2_ways", "l1_lat",
     "mem_lat", "op_thr", "shared_thr", "bg_thr", "shared_lines", "private_lines",
-    "zipf_shared_s", "zipf_private_s",
+    "zipf_shared_s", "zipf_private_s", "reply_flits",
 )
 
 
@@ -69,6 +69,7 @@ class SimParams:
     private_lines: int = 0
     zipf_shared_s: float = 0.8
     zipf_private_s: float = 0.9
+    reply_flits: int = 1      # flits per reply packet (the paper's Table 1: 4 for a remote L2 access)
 
     @property
     def tiles(self) -> int:

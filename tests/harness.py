@@ -21,7 +21,8 @@ STAT = {
 }
 CORE = {"state": 0, "wake": 1, "line": 2, "issue": 3, "l2q": 4, "l2q_line": 5, "hit_head": 6,
         "hit_tail": 7, "miss_head": 8, "miss_tail": 9, "bg_pending": 10, "node_next": 11,
-        "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15}
+        "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15, "reply_flits_received": 16,
+        "node_flits_sent": 17}
 
 
 def load_golden(name):
@@ -34,7 +35,8 @@ def split_dump(buf, params):
     o = 16
     out = {"header": buf[:16]}
     out["links"] = buf[o:o + N * 16].reshape(N, 4, 4); o += N * 16
-    out["core"] = buf[o:o + N * 16].reshape(N, 16); o += N * 16
+    cw = int(buf[11])   # core-record words (header word 11)
+    out["core"] = buf[o:o + N * cw].reshape(N, cw); o += N * cw
     n1 = N * params.l1_sets * params.l1_ways
     out["l1"] = buf[o:o + n1].reshape(N, params.l1_sets, params.l1_ways); o += n1
     n2 = N * params.l2_sets * params.l2_ways

@@ -18,8 +18,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1508_03235_amd import workload as W
-from tests.harness import (STAT, load_golden, quiet_params, run_flit_trace, run_op_trace,
-                           split_dump)
+from tests.harness import (STAT, load_golden, quiet_params, run_flit_trace, run_op_trace, split_dump, CORE)
 
 
 def make_oracle(p):
@@ -309,3 +308,91 @@ def test_reduces_to_uniform_traffic_without_cache_ops():
     mean_man = (2 * (k * k - 1) / (3 * k)) * n / (n - 1)
     assert abs(avg - mean_man) < 0.1 * mean_man, (avg, mean_man)
     assert st[STAT["deflections"]] < 0.02 * st[STAT["traversals"]]
+
+
+# ---- multi-flit reply packets (Sec. 3.6, Table 1) -------------------------------------------
+
+def _op_latencies(p, ops, max_cycles=2000):
+    """Runs forced ops one after another on a quiet chip; returns each op's latency."""
+    sim = O.OracleSim(p)
+    out = []
+    for tile, line in ops:
+        st0 = sim.stats()
+        sim.force_op(tile, line)
+        for _ in range(max_cycles):
+            sim.step(1, check=True)
+            st = sim.stats()
+            if st[STAT["ops_done"]] > st0[STAT["ops_done"]]:
+                break
+        else:
+            raise AssertionError("op did not finish")
+        out.append(int(st[STAT["op_lat"]] - st0[STAT["op_lat"]]))
+    return out, sim
+
+
+@pytest.mark.parametrize("flits", [1, 2, 4, 16])
+def test_packet_latency_adds_one_cycle_per_extra_flit(flits):
+    """At zero load the F flits of a reply leave the home on consecutive cycles over the same
+    free path, so the block is complete F-1 cycles after its first flit arrives: each op that
+    crosses the network takes F-1 cycles longer than with one flit (the hand trace T4 gives
+    205, 5 and 7 for one flit), and an L1 hit is unchanged."""
+    tr = next(t for t in load_golden("hand_traces.json")["op_traces"] if t["name"] == "T4_2x2_cache_round_trip")
+    p = quiet_params(tr["width"], tr["height"], l1_sets=tr["l1_sets"], l1_ways=tr["l1_ways"], l2_sets=tr["l2_sets"],
+                     l2_ways=tr["l2_ways"], l1_lat=tr["l1_lat"], mem_lat=tr["mem_lat"], reply_flits=flits)
+    lat, sim = _op_latencies(p, [(o["tile"], o["line"]) for o in tr["ops"]])
+    want = [o["latency"] + (flits - 1 if o["latency"] > 0 else 0) for o in tr["ops"]]
+    assert lat == want
+    st = sim.stats()
+    assert st[STAT["inj_reply"]] == st[STAT["ej_reply"]] == flits * st[STAT["reply_sent"]]
+    assert st[STAT["reply_sent"]] == st[STAT["reply_received"]] == st[STAT["req_made"]]
+
+
+@pytest.mark.parametrize("flits", [2, 4, 16])
+@pytest.mark.parametrize("w,h", [(2, 2), (3, 3), (4, 5)])
+def test_packets_keep_invariants_and_drain(w, h, flits):
+    """Under load, with replies interleaving at their homes: every cycle's invariants hold
+    (a queued requester's flits in flight = flits sent - flits received; a requester whose
+    reply has left its home has F - received in flight), the chip drains, and reply flits
+    injected = ejected = F x packets sent = F x packets received."""
+    rng = random.Random(w * 100 + h + flits)
+    p = _random_params(rng, w, h).with_(op_thr=W.thr(0.5), bg_thr=W.thr(0.2), reply_flits=flits)
+    sim = O.OracleSim(p)
+    sim.step(1500, check=True)
+    sim.set_rates(0, 0)
+    for _ in range(400):
+        if sim.quiescent():
+            break
+        sim.step(50, check=True)
+    assert sim.quiescent()
+    st = sim.stats()
+    assert st[STAT["req_made"]] == st[STAT["req_received"]] == st[STAT["reply_sent"]] == st[STAT["reply_received"]] > 0
+    assert st[STAT["inj_reply"]] == st[STAT["ej_reply"]] == flits * st[STAT["reply_sent"]]
+    assert st[STAT["ops_issued"]] == st[STAT["ops_done"]]
+
+
+def test_packets_checkpoint_mid_packet_resumes_exactly():
+    """A checkpoint taken while a reply is half sent and half received resumes exactly."""
+    p = W.config0().with_(reply_flits=4, op_thr=W.thr(0.5))
+    b = O.OracleSim(p)
+    for _ in range(3000):  # the first cycle with a packet partly sent and one partly received
+        b.step(1)
+        core = split_dump(b.dump(), p)["core"]
+        if (core[:, CORE["node_flits_sent"]] > 0).any() and (core[:, CORE["reply_flits_received"]] > 0).any():
+            break
+    else:
+        raise AssertionError("no partial packet in 3000 cycles")
+    k = b.cycle
+    snap = b.dump()
+    a = O.OracleSim(p)
+    da = a.step(k + 1000, digests=True)
+    c = O.OracleSim(p)
+    c.load(snap)
+    dc = c.step(1000, digests=True)
+    assert (dc == da[k:]).all()
+    assert (c.dump() == a.dump()).all()
+
+
+def test_single_flit_replies_are_the_default():
+    p = W.config0()
+    assert (O.OracleSim(p.with_(reply_flits=1)).step(800, digests=True) ==
+            O.OracleSim(p.with_(reply_flits=0)).step(800, digests=True)).all()
