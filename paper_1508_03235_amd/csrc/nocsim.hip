@@ -32,6 +32,10 @@ namespace {
 constexpr int KIND_REQ = 0, KIND_REPLY = 1, KIND_BG = 2;
 constexpr int CORE_IDLE = 0, CORE_L1MISS = 1, CORE_SEND = 2, CORE_WAIT = 3, CORE_FILL = 4;
 constexpr int32_t LINE_MASK = 0x3FFFFFFF;
+// words of a tile's record in the canonical dump: state, wake, line, issue, l2q, l2q_line,
+// hit head/tail, miss head/tail, bg_pending, node next/ready/line, force_line, force_dst,
+// reply flits received, node flits sent
+constexpr int CORE_RECORD = 18;
 constexpr int ZIPF_K = 65536;
 constexpr int MAX_PATCHES = 4096;
 constexpr int FLAG_STRIDE = 32;  // ints between patch flags (128 B)
@@ -47,11 +51,12 @@ struct ChipDev {
   int32_t w1_shift, w2_shift; // log2 of the way counts
   int32_t s1, w1, s2, w2;
   int32_t l1_lat, mem_lat, shared_lines, private_lines;
+  int32_t reply_flits;       // flits per reply packet (Sec. 3.6, Table 1); 1 = single-flit replies
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int4* link;                // [2 parity][4 port][N]
   int4* core;                // [4][N]
-  int4* node;                // [N]: next, ready, line, 0
+  int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
   int32_t* l2;               // [N][s2][w2]
   const uint32_t* zs;
@@ -319,7 +324,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int4 k0 = gload4(&C.core[t]);          // state, wake, line, issue
   int4 k1 = gload4(&C.core[N + t]);      // l2q, l2q_line, hit_head, hit_tail
   int4 k2 = gload4(&C.core[2 * N + t]);  // miss_head, miss_tail, bg_pending, force_line
-  int fdst = *gp(reinterpret_cast<const int*>(&C.core[3 * N + t]));
+  const int4 k3 = gload4(&C.core[3 * N + t]);  // force_dst, reply flits received
+  int fdst = k3.x, rcv = k3.y;
 
   if (digest) {  // state owned by t after cycle c-1: its inputs of cycle c and its core words
     unsigned long long h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
@@ -333,6 +339,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, k2.z, 0);   // bg_pending; the queue-node words are written by the home
     h = mix_pair(h, 0, 0);
     h = mix_pair(h, k2.w, fdst);
+    h = mix_pair(h, rcv, 0);    // reply flits received; the node's sent count is the home's
     dsum += h;
   }
   if (!step) return true;
@@ -377,7 +384,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
 
   // ---- phase one: home L2 service, then the core (Sec. 7.1, phase one; Sec. 3.5) ----------
   bool dirtyR = false, dirtyL = false, dirty1 = false;
-  int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
+  int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0, node_w = 0;
   if (svc) {
     const int rq = k1.x, line = k1.y;
     const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
@@ -469,19 +476,29 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (cls >= 0) {
     fi.y = c;
     fi.z = t;
-    if (cls <= 1) {  // reply: pop the queue head
+    if (cls <= 1) {  // a flit of the head's reply; the head is popped with the packet's last flit
       const int4 hd = cls == 0 ? nm : nh;
       const int rq = cls == 0 ? k2.x : k1.z;
-      if (cls == 0) {
-        k2.x = hd.x;
-        if (hd.x < 0) k2.y = -1;
-      } else {
-        k1.z = hd.x;
-        if (hd.x < 0) k1.w = -1;
+      const int sent = hd.w + 1;
+      const bool last = sent >= C.reply_flits;
+      if (last) {
+        if (cls == 0) {
+          k2.x = hd.x;
+          if (hd.x < 0) k2.y = -1;
+        } else {
+          k1.z = hd.x;
+          if (hd.x < 0) k1.w = -1;
+        }
+        lds_add(L, SIM_ST_REPLY_SENT, 1);
+      }
+      // the sent count goes to the head's node; a node appended this cycle is written whole
+      // below, so its count rides with that store
+      if (C.reply_flits > 1) {
+        if (rq == node_rq) node_w = last ? 0 : sent;
+        else st_i<MULTI>(reinterpret_cast<int*>(&C.node[rq]) + 3, last ? 0 : sent);
       }
       fi.x = rq;
       fi.w = (KIND_REPLY << 30) | hd.z;
-      lds_add(L, SIM_ST_REPLY_SENT, 1);
       acc.inj_reply++;
       d1 = true;
       d2 = true;
@@ -563,7 +580,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (dirtyL) set_store(setL, C.w2, vL);
   if (dirty1) set_store(set1, C.w1, u);
   if (node_rq >= 0) {
-    st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
+    st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, node_w));
     if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
   }
   int4 oe = EMPTY;
@@ -605,11 +622,16 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       k1.x = oe.z;
       k1.y = oe.w & LINE_MASK;
       d1 = true;
-    } else if (kind == KIND_REPLY) {
-      lds_add(L, SIM_ST_REPLY_RECV, 1);
-      k0.x = CORE_FILL;
-      k0.y = c + 1;
-      d0 = true;
+    } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
+      rcv += 1;
+      d3 = true;
+      if (rcv >= C.reply_flits) {
+        rcv = 0;
+        lds_add(L, SIM_ST_REPLY_RECV, 1);
+        k0.x = CORE_FILL;
+        k0.y = c + 1;
+        d0 = true;
+      }
     }
   }
   if (N > 1 && r.w < C.bg_thr) {
@@ -620,7 +642,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (d0) gstore4(&C.core[t], k0);
   if (d1) gstore4(&C.core[N + t], k1);
   if (d2) gstore4(&C.core[2 * N + t], k2);
-  if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, 0, 0, 0));
+  if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, 0, 0));
 #undef GUARD
   return true;
 }
@@ -873,7 +895,9 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   draw_ahead(C, t, c + 1, P);
 }
 
-template <bool MULTI, bool DIGEST>
+// PACKETS: replies may have several flits (the chip's reply_flits); without it the kernel is
+// the single-flit model, compiled without the per-flit counts.
+template <bool MULTI, bool DIGEST, bool PACKETS>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   __shared__ LdsStats L;
@@ -918,14 +942,16 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   int c_done = c0;
 
   int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
-  int fdst = -1;
+  int fdst = -1, rcv = 0;  // forced background destination; flits of the awaited reply received
   uint32_t geo = geo0;
   const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
   if (active) {
     k0 = gload4(&C.core[t]);
     k1 = gload4(&C.core[N + t]);
     k2 = gload4(&C.core[2 * N + t]);
-    fdst = *gp(reinterpret_cast<const int*>(&C.core[3 * N + t]));
+    const int4 k3 = gload4(&C.core[3 * N + t]);
+    fdst = k3.x;
+    rcv = k3.y;
     const int par = c0 & 1;
     if (i0) s_link[par][0][j] = slot_decode(gload4(&C.link[(par * 4 + 0) * N + t]));
     if (i1) s_link[par][1][j] = slot_decode(gload4(&C.link[(par * 4 + 1) * N + t]));
@@ -976,7 +1002,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       const bool p_forced = (pf & PF_FORCED) != 0, p_drawn = (pf & PF_DRAWN) != 0;
       // the core words as they stand after cycle c-1 (the digest hashes them after the links)
       const int4 d0 = k0, d1 = k1, d2 = k2;
-      const int dfd = fdst;
+      const int dfd = fdst, drcv = rcv;
       if (step) {
         if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
             (k2.y >= 0 && (unsigned)k2.y >= (unsigned)N) || (k1.z >= 0 && (unsigned)k1.z >= (unsigned)N) ||
@@ -986,7 +1012,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       bool dirtyR = false, dirtyL = false, dirty1 = false;
-      int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0;
+      int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0, node_w = 0;
       int4 nh = P.nh, nm = P.nm;
       if (step && ok) {
         // phase one reads no link input: it runs while this cycle's patch-edge reads are in flight
@@ -1092,6 +1118,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, d2.z, 0);
         h = mix_pair(h, 0, 0);
         h = mix_pair(h, d2.w, dfd);
+        h = mix_pair(h, drcv, 0);
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1111,13 +1138,23 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         if (cls >= 0) {
           fi.y = c;
           fi.z = t;
-          if (cls <= 1) {
+          if (cls <= 1) {  // a flit of the head's reply; the head is popped with the last one
             const int4 hd = cls == 0 ? nm : nh;
             fi.x = cls == 0 ? k2.x : k1.z;
-            if (cls == 0) { k2.x = hd.x; if (hd.x < 0) k2.y = -1; }
-            else { k1.z = hd.x; if (hd.x < 0) k1.w = -1; }
+            const int sent = hd.w + 1;
+            const bool last = !PACKETS || sent >= C.reply_flits;
+            if (last) {
+              if (cls == 0) { k2.x = hd.x; if (hd.x < 0) k2.y = -1; }
+              else { k1.z = hd.x; if (hd.x < 0) k1.w = -1; }
+            }
+            // the sent count goes to the head's node; a node appended this cycle is written
+            // whole with phase one's stores, so its count rides with that store
+            if (PACKETS && C.reply_flits > 1) {
+              if (fi.x == node_rq) node_w = last ? 0 : sent;
+              else st_i<MULTI>(reinterpret_cast<int*>(&C.node[fi.x]) + 3, last ? 0 : sent);
+            }
             fi.w = (KIND_REPLY << 30) | hd.z;
-            acc.reply_sent++;
+            acc.reply_sent += last;
             acc.inj_reply++;
           } else if (cls == 2) {
             fi.x = (int)mod_n(C, (uint32_t)k0.z);
@@ -1184,7 +1221,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         if (dirtyL) set_store(P.setL, C.w2, P.vL);
         if (dirty1) set_store(P.set1, C.w1, P.u);
         if (node_rq >= 0) {
-          st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, 0));
+          st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, node_w));
           if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
         }
         if (oe.x >= 0) {
@@ -1203,10 +1240,14 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             acc.req_recv++;
             k1.x = oe.z;
             k1.y = oe.w & LINE_MASK;
-          } else if (kind == KIND_REPLY) {
-            acc.reply_recv++;
-            k0.x = CORE_FILL;
-            k0.y = c + 1;
+          } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
+            rcv += PACKETS ? 1 : 0;
+            if (!PACKETS || rcv >= C.reply_flits) {
+              rcv = 0;
+              acc.reply_recv++;
+              k0.x = CORE_FILL;
+              k0.y = c + 1;
+            }
           }
         }
         if (N > 1 && P.r.w < C.bg_thr) {
@@ -1235,7 +1276,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     gstore4(&C.core[t], k0);
     gstore4(&C.core[N + t], k1);
     gstore4(&C.core[2 * N + t], k2);
-    gstore4(&C.core[3 * N + t], make_int4(fdst, 0, 0, 0));
+    gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, 0, 0));
     const int par = c_done & 1;
     if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
     if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
@@ -1264,12 +1305,13 @@ __global__ void init_links(int4* link, int N, int c) {
   }
 }
 // core words of a fresh chip: state idle, bg 0, everything else -1
-__global__ void init_core(int4* core, int N) {
+__global__ void init_core(int4* core, int4* node, int N) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N; t += gridDim.x * blockDim.x) {
     core[t] = make_int4(CORE_IDLE, -1, -1, -1);
     core[N + t] = make_int4(-1, -1, -1, -1);
     core[2 * N + t] = make_int4(-1, -1, 0, -1);
-    core[3 * N + t] = make_int4(-1, 0, 0, 0);
+    core[3 * N + t] = make_int4(-1, 0, 0, 0);  // forced background destination, reply flits received
+    node[t] = make_int4(-1, -1, -1, 0);
   }
 }
 
@@ -1308,6 +1350,7 @@ struct sim_group {
   std::vector<sim_launch_group> groups;
   int32_t block;
   bool multi, fast;
+  bool packets;                      // some chip has multi-flit replies
   hipStream_t stream;
   LaunchEntry* table_dev;
   LaunchEntry* table_host;
@@ -1335,6 +1378,7 @@ bool config_ok(const sim_config* c) {
   if (N >= (1 << 20)) return false;  // tile indices take 20 bits in a slot word, all ones = empty
   if (!pow2(c->l1_sets) || !ways_ok(c->l1_ways) || !pow2(c->l2_sets) || !ways_ok(c->l2_ways)) return false;
   if (c->l1_lat < 1 || c->mem_lat < 1 || c->shared_lines < 1 || c->private_lines < 0) return false;
+  if (c->reply_flits < 0 || c->reply_flits > 16) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
@@ -1406,9 +1450,13 @@ int device_cus() {
   return cus;
 }
 
-const void* multi_kernel(bool fast, bool digest = false) {
+const void* multi_kernel(bool fast, bool digest = false, bool packets = false) {
   if (!fast) return reinterpret_cast<const void*>(step_kernel<true>);
-  return digest ? reinterpret_cast<const void*>(step_fast<true, true>) : reinterpret_cast<const void*>(step_fast<true, false>);
+  if (packets)
+    return digest ? reinterpret_cast<const void*>(step_fast<true, true, true>)
+                  : reinterpret_cast<const void*>(step_fast<true, false, true>);
+  return digest ? reinterpret_cast<const void*>(step_fast<true, true, false>)
+                : reinterpret_cast<const void*>(step_fast<true, false, false>);
 }
 // how many workgroups of `block` threads of the multi-patch kernel can be resident at once
 int resident_limit(int block, bool fast) {
@@ -1471,17 +1519,20 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 }
 
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
+// packets: some chip of the table has multi-flit replies (the kernel then reads each chip's count)
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
-                   unsigned long long* digests, int digest_base, hipStream_t s) {
+                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets) {
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr), dim3((unsigned)n), dim3(block), args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, packets), dim3((unsigned)n), dim3(block),
+                                        args, 0, s));
   } else if (fast) {
-    if (digests)
-      hipLaunchKernelGGL((step_fast<false, true>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
-    else
-      hipLaunchKernelGGL((step_fast<false, false>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    const dim3 g((unsigned)n), b(block);
+    if (digests && packets) hipLaunchKernelGGL((step_fast<false, true, true>), g, b, 0, s, table, chunk, digests, digest_base);
+    else if (digests) hipLaunchKernelGGL((step_fast<false, true, false>), g, b, 0, s, table, chunk, digests, digest_base);
+    else if (packets) hipLaunchKernelGGL((step_fast<false, false, true>), g, b, 0, s, table, chunk, digests, digest_base);
+    else hipLaunchKernelGGL((step_fast<false, false, false>), g, b, 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   } else {
     hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
@@ -1558,6 +1609,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.w2 = cfg->l2_ways;
   d.l1_lat = cfg->l1_lat;
   d.mem_lat = cfg->mem_lat;
+  d.reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
   d.shared_lines = cfg->shared_lines;
   d.private_lines = cfg->private_lines;
   d.stop = 0;
@@ -1582,9 +1634,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   auto fail = [&](int code) { (void)hipHostFree(h->table_host); delete h; return code; };
   hipLaunchKernelGGL(init_links, dim3(std::min((8 * N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.link, N, 0);
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
-  hipLaunchKernelGGL(init_core, dim3(std::min((N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.core, N);
+  hipLaunchKernelGGL(init_core, dim3(std::min((N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.core, d.node, N);
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
-  if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.node), -1, (size_t)N * 4, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l1, -1, (size_t)N * cfg->l1_sets * cfg->l1_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l2, -1, (size_t)N * cfg->l2_sets * cfg->l2_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_u64(d.stats, 0, NSTAT, h->stream))) return fail(rc);
@@ -1644,7 +1695,8 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   }
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
-    int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream);
+    int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
+                            h->hd.reply_flits > 1);
     if (rc) return rc;
   }
   h->cycle += n;
@@ -1665,7 +1717,7 @@ int sim_stats(sim_t* h, sim_stats_t* out) {
 size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
-  return 16 + N * 16 + N * 16 + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT;
+  return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT;
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
@@ -1678,25 +1730,26 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   HIPCHECK(hipMemcpyAsync(node.data(), h->hd.node, N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
   size_t o = 16;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
-  int32_t* l1 = buf + 16 + N * 32;
+  int32_t* l1 = buf + 16 + N * (16 + CORE_RECORD);
   int32_t* l2 = l1 + n1;
   HIPCHECK(hipMemcpyAsync(l1, h->hd.l1, n1 * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipMemcpyAsync(l2, h->hd.l2, n2 * 4, hipMemcpyDeviceToHost, h->stream));
   unsigned long long st[NSTAT];
   HIPCHECK(hipMemcpyAsync(st, h->hd.stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  const int32_t hdr[16] = {0x4E4F4353, 1, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle, (int32_t)(h->cycle >> 32),
-                           h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, 0, 0, 0, 0, 0, 0};
+  const int32_t hdr[16] = {0x4E4F4353, 2, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle, (int32_t)(h->cycle >> 32),
+                           h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits, CORE_RECORD, 0, 0, 0, 0};
   std::memcpy(buf, hdr, sizeof hdr);
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) host_decode(link[p * N + t], buf + o + t * 16 + p * 4);
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
     const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], nd = node[t];
-    const int32_t rec[16] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y, k2.z, nd.x, nd.y, nd.z, k2.w, k3.x};
-    std::memcpy(buf + o + t * 16, rec, sizeof rec);
+    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x,
+                                      k2.y, k2.z, nd.x, nd.y, nd.z, k2.w, k3.x, k3.y, nd.w};
+    std::memcpy(buf + o + t * CORE_RECORD, rec, sizeof rec);
   }
-  o += N * 16 + n1 + n2;
+  o += N * CORE_RECORD + n1 + n2;
   for (int i = 0; i < NSTAT; ++i) {
     buf[o++] = (int32_t)(uint32_t)st[i];
     buf[o++] = (int32_t)(st[i] >> 32);
@@ -1706,8 +1759,9 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
 
 int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (!h || !buf || words < sim_dump_words(h)) return SIM_EINVAL;
-  if (buf[0] != 0x4E4F4353 || buf[2] != h->hd.W || buf[3] != h->hd.H || buf[6] != h->hd.s1 || buf[7] != h->hd.w1 ||
-      buf[8] != h->hd.s2 || buf[9] != h->hd.w2)
+  if (buf[0] != 0x4E4F4353 || buf[1] != 2 || buf[2] != h->hd.W || buf[3] != h->hd.H || buf[6] != h->hd.s1 ||
+      buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 || buf[10] != h->hd.reply_flits ||
+      buf[11] != CORE_RECORD)
     return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const int64_t cyc = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
@@ -1722,14 +1776,14 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     }
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
-    const int32_t* r = buf + o + t * 16;
+    const int32_t* r = buf + o + t * CORE_RECORD;
     core[t] = make_int4(r[0], r[1], r[2], r[3]);
     core[N + t] = make_int4(r[4], r[5], r[6], r[7]);
     core[2 * N + t] = make_int4(r[8], r[9], r[10], r[14]);
-    core[3 * N + t] = make_int4(r[15], 0, 0, 0);
-    node[t] = make_int4(r[11], r[12], r[13], 0);
+    core[3 * N + t] = make_int4(r[15], r[16], 0, 0);
+    node[t] = make_int4(r[11], r[12], r[13], r[17]);
   }
-  o += N * 16;
+  o += N * CORE_RECORD;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
   const int par = (int)(cyc & 1);
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)par * 4 * N, link.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
@@ -1765,8 +1819,9 @@ int sim_force_op(sim_t* h, int32_t tile, int32_t line) {
 
 int sim_force_bg(sim_t* h, int32_t tile, int32_t dst) {
   if (!h || tile < 0 || tile >= h->hd.N || dst < 0 || dst >= h->hd.N || dst == tile) return SIM_EINVAL;
-  const int4 k3 = make_int4(dst, 0, 0, 0);
-  HIPCHECK(hipMemcpyAsync(h->hd.core + 3 * (size_t)h->hd.N + tile, &k3, sizeof k3, hipMemcpyHostToDevice, h->stream));
+  const int32_t d = dst;  // the forced destination word only (the reply-flit count beside it stays)
+  HIPCHECK(hipMemcpyAsync(reinterpret_cast<int32_t*>(h->hd.core + 3 * (size_t)h->hd.N + tile), &d, sizeof d,
+                          hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   return SIM_OK;
 }
@@ -1839,6 +1894,8 @@ int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, si
   g->block = blk;
   g->multi = multi;
   g->fast = fast;
+  g->packets = false;
+  for (int i = 0; i < n; ++i) g->packets = g->packets || chips[i]->hd.reply_flits > 1;
   g->groups = groups;
   g->stream = static_cast<hipStream_t>(stream);
   g->table_dev = static_cast<LaunchEntry*>(dev_mem);
@@ -1878,7 +1935,7 @@ int simb_step(simb_t* g, const int64_t* cycles) {
     const int launches = (int)((lg_longest + chunk - 1) / chunk);
     for (int k = 0; k < launches; ++k) {
       int rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
-                              g->stream);
+                              g->stream, g->packets);
       if (rc) return rc;
     }
   }

@@ -189,3 +189,66 @@ def test_autotuned_mapping_gives_the_same_run(tmp_path):
     assert len(best) == 3
     assert autotune.tune(p, cache_path=str(tmp_path / "tune.json")) == best   # cached
     assert_same_run(p, 400, launch=(best[0], best[1], best[2], 0))
+
+
+# ---- multi-flit reply packets (Sec. 3.6, Table 1) --------------------------------------------
+
+def test_packets_config0_full_run():
+    """4x4, 10,000 cycles with 4-flit replies (the paper's remote L2 access)."""
+    assert_same_run(W.config0().with_(reply_flits=4), 10_000, step_sizes=[1, 999, 4000, 5000])
+
+
+@pytest.mark.parametrize("flits", [2, 16])
+@pytest.mark.parametrize("w,h", [(1, 7), (5, 5), (13, 7)])
+def test_packets_small_shapes(w, h, flits):
+    p = W.config0().with_(width=w, height=h, seed=w * 100 + h + flits, bg_thr=W.thr(0.2), op_thr=W.thr(0.5),
+                          reply_flits=flits)
+    assert_same_run(p, 3000)
+
+
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+@pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37)])
+def test_packets_patch_mappings(launch, generic):
+    """Partially sent replies (node words written by the home) and partially received ones
+    (a core word) cross patch edges and launch boundaries exactly."""
+    p = W.config0().with_(width=20, height=13, seed=6, bg_thr=W.thr(0.15), op_thr=W.thr(0.5), reply_flits=4)
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800], generic=generic)
+
+
+def test_packets_config2_full_size_prefix():
+    assert_same_run(W.config2(0.05).with_(reply_flits=4), 120, step_sizes=[50, 70])
+
+
+def test_packets_checkpoint_and_drain_on_gpu():
+    p = W.config0().with_(width=6, height=6, seed=23, bg_thr=W.thr(0.2), op_thr=W.thr(0.5), reply_flits=4)
+    a = gpu_sim(p)
+    da = a.step(1000, digests=True)
+    b = gpu_sim(p)
+    b.step(437)
+    c = gpu_sim(p)
+    c.load(b.dump())
+    assert (c.step(563, digests=True) == da[437:]).all()
+    o = O.OracleSim(p)
+    o.step(1000)
+    for s in (a, o):
+        s.set_rates(0, 0)
+        s.step(3000)
+    assert (a.dump() == o.dump()).all()
+    assert o.quiescent()
+    st = a.stats()
+    assert st[STAT["inj_reply"]] == st[STAT["ej_reply"]] == 4 * st[STAT["reply_sent"]]
+    assert st[STAT["reply_sent"]] == st[STAT["reply_received"]] == st[STAT["req_made"]]
+
+
+def test_packets_batch_of_mixed_reply_sizes():
+    """One launch over chips with 1-, 2-, 4- and 16-flit replies equals their own runs."""
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=3000 + i, bg_thr=W.thr(0.1), reply_flits=f)
+              for i, (s, f) in enumerate([(8, 1), (16, 4), (8, 16), (24, 2), (16, 1)])]
+    sims = [gpu_sim(p) for p in params]
+    b = nocsim.Batch(sims)
+    b.step([300, 250, 300, 123, 200])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200]):
+        o = O.OracleSim(p)
+        o.step(n)
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} reply_flits {p.reply_flits}"

@@ -40,9 +40,10 @@ def test_oracle_backend_every_job_equals_its_solo_run():
 
 
 def test_budget_forces_queueing_in_arrival_order():
-    jobs = small_jobs(10)
+    # jobs of one size, and a budget of exactly one job: never two resident at once
+    jobs = [W.Job(j.index, j.arrival_s, j.cycles, j.params.with_(width=4, height=4)) for j in small_jobs(10)]
     be = OracleBackend()
-    budget = max(be.state_bytes(j.params) for j in jobs)  # one resident job at a time
+    budget = be.state_bytes(jobs[0].params)
     rep = Server(be, budget, tick_cycles=1000).run(jobs)
     order = sorted(rep.results, key=lambda r: r.admit_s)
     assert [r.index for r in order] == sorted(r.index for r in rep.results)
