@@ -14,6 +14,9 @@ Besides the headline line the JSON carries:
                  prefix;
   sweep        - per-rate throughput and the sweep's outputs (deflection rate, average
                  latency, L2 hit rate) (skip with --no-sweep);
+  packets      - the same chip with replies of 4 flits (the paper's Table 1, remote L2 access):
+                 throughput, flit and op latency against single-flit replies, and per-cycle
+                 digests of a prefix against the oracle (--no-packets);
   batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
   serving      - Poisson-arriving simulation jobs under continuous batching: p50/p99 job
                  latency and aggregate throughput, against one job at a time (--no-serving).
@@ -128,6 +131,35 @@ def run_sweep(nocsim, W, torch, cycles):
     return out
 
 
+def run_packets(nocsim, W, torch, O, cycles, parity_cycles=200, flits=4):
+    """The 208x208 chip at background 0.05 with multi-flit replies, beside single-flit ones."""
+    out = {"reply_flits": flits}
+    for f in (1, flits):
+        p = W.config2(0.05).with_(reply_flits=f)
+        sim = nocsim.Sim(p)
+        sim.step(500)
+        st0 = sim.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(cycles)
+        dt = time.perf_counter() - t0
+        st = sim.stats() - st0
+        S = nocsim.STAT
+        ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
+        lat = st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]
+        out[f"flits_{f}"] = {"tile_cycles_per_s": p.tiles * cycles / dt,
+                             "avg_flit_latency": float(lat / max(1, ej)),
+                             "avg_op_latency": float(st[S["op_lat"]] / max(1, st[S["ops_done"]])),
+                             "ops_per_tile_cycle": float(st[S["ops_done"]] / (p.tiles * cycles))}
+        del sim
+    if O is not None:
+        p = W.config2(0.05).with_(reply_flits=flits)
+        g = nocsim.Sim(p).step(parity_cycles, digests=True)
+        o = O.OracleSim(p).step(parity_cycles, digests=True)
+        out["parity"] = {"cycles": parity_cycles, "digests_equal": bool((g == o).all())}
+    return out
+
+
 def run_batched(nocsim, W, torch, cycles, plain_chips):
     params = W.config3()
     sims = [nocsim.Sim(p) for p in params]
@@ -196,6 +228,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-packets", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=60)
@@ -299,6 +332,15 @@ def main():
             out["sweep"] = run_sweep(nocsim, W, torch, 5000)
         except Exception as e:  # an optional leg must not hide the headline number
             out["sweep"] = {"error": repr(e)}
+    if not args.no_packets:
+        try:
+            from oracle import oracle as O
+        except Exception:
+            O = None
+        try:
+            out["packets"] = run_packets(nocsim, W, torch, O if cpu else None, 5000)
+        except Exception as e:
+            out["packets"] = {"error": repr(e)}
     if not args.no_batched:
         try:
             out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
