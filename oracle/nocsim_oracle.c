@@ -21,8 +21,11 @@
  * Where the paper is silent or ambiguous the oracle follows the readings listed
  * in the design notes (static home = line mod N, injection-time age, one eject
  * per cycle, per-home reply queues as intrusive lists, Philox4x32-10 draws keyed
- * by (seed; cycle, tile, stream)).  Every function below names the passage it
- * follows.
+ * by (seed; cycle, tile, stream)).  Three more literal readings can be switched
+ * on as variants (ORACLE_FLAG_*): priority by deflection count, hits served
+ * under an outstanding miss, and injection through the router's injection
+ * register one cycle after a flit is made.  Every function below names the
+ * passage it follows.
  *
  * Parity pins: the Philox generator is pinned to published known-answer
  * vectors; routing to closed-form zero-load latencies and hand traces; the
@@ -41,7 +44,7 @@
 enum { K_REQ = 0, K_REPLY = 1, K_BG = 2 };                              /* flit kinds */
 enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4 }; /* core states */
 enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
-/* per-tile core record (18 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
+/* per-tile core record (20 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
    node as a requester, written by its home while it waits there */
 enum {
   C_STATE = 0, C_WAKE = 1, C_LINE = 2, C_ISSUE = 3, C_L2Q = 4, C_L2Q_LINE = 5,
@@ -49,10 +52,16 @@ enum {
   C_NEXT = 11, C_READY = 12, C_NLINE = 13, C_FLINE = 14, C_FDST = 15,
   C_RCV = 16,   /* flits of the awaited reply received so far */
   C_NSENT = 17, /* flits of this tile's reply already injected by its home */
-  C_WORDS = 18
+  C_DLINE = 18, /* hit under miss: line of the op waiting for the outstanding miss, -1 = none */
+  C_DISSUE = 19,/* hit under miss: the waiting op's issue cycle */
+  C_WORDS = 20
 };
-/* flit record (4 words) */
-enum { F_DST = 0, F_INJ = 1, F_SRC = 2, F_INFO = 3, F_WORDS = 4 };
+/* flit record: destination, injection cycle, source, kind<<30 | line, and the number of times
+   the flit has been deflected (kept for the AGE_DEFLECT variant, 0 otherwise); the first four
+   words are the flit as the canonical dump shows it */
+enum { F_DST = 0, F_INJ = 1, F_SRC = 2, F_INFO = 3, F_AGE = 4, F_WORDS = 5 };
+#define SLOT_WORDS (4 * F_WORDS) /* the four input slots of a tile */
+#define AGE_LIMIT 65535          /* deflections a flit may take before the run is declared livelocked */
 #define LINE_MASK 0x3FFFFFFF
 #define DUMP_MAGIC 0x4E4F4353
 #define DUMP_HEADER 16
@@ -66,15 +75,15 @@ struct oracle_sim {
   int32_t zk;
   uint32_t* zs;          /* shared-region quantile table, zk+1 entries */
   uint32_t* zp;          /* private-region quantile table */
-  int32_t* link[2];      /* [N][4 ports][4 words]: input slots, double buffered by cycle parity */
+  int32_t* link[2];      /* [N][4 ports][F_WORDS]: input slots, double buffered by cycle parity */
   int32_t* core;         /* [N][C_WORDS] */
   int32_t* l1;           /* [N][S1][W1], most recently used first, -1 = invalid */
   int32_t* l2;           /* [N][S2][W2] */
   int64_t stats[OS_COUNT];
   /* scratch of one cycle */
   uint32_t* rnd;         /* [N][4] the tile's main draw of this cycle */
-  int32_t* outp;         /* [N][4 ports][4 words] flits routed out this cycle */
-  int32_t* ej;           /* [N][4 words] flit ejected this cycle (dst < 0: none) */
+  int32_t* outp;         /* [N][4 ports][F_WORDS] flits routed out this cycle */
+  int32_t* ej;           /* [N][F_WORDS] flit ejected this cycle (dst < 0: none) */
   int32_t* oldest_ok;    /* [N] 1 if the router's oldest flit was ejected or moved productively */
   int32_t check;
   int32_t bad;
@@ -211,24 +220,41 @@ static int32_t list_pop(oracle_sim* s, int32_t home, int head_w, int tail_w) {
   return rq;
 }
 
+/* The line a drawn op addresses: the shared region, or the tile's private region (the
+   synthetic stand-in for the per-core address traces of Sec. 6.2.3). */
+static int32_t drawn_line(const oracle_sim* s, int32_t t, const uint32_t* r) {
+  if (s->cfg.private_lines > 0 && r[1] >= s->cfg.shared_thr)
+    return s->cfg.shared_lines + t * s->cfg.private_lines + zipf_rank(s->zp, r[2]);
+  return zipf_rank(s->zs, r[2]);
+}
+
+/* Cycles between making a flit and its first chance to enter the network: 1 when the
+   router's injection register sits in between (INJECT_DELAY), else 0. */
+static int32_t inject_delay(const oracle_sim* s) { return (s->cfg.flags & ORACLE_FLAG_INJECT_DELAY) ? 1 : 0; }
+
 /* ---- phase one: memory access (Sec. 7.1, work in phase one; Sec. 3.5) -------------- */
 static void phase_memory(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
   int32_t* k = s->core + (size_t)t * C_WORDS;
   const uint32_t* r = s->rnd + (size_t)t * 4;
+  const int32_t delay = inject_delay(s);
 
-  /* home L2 slice serves the request that was ejected here in the previous cycle */
+  /* home L2 slice serves the request that was ejected here in the previous cycle; the reply
+     can leave once the block is there (at once on a hit, after mem_lat on a miss) */
   if (k[C_L2Q] >= 0) {
     int32_t rq = k[C_L2Q], line = k[C_L2Q_LINE];
-    if (l2_lookup(s, t, line)) list_append(s, t, C_HIT_H, C_HIT_T, rq, (int32_t)c, line);
-    else list_append(s, t, C_MISS_H, C_MISS_T, rq, (int32_t)(c + s->cfg.mem_lat), line);
+    if (l2_lookup(s, t, line)) list_append(s, t, C_HIT_H, C_HIT_T, rq, (int32_t)(c + delay), line);
+    else list_append(s, t, C_MISS_H, C_MISS_T, rq, (int32_t)(c + s->cfg.mem_lat + delay), line);
     k[C_L2Q] = -1;
     k[C_L2Q_LINE] = -1;
   }
 
-  switch (k[C_STATE]) {
+  const int state = k[C_STATE];
+  int l1_used = 0; /* the L1 serves at most one access per cycle */
+  switch (state) {
     case ST_FILL:
       if (k[C_WAKE] == (int32_t)c) {            /* block arrives: L1 fill, op complete */
+        l1_used = 1;
         int32_t* set = l1_set(s, t, k[C_LINE]);
         cache_touch(set, s->cfg.l1_ways, k[C_LINE], 1);
         if (s->check) check_set(s, set, s->cfg.l1_ways, "L1", t);
@@ -254,26 +280,33 @@ static void phase_memory(oracle_sim* s, int32_t t) {
       break;
     case ST_IDLE: {
       int issue = 0;
-      int32_t line = 0;
-      if (k[C_FLINE] >= 0) {
+      int32_t line = 0, issued = (int32_t)c;
+      if (k[C_DLINE] >= 0) {                    /* the op that waited for the last miss */
+        line = k[C_DLINE];
+        issued = k[C_DISSUE];
+        k[C_DLINE] = -1;
+        k[C_DISSUE] = 0;
+        issue = 2;
+      } else if (k[C_FLINE] >= 0) {
         line = k[C_FLINE];
         k[C_FLINE] = -1;
         issue = 1;
       } else if (r[0] < s->cfg.op_thr) {
         issue = 1;
-        if (s->cfg.private_lines > 0 && r[1] >= s->cfg.shared_thr)
-          line = s->cfg.shared_lines + t * s->cfg.private_lines + zipf_rank(s->zp, r[2]);
-        else
-          line = zipf_rank(s->zs, r[2]);
+        line = drawn_line(s, t, r);
       }
       if (issue) {
-        s->stats[OS_OPS_ISSUED]++;
+        if (issue == 1) s->stats[OS_OPS_ISSUED]++;
+        l1_used = 1;
         k[C_LINE] = line;
-        k[C_ISSUE] = (int32_t)c;
+        k[C_ISSUE] = issued;
         int32_t* set = l1_set(s, t, line);
         if (cache_touch(set, s->cfg.l1_ways, line, 0)) {
+          int64_t lat = c - issued;
           s->stats[OS_L1_HIT]++;
           s->stats[OS_OPS_DONE]++;
+          s->stats[OS_OP_LAT] += lat;
+          if (lat > s->stats[OS_OP_LAT_MAX]) s->stats[OS_OP_LAT_MAX] = lat;
         } else {
           s->stats[OS_L1_MISS]++;
           k[C_STATE] = ST_L1MISS;
@@ -285,19 +318,43 @@ static void phase_memory(oracle_sim* s, int32_t t) {
     default:
       break;
   }
+
+  /* Hit under miss (Sec. 3.5): while its miss is outstanding the core keeps drawing; a hit
+     completes at once, a miss waits (no miss under a miss) and stops further issue until the
+     outstanding block is filled.  Its L1 outcome is counted when it is looked up again. */
+  if ((s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS) && state != ST_IDLE && !l1_used && k[C_DLINE] < 0 &&
+      r[0] < s->cfg.op_thr) {
+    int32_t line = drawn_line(s, t, r);
+    s->stats[OS_OPS_ISSUED]++;
+    if (cache_touch(l1_set(s, t, line), s->cfg.l1_ways, line, 0)) {
+      s->stats[OS_L1_HIT]++;
+      s->stats[OS_OPS_DONE]++;
+    } else {
+      k[C_DLINE] = line;
+      k[C_DISSUE] = (int32_t)c;
+    }
+  }
 }
 
 /* ---- phase two: oldest-first deflection arbitration (Sec. 4.3, Sec. 6.2.1) ---------- */
-/* Flits are considered oldest first (key: injection cycle, then source tile).  Each takes
-   the eject link if it is destined here and the link is still free, else its first free
-   productive port (X before Y), else the lowest-numbered free port (a deflection). */
+/* Flit a goes before flit b: oldest first, by injection cycle, then source tile; with
+   deflection counts (AGE_DEFLECT) the more deflected flit first, then as before. */
+static int goes_before(int a, int b, const int32_t* inj, const int32_t* src, const int32_t* age) {
+  if (age && age[a] != age[b]) return age[a] > age[b];
+  if (inj[a] != inj[b]) return inj[a] < inj[b];
+  return src[a] < src[b];
+}
+
+/* Flits are considered in priority order.  Each takes the eject link if it is destined here
+   and the link is still free, else its first free productive port (X before Y), else the
+   lowest-numbered free port (a deflection). */
 static int arbitrate_router(int32_t W, int32_t H, int32_t t, int n, const int32_t* dst, const int32_t* inj,
-                            const int32_t* src, int32_t* port, int32_t* defl) {
+                            const int32_t* src, const int32_t* age, int32_t* port, int32_t* defl) {
   int order[8];
   for (int i = 0; i < n; ++i) order[i] = i;
-  for (int i = 1; i < n; ++i) {                 /* insertion sort by (inj, src) */
+  for (int i = 1; i < n; ++i) {                 /* insertion sort by priority */
     int v = order[i], j = i - 1;
-    while (j >= 0 && (inj[order[j]] > inj[v] || (inj[order[j]] == inj[v] && src[order[j]] > src[v]))) {
+    while (j >= 0 && goes_before(v, order[j], inj, src, age)) {
       order[j + 1] = order[j];
       --j;
     }
@@ -335,9 +392,9 @@ static int arbitrate_router(int32_t W, int32_t H, int32_t t, int n, const int32_
 }
 
 int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, const int32_t* dst, const int32_t* inj,
-                     const int32_t* src, int32_t* port, int32_t* deflected) {
+                     const int32_t* src, const int32_t* age, int32_t* port, int32_t* deflected) {
   if (width < 1 || height < 1 || tile < 0 || tile >= width * height || n < 0 || n > 5) return ORACLE_EINVAL;
-  return arbitrate_router(width, height, tile, n, dst, inj, src, port, deflected);
+  return arbitrate_router(width, height, tile, n, dst, inj, src, age, port, deflected);
 }
 
 /* Phase two of tile t: gather arrivals, add at most one injected flit when an input is
@@ -349,23 +406,24 @@ int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, con
 static void phase_route(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
   int32_t* k = s->core + (size_t)t * C_WORDS;
-  const int32_t* in = s->link[c & 1] + (size_t)t * 16;
+  const int32_t* in = s->link[c & 1] + (size_t)t * SLOT_WORDS;
   int32_t fl[5][F_WORDS];
   int n = 0, deg = 0;
   for (int p = 0; p < 4; ++p) {
     if (port_valid(s, t, p)) deg++;
-    if (in[p * 4 + F_DST] >= 0) {
-      memcpy(fl[n], in + p * 4, sizeof fl[n]);
+    if (in[p * F_WORDS + F_DST] >= 0) {
+      memcpy(fl[n], in + p * F_WORDS, sizeof fl[n]);
       n++;
     }
   }
   int arrivals = n;
 
-  /* injection candidate: ready miss reply, hit reply, own request, test flit, background */
+  /* injection candidate: ready miss reply, ready hit reply, own request (made at least
+     inject_delay cycles ago), test flit, background */
   int cls = -1;
   if (k[C_MISS_H] >= 0 && s->core[(size_t)k[C_MISS_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 0;
-  else if (k[C_HIT_H] >= 0) cls = 1;
-  else if (k[C_STATE] == ST_SEND) cls = 2;
+  else if (k[C_HIT_H] >= 0 && s->core[(size_t)k[C_HIT_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 1;
+  else if (k[C_STATE] == ST_SEND && k[C_WAKE] + inject_delay(s) <= (int32_t)c) cls = 2;
   else if (k[C_FDST] >= 0) cls = 3;
   else if (k[C_BG] > 0) cls = 4;
   if (cls >= 0 && arrivals >= deg) {
@@ -376,6 +434,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
     int32_t* f = fl[n++];
     f[F_INJ] = (int32_t)c;
     f[F_SRC] = t;
+    f[F_AGE] = 0;
     if (cls == 0 || cls == 1) {
       int32_t rq = k[cls == 0 ? C_MISS_H : C_HIT_H];
       int32_t* node = s->core + (size_t)rq * C_WORDS;
@@ -410,27 +469,34 @@ static void phase_route(oracle_sim* s, int32_t t) {
     }
   }
 
-  int32_t dst[5], inj[5], src[5], port[5], defl[5];
-  for (int i = 0; i < n; ++i) { dst[i] = fl[i][F_DST]; inj[i] = fl[i][F_INJ]; src[i] = fl[i][F_SRC]; }
-  int rc = arbitrate_router(s->W, s->H, t, n, dst, inj, src, port, defl);
+  const int aged = (s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT) != 0;
+  int32_t dst[5], inj[5], src[5], age[5], port[5], defl[5];
+  for (int i = 0; i < n; ++i) {
+    dst[i] = fl[i][F_DST]; inj[i] = fl[i][F_INJ]; src[i] = fl[i][F_SRC]; age[i] = fl[i][F_AGE];
+  }
+  int rc = arbitrate_router(s->W, s->H, t, n, dst, inj, src, aged ? age : NULL, port, defl);
   if (rc != ORACLE_OK && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "router %d: no port", t); }
 
-  int32_t* out = s->outp + (size_t)t * 16;
-  int32_t* ej = s->ej + (size_t)t * 4;
-  for (int i = 0; i < 16; ++i) out[i] = -1;
-  for (int i = 0; i < 4; ++i) ej[i] = -1;
-  int oldest = -1;
+  int32_t* out = s->outp + (size_t)t * SLOT_WORDS;
+  int32_t* ej = s->ej + (size_t)t * F_WORDS;
+  for (int i = 0; i < SLOT_WORDS; ++i) out[i] = -1;
+  for (int i = 0; i < F_WORDS; ++i) ej[i] = -1;
+  int first = -1; /* the router's highest-priority flit */
   for (int i = 0; i < n; ++i) {
-    if (oldest < 0 || inj[i] < inj[oldest] || (inj[i] == inj[oldest] && src[i] < src[oldest])) oldest = i;
+    if (first < 0 || goes_before(i, first, inj, src, aged ? age : NULL)) first = i;
     if (port[i] == PX) {
       memcpy(ej, fl[i], sizeof fl[i]);
     } else if (port[i] >= 0) {
-      memcpy(out + port[i] * 4, fl[i], sizeof fl[i]);
+      if (defl[i] && aged) {                    /* Sec. 6.2.1: a deflected flit ages by one */
+        if (fl[i][F_AGE] >= AGE_LIMIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "deflection count overflow at %d", t); }
+        fl[i][F_AGE]++;
+      }
+      memcpy(out + port[i] * F_WORDS, fl[i], sizeof fl[i]);
       s->stats[OS_TRAVERSALS]++;
       if (defl[i]) s->stats[OS_DEFLECTIONS]++;
     }
   }
-  s->oldest_ok[t] = oldest < 0 || !defl[oldest];
+  s->oldest_ok[t] = first < 0 || !defl[first];
 }
 
 /* ---- phase three: traversal, ejection, generation (Sec. 7.1, work in phase three) --- */
@@ -438,13 +504,13 @@ static void phase_move(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
   int32_t* k = s->core + (size_t)t * C_WORDS;
   int32_t* nxt = s->link[(c + 1) & 1];
-  const int32_t* out = s->outp + (size_t)t * 16;
+  const int32_t* out = s->outp + (size_t)t * SLOT_WORDS;
   for (int p = 0; p < 4; ++p) {
     if (!port_valid(s, t, p)) continue;
     int32_t nb = neighbour(s, t, p);
-    memcpy(nxt + (size_t)nb * 16 + opposite(p) * 4, out + p * 4, 4 * sizeof(int32_t));
+    memcpy(nxt + (size_t)nb * SLOT_WORDS + opposite(p) * F_WORDS, out + p * F_WORDS, F_WORDS * sizeof(int32_t));
   }
-  const int32_t* ej = s->ej + (size_t)t * 4;
+  const int32_t* ej = s->ej + (size_t)t * F_WORDS;
   if (ej[F_DST] >= 0) {
     int kind = (int)((uint32_t)ej[F_INFO] >> 30);
     int64_t lat = c - ej[F_INJ];
@@ -485,17 +551,29 @@ static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-/* Digest of the words tile t owns after cycle c: its 16 input-slot words for the next cycle
-   and its core record.  The queue-node words (next, ready, line, flits sent) are written by
-   the requester's home, not by the tile, so they are left out (zeroed); they are compared
-   through the canonical dump instead. */
+/* Digest of the words tile t owns after cycle c: the four words of each of its input slots
+   for the next cycle and its core record, then, in the AGE_DEFLECT variant, the deflection
+   counts of those slots' flits packed in pairs (16 bits each, 0 for an empty slot).  The
+   queue-node words (next, ready, line, flits sent) are written by the requester's home, not
+   by the tile, so they are left out (zeroed); they are compared through the canonical dump
+   instead. */
 static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
-  int32_t w[16 + C_WORDS];
-  memcpy(w, s->link[(c + 1) & 1] + (size_t)t * 16, 16 * sizeof(int32_t));
+  int32_t w[16 + C_WORDS + 2];
+  const int32_t* slots = s->link[(c + 1) & 1] + (size_t)t * SLOT_WORDS;
+  int32_t age[4];
+  for (int p = 0; p < 4; ++p) {
+    memcpy(w + 4 * p, slots + p * F_WORDS, 4 * sizeof(int32_t));
+    age[p] = slots[p * F_WORDS + F_DST] >= 0 ? slots[p * F_WORDS + F_AGE] : 0;
+  }
   memcpy(w + 16, s->core + (size_t)t * C_WORDS, C_WORDS * sizeof(int32_t));
   w[16 + C_NEXT] = w[16 + C_READY] = w[16 + C_NLINE] = w[16 + C_NSENT] = 0;
+  int nw = 16 + C_WORDS;
+  if (s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT) {
+    w[nw++] = (int32_t)((uint32_t)age[0] | ((uint32_t)age[1] << 16));
+    w[nw++] = (int32_t)((uint32_t)age[2] | ((uint32_t)age[3] << 16));
+  }
   uint64_t h = mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)t);
-  for (int i = 0; i < (16 + C_WORDS) / 2; ++i)
+  for (int i = 0; i < nw / 2; ++i)
     h = mix64(h ^ (((uint64_t)(uint32_t)w[2 * i] << 32) | (uint32_t)w[2 * i + 1]));
   return h;
 }
@@ -510,7 +588,7 @@ static void check_cycle(oracle_sim* s) {
   memset(s->scratch, 0, (size_t)s->N * 2 * sizeof(int32_t));
   for (int32_t t = 0; t < s->N; ++t) {
     for (int p = 0; p < 4; ++p) {
-      const int32_t* f = nxt + (size_t)t * 16 + p * 4;
+      const int32_t* f = nxt + (size_t)t * SLOT_WORDS + p * F_WORDS;
       if (f[F_DST] < 0) continue;
       occupied++;
       int kind = (int)((uint32_t)f[F_INFO] >> 30);
@@ -518,7 +596,7 @@ static void check_cycle(oracle_sim* s) {
       if (kind == K_REPLY) rep_to[f[F_DST]]++;
       if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
     }
-    if (!s->oldest_ok[t] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "oldest flit deflected at %d", t); }
+    if (!s->oldest_ok[t] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "first flit deflected at %d", t); }
   }
   int64_t inj = s->stats[OS_INJ_REQ] + s->stats[OS_INJ_REPLY] + s->stats[OS_INJ_BG];
   int64_t ejc = s->stats[OS_EJ_REQ] + s->stats[OS_EJ_REPLY] + s->stats[OS_EJ_BG];
@@ -608,6 +686,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   if ((int64_t)cfg->shared_lines + N * cfg->private_lines > (int64_t)LINE_MASK + 1) return ORACLE_EINVAL;
   if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
   if (cfg->reply_flits < 0 || cfg->reply_flits > 16) return ORACLE_EINVAL;
+  if (cfg->flags & ~(ORACLE_FLAG_AGE_DEFLECT | ORACLE_FLAG_HIT_UNDER_MISS | ORACLE_FLAG_INJECT_DELAY)) return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
   s->cfg = *cfg;
@@ -618,14 +697,14 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->zk = zk;
   s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
   s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
-  s->link[0] = (int32_t*)malloc((size_t)N * 16 * 4);
-  s->link[1] = (int32_t*)malloc((size_t)N * 16 * 4);
+  s->link[0] = (int32_t*)malloc((size_t)N * SLOT_WORDS * 4);
+  s->link[1] = (int32_t*)malloc((size_t)N * SLOT_WORDS * 4);
   s->core = (int32_t*)malloc((size_t)N * C_WORDS * 4);
   s->l1 = (int32_t*)malloc((size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
   s->l2 = (int32_t*)malloc((size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
   s->rnd = (uint32_t*)malloc((size_t)N * 4 * 4);
-  s->outp = (int32_t*)malloc((size_t)N * 16 * 4);
-  s->ej = (int32_t*)malloc((size_t)N * 4 * 4);
+  s->outp = (int32_t*)malloc((size_t)N * SLOT_WORDS * 4);
+  s->ej = (int32_t*)malloc((size_t)N * F_WORDS * 4);
   s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
   s->scratch = (int32_t*)malloc((size_t)N * 2 * 4);
   if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
@@ -636,14 +715,15 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   memcpy(s->zs, zs, (size_t)(zk + 1) * 4);
   if (zp) memcpy(s->zp, zp, (size_t)(zk + 1) * 4);
   else memcpy(s->zp, zs, (size_t)(zk + 1) * 4);
-  memset(s->link[0], 0xFF, (size_t)N * 16 * 4);
-  memset(s->link[1], 0xFF, (size_t)N * 16 * 4);
+  memset(s->link[0], 0xFF, (size_t)N * SLOT_WORDS * 4);
+  memset(s->link[1], 0xFF, (size_t)N * SLOT_WORDS * 4);
   memset(s->core, 0xFF, (size_t)N * C_WORDS * 4);
   for (int64_t t = 0; t < N; ++t) {
     s->core[t * C_WORDS + C_STATE] = ST_IDLE;
     s->core[t * C_WORDS + C_BG] = 0;
     s->core[t * C_WORDS + C_RCV] = 0;
     s->core[t * C_WORDS + C_NSENT] = 0;
+    s->core[t * C_WORDS + C_DISSUE] = 0;
   }
   memset(s->l1, 0xFF, (size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
   memset(s->l2, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
@@ -668,21 +748,28 @@ int64_t oracle_cycle(const oracle_sim* s) { return s ? s->cycle : -1; }
 
 size_t oracle_dump_words(const oracle_sim* s) {
   size_t N = (size_t)s->N;
-  return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways + 2 * OS_COUNT;
+  return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways +
+         2 * OS_COUNT + N * 4;
 }
 
-/* Canonical state: header {magic, version 2, W, H, cycle (low, high), L1 sets, L1 ways, L2 sets,
-   L2 ways, reply flits, core-record words, 0...}, input slots of the next cycle, core records,
-   L1 and L2 tags (most recently used first), statistics as (low, high) word pairs. */
+/* Canonical state (format version 3): header {magic, 3, W, H, cycle (low, high), L1 sets,
+   L1 ways, L2 sets, L2 ways, reply flits, core-record words, variant flags, 0...}, the four
+   words of each input slot of the next cycle, core records, L1 and L2 tags (most recently used
+   first), statistics as (low, high) word pairs, and the deflection count of each input slot's
+   flit (0 for an empty slot and outside the AGE_DEFLECT variant). */
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
-  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 2, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
+  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 3, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
                               s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
-                              C_WORDS, 0, 0, 0, 0};
+                              C_WORDS, s->cfg.flags, 0, 0, 0};
   memcpy(buf, hdr, sizeof hdr);
   o += DUMP_HEADER;
-  memcpy(buf + o, s->link[s->cycle & 1], N * 16 * 4); o += N * 16;
+  const int32_t* slots = s->link[s->cycle & 1];
+  for (size_t i = 0; i < N * 4; ++i) {
+    memcpy(buf + o, slots + i * F_WORDS, 4 * sizeof(int32_t));
+    o += 4;
+  }
   memcpy(buf + o, s->core, N * C_WORDS * 4); o += N * C_WORDS;
   size_t n1 = N * s->cfg.l1_sets * s->cfg.l1_ways, n2 = N * s->cfg.l2_sets * s->cfg.l2_ways;
   memcpy(buf + o, s->l1, n1 * 4); o += n1;
@@ -691,19 +778,24 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
     buf[o++] = (int32_t)(uint32_t)(uint64_t)s->stats[i];
     buf[o++] = (int32_t)((uint64_t)s->stats[i] >> 32);
   }
+  for (size_t i = 0; i < N * 4; ++i) buf[o++] = slots[i * F_WORDS + F_DST] >= 0 ? slots[i * F_WORDS + F_AGE] : 0;
   return ORACLE_OK;
 }
 
 int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
-  if (buf[0] != DUMP_MAGIC || buf[1] != 2 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
+  if (buf[0] != DUMP_MAGIC || buf[1] != 3 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
       buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
-      buf[11] != C_WORDS)
+      buf[11] != C_WORDS || buf[12] != s->cfg.flags)
     return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = DUMP_HEADER;
   s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
-  memcpy(s->link[s->cycle & 1], buf + o, N * 16 * 4); o += N * 16;
-  memset(s->link[(s->cycle + 1) & 1], 0xFF, N * 16 * 4);
+  int32_t* slots = s->link[s->cycle & 1];
+  for (size_t i = 0; i < N * 4; ++i) {
+    memcpy(slots + i * F_WORDS, buf + o, 4 * sizeof(int32_t));
+    o += 4;
+  }
+  memset(s->link[(s->cycle + 1) & 1], 0xFF, N * SLOT_WORDS * 4);
   memcpy(s->core, buf + o, N * C_WORDS * 4); o += N * C_WORDS;
   size_t n1 = N * s->cfg.l1_sets * s->cfg.l1_ways, n2 = N * s->cfg.l2_sets * s->cfg.l2_ways;
   memcpy(s->l1, buf + o, n1 * 4); o += n1;
@@ -712,6 +804,7 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
     s->stats[i] = (int64_t)(((uint64_t)(uint32_t)buf[o + 1] << 32) | (uint32_t)buf[o]);
     o += 2;
   }
+  for (size_t i = 0; i < N * 4; ++i) slots[i * F_WORDS + F_AGE] = slots[i * F_WORDS + F_DST] >= 0 ? buf[o + i] : -1;
   return ORACLE_OK;
 }
 
@@ -738,10 +831,10 @@ int oracle_quiescent(const oracle_sim* s) {
   const int32_t* cur = s->link[s->cycle & 1];
   for (int32_t t = 0; t < s->N; ++t) {
     for (int p = 0; p < 4; ++p)
-      if (cur[(size_t)t * 16 + p * 4] >= 0) return 0;
+      if (cur[(size_t)t * SLOT_WORDS + p * F_WORDS] >= 0) return 0;
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
-        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0)
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0)
       return 0;
   }
   return 1;

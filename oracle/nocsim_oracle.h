@@ -34,9 +34,21 @@ typedef struct {
   uint32_t bg_thr;             /* background flit generated iff draw < bg_thr */
   int32_t shared_lines;        /* lines [0, shared_lines) form the shared region */
   int32_t private_lines;       /* per-tile private region size (0 = no private region) */
-  int32_t flags;               /* reserved, 0 */
+  int32_t flags;               /* model variants, ORACLE_FLAG_* below (0 = the base model) */
   int32_t reply_flits;         /* flits of a reply packet, 1..16 (0 counts as 1) */
 } oracle_config;
+
+/* Model variants: each bit replaces one reading of the base model by a more literal one.
+   AGE_DEFLECT: a flit's priority is the number of times it has been deflected so far (more
+     first; 0 at injection), ties by (injection cycle, source) (Sec. 4.2, Sec. 6.2.1, Sec. 7.1
+     phase two).  The base model ranks by injection cycle alone.
+   HIT_UNDER_MISS: a core with a miss outstanding keeps drawing ops; an L1 hit completes at
+     once, a second miss waits until the first is filled and is then looked up again
+     (Sec. 3.5).  The base model's core issues nothing while a miss is outstanding.
+   INJECT_DELAY: a request or reply made in a cycle can enter the network from the next cycle
+     on (the router's injection register, filled in phase three: Sec. 6.2.1, Sec. 7.1).  The
+     base model injects it in the cycle it is made. */
+enum { ORACLE_FLAG_AGE_DEFLECT = 1, ORACLE_FLAG_HIT_UNDER_MISS = 2, ORACLE_FLAG_INJECT_DELAY = 4 };
 
 enum {
   ORACLE_OK = 0,
@@ -86,10 +98,13 @@ void oracle_destroy(oracle_sim* s);
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Zipf ranks of n uniform draws through a quantile table (the sampler used in phase one). */
 void oracle_zipf_ranks(const uint32_t* table, const uint32_t* u, int64_t n, int32_t* out);
-/* Arbitration of one router: n flits given by (dst, inj, src); writes for each flit the
-   port it takes (0..3 = N,S,E,W, 4 = eject) and whether it was deflected. */
+/* Arbitration of one router: n flits given by (dst, inj, src) and, for the AGE_DEFLECT
+   variant, their deflection counts (age = NULL: the base model's injection-time priority);
+   writes for each flit the port it takes (0..3 = N,S,E,W, 4 = eject) and whether it was
+   deflected. */
 int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, const int32_t* dst,
-                     const int32_t* inj, const int32_t* src, int32_t* port, int32_t* deflected);
+                     const int32_t* inj, const int32_t* src, const int32_t* age, int32_t* port,
+                     int32_t* deflected);
 
 #ifdef __cplusplus
 }

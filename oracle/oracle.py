@@ -80,7 +80,7 @@ def lib():
         L.oracle_philox4x32_10.restype = None
         L.oracle_zipf_ranks.argtypes = [p, p, i64, p]
         L.oracle_zipf_ranks.restype = None
-        L.oracle_arbitrate.argtypes = [i32, i32, i32, i32, p, p, p, p, p]
+        L.oracle_arbitrate.argtypes = [i32, i32, i32, i32, p, p, p, p, p, p]
         _lib = L
     return _lib
 
@@ -105,15 +105,18 @@ def zipf_ranks(table: np.ndarray, u: np.ndarray) -> np.ndarray:
     return out
 
 
-def arbitrate(width, height, tile, dst, inj, src):
-    """(ports, deflected) for one router; raises ValueError when there are too few ports."""
+def arbitrate(width, height, tile, dst, inj, src, age=None):
+    """(ports, deflected) for one router (age: deflection counts for the AGE_DEFLECT priority,
+    None for injection-time priority); raises ValueError when there are too few ports."""
     n = len(dst)
     d = np.asarray(dst, dtype=np.int32)
     i = np.asarray(inj, dtype=np.int32)
     s = np.asarray(src, dtype=np.int32)
+    a = np.asarray(age, dtype=np.int32) if age is not None else None
     port = np.zeros(max(n, 1), dtype=np.int32)
     defl = np.zeros(max(n, 1), dtype=np.int32)
-    rc = lib().oracle_arbitrate(width, height, tile, n, _ptr(d), _ptr(i), _ptr(s), _ptr(port), _ptr(defl))
+    rc = lib().oracle_arbitrate(width, height, tile, n, _ptr(d), _ptr(i), _ptr(s),
+                                _ptr(a) if a is not None else None, _ptr(port), _ptr(defl))
     if rc != 0:
         raise ValueError(f"arbitrate rc={rc}")
     return port[:n].copy(), defl[:n].copy()
@@ -134,7 +137,7 @@ class OracleSim:
             l2_sets=params.l2_sets, l2_ways=params.l2_ways,
             l1_lat=params.l1_lat, mem_lat=params.mem_lat,
             op_thr=params.op_thr, shared_thr=params.shared_thr, bg_thr=params.bg_thr,
-            shared_lines=params.shared_lines, private_lines=params.private_lines, flags=0,
+            shared_lines=params.shared_lines, private_lines=params.private_lines, flags=params.flags,
             reply_flits=params.reply_flits)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(cfg), _ptr(self._zs), _ptr(self._zp), len(self._zs) - 1, C.byref(h))
@@ -196,18 +199,3 @@ class OracleSim:
 
     def quiescent(self) -> bool:
         return bool(lib().oracle_quiescent(self._h))
-
-
-def split_dump(buf: np.ndarray, params) -> dict:
-    """Views of a canonical dump: header, links [N,4,4], core [N,16], l1, l2, stats."""
-    N = params.width * params.height
-    o = 16
-    out = {"header": buf[:16]}
-    out["links"] = buf[o:o + N * 16].reshape(N, 4, 4); o += N * 16
-    out["core"] = buf[o:o + N * 16].reshape(N, 16); o += N * 16
-    n1 = N * params.l1_sets * params.l1_ways
-    out["l1"] = buf[o:o + n1].reshape(N, params.l1_sets, params.l1_ways); o += n1
-    n2 = N * params.l2_sets * params.l2_ways
-    out["l2"] = buf[o:o + n2].reshape(N, params.l2_sets, params.l2_ways); o += n2
-    out["stats"] = buf[o:o + 2 * N_STATS].copy().view(np.int64)
-    return out

@@ -25,8 +25,16 @@ ZIPF_K = 65536
 FIELDS = (
     "width", "height", "seed", "l1_sets", "l1_ways", "l2_sets", "l2_ways", "l1_lat",
     "mem_lat", "op_thr", "shared_thr", "bg_thr", "shared_lines", "private_lines",
-    "zipf_shared_s", "zipf_private_s", "reply_flits",
+    "zipf_shared_s", "zipf_private_s", "reply_flits", "flags",
 )
+
+# Model variants (bits of SimParams.flags), each a more literal reading of one passage of the
+# paper than the base model's: priority by deflection count (AGE_DEFLECT), a core that keeps
+# serving hits while its miss is outstanding (HIT_UNDER_MISS), and a flit entering the network
+# the cycle after it is made (INJECT_DELAY).
+AGE_DEFLECT = 1
+HIT_UNDER_MISS = 2
+INJECT_DELAY = 4
 
 
 def thr(p: float) -> int:
@@ -70,6 +78,7 @@ class SimParams:
     zipf_shared_s: float = 0.8
     zipf_private_s: float = 0.9
     reply_flits: int = 1      # flits per reply packet (the paper's Table 1: 4 for a remote L2 access)
+    flags: int = 0            # model variants: AGE_DEFLECT | HIT_UNDER_MISS | INJECT_DELAY
 
     @property
     def tiles(self) -> int:

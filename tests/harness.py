@@ -22,7 +22,7 @@ STAT = {
 CORE = {"state": 0, "wake": 1, "line": 2, "issue": 3, "l2q": 4, "l2q_line": 5, "hit_head": 6,
         "hit_tail": 7, "miss_head": 8, "miss_tail": 9, "bg_pending": 10, "node_next": 11,
         "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15, "reply_flits_received": 16,
-        "node_flits_sent": 17}
+        "node_flits_sent": 17, "deferred_line": 18, "deferred_issue": 19}
 
 
 def load_golden(name):
@@ -41,8 +41,39 @@ def split_dump(buf, params):
     out["l1"] = buf[o:o + n1].reshape(N, params.l1_sets, params.l1_ways); o += n1
     n2 = N * params.l2_sets * params.l2_ways
     out["l2"] = buf[o:o + n2].reshape(N, params.l2_sets, params.l2_ways); o += n2
-    out["stats"] = buf[o:o + 96].copy().view(np.int64)
+    out["stats"] = buf[o:o + 96].copy().view(np.int64); o += 96
+    out["ages"] = buf[o:o + N * 4].reshape(N, 4)   # deflection count of each input slot's flit
     return out
+
+
+def check_router_rules(w, h, tile, dst, order, port, defl):
+    """The arbitration rules of one router (Sec. 4.3, Sec. 6.2.1), given the priority order of
+    its flits: distinct ports on the mesh; a destined flit ejects if no flit before it did;
+    otherwise its first free productive port, X before Y; otherwise the lowest-numbered free
+    port, counted as a deflection; so the first flit is never deflected."""
+    x, y = tile % w, tile // w
+    valid = [y > 0, y < h - 1, x < w - 1, x > 0]
+    used = set()
+    for rank, i in enumerate(order):
+        p = int(port[i])
+        assert p not in used, "two flits on one port"
+        assert p == 4 or valid[p], "flit sent off the mesh"
+        used.add(p)
+        dx, dy = dst[i] % w - x, dst[i] // w - y
+        prefs = ([2] if dx > 0 else [3] if dx < 0 else []) + ([1] if dy > 0 else [0] if dy < 0 else [])
+        taken_before = {int(port[j]) for j in order[:rank]}
+        if dst[i] == tile and 4 not in taken_before:
+            assert p == 4 and not defl[i], "destined flit with a free eject must eject"
+            continue
+        assert p != 4, "only the first destined flit ejects"
+        free_prefs = [q for q in prefs if q not in taken_before]
+        if free_prefs:
+            assert p == free_prefs[0] and not defl[i], "first free productive port, X before Y"
+        else:
+            free = [q for q in range(4) if valid[q] and q not in taken_before]
+            assert p == free[0] and defl[i], "deflection to the lowest free port"
+    if order:
+        assert not defl[order[0]], "the first flit is never deflected"
 
 
 def quiet_params(width, height, **kw):

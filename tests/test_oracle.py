@@ -18,7 +18,8 @@ import pytest
 
 from oracle import oracle as O
 from paper_1508_03235_amd import workload as W
-from tests.harness import (STAT, load_golden, quiet_params, run_flit_trace, run_op_trace, split_dump, CORE)
+from tests.harness import (STAT, load_golden, quiet_params, run_flit_trace, run_op_trace, split_dump, CORE,
+                           check_router_rules)
 
 
 def make_oracle(p):
@@ -117,30 +118,8 @@ def _check_arbitration(w, h, tile, flits):
     inj = [f[1] for f in flits]
     src = [f[2] for f in flits]
     port, defl = O.arbitrate(w, h, tile, dst, inj, src)
-    x, y = tile % w, tile // w
-    valid = [y > 0, y < h - 1, x < w - 1, x > 0]
     order = sorted(range(len(flits)), key=lambda i: (inj[i], src[i]))
-    used = set()
-    for rank, i in enumerate(order):
-        p = int(port[i])
-        assert p not in used, "two flits on one port"
-        assert p == 4 or valid[p], "flit sent off the mesh"
-        used.add(p)
-        dx, dy = dst[i] % w - x, dst[i] // w - y
-        prefs = ([2] if dx > 0 else [3] if dx < 0 else []) + ([1] if dy > 0 else [0] if dy < 0 else [])
-        taken_before = {int(port[j]) for j in order[:rank]}
-        if dst[i] == tile and 4 not in taken_before:
-            assert p == 4 and not defl[i], "destined flit with a free eject must eject"
-            continue
-        assert p != 4, "only the oldest destined flit ejects"
-        free_prefs = [q for q in prefs if q not in taken_before]
-        if free_prefs:
-            assert p == free_prefs[0] and not defl[i], "first free productive port, X before Y"
-        else:
-            free = [q for q in range(4) if valid[q] and q not in taken_before]
-            assert p == free[0] and defl[i], "deflection to the lowest free port"
-    if flits:
-        assert not defl[order[0]], "the oldest flit is never deflected"
+    check_router_rules(w, h, tile, dst, order, port, defl)
 
 
 def test_arbitration_bruteforce():
