@@ -59,10 +59,24 @@ typedef struct {
   int32_t shared_lines;       /* shared region = lines [0, shared_lines) */
   int32_t private_lines;      /* per-tile private region (0 = none); shared_lines +
                                  width*height*private_lines must be <= 2^30 */
-  int32_t flags;              /* 0 */
+  int32_t flags;              /* model variants, SIM_FLAG_* (0 = the base model) */
   int32_t reply_flits;        /* flits of a reply packet, 1..16 (0 counts as 1); requests and
                                  background flits are one flit */
 } sim_config;
+
+/* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
+   more literal reading of the paper; chips with any of them run on the general kernel.
+   AGE_DEFLECT: a flit's priority is the number of times it has been deflected (more first,
+     0 at injection; Sec. 4.2, Sec. 6.2.1, Sec. 7.1 phase two), ties by (injection cycle,
+     source).  The base model ranks by (injection cycle, source) alone.  A flit deflected
+     65,536 times stops the run with SIM_EINVARIANT.
+   HIT_UNDER_MISS: a core with a miss outstanding keeps drawing ops; an L1 hit completes at
+     once, a second miss is held and looked up again the cycle after the first is filled,
+     its latency counted from its first issue (Sec. 3.5).
+   INJECT_DELAY: requests and replies pass through the router's injection register and can
+     enter the network only from the cycle after they are made (Sec. 6.2.1, Sec. 7.1 phase
+     three). */
+enum { SIM_FLAG_AGE_DEFLECT = 1, SIM_FLAG_HIT_UNDER_MISS = 2, SIM_FLAG_INJECT_DELAY = 4 };
 
 /* Statistics: 48 int64 counters (index = position in `v`).  Latencies are in cycles from
    injection to ejection; op latency from issue to L1 fill. */
@@ -114,17 +128,21 @@ int64_t sim_cycle(const sim_t* h);
 /* Statistics of the chip (synchronises). */
 int sim_stats(sim_t* h, sim_stats_t* out);
 
-/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 1, width,
-   height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, 0...}, then per tile the 4
-   input slots of the next cycle ({dst (-1 = empty), inject cycle, source, kind<<30 | line}),
-   then per tile 16 core words {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail,
-   miss_head, miss_tail, bg_pending, node_next, node_ready, node_line, force_line,
-   force_dst}, then L1 and L2 tags per tile per set (most recently used first, -1 invalid),
-   then the 48 statistics as (low, high) word pairs.  sim_dump_words() gives the size in
-   int32 words. */
+/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 3, width,
+   height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, reply_flits (>= 1),
+   core-record words (20), flags, 0...}, then per tile the 4 input slots of the next cycle
+   ({dst (-1 = empty), inject cycle, source, kind<<30 | line}), then per tile 20 core words
+   {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail, miss_head, miss_tail,
+   bg_pending, node_next, node_ready, node_line, force_line, force_dst, reply flits received,
+   node flits sent, held line (-1 = none), held issue cycle}, then L1 and L2 tags per tile per
+   set (most recently used first, -1 invalid), then the 48 statistics as (low, high) word
+   pairs, then per tile the deflection counts of the 4 input slots' flits (0 when empty or
+   without AGE_DEFLECT).  sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);
-/* Restores a canonical state produced by sim_dump (checkpoint / resume). */
+/* Restores a canonical state produced by sim_dump (checkpoint / resume).  EINVAL when the
+   header does not match the chip (shape, caches, reply_flits, flags) or a word is out of
+   range. */
 int sim_load(sim_t* h, const int32_t* host_buf, size_t words);
 
 /* Test hooks (synchronise): make `tile` issue a memory op on `line` at its next idle cycle;

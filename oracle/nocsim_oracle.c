@@ -805,6 +805,11 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
     o += 2;
   }
   for (size_t i = 0; i < N * 4; ++i) slots[i * F_WORDS + F_AGE] = slots[i * F_WORDS + F_DST] >= 0 ? buf[o + i] : -1;
+  /* state that only a variant can hold */
+  for (size_t i = 0; i < N * 4; ++i)
+    if (buf[o + i] != 0 && !(s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT)) return ORACLE_EINVAL;
+  for (size_t t = 0; t < N; ++t)
+    if (s->core[t * C_WORDS + C_DLINE] >= 0 && !(s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS)) return ORACLE_EINVAL;
   return ORACLE_OK;
 }
 

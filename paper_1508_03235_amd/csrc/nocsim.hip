@@ -34,8 +34,12 @@ constexpr int CORE_IDLE = 0, CORE_L1MISS = 1, CORE_SEND = 2, CORE_WAIT = 3, CORE
 constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // words of a tile's record in the canonical dump: state, wake, line, issue, l2q, l2q_line,
 // hit head/tail, miss head/tail, bg_pending, node next/ready/line, force_line, force_dst,
-// reply flits received, node flits sent
-constexpr int CORE_RECORD = 18;
+// reply flits received, node flits sent, held line, held issue cycle
+constexpr int CORE_RECORD = 20;
+constexpr int DUMP_VERSION = 3;
+// model variants (sim_config.flags); the one-tile-per-thread kernel runs the base model only
+constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
+constexpr int AGE_MAX = 0xFFFF;  // deflections a flit may take; one more stops the run (livelock)
 constexpr int ZIPF_K = 65536;
 constexpr int MAX_PATCHES = 4096;
 constexpr int FLAG_STRIDE = 32;  // ints between patch flags (128 B)
@@ -52,10 +56,12 @@ struct ChipDev {
   int32_t s1, w1, s2, w2;
   int32_t l1_lat, mem_lat, shared_lines, private_lines;
   int32_t reply_flits;       // flits per reply packet (Sec. 3.6, Table 1); 1 = single-flit replies
+  int32_t variants;          // SIM_FLAG_* model variants
+  int32_t inj_delay;         // 1 when a flit can enter the network only the cycle after it is made
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int4* link;                // [2 parity][4 port][N]
-  int4* core;                // [4][N]
+  int4* core;                // [4][N]; word group 3: force_dst, reply flits received, held line, held issue
   int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
   int32_t* l2;               // [N][s2][w2]
@@ -129,20 +135,35 @@ template <bool COH> __device__ __forceinline__ void st_i(int* p, int v) { if (CO
 
 // ---- link-slot encoding -------------------------------------------------------------------------
 // A slot holds a flit {dst, inject cycle, src, kind<<30 | line} for the cycle it is an input of.
-// Tile indices take 20 bits; the top 12 bits of the dst and src words carry that cycle
-// (mod 4096), so each 64-bit half of a slot says by itself which cycle it belongs to.  A tile on
-// a patch edge polls its neighbour's slot until both halves carry the cycle it needs: the data
-// and the "ready" signal arrive together, with no separate flag and no store drain.  An empty
-// slot has dst = src = 0xFFFFF.
+// Tile indices take bits 0-19 of the dst and src words; bits 28-31 of both carry that cycle
+// (mod 16), so each 64-bit half of a slot says by itself which cycle it belongs to.  A tile on a
+// patch edge polls its neighbour's slot until both halves carry the cycle it needs: the data and
+// the "ready" signal arrive together, with no separate flag and no store drain.  A slot is
+// rewritten every second cycle, so the stamp it can hold besides the awaited cycle c is c-2.
+// Bits 20-27 of the dst word and of the src word hold the low and high byte of the flit's
+// deflection count (priority by deflection count; 0 otherwise).  An empty slot has
+// dst = src = 0xFFFFF and count 0.
 constexpr uint32_t TILE_BITS_MASK = 0xFFFFFu;
-constexpr int STAMP_SHIFT = 20;
-constexpr uint32_t STAMP_MASK = 0xFFFu;
+constexpr int AGE_SHIFT = 20;
+constexpr int STAMP_SHIFT = 28;
+constexpr uint32_t STAMP_MASK = 0xFu;
 
 __device__ __forceinline__ int4 slot_encode(const int4& f, uint32_t stamp) {
   const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
   const bool empty = f.x < 0;  // selects, not a branch: every word of f is read either way
   return make_int4((int)((empty ? TILE_BITS_MASK : (uint32_t)f.x) | s), empty ? -1 : f.y,
                    (int)((empty ? TILE_BITS_MASK : (uint32_t)f.z) | s), empty ? -1 : f.w);
+}
+__device__ __forceinline__ int4 slot_encode_aged(const int4& f, uint32_t stamp, uint32_t age) {
+  int4 w = slot_encode(f, stamp);
+  if (f.x >= 0) {
+    w.x |= (int)((age & 0xFFu) << AGE_SHIFT);
+    w.z |= (int)((age >> 8) << AGE_SHIFT);
+  }
+  return w;
+}
+__device__ __forceinline__ uint32_t slot_age(const int4& w) {
+  return (((uint32_t)w.x >> AGE_SHIFT) & 0xFFu) | ((((uint32_t)w.z >> AGE_SHIFT) & 0xFFu) << 8);
 }
 __device__ __forceinline__ int4 slot_decode(const int4& w) {
   const uint32_t d = (uint32_t)w.x & TILE_BITS_MASK;
@@ -324,8 +345,11 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int4 k0 = gload4(&C.core[t]);          // state, wake, line, issue
   int4 k1 = gload4(&C.core[N + t]);      // l2q, l2q_line, hit_head, hit_tail
   int4 k2 = gload4(&C.core[2 * N + t]);  // miss_head, miss_tail, bg_pending, force_line
-  const int4 k3 = gload4(&C.core[3 * N + t]);  // force_dst, reply flits received
-  int fdst = k3.x, rcv = k3.y;
+  const int4 k3 = gload4(&C.core[3 * N + t]);  // force_dst, reply flits received, held op
+  int fdst = k3.x, rcv = k3.y, hline = k3.z, hissue = k3.w;
+  const bool aged = C.variants & SIM_FLAG_AGE_DEFLECT;
+  const uint32_t a0 = aged && v0 ? slot_age(w0) : 0u, a1 = aged && v1 ? slot_age(w1) : 0u;
+  const uint32_t a2 = aged && v2 ? slot_age(w2) : 0u, a3 = aged && v3 ? slot_age(w3) : 0u;
 
   if (digest) {  // state owned by t after cycle c-1: its inputs of cycle c and its core words
     unsigned long long h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
@@ -340,6 +364,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, 0, 0);
     h = mix_pair(h, k2.w, fdst);
     h = mix_pair(h, rcv, 0);    // reply flits received; the node's sent count is the home's
+    h = mix_pair(h, hline, hissue);
+    if (aged) h = mix_pair(h, (int)(a0 | (a1 << 16)), (int)(a2 | (a3 << 16)));
     dsum += h;
   }
   if (!step) return true;
@@ -364,8 +390,14 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const bool fill = k0.x == CORE_FILL && wake;
   const bool missed = k0.x == CORE_L1MISS && wake;
   const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
-  const bool forced = k0.x == CORE_IDLE && k2.w >= 0;
-  const bool drawn = k0.x == CORE_IDLE && !forced && r.x < C.op_thr;
+  const bool retry = k0.x == CORE_IDLE && hline >= 0;  // the op held back by the last miss
+  const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
+  const bool drawn_idle = k0.x == CORE_IDLE && !retry && !forced && r.x < C.op_thr;
+  // hit under miss (Sec. 3.5): a core with a miss outstanding still draws, unless the L1 is busy
+  // with the fill or an op is already held
+  const bool drawn_hum = (C.variants & SIM_FLAG_HIT_UNDER_MISS) && k0.x != CORE_IDLE && !fill && hline < 0 &&
+                         r.x < C.op_thr;
+  const bool drawn = drawn_idle || drawn_hum;
   int* setR = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1))) * C.w2;
   int* setL = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1))) * C.w2;
   int vR[8], vL[8], u[8];
@@ -375,12 +407,13 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (k1.z >= 0) nh = ld_node<MULTI>(&C.node[k1.z]);
   if (k2.x >= 0) nm = ld_node<MULTI>(&C.node[k2.x]);
   int line_op = k0.z;  // the line of the op that touches L1 this cycle (fill or issue)
-  if (forced) line_op = k2.w;
+  if (retry) line_op = hline;
+  else if (forced) line_op = k2.w;
   else if (drawn)
     line_op = (C.private_lines > 0 && r.y >= C.shared_thr) ? C.shared_lines + t * C.private_lines + zipf_rank(C.zp, r.z)
                                                            : zipf_rank(C.zs, r.z);
   int* set1 = C.l1 + ((size_t)t * C.s1 + (line_op & (C.s1 - 1))) * C.w1;
-  if (fill || forced || drawn) set_load(set1, C.w1, u);
+  if (fill || retry || forced || drawn) set_load(set1, C.w1, u);
 
   // ---- phase one: home L2 service, then the core (Sec. 7.1, phase one; Sec. 3.5) ----------
   bool dirtyR = false, dirtyL = false, dirty1 = false;
@@ -390,7 +423,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
     lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
     node_rq = rq;
-    node_ready = hit ? c : c + C.mem_lat;
+    node_ready = (hit ? c : c + C.mem_lat) + C.inj_delay;
     node_line = line;
     const int4 fresh = make_int4(-1, node_ready, line, 0);
     if (hit) {
@@ -440,22 +473,45 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       lds_add(L, SIM_ST_REQ_MADE, 1);
     }
     d0 = true;
-  } else if (forced || drawn) {
+  } else if (retry || forced || drawn_idle) {
+    const int issued = retry ? hissue : c;  // a held op counts from its first issue
+    if (retry) {
+      hline = -1;
+      hissue = 0;
+      d3 = true;
+    } else {
+      lds_add(L, SIM_ST_OPS_ISSUED, 1);
+    }
     if (forced) {
       k2.w = -1;
       d2 = true;
     }
-    lds_add(L, SIM_ST_OPS_ISSUED, 1);
     k0.z = line_op;
-    k0.w = c;
+    k0.w = issued;
     d0 = true;
     if (set_touch(u, C.w1, line_op, false, dirty1)) {
+      const unsigned long long lat = (unsigned long long)(c - issued);
       lds_add(L, SIM_ST_L1_HIT, 1);
       lds_add(L, SIM_ST_OPS_DONE, 1);
+      if (retry) {
+        lds_add(L, SIM_ST_OP_LAT, lat);
+        atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
+      }
     } else {
       lds_add(L, SIM_ST_L1_MISS, 1);
       k0.x = CORE_L1MISS;
       k0.y = c + C.l1_lat;
+    }
+  }
+  if (drawn_hum) {  // a hit completes under the miss; a miss is held until the fill
+    lds_add(L, SIM_ST_OPS_ISSUED, 1);
+    if (set_touch(u, C.w1, line_op, false, dirty1)) {
+      lds_add(L, SIM_ST_L1_HIT, 1);
+      lds_add(L, SIM_ST_OPS_DONE, 1);
+    } else {
+      hline = line_op;
+      hissue = c;
+      d3 = true;
     }
   }
 
@@ -464,8 +520,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
   int cls = -1;
   if (k2.x >= 0 && nm.y <= c) cls = 0;
-  else if (k1.z >= 0) cls = 1;
-  else if (k0.x == CORE_SEND) cls = 2;
+  else if (k1.z >= 0 && nh.y <= c) cls = 1;
+  else if (k0.x == CORE_SEND && k0.y + C.inj_delay <= c) cls = 2;
   else if (fdst >= 0) cls = 3;
   else if (k2.z > 0) cls = 4;
   if (cls >= 0 && arrivals >= deg) {
@@ -525,9 +581,13 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     }
   }
 
-  // Oldest first (key: inject cycle, then source tile; empty slots sort last).  Only
+  // Oldest first (key: inject cycle, then source tile; empty slots sort last); with priority by
+  // deflection count the count comes first, most deflected first (key 0xFFFF - count).  Only
   // (key, dst, index) tuples are sorted; the port of flit i is packed at bits 3i..3i+2 of
   // `ports` (7 = none) and each flit is stored straight into its neighbour's slot.
+  uint32_t qa0 = f0.x < 0 ? ~0u : aged ? AGE_MAX - a0 : 0u, qa1 = f1.x < 0 ? ~0u : aged ? AGE_MAX - a1 : 0u;
+  uint32_t qa2 = f2.x < 0 ? ~0u : aged ? AGE_MAX - a2 : 0u, qa3 = f3.x < 0 ? ~0u : aged ? AGE_MAX - a3 : 0u;
+  uint32_t qa4 = fi.x < 0 ? ~0u : aged ? (uint32_t)AGE_MAX : 0u;
   uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
   uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
   uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
@@ -536,7 +596,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int sd0 = f0.x, sd1 = f1.x, sd2 = f2.x, sd3 = f3.x, sd4 = fi.x;
   int si0 = 0, si1 = 1, si2 = 2, si3 = 3, si4 = 4;
 #define CSWAP(a, b)                                                                              \
-  if (qh##b < qh##a || (qh##b == qh##a && ql##b < ql##a)) {                                      \
+  if (qa##b < qa##a || (qa##b == qa##a && (qh##b < qh##a || (qh##b == qh##a && ql##b < ql##a)))) { \
+    uint32_t ta = qa##a; qa##a = qa##b; qa##b = ta;                                              \
     uint32_t th = qh##a; qh##a = qh##b; qh##b = th;                                              \
     uint32_t tl = ql##a; ql##a = ql##b; ql##b = tl;                                              \
     int td = sd##a; sd##a = sd##b; sd##b = td;                                                   \
@@ -546,7 +607,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
 #undef CSWAP
 
   const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
-  unsigned used = 0;
+  unsigned used = 0, dm = 0;  // dm: bit i set when flit i is deflected
   uint32_t ports = 0x7FFFu;
   auto assign = [&](int dst, int idx) {
     if (dst < 0) return;
@@ -563,6 +624,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       else {
         port = (unsigned)__builtin_ctz(valid & ~used & 15u);
         acc.defl++;
+        dm |= 1u << idx;
       }
       acc.trav++;
     }
@@ -585,19 +647,29 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   }
   int4 oe = EMPTY;
   const uint32_t ns = (uint32_t)(c + 1);
-  auto send = [&](const int4& f, unsigned port) {
+  // a flit's deflection count after this cycle (Sec. 6.2.1: one more when deflected here)
+  auto age_out = [&](uint32_t a, int i) -> uint32_t {
+    if (!aged) return 0u;
+    const uint32_t n = a + ((dm >> i) & 1u);
+    if (n > (uint32_t)AGE_MAX) {
+      st_coh(C.err, 4);  // a flit deflected 65,536 times: reported as an invariant failure
+      return (uint32_t)AGE_MAX;
+    }
+    return n;
+  };
+  auto send = [&](const int4& f, unsigned port, uint32_t age) {
     if (port == 4) { oe = f; return; }
     if (port > 3) return;
     const int nbr = port == 0 ? t - C.W : port == 1 ? t + C.W : port == 2 ? t + 1 : t - 1;
     const int slot = (int)(port ^ 1u);
     const bool cx = MULTI && (port == 0 ? cross[0] : port == 1 ? cross[1] : port == 2 ? cross[2] : cross[3]);
-    st_slot(&C.link[(nxt * 4 + slot) * N + nbr], slot_encode(f, ns), cx);
+    st_slot(&C.link[(nxt * 4 + slot) * N + nbr], slot_encode_aged(f, ns, age), cx);
   };
-  send(f0, ports & 7u);
-  send(f1, (ports >> 3) & 7u);
-  send(f2, (ports >> 6) & 7u);
-  send(f3, (ports >> 9) & 7u);
-  send(fi, (ports >> 12) & 7u);
+  send(f0, ports & 7u, age_out(a0, 0));
+  send(f1, (ports >> 3) & 7u, age_out(a1, 1));
+  send(f2, (ports >> 6) & 7u, age_out(a2, 2));
+  send(f3, (ports >> 9) & 7u, age_out(a3, 3));
+  send(fi, (ports >> 12) & 7u, age_out(0u, 4));
   const unsigned idle = valid & ~used;  // links that carry nothing next cycle
   const int4 E = slot_encode(EMPTY, ns);
   if (idle & 1u) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], E, MULTI && cross[0]);
@@ -642,7 +714,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (d0) gstore4(&C.core[t], k0);
   if (d1) gstore4(&C.core[N + t], k1);
   if (d2) gstore4(&C.core[2 * N + t], k2);
-  if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, 0, 0));
+  if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, hline, hissue));
 #undef GUARD
   return true;
 }
@@ -1119,6 +1191,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, 0, 0);
         h = mix_pair(h, d2.w, dfd);
         h = mix_pair(h, drcv, 0);
+        h = mix_pair(h, -1, 0);  // no op is held in the base model
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1276,7 +1349,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     gstore4(&C.core[t], k0);
     gstore4(&C.core[N + t], k1);
     gstore4(&C.core[2 * N + t], k2);
-    gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, 0, 0));
+    gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, -1, 0));
     const int par = c_done & 1;
     if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
     if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
@@ -1310,7 +1383,7 @@ __global__ void init_core(int4* core, int4* node, int N) {
     core[t] = make_int4(CORE_IDLE, -1, -1, -1);
     core[N + t] = make_int4(-1, -1, -1, -1);
     core[2 * N + t] = make_int4(-1, -1, 0, -1);
-    core[3 * N + t] = make_int4(-1, 0, 0, 0);  // forced background destination, reply flits received
+    core[3 * N + t] = make_int4(-1, 0, -1, 0);  // forced background destination, reply flits received, held op
     node[t] = make_int4(-1, -1, -1, 0);
   }
 }
@@ -1379,6 +1452,7 @@ bool config_ok(const sim_config* c) {
   if (!pow2(c->l1_sets) || !ways_ok(c->l1_ways) || !pow2(c->l2_sets) || !ways_ok(c->l2_ways)) return false;
   if (c->l1_lat < 1 || c->mem_lat < 1 || c->shared_lines < 1 || c->private_lines < 0) return false;
   if (c->reply_flits < 0 || c->reply_flits > 16) return false;
+  if (c->flags & ~VARIANT_FLAGS) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
@@ -1411,16 +1485,19 @@ Layout layout(const sim_config* c) {
   return L;
 }
 
-// host copies of the slot encoding (dump and load)
-void host_decode(const int4& w, int32_t* out) {
+// host copies of the slot encoding (dump and load); *age = the flit's deflection count
+void host_decode(const int4& w, int32_t* out, int32_t* age) {
   const uint32_t d = (uint32_t)w.x & TILE_BITS_MASK;
+  *age = 0;
   if (d == TILE_BITS_MASK) { out[0] = out[1] = out[2] = out[3] = -1; return; }
   out[0] = (int32_t)d; out[1] = w.y; out[2] = (int32_t)((uint32_t)w.z & TILE_BITS_MASK); out[3] = w.w;
+  *age = (int32_t)((((uint32_t)w.x >> AGE_SHIFT) & 0xFFu) | ((((uint32_t)w.z >> AGE_SHIFT) & 0xFFu) << 8));
 }
-int4 host_encode(const int32_t* f, uint32_t stamp) {
+int4 host_encode(const int32_t* f, uint32_t stamp, int32_t age) {
   const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
   if (f[0] < 0) return make_int4((int)(TILE_BITS_MASK | s), -1, (int)(TILE_BITS_MASK | s), -1);
-  return make_int4((int)((uint32_t)f[0] | s), f[1], (int)((uint32_t)f[2] | s), f[3]);
+  const uint32_t lo = ((uint32_t)age & 0xFFu) << AGE_SHIFT, hi = (((uint32_t)age >> 8) & 0xFFu) << AGE_SHIFT;
+  return make_int4((int)((uint32_t)f[0] | lo | s), f[1], (int)((uint32_t)f[2] | hi | s), f[3]);
 }
 
 int launch_grid_fill_i32(int32_t* p, int32_t v, size_t n, hipStream_t s) {
@@ -1502,7 +1579,7 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   const int pgx = (h->cfg.width + pw - 1) / pw, pgy = (h->cfg.height + ph - 1) / ph;
   const int np = pgx * pgy;
   if (np > h->hd.max_patches) return SIM_EINVAL;
-  if (np > 1 && np > resident_limit(block, pw * ph <= block)) return SIM_EINVAL;
+  if (np > 1 && np > resident_limit(block, pw * ph <= block && h->use_fast)) return SIM_EINVAL;
   h->hd.pw = pw;
   h->hd.ph = ph;
   h->hd.pgx = pgx;
@@ -1581,7 +1658,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  h->use_fast = true;
+  h->use_fast = (cfg->flags & VARIANT_FLAGS) == 0;  // the variants run on the general kernel
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -1610,6 +1687,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.l1_lat = cfg->l1_lat;
   d.mem_lat = cfg->mem_lat;
   d.reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
+  d.variants = cfg->flags;
+  d.inj_delay = (cfg->flags & SIM_FLAG_INJECT_DELAY) ? 1 : 0;
   d.shared_lines = cfg->shared_lines;
   d.private_lines = cfg->private_lines;
   d.stop = 0;
@@ -1662,7 +1741,10 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  h->use_fast = !generic_only;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS) == 0;
+  const int np = h->hd.n_patches;
+  if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
+  h->use_fast = use_fast;
   return SIM_OK;
 }
 
@@ -1717,7 +1799,7 @@ int sim_stats(sim_t* h, sim_stats_t* out) {
 size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
-  return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT;
+  return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4;
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
@@ -1737,16 +1819,18 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   unsigned long long st[NSTAT];
   HIPCHECK(hipMemcpyAsync(st, h->hd.stats, sizeof st, hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  const int32_t hdr[16] = {0x4E4F4353, 2, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle, (int32_t)(h->cycle >> 32),
-                           h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits, CORE_RECORD, 0, 0, 0, 0};
+  const int32_t hdr[16] = {0x4E4F4353, DUMP_VERSION, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle,
+                           (int32_t)(h->cycle >> 32), h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits,
+                           CORE_RECORD, h->hd.variants, 0, 0, 0};
   std::memcpy(buf, hdr, sizeof hdr);
+  int32_t* ages = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT;
   for (size_t t = 0; t < N; ++t)
-    for (int p = 0; p < 4; ++p) host_decode(link[p * N + t], buf + o + t * 16 + p * 4);
+    for (int p = 0; p < 4; ++p) host_decode(link[p * N + t], buf + o + t * 16 + p * 4, ages + t * 4 + p);
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
     const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], nd = node[t];
-    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x,
-                                      k2.y, k2.z, nd.x, nd.y, nd.z, k2.w, k3.x, k3.y, nd.w};
+    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y,
+                                      k2.z, nd.x, nd.y, nd.z, k2.w, k3.x, k3.y, nd.w, k3.z, k3.w};
     std::memcpy(buf + o + t * CORE_RECORD, rec, sizeof rec);
   }
   o += N * CORE_RECORD + n1 + n2;
@@ -1759,11 +1843,14 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
 
 int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (!h || !buf || words < sim_dump_words(h)) return SIM_EINVAL;
-  if (buf[0] != 0x4E4F4353 || buf[1] != 2 || buf[2] != h->hd.W || buf[3] != h->hd.H || buf[6] != h->hd.s1 ||
-      buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 || buf[10] != h->hd.reply_flits ||
-      buf[11] != CORE_RECORD)
+  if (buf[0] != 0x4E4F4353 || buf[1] != DUMP_VERSION || buf[2] != h->hd.W || buf[3] != h->hd.H ||
+      buf[6] != h->hd.s1 || buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 ||
+      buf[10] != h->hd.reply_flits || buf[11] != CORE_RECORD || buf[12] != h->hd.variants)
     return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
+  const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
+  const int32_t* ages = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT;
+  const bool aged = h->hd.variants & SIM_FLAG_AGE_DEFLECT;
   const int64_t cyc = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
   if (cyc < 0 || cyc > 0x7FFFFFFF) return SIM_EINVAL;
   std::vector<int4> link(4 * N), core(4 * N), node(N);
@@ -1771,8 +1858,10 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) {
       const int32_t* w = buf + o + t * 16 + p * 4;
+      const int32_t a = ages[t * 4 + p];
       if (w[0] >= (int32_t)N || w[2] >= (int32_t)N || (w[0] >= 0 && w[2] < 0)) return SIM_EINVAL;
-      link[p * N + t] = host_encode(w, (uint32_t)cyc);
+      if (a < 0 || a > AGE_MAX || (a && (!aged || w[0] < 0))) return SIM_EINVAL;
+      link[p * N + t] = host_encode(w, (uint32_t)cyc, a);
     }
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
@@ -1780,15 +1869,16 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     core[t] = make_int4(r[0], r[1], r[2], r[3]);
     core[N + t] = make_int4(r[4], r[5], r[6], r[7]);
     core[2 * N + t] = make_int4(r[8], r[9], r[10], r[14]);
-    core[3 * N + t] = make_int4(r[15], r[16], 0, 0);
+    // a held op exists only with hit under miss (the base kernel keeps none)
+    if (r[18] >= 0 && !(h->hd.variants & SIM_FLAG_HIT_UNDER_MISS)) return SIM_EINVAL;
+    core[3 * N + t] = make_int4(r[15], r[16], r[18], r[19]);
     node[t] = make_int4(r[11], r[12], r[13], r[17]);
   }
   o += N * CORE_RECORD;
-  const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
   const int par = (int)(cyc & 1);
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)par * 4 * N, link.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   // the other parity: empty, stamped cyc-1 (it is rewritten during cycle cyc)
-  std::vector<int4> other(4 * N, host_encode(std::vector<int32_t>{-1, -1, -1, -1}.data(), (uint32_t)(cyc - 1)));
+  std::vector<int4> other(4 * N, host_encode(std::vector<int32_t>{-1, -1, -1, -1}.data(), (uint32_t)(cyc - 1), 0));
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)(par ^ 1) * 4 * N, other.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   int rc = SIM_OK;

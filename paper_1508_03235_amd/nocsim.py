@@ -53,7 +53,7 @@ class SimConfig(C.Structure):
                    seed_hi=(p.seed >> 32) & 0xFFFFFFFF, l1_sets=p.l1_sets, l1_ways=p.l1_ways,
                    l2_sets=p.l2_sets, l2_ways=p.l2_ways, l1_lat=p.l1_lat, mem_lat=p.mem_lat,
                    op_thr=p.op_thr, shared_thr=p.shared_thr, bg_thr=p.bg_thr,
-                   shared_lines=p.shared_lines, private_lines=p.private_lines, flags=0,
+                   shared_lines=p.shared_lines, private_lines=p.private_lines, flags=p.flags,
                    reply_flits=p.reply_flits)
 
 

@@ -1,0 +1,109 @@
+"""Parity of the model variants (SimParams.flags) on the GPU with the serial oracle.
+
+The variants run on the general kernel.  Bar: bit-exact, as for the base model: every
+per-cycle digest and the final canonical dump, including each in-flight flit's deflection
+count and each core's held op.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1508_03235_amd import workload as W
+from tests.harness import STAT, split_dump
+from tests.test_gpu_parity import assert_same_run, gpu_sim
+
+pytestmark = pytest.mark.gpu
+
+AGE, HUM, DELAY = W.AGE_DEFLECT, W.HIT_UNDER_MISS, W.INJECT_DELAY
+FLAG_SETS = [AGE, HUM, DELAY, AGE | HUM | DELAY]
+IDS = ["age", "hum", "delay", "all"]
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS, ids=IDS)
+def test_variants_config0_full_run(flags):
+    """4x4, 10,000 cycles of config 0 under each variant."""
+    assert_same_run(W.config0().with_(flags=flags, op_thr=W.thr(0.5)), 10_000, step_sizes=[1, 999, 4000, 5000])
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS, ids=IDS)
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (5, 5), (13, 7)])
+def test_variants_small_shapes(w, h, flags):
+    p = W.config0().with_(width=w, height=h, seed=w * 100 + h + flags, bg_thr=W.thr(0.25) if w * h > 1 else 0,
+                          op_thr=W.thr(0.6), l1_sets=8, l1_ways=2, shared_lines=256, flags=flags, reply_flits=2)
+    assert_same_run(p, 3000)
+
+
+@pytest.mark.parametrize("flags", [AGE, AGE | HUM | DELAY], ids=["age", "all"])
+@pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
+def test_variants_patch_mappings(launch, flags):
+    """Deflection counts travel in the link slots across patch edges (stamped halves), and
+    held ops and delayed injections across launch boundaries, exactly."""
+    p = W.config0().with_(width=20, height=13, seed=8, bg_thr=W.thr(0.3), op_thr=W.thr(0.5), flags=flags)
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS, ids=IDS)
+def test_variants_config2_full_size_prefix(flags):
+    """208x208 (43,264 tiles) in the default launch configuration."""
+    assert_same_run(W.config2(0.1).with_(flags=flags), 100, step_sizes=[40, 60])
+
+
+def test_variants_refuse_the_base_kernel():
+    """Asking for the one-tile-per-thread kernel keeps a variant chip on the general kernel."""
+    p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM)
+    a = gpu_sim(p)
+    a.set_kernel(False)
+    b = gpu_sim(p, generic=True)
+    assert (a.step(600, digests=True) == b.step(600, digests=True)).all()
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS, ids=IDS)
+def test_variants_checkpoint_and_drain_on_gpu(flags):
+    p = W.config0().with_(width=6, height=6, seed=31 + flags, bg_thr=W.thr(0.25), op_thr=W.thr(0.5), flags=flags,
+                          reply_flits=2, l1_sets=8, shared_lines=512)
+    a = gpu_sim(p)
+    da = a.step(1000, digests=True)
+    b = gpu_sim(p)
+    b.step(451)
+    snap = b.dump()
+    if flags & AGE:
+        assert (split_dump(snap, p)["ages"] > 0).any()
+    c = gpu_sim(p)
+    c.load(snap)
+    assert (c.step(549, digests=True) == da[451:]).all()
+    o = O.OracleSim(p)
+    o.load(snap)
+    o.step(549)
+    assert (c.dump() == o.dump()).all()
+    for s in (a, o):
+        s.set_rates(0, 0)
+        s.step(3000)
+    assert (a.dump() == o.dump()).all()
+    assert o.quiescent()
+    st = a.stats()
+    assert st[STAT["req_made"]] == st[STAT["req_received"]] == st[STAT["reply_sent"]] == st[STAT["reply_received"]]
+    assert st[STAT["ops_issued"]] == st[STAT["ops_done"]]
+
+
+def test_variant_dump_is_refused_by_another_variant():
+    p = W.config0().with_(width=4, height=4, flags=AGE)
+    a = gpu_sim(p)
+    a.step(300)
+    other = gpu_sim(p.with_(flags=HUM))
+    with pytest.raises(Exception):
+        other.load(a.dump())
+
+
+def test_variants_batch_with_base_chips():
+    """One launch over chips of different variants and base-model chips: each equals its
+    own oracle run (the whole batch runs on the general kernel)."""
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=4000 + i, bg_thr=W.thr(0.15), flags=f)
+              for i, (s, f) in enumerate([(8, 0), (16, AGE), (8, HUM), (24, DELAY), (16, AGE | HUM | DELAY)])]
+    sims = [gpu_sim(p) for p in params]
+    b = nocsim.Batch(sims)
+    b.step([300, 250, 300, 123, 200])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200]):
+        o = O.OracleSim(p)
+        o.step(n)
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags}"
