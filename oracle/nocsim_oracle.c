@@ -70,12 +70,15 @@ struct oracle_sim {
   oracle_config cfg;
   int32_t W, H, N;
   int32_t reply_flits;   /* flits per reply packet */
+  int32_t delay;         /* router delay D >= 1: cycles per hop */
   int32_t* scratch;      /* [2N], invariant checks */
   int64_t cycle;
   int32_t zk;
   uint32_t* zs;          /* shared-region quantile table, zk+1 entries */
   uint32_t* zp;          /* private-region quantile table */
   int32_t* link[2];      /* [N][4 ports][F_WORDS]: input slots, double buffered by cycle parity */
+  int32_t* pipe;         /* [D-1][N][4 ports][F_WORDS]: flits that arrived at a router and wait for
+                            arbitration; ring entry (a mod (D-1)) holds those arbitrated at cycle a */
   int32_t* core;         /* [N][C_WORDS] */
   int32_t* l1;           /* [N][S1][W1], most recently used first, -1 = invalid */
   int32_t* l2;           /* [N][S2][W2] */
@@ -336,6 +339,11 @@ static void phase_memory(oracle_sim* s, int32_t t) {
   }
 }
 
+/* The pipeline stage of tile t holding the flits it arbitrates in cycle a (router delay > 1). */
+static int32_t* pipe_stage(const oracle_sim* s, int64_t a, int32_t t) {
+  return s->pipe + ((size_t)(a % (s->delay - 1)) * s->N + t) * SLOT_WORDS;
+}
+
 /* ---- phase two: oldest-first deflection arbitration (Sec. 4.3, Sec. 6.2.1) ---------- */
 /* Flit a goes before flit b: oldest first, by injection cycle, then source tile; with
    deflection counts (AGE_DEFLECT) the more deflected flit first, then as before. */
@@ -406,7 +414,17 @@ int oracle_arbitrate(int32_t width, int32_t height, int32_t tile, int32_t n, con
 static void phase_route(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
   int32_t* k = s->core + (size_t)t * C_WORDS;
-  const int32_t* in = s->link[c & 1] + (size_t)t * SLOT_WORDS;
+  const int32_t* arrived = s->link[c & 1] + (size_t)t * SLOT_WORDS;
+  /* with a router delay D > 1 the flits arbitrated now arrived D-1 cycles ago; this cycle's
+     arrivals take their place in the pipeline */
+  int32_t in[SLOT_WORDS];
+  if (s->delay > 1) {
+    int32_t* st = pipe_stage(s, c, t);
+    memcpy(in, st, sizeof in);
+    memcpy(st, arrived, sizeof in);
+  } else {
+    memcpy(in, arrived, sizeof in);
+  }
   int32_t fl[5][F_WORDS];
   int n = 0, deg = 0;
   for (int p = 0; p < 4; ++p) {
@@ -520,10 +538,13 @@ static void phase_move(oracle_sim* s, int32_t t) {
     int bin = 0;
     while (bin < 15 && (lat >> (bin + 1)) > 0) bin++;
     s->stats[OS_HIST + bin]++;
-    if (s->check) {
+    if (s->check) {  /* every hop takes D cycles, and a route is Manhattan plus detours */
       int32_t sx = ej[F_SRC] % s->W, sy = ej[F_SRC] / s->W, x = t % s->W, y = t / s->W;
       int64_t man = labs((long)(sx - x)) + labs((long)(sy - y));
-      if (lat < man && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit faster than Manhattan at %d", t); }
+      if ((lat < s->delay * man || lat % s->delay != 0) && !s->bad) {
+        s->bad = 1;
+        snprintf(s->msg, sizeof s->msg, "flit latency %lld over %lld hops at %d", (long long)lat, (long long)man, t);
+      }
     }
     if (kind == K_REQ) {                       /* request reaches its home slice */
       s->stats[OS_REQ_RECV]++;
@@ -558,9 +579,10 @@ static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 
    by the tile, so they are left out (zeroed); they are compared through the canonical dump
    instead. */
 static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
-  int32_t w[16 + C_WORDS + 2];
-  const int32_t* slots = s->link[(c + 1) & 1] + (size_t)t * SLOT_WORDS;
+  int32_t w[16 + C_WORDS + 2 + 7 * 18];
   int32_t age[4];
+  const int aged = (s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT) != 0;
+  const int32_t* slots = s->link[(c + 1) & 1] + (size_t)t * SLOT_WORDS;
   for (int p = 0; p < 4; ++p) {
     memcpy(w + 4 * p, slots + p * F_WORDS, 4 * sizeof(int32_t));
     age[p] = slots[p * F_WORDS + F_DST] >= 0 ? slots[p * F_WORDS + F_AGE] : 0;
@@ -568,9 +590,22 @@ static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
   memcpy(w + 16, s->core + (size_t)t * C_WORDS, C_WORDS * sizeof(int32_t));
   w[16 + C_NEXT] = w[16 + C_READY] = w[16 + C_NLINE] = w[16 + C_NSENT] = 0;
   int nw = 16 + C_WORDS;
-  if (s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT) {
+  if (aged) {
     w[nw++] = (int32_t)((uint32_t)age[0] | ((uint32_t)age[1] << 16));
     w[nw++] = (int32_t)((uint32_t)age[2] | ((uint32_t)age[3] << 16));
+  }
+  /* the router's pipeline, stage by stage in the order the stages are arbitrated */
+  for (int st = 1; st < s->delay; ++st) {
+    const int32_t* f = pipe_stage(s, c + st, t);
+    for (int p = 0; p < 4; ++p) {
+      memcpy(w + nw, f + p * F_WORDS, 4 * sizeof(int32_t));
+      nw += 4;
+      age[p] = f[p * F_WORDS + F_DST] >= 0 ? f[p * F_WORDS + F_AGE] : 0;
+    }
+    if (aged) {
+      w[nw++] = (int32_t)((uint32_t)age[0] | ((uint32_t)age[1] << 16));
+      w[nw++] = (int32_t)((uint32_t)age[2] | ((uint32_t)age[3] << 16));
+    }
   }
   uint64_t h = mix64(((uint64_t)(uint32_t)c << 32) | (uint32_t)t);
   for (int i = 0; i < nw / 2; ++i)
@@ -587,14 +622,17 @@ static void check_cycle(oracle_sim* s) {
   int32_t* queued_at = s->scratch + s->N;    /* 1 while the requester sits in a home's queue */
   memset(s->scratch, 0, (size_t)s->N * 2 * sizeof(int32_t));
   for (int32_t t = 0; t < s->N; ++t) {
-    for (int p = 0; p < 4; ++p) {
-      const int32_t* f = nxt + (size_t)t * SLOT_WORDS + p * F_WORDS;
-      if (f[F_DST] < 0) continue;
-      occupied++;
-      int kind = (int)((uint32_t)f[F_INFO] >> 30);
-      if (kind == K_REQ) req_fl++;
-      if (kind == K_REPLY) rep_to[f[F_DST]]++;
-      if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
+    for (int st = 0; st < s->delay; ++st) {    /* the link slots, then the pipeline stages */
+      const int32_t* sl = st == 0 ? nxt + (size_t)t * SLOT_WORDS : pipe_stage(s, c + st, t);
+      for (int p = 0; p < 4; ++p) {
+        const int32_t* f = sl + p * F_WORDS;
+        if (f[F_DST] < 0) continue;
+        occupied++;
+        int kind = (int)((uint32_t)f[F_INFO] >> 30);
+        if (kind == K_REQ) req_fl++;
+        if (kind == K_REPLY) rep_to[f[F_DST]]++;
+        if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
+      }
     }
     if (!s->oldest_ok[t] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "first flit deflected at %d", t); }
   }
@@ -687,6 +725,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
   if (cfg->reply_flits < 0 || cfg->reply_flits > 16) return ORACLE_EINVAL;
   if (cfg->flags & ~(ORACLE_FLAG_AGE_DEFLECT | ORACLE_FLAG_HIT_UNDER_MISS | ORACLE_FLAG_INJECT_DELAY)) return ORACLE_EINVAL;
+  if (cfg->router_delay < 0 || cfg->router_delay > 8) return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
   s->cfg = *cfg;
@@ -694,6 +733,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->H = cfg->height;
   s->N = (int32_t)N;
   s->reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
+  s->delay = cfg->router_delay > 0 ? cfg->router_delay : 1;
   s->zk = zk;
   s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
   s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
@@ -707,8 +747,9 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->ej = (int32_t*)malloc((size_t)N * F_WORDS * 4);
   s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
   s->scratch = (int32_t*)malloc((size_t)N * 2 * 4);
+  s->pipe = (int32_t*)malloc((size_t)(s->delay - 1) * N * SLOT_WORDS * 4 + 4);
   if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
-      !s->oldest_ok || !s->scratch) {
+      !s->oldest_ok || !s->scratch || !s->pipe) {
     oracle_destroy(s);
     return ORACLE_ENOMEM;
   }
@@ -717,6 +758,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   else memcpy(s->zp, zs, (size_t)(zk + 1) * 4);
   memset(s->link[0], 0xFF, (size_t)N * SLOT_WORDS * 4);
   memset(s->link[1], 0xFF, (size_t)N * SLOT_WORDS * 4);
+  memset(s->pipe, 0xFF, (size_t)(s->delay - 1) * N * SLOT_WORDS * 4);
   memset(s->core, 0xFF, (size_t)N * C_WORDS * 4);
   for (int64_t t = 0; t < N; ++t) {
     s->core[t * C_WORDS + C_STATE] = ST_IDLE;
@@ -734,7 +776,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
 void oracle_destroy(oracle_sim* s) {
   if (!s) return;
   free(s->zs); free(s->zp); free(s->link[0]); free(s->link[1]); free(s->core); free(s->l1); free(s->l2);
-  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch);
+  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch); free(s->pipe);
   free(s);
 }
 
@@ -749,20 +791,23 @@ int64_t oracle_cycle(const oracle_sim* s) { return s ? s->cycle : -1; }
 size_t oracle_dump_words(const oracle_sim* s) {
   size_t N = (size_t)s->N;
   return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways +
-         2 * OS_COUNT + N * 4;
+         2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20;
 }
 
 /* Canonical state (format version 3): header {magic, 3, W, H, cycle (low, high), L1 sets,
    L1 ways, L2 sets, L2 ways, reply flits, core-record words, variant flags, 0...}, the four
    words of each input slot of the next cycle, core records, L1 and L2 tags (most recently used
-   first), statistics as (low, high) word pairs, and the deflection count of each input slot's
-   flit (0 for an empty slot and outside the AGE_DEFLECT variant). */
+   first), statistics as (low, high) word pairs, the deflection count of each input slot's
+   flit (0 for an empty slot and outside the AGE_DEFLECT variant), and with a router delay
+   D > 1 (header word 13) the routers' pipelines: stages 1..D-1, stage k holding the flits
+   arbitrated k-1 cycles after the dump's cycle, four words per slot, then their deflection
+   counts. */
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
   int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 3, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
                               s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
-                              C_WORDS, s->cfg.flags, 0, 0, 0};
+                              C_WORDS, s->cfg.flags, s->delay, 0, 0};
   memcpy(buf, hdr, sizeof hdr);
   o += DUMP_HEADER;
   const int32_t* slots = s->link[s->cycle & 1];
@@ -779,6 +824,17 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
     buf[o++] = (int32_t)((uint64_t)s->stats[i] >> 32);
   }
   for (size_t i = 0; i < N * 4; ++i) buf[o++] = slots[i * F_WORDS + F_DST] >= 0 ? slots[i * F_WORDS + F_AGE] : 0;
+  for (int st = 1; st < s->delay; ++st) {
+    const int32_t* f = pipe_stage(s, s->cycle + st - 1, 0);
+    for (size_t i = 0; i < N * 4; ++i) {
+      memcpy(buf + o, f + i * F_WORDS, 4 * sizeof(int32_t));
+      o += 4;
+    }
+  }
+  for (int st = 1; st < s->delay; ++st) {
+    const int32_t* f = pipe_stage(s, s->cycle + st - 1, 0);
+    for (size_t i = 0; i < N * 4; ++i) buf[o++] = f[i * F_WORDS + F_DST] >= 0 ? f[i * F_WORDS + F_AGE] : 0;
+  }
   return ORACLE_OK;
 }
 
@@ -786,7 +842,7 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   if (buf[0] != DUMP_MAGIC || buf[1] != 3 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
       buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
-      buf[11] != C_WORDS || buf[12] != s->cfg.flags)
+      buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay)
     return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = DUMP_HEADER;
   s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
@@ -808,6 +864,16 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   /* state that only a variant can hold */
   for (size_t i = 0; i < N * 4; ++i)
     if (buf[o + i] != 0 && !(s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT)) return ORACLE_EINVAL;
+  o += N * 4;
+  for (int st = 1; st < s->delay; ++st) {
+    int32_t* f = pipe_stage(s, s->cycle + st - 1, 0);
+    const int32_t* ages = buf + o + (size_t)(s->delay - 1) * N * 16 + (size_t)(st - 1) * N * 4;
+    for (size_t i = 0; i < N * 4; ++i) {
+      memcpy(f + i * F_WORDS, buf + o + (size_t)(st - 1) * N * 16 + i * 4, 4 * sizeof(int32_t));
+      if (ages[i] != 0 && !(s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT)) return ORACLE_EINVAL;
+      f[i * F_WORDS + F_AGE] = f[i * F_WORDS + F_DST] >= 0 ? ages[i] : -1;
+    }
+  }
   for (size_t t = 0; t < N; ++t)
     if (s->core[t * C_WORDS + C_DLINE] >= 0 && !(s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS)) return ORACLE_EINVAL;
   return ORACLE_OK;
@@ -834,6 +900,8 @@ int oracle_set_rates(oracle_sim* s, uint32_t op_thr, uint32_t bg_thr) {
 
 int oracle_quiescent(const oracle_sim* s) {
   const int32_t* cur = s->link[s->cycle & 1];
+  for (size_t i = 0; i < (size_t)(s->delay - 1) * s->N * 4; ++i)
+    if (s->pipe[i * F_WORDS + F_DST] >= 0) return 0;
   for (int32_t t = 0; t < s->N; ++t) {
     for (int p = 0; p < 4; ++p)
       if (cur[(size_t)t * SLOT_WORDS + p * F_WORDS] >= 0) return 0;

@@ -36,6 +36,9 @@ typedef struct {
   int32_t private_lines;       /* per-tile private region size (0 = no private region) */
   int32_t flags;               /* model variants, ORACLE_FLAG_* below (0 = the base model) */
   int32_t reply_flits;         /* flits of a reply packet, 1..16 (0 counts as 1) */
+  int32_t router_delay;        /* cycles a flit takes per hop, 1..8 (0 counts as 1): a flit that
+                                  arrives at a router waits router_delay - 1 cycles in its
+                                  pipeline before it is arbitrated */
 } oracle_config;
 
 /* Model variants: each bit replaces one reading of the base model by a more literal one.

@@ -47,7 +47,7 @@ class OracleConfig(C.Structure):
         ("l1_lat", C.c_int32), ("mem_lat", C.c_int32),
         ("op_thr", C.c_uint32), ("shared_thr", C.c_uint32), ("bg_thr", C.c_uint32),
         ("shared_lines", C.c_int32), ("private_lines", C.c_int32), ("flags", C.c_int32),
-        ("reply_flits", C.c_int32),
+        ("reply_flits", C.c_int32), ("router_delay", C.c_int32),
     ]
 
 
@@ -138,7 +138,7 @@ class OracleSim:
             l1_lat=params.l1_lat, mem_lat=params.mem_lat,
             op_thr=params.op_thr, shared_thr=params.shared_thr, bg_thr=params.bg_thr,
             shared_lines=params.shared_lines, private_lines=params.private_lines, flags=params.flags,
-            reply_flits=params.reply_flits)
+            reply_flits=params.reply_flits, router_delay=params.router_delay)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(cfg), _ptr(self._zs), _ptr(self._zp), len(self._zs) - 1, C.byref(h))
         if rc != 0:

@@ -44,7 +44,7 @@ class SimConfig(C.Structure):
         ("l1_lat", C.c_int32), ("mem_lat", C.c_int32),
         ("op_thr", C.c_uint32), ("shared_thr", C.c_uint32), ("bg_thr", C.c_uint32),
         ("shared_lines", C.c_int32), ("private_lines", C.c_int32), ("flags", C.c_int32),
-        ("reply_flits", C.c_int32),
+        ("reply_flits", C.c_int32), ("router_delay", C.c_int32),
     ]
 
     @classmethod
@@ -54,7 +54,7 @@ class SimConfig(C.Structure):
                    l2_sets=p.l2_sets, l2_ways=p.l2_ways, l1_lat=p.l1_lat, mem_lat=p.mem_lat,
                    op_thr=p.op_thr, shared_thr=p.shared_thr, bg_thr=p.bg_thr,
                    shared_lines=p.shared_lines, private_lines=p.private_lines, flags=p.flags,
-                   reply_flits=p.reply_flits)
+                   reply_flits=p.reply_flits, router_delay=p.router_delay)
 
 
 _L = None

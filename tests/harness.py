@@ -42,7 +42,10 @@ def split_dump(buf, params):
     n2 = N * params.l2_sets * params.l2_ways
     out["l2"] = buf[o:o + n2].reshape(N, params.l2_sets, params.l2_ways); o += n2
     out["stats"] = buf[o:o + 96].copy().view(np.int64); o += 96
-    out["ages"] = buf[o:o + N * 4].reshape(N, 4)   # deflection count of each input slot's flit
+    out["ages"] = buf[o:o + N * 4].reshape(N, 4); o += N * 4   # deflection count of each input slot's flit
+    D = max(1, int(buf[13]))   # router delay: stages 1..D-1 of the routers' pipelines follow
+    out["pipe"] = buf[o:o + (D - 1) * N * 16].reshape(D - 1, N, 4, 4); o += (D - 1) * N * 16
+    out["pipe_ages"] = buf[o:o + (D - 1) * N * 4].reshape(D - 1, N, 4)
     return out
 
 

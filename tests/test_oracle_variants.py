@@ -417,3 +417,127 @@ def test_variants_change_the_run():
 def test_unknown_flags_are_refused():
     with pytest.raises(ValueError):
         O.OracleSim(quiet_params(2, 2, flags=8))
+
+
+# ---- router delay: every hop takes D cycles ----------------------------------------------------
+@pytest.mark.parametrize("D", [2, 3, 5])
+@pytest.mark.parametrize("w,h", [(1, 5), (3, 3), (4, 3)])
+def test_router_delay_zero_load_is_d_times_manhattan(w, h, D):
+    """A lone flit spends D-1 cycles in each router's pipeline after every hop, so its
+    latency is exactly D x Manhattan, without deflection."""
+    p = quiet_params(w, h, router_delay=D)
+    sim = O.OracleSim(p)
+    N = w * h
+    for s in range(N):
+        for d in range(N):
+            if s == d:
+                continue
+            st0 = sim.stats()
+            sim.force_bg(s, d)
+            sim.step(D * _man(w, s, d) + 1, check=True)
+            st = sim.stats()
+            assert st[STAT["ej_bg"]] - st0[STAT["ej_bg"]] == 1
+            assert st[STAT["lat_bg"]] - st0[STAT["lat_bg"]] == D * _man(w, s, d)
+    assert sim.stat("deflections") == 0
+
+
+@pytest.mark.parametrize("D", [2, 4])
+def test_router_delay_op_latency(D):
+    """The hand trace's remote ops take 2 (D-1) cycles more per hop between requester and
+    home (the request's path and the reply's), the L1 hit nothing."""
+    tr = _t4()
+    p = quiet_params(tr["width"], tr["height"], l1_sets=tr["l1_sets"], l1_ways=tr["l1_ways"], l2_sets=tr["l2_sets"],
+                     l2_ways=tr["l2_ways"], l1_lat=tr["l1_lat"], mem_lat=tr["mem_lat"], router_delay=D)
+    ops = [(o["tile"], o["line"]) for o in tr["ops"]]
+    lat, _ = _op_latencies(p, ops)
+    w = tr["width"]
+    hops = [_man(w, t, line % (tr["width"] * tr["height"])) for t, line in ops]
+    assert lat == [o["latency"] + (2 * (D - 1) * hp if o["latency"] > 0 else 0) for o, hp in zip(tr["ops"], hops)]
+
+
+@pytest.mark.parametrize("flags", [0, AGE])
+def test_router_delay_flits_move_on_the_beat(flags):
+    """From the dumps of every cycle of a loaded chip with D = 3: a flit on a link was sent in
+    a cycle congruent to its injection cycle mod D, a flit in pipeline stage k will be
+    arbitrated in such a cycle, every flit counted by the statistics is in a slot or a stage,
+    and (priority by deflection count) each flit's count equals the closed form with the hops
+    it has made."""
+    D = 3
+    rng = random.Random(17 + flags)
+    p = _params(rng, 4, 4, flags, router_delay=D, bg_thr=W.thr(0.35))
+    w = p.width
+    sim = O.OracleSim(p)
+    seen_pipe = 0
+    for _ in range(400):
+        sim.step(1, check=True)
+        C = sim.cycle
+        d = split_dump(sim.dump(), p)
+        st = sim.stats()
+        in_flight = (st[STAT["inj_req"]] + st[STAT["inj_reply"]] + st[STAT["inj_bg"]] -
+                     st[STAT["ej_req"]] - st[STAT["ej_reply"]] - st[STAT["ej_bg"]])
+        count = 0
+        stages = [(0, d["links"], d["ages"])] + [(k, d["pipe"][k - 1], d["pipe_ages"][k - 1]) for k in range(1, D)]
+        for k, slots, ages in stages:
+            for t in range(p.tiles):
+                for q in range(4):
+                    f = slots[t, q]
+                    if f[0] < 0:
+                        continue
+                    count += 1
+                    seen_pipe += k > 0
+                    sent = C - 1 if k == 0 else C + k - 1 - D   # its last arbitration
+                    assert (sent - f[1]) % D == 0, (C, k, t, q, f.tolist())
+                    hops = (sent - f[1]) // D + 1
+                    expect = (_man(w, t, f[0]) - _man(w, f[2], f[0]) + hops) // 2 if flags & AGE else 0
+                    assert ages[t, q] == expect
+        assert count == in_flight
+    assert seen_pipe > 0
+
+
+@pytest.mark.parametrize("D", [2, 4])
+@pytest.mark.parametrize("flags", [0, AGE | HUM | DELAY])
+def test_router_delay_invariants_drain_checkpoint(D, flags):
+    rng = random.Random(D * 10 + flags)
+    p = _params(rng, 4, 3, flags, router_delay=D, reply_flits=2)
+    a = O.OracleSim(p)
+    da = a.step(1200, digests=True, check=True)
+    b = O.OracleSim(p)
+    b.step(613)
+    snap = b.dump()
+    assert (split_dump(snap, p)["pipe"][..., 0] >= 0).any()
+    c = O.OracleSim(p)
+    c.load(snap)
+    assert (c.step(587, digests=True) == da[613:]).all()
+    assert (c.dump() == a.dump()).all()
+    with pytest.raises(Exception):
+        O.OracleSim(p.with_(router_delay=D + 1)).load(snap)
+    a.set_rates(0, 0)
+    for _ in range(400):
+        if a.quiescent():
+            break
+        a.step(50, check=True)
+    assert a.quiescent()
+    st = a.stats()
+    assert st[STAT["req_made"]] == st[STAT["req_received"]] == st[STAT["reply_sent"]] == st[STAT["reply_received"]] > 0
+    assert st[STAT["ops_issued"]] == st[STAT["ops_done"]]
+
+
+def test_router_delay_uniform_traffic_limit():
+    """With ops off and low load the mean latency approaches D x the mean Manhattan distance."""
+    k, D = 6, 2
+    p = quiet_params(k, k, bg_thr=W.thr(0.004), seed=9, router_delay=D)
+    sim = O.OracleSim(p)
+    sim.step(20000)
+    st = sim.stats()
+    n = k * k
+    mean_man = (2 * (k * k - 1) / (3 * k)) * n / (n - 1)
+    avg = st[STAT["lat_bg"]] / st[STAT["ej_bg"]]
+    assert abs(avg - D * mean_man) < 0.1 * D * mean_man, (avg, D * mean_man)
+
+
+def test_router_delay_one_is_the_default():
+    p = W.config0()
+    assert (O.OracleSim(p.with_(router_delay=1)).step(600, digests=True) ==
+            O.OracleSim(p.with_(router_delay=0)).step(600, digests=True)).all()
+    with pytest.raises(ValueError):
+        O.OracleSim(p.with_(router_delay=9))
