@@ -17,6 +17,10 @@ Besides the headline line the JSON carries:
   packets      - the same chip with replies of 4 flits (the paper's Table 1, remote L2 access):
                  throughput, flit and op latency against single-flit replies, and per-cycle
                  digests of a prefix against the oracle (--no-packets);
+  variants     - the same chip under each model variant (priority by deflection count, hit
+                 under miss, injection register, all three; router delay 2) on the general kernel, beside the
+                 base model on that kernel: throughput, deflection rate, latencies, ops per
+                 tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
   batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
   serving      - Poisson-arriving simulation jobs under continuous batching: p50/p99 job
                  latency and aggregate throughput, against one job at a time (--no-serving).
@@ -160,6 +164,43 @@ def run_packets(nocsim, W, torch, O, cycles, parity_cycles=200, flits=4):
     return out
 
 
+def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
+    """The 208x208 chip at background 0.05 under each model variant (general kernel)."""
+    out = {}
+    cases = [("base", 0), ("age_deflect", W.AGE_DEFLECT), ("hit_under_miss", W.HIT_UNDER_MISS),
+             ("inject_delay", W.INJECT_DELAY), ("all", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
+             ("router_delay_2", 0)]
+    S = nocsim.STAT
+    for name, flags in cases:
+        p = W.config2(0.05).with_(flags=flags, router_delay=2 if name == "router_delay_2" else 1)
+        sim = nocsim.Sim(p)
+        sim.set_kernel(True)
+        sim.step(300)
+        st0 = sim.stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(cycles)
+        dt = time.perf_counter() - t0
+        st = sim.stats() - st0
+        ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
+        lat = st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]
+        r = {"flags": flags, "router_delay": p.router_delay, "tile_cycles_per_s": p.tiles * cycles / dt,
+             "deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
+             "avg_flit_latency": float(lat / max(1, ej)),
+             "max_flit_latency": int(sim.stats()[S["lat_max"]]),
+             "avg_op_latency": float(st[S["op_lat"]] / max(1, st[S["ops_done"]])),
+             "ops_per_tile_cycle": float(st[S["ops_done"]] / (p.tiles * cycles))}
+        del sim
+        if O is not None:
+            g = nocsim.Sim(p)
+            g.set_kernel(True)
+            r["parity"] = {"cycles": parity_cycles, "digests_equal": bool(
+                (g.step(parity_cycles, digests=True) == O.OracleSim(p).step(parity_cycles, digests=True)).all())}
+            del g
+        out[name] = r
+    return out
+
+
 def run_batched(nocsim, W, torch, cycles, plain_chips):
     params = W.config3()
     sims = [nocsim.Sim(p) for p in params]
@@ -229,6 +270,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-packets", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=60)
@@ -332,15 +374,19 @@ def main():
             out["sweep"] = run_sweep(nocsim, W, torch, 5000)
         except Exception as e:  # an optional leg must not hide the headline number
             out["sweep"] = {"error": repr(e)}
+    O = None  # the oracle checks the optional legs' prefixes when the CPU leg ran
+    if cpu:
+        from oracle import oracle as O
     if not args.no_packets:
         try:
-            from oracle import oracle as O
-        except Exception:
-            O = None
-        try:
-            out["packets"] = run_packets(nocsim, W, torch, O if cpu else None, 5000)
+            out["packets"] = run_packets(nocsim, W, torch, O, 5000)
         except Exception as e:
             out["packets"] = {"error": repr(e)}
+    if not args.no_variants:
+        try:
+            out["variants"] = run_variants(nocsim, W, torch, O, 3000)
+        except Exception as e:
+            out["variants"] = {"error": repr(e)}
     if not args.no_batched:
         try:
             out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)

@@ -62,6 +62,9 @@ typedef struct {
   int32_t flags;              /* model variants, SIM_FLAG_* (0 = the base model) */
   int32_t reply_flits;        /* flits of a reply packet, 1..16 (0 counts as 1); requests and
                                  background flits are one flit */
+  int32_t router_delay;       /* cycles per hop, 1..8 (0 counts as 1): a flit that arrives at a
+                                 router waits router_delay - 1 cycles in the router's pipeline
+                                 before it is arbitrated; > 1 runs on the general kernel */
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
@@ -137,7 +140,10 @@ int sim_stats(sim_t* h, sim_stats_t* out);
    node flits sent, held line (-1 = none), held issue cycle}, then L1 and L2 tags per tile per
    set (most recently used first, -1 invalid), then the 48 statistics as (low, high) word
    pairs, then per tile the deflection counts of the 4 input slots' flits (0 when empty or
-   without AGE_DEFLECT).  sim_dump_words() gives the size in int32 words. */
+   without AGE_DEFLECT), then, when router_delay D > 1 (header word 13 = D), the routers'
+   pipelines: stages k = 1..D-1 (stage k holds the flits arbitrated k-1 cycles after the
+   dump's cycle), each as per tile 4 slots of 4 words, then the stages' deflection counts.
+   sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);
 /* Restores a canonical state produced by sim_dump (checkpoint / resume).  EINVAL when the

@@ -58,9 +58,12 @@ struct ChipDev {
   int32_t reply_flits;       // flits per reply packet (Sec. 3.6, Table 1); 1 = single-flit replies
   int32_t variants;          // SIM_FLAG_* model variants
   int32_t inj_delay;         // 1 when a flit can enter the network only the cycle after it is made
+  int32_t rdelay;            // router delay D >= 1: cycles per hop
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int4* link;                // [2 parity][4 port][N]
+  int4* pipe;                // [D-1][4 port][N]: raw slot words of flits waiting in the routers'
+                             // pipelines; entry (a mod (D-1)) holds those arbitrated in cycle a
   int4* core;                // [4][N]; word group 3: force_dst, reply flits received, held line, held issue
   int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
@@ -162,7 +165,8 @@ __device__ __forceinline__ int4 slot_encode_aged(const int4& f, uint32_t stamp, 
   }
   return w;
 }
-__device__ __forceinline__ uint32_t slot_age(const int4& w) {
+__device__ __forceinline__ uint32_t slot_age(const int4& w) {  // 0 for an empty slot (also all ones)
+  if (((uint32_t)w.x & TILE_BITS_MASK) == TILE_BITS_MASK) return 0u;
   return (((uint32_t)w.x >> AGE_SHIFT) & 0xFFu) | ((((uint32_t)w.z >> AGE_SHIFT) & 0xFFu) << 8);
 }
 __device__ __forceinline__ int4 slot_decode(const int4& w) {
@@ -338,6 +342,17 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     st_coh(C.err, 3);  // an interior slot from the wrong cycle: a synchronisation bug
     return false;
   }
+  // Router delay D > 1: this cycle's arrivals wait D-1 cycles in the router's pipeline; the
+  // flits arbitrated now are the ones that arrived D-1 cycles ago (stored below, in phase three)
+  const int4 a0w = w0, a1w = w1, a2w = w2, a3w = w3;
+  int4* pipe_now = nullptr;
+  if (C.rdelay > 1) {
+    pipe_now = &C.pipe[(size_t)((uint32_t)c % (uint32_t)(C.rdelay - 1)) * 4 * N + t];
+    w0 = v0 ? gload4(pipe_now) : EMPTY;
+    w1 = v1 ? gload4(pipe_now + N) : EMPTY;
+    w2 = v2 ? gload4(pipe_now + 2 * N) : EMPTY;
+    w3 = v3 ? gload4(pipe_now + 3 * N) : EMPTY;
+  }
   int4 f0 = v0 ? slot_decode(w0) : EMPTY;
   int4 f1 = v1 ? slot_decode(w1) : EMPTY;
   int4 f2 = v2 ? slot_decode(w2) : EMPTY;
@@ -351,12 +366,22 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const uint32_t a0 = aged && v0 ? slot_age(w0) : 0u, a1 = aged && v1 ? slot_age(w1) : 0u;
   const uint32_t a2 = aged && v2 ? slot_age(w2) : 0u, a3 = aged && v3 ? slot_age(w3) : 0u;
 
-  if (digest) {  // state owned by t after cycle c-1: its inputs of cycle c and its core words
+  if (digest) {  // state owned by t after cycle c-1: its inputs of cycle c, its core words, its pipeline
     unsigned long long h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
-    h = mix_pair(h, f0.x, f0.y); h = mix_pair(h, f0.z, f0.w);
-    h = mix_pair(h, f1.x, f1.y); h = mix_pair(h, f1.z, f1.w);
-    h = mix_pair(h, f2.x, f2.y); h = mix_pair(h, f2.z, f2.w);
-    h = mix_pair(h, f3.x, f3.y); h = mix_pair(h, f3.z, f3.w);
+    auto mix_slots = [&](const int4& x0, const int4& x1, const int4& x2, const int4& x3) {
+      const int4 g0 = v0 ? slot_decode(x0) : EMPTY, g1 = v1 ? slot_decode(x1) : EMPTY;
+      const int4 g2 = v2 ? slot_decode(x2) : EMPTY, g3 = v3 ? slot_decode(x3) : EMPTY;
+      h = mix_pair(h, g0.x, g0.y); h = mix_pair(h, g0.z, g0.w);
+      h = mix_pair(h, g1.x, g1.y); h = mix_pair(h, g1.z, g1.w);
+      h = mix_pair(h, g2.x, g2.y); h = mix_pair(h, g2.z, g2.w);
+      h = mix_pair(h, g3.x, g3.y); h = mix_pair(h, g3.z, g3.w);
+    };
+    auto mix_ages = [&](const int4& x0, const int4& x1, const int4& x2, const int4& x3) {
+      const uint32_t b0 = v0 ? slot_age(x0) : 0u, b1 = v1 ? slot_age(x1) : 0u;
+      const uint32_t b2 = v2 ? slot_age(x2) : 0u, b3 = v3 ? slot_age(x3) : 0u;
+      h = mix_pair(h, (int)(b0 | (b1 << 16)), (int)(b2 | (b3 << 16)));
+    };
+    mix_slots(a0w, a1w, a2w, a3w);
     h = mix_pair(h, k0.x, k0.y); h = mix_pair(h, k0.z, k0.w);
     h = mix_pair(h, k1.x, k1.y); h = mix_pair(h, k1.z, k1.w);
     h = mix_pair(h, k2.x, k2.y);
@@ -365,7 +390,14 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, k2.w, fdst);
     h = mix_pair(h, rcv, 0);    // reply flits received; the node's sent count is the home's
     h = mix_pair(h, hline, hissue);
-    if (aged) h = mix_pair(h, (int)(a0 | (a1 << 16)), (int)(a2 | (a3 << 16)));
+    if (aged) mix_ages(a0w, a1w, a2w, a3w);
+    for (int st = 1; st < C.rdelay; ++st) {  // stage st: the flits arbitrated in cycle c-1+st
+      const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)(C.rdelay - 1)) * 4 * N + t];
+      const int4 x0 = v0 ? gload4(pp) : EMPTY, x1 = v1 ? gload4(pp + N) : EMPTY;
+      const int4 x2 = v2 ? gload4(pp + 2 * N) : EMPTY, x3 = v3 ? gload4(pp + 3 * N) : EMPTY;
+      mix_slots(x0, x1, x2, x3);
+      if (aged) mix_ages(x0, x1, x2, x3);
+    }
     dsum += h;
   }
   if (!step) return true;
@@ -638,6 +670,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   assign(sd4, si4);
 
   // ---- phase three: stores (caches, queue nodes, slots, core words) -------------------------
+  if (pipe_now) {  // this cycle's arrivals enter the pipeline
+    if (v0) gstore4(pipe_now, a0w);
+    if (v1) gstore4(pipe_now + N, a1w);
+    if (v2) gstore4(pipe_now + 2 * N, a2w);
+    if (v3) gstore4(pipe_now + 3 * N, a3w);
+  }
   if (dirtyR) set_store(setR, C.w2, vR);
   if (dirtyL) set_store(setL, C.w2, vL);
   if (dirty1) set_store(set1, C.w1, u);
@@ -1453,13 +1491,15 @@ bool config_ok(const sim_config* c) {
   if (c->l1_lat < 1 || c->mem_lat < 1 || c->shared_lines < 1 || c->private_lines < 0) return false;
   if (c->reply_flits < 0 || c->reply_flits > 16) return false;
   if (c->flags & ~VARIANT_FLAGS) return false;
+  if (c->router_delay < 0 || c->router_delay > 8) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
 
 struct Layout {
-  size_t desc, link, core, node, l1, l2, zs, zp, flags, table, stats, err, total;
+  size_t desc, link, pipe, core, node, l1, l2, zs, zp, flags, table, stats, err, total;
 };
+int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_delay : 1; }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
 
@@ -1471,6 +1511,7 @@ Layout layout(const sim_config* c) {
   auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, 256); return at; };
   L.desc = take(sizeof(ChipDev));
   L.link = take(2 * 4 * N * sizeof(int4));
+  L.pipe = take((size_t)(router_delay(c) - 1) * 4 * N * sizeof(int4));
   L.core = take(4 * N * sizeof(int4));
   L.node = take(N * sizeof(int4));
   L.l1 = take(N * c->l1_sets * c->l1_ways * sizeof(int32_t));
@@ -1658,7 +1699,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  h->use_fast = (cfg->flags & VARIANT_FLAGS) == 0;  // the variants run on the general kernel
+  h->use_fast = (cfg->flags & VARIANT_FLAGS) == 0 && router_delay(cfg) == 1;  // variants: general kernel
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -1689,11 +1730,13 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
   d.variants = cfg->flags;
   d.inj_delay = (cfg->flags & SIM_FLAG_INJECT_DELAY) ? 1 : 0;
+  d.rdelay = router_delay(cfg);
   d.shared_lines = cfg->shared_lines;
   d.private_lines = cfg->private_lines;
   d.stop = 0;
   d.max_patches = max_patches(cfg);
   d.link = reinterpret_cast<int4*>(h->base + Lo.link);
+  d.pipe = reinterpret_cast<int4*>(h->base + Lo.pipe);
   d.core = reinterpret_cast<int4*>(h->base + Lo.core);
   d.node = reinterpret_cast<int4*>(h->base + Lo.node);
   d.l1 = reinterpret_cast<int32_t*>(h->base + Lo.l1);
@@ -1715,6 +1758,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
   hipLaunchKernelGGL(init_core, dim3(std::min((N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.core, d.node, N);
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
+  if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.pipe), -1, (size_t)(d.rdelay - 1) * 4 * N * 4, h->stream)))
+    return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l1, -1, (size_t)N * cfg->l1_sets * cfg->l1_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l2, -1, (size_t)N * cfg->l2_sets * cfg->l2_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_u64(d.stats, 0, NSTAT, h->stream))) return fail(rc);
@@ -1741,7 +1786,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS) == 0;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS) == 0 && h->hd.rdelay == 1;
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;
@@ -1799,7 +1844,8 @@ int sim_stats(sim_t* h, sim_stats_t* out) {
 size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
-  return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4;
+  return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4 +
+         (size_t)(h->hd.rdelay - 1) * N * 20;
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
@@ -1821,7 +1867,7 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   HIPCHECK(hipStreamSynchronize(h->stream));
   const int32_t hdr[16] = {0x4E4F4353, DUMP_VERSION, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle,
                            (int32_t)(h->cycle >> 32), h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits,
-                           CORE_RECORD, h->hd.variants, 0, 0, 0};
+                           CORE_RECORD, h->hd.variants, h->hd.rdelay, 0, 0};
   std::memcpy(buf, hdr, sizeof hdr);
   int32_t* ages = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT;
   for (size_t t = 0; t < N; ++t)
@@ -1838,6 +1884,21 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
     buf[o++] = (int32_t)(uint32_t)st[i];
     buf[o++] = (int32_t)(st[i] >> 32);
   }
+  o += N * 4;  // slot deflection counts, written above
+  const int D = h->hd.rdelay;
+  if (D > 1) {  // pipeline stages k = 1..D-1: ring entry (cycle + k - 1) mod (D-1)
+    std::vector<int4> pipe((size_t)(D - 1) * 4 * N);
+    HIPCHECK(hipMemcpyAsync(pipe.data(), h->hd.pipe, pipe.size() * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    int32_t* pa = buf + o + (size_t)(D - 1) * N * 16;
+    for (int k = 1; k < D; ++k) {
+      const size_t ring = (size_t)((h->cycle + k - 1) % (D - 1));
+      for (size_t t = 0; t < N; ++t)
+        for (int p = 0; p < 4; ++p)
+          host_decode(pipe[(ring * 4 + p) * N + t], buf + o + ((size_t)(k - 1) * N + t) * 16 + p * 4,
+                      pa + ((size_t)(k - 1) * N + t) * 4 + p);
+    }
+  }
   return SIM_OK;
 }
 
@@ -1845,7 +1906,8 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (!h || !buf || words < sim_dump_words(h)) return SIM_EINVAL;
   if (buf[0] != 0x4E4F4353 || buf[1] != DUMP_VERSION || buf[2] != h->hd.W || buf[3] != h->hd.H ||
       buf[6] != h->hd.s1 || buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 ||
-      buf[10] != h->hd.reply_flits || buf[11] != CORE_RECORD || buf[12] != h->hd.variants)
+      buf[10] != h->hd.reply_flits || buf[11] != CORE_RECORD || buf[12] != h->hd.variants ||
+      buf[13] != h->hd.rdelay)
     return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
@@ -1875,6 +1937,25 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     node[t] = make_int4(r[11], r[12], r[13], r[17]);
   }
   o += N * CORE_RECORD;
+  // pipeline stages (router delay > 1), validated before anything is copied: stage k goes to
+  // ring entry (cycle + k - 1) mod (D-1)
+  const int D = h->hd.rdelay;
+  std::vector<int4> pipe((size_t)(D - 1) * 4 * N);
+  {
+    const int32_t* pw = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT + N * 4;
+    const int32_t* pa = pw + (size_t)(D - 1) * N * 16;
+    for (int k = 1; k < D; ++k) {
+      const size_t ring = (size_t)((cyc + k - 1) % (D - 1));
+      for (size_t t = 0; t < N; ++t)
+        for (int p = 0; p < 4; ++p) {
+          const int32_t* w = pw + ((size_t)(k - 1) * N + t) * 16 + p * 4;
+          const int32_t a = pa[((size_t)(k - 1) * N + t) * 4 + p];
+          if (w[0] >= (int32_t)N || w[2] >= (int32_t)N || (w[0] >= 0 && w[2] < 0)) return SIM_EINVAL;
+          if (a < 0 || a > AGE_MAX || (a && (!aged || w[0] < 0))) return SIM_EINVAL;
+          pipe[(ring * 4 + p) * N + t] = host_encode(w, 0u, a);
+        }
+    }
+  }
   const int par = (int)(cyc & 1);
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)par * 4 * N, link.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   // the other parity: empty, stamped cyc-1 (it is rewritten during cycle cyc)
@@ -1890,6 +1971,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   unsigned long long st[NSTAT];
   for (int i = 0; i < NSTAT; ++i) st[i] = (unsigned long long)(uint32_t)buf[o + 2 * i] | ((unsigned long long)(uint32_t)buf[o + 2 * i + 1] << 32);
   HIPCHECK(hipMemcpyAsync(h->hd.stats, st, sizeof st, hipMemcpyHostToDevice, h->stream));
+  if (D > 1) HIPCHECK(hipMemcpyAsync(h->hd.pipe, pipe.data(), pipe.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   h->cycle = cyc;
   if ((rc = launch_grid_fill_i32(h->hd.flags, (int32_t)cyc, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream))) return rc;
   HIPCHECK(hipStreamSynchronize(h->stream));

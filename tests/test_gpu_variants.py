@@ -107,3 +107,68 @@ def test_variants_batch_with_base_chips():
         o = O.OracleSim(p)
         o.step(n)
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags}"
+
+
+# ---- router delay -------------------------------------------------------------------------------
+@pytest.mark.parametrize("D", [2, 3, 8])
+def test_router_delay_config0_full_run(D):
+    assert_same_run(W.config0().with_(router_delay=D, op_thr=W.thr(0.5)), 6000, step_sizes=[1, 999, 5000])
+
+
+@pytest.mark.parametrize("D,flags", [(2, 0), (3, AGE), (4, AGE | HUM | DELAY)])
+@pytest.mark.parametrize("w,h", [(1, 7), (5, 5), (13, 7)])
+def test_router_delay_small_shapes(w, h, D, flags):
+    p = W.config0().with_(width=w, height=h, seed=w * 100 + h + D, bg_thr=W.thr(0.25), op_thr=W.thr(0.6),
+                          l1_sets=8, shared_lines=256, flags=flags, router_delay=D, reply_flits=2)
+    assert_same_run(p, 2500)
+
+
+@pytest.mark.parametrize("launch", [(4, 4, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
+def test_router_delay_patch_mappings(launch):
+    """Pipelines are tile-owned: any patch mapping and chunk length gives the same run."""
+    p = W.config0().with_(width=20, height=13, seed=9, bg_thr=W.thr(0.3), op_thr=W.thr(0.5), router_delay=3,
+                          flags=AGE)
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+
+
+def test_router_delay_config2_full_size_prefix():
+    assert_same_run(W.config2(0.1).with_(router_delay=2), 100, step_sizes=[40, 60])
+
+
+@pytest.mark.parametrize("D", [2, 5])
+def test_router_delay_checkpoint_and_drain_on_gpu(D):
+    p = W.config0().with_(width=6, height=6, seed=41 + D, bg_thr=W.thr(0.25), op_thr=W.thr(0.5), router_delay=D,
+                          flags=AGE)
+    a = gpu_sim(p)
+    da = a.step(1000, digests=True)
+    b = gpu_sim(p)
+    b.step(433)
+    snap = b.dump()
+    assert (split_dump(snap, p)["pipe"][..., 0] >= 0).any()
+    c = gpu_sim(p)
+    c.load(snap)
+    assert (c.step(567, digests=True) == da[433:]).all()
+    o = O.OracleSim(p)
+    o.load(snap)
+    o.step(567)
+    assert (c.dump() == o.dump()).all()
+    for s in (a, o):
+        s.set_rates(0, 0)
+        s.step(3000)
+    assert (a.dump() == o.dump()).all()
+    assert o.quiescent()
+    with pytest.raises(Exception):
+        gpu_sim(p.with_(router_delay=D + 1)).load(snap)
+
+
+def test_router_delay_batch_mixed():
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=5000 + i, bg_thr=W.thr(0.15), router_delay=d)
+              for i, (s, d) in enumerate([(8, 1), (16, 2), (8, 5), (24, 3)])]
+    sims = [gpu_sim(p) for p in params]
+    b = nocsim.Batch(sims)
+    b.step([300, 250, 300, 123])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123]):
+        o = O.OracleSim(p)
+        o.step(n)
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} router_delay {p.router_delay}"
