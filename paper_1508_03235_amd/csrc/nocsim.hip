@@ -300,7 +300,8 @@ __device__ __forceinline__ unsigned long long mix_pair(unsigned long long h, int
   return mix64(h ^ (((unsigned long long)(uint32_t)a << 32) | (uint32_t)b));
 }
 
-template <bool MULTI>
+// VAR: the chip may run a model variant or a router delay > 1 (compiled out otherwise)
+template <bool MULTI, bool VAR>
 __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y, int c, const bool cross[4], bool step,
                                           bool digest, unsigned long long& dsum, Acc& acc, LdsStats& L) {
   const int N = C.N;
@@ -346,7 +347,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   // flits arbitrated now are the ones that arrived D-1 cycles ago (stored below, in phase three)
   const int4 a0w = w0, a1w = w1, a2w = w2, a3w = w3;
   int4* pipe_now = nullptr;
-  if (C.rdelay > 1) {
+  if (VAR && C.rdelay > 1) {
     pipe_now = &C.pipe[(size_t)((uint32_t)c % (uint32_t)(C.rdelay - 1)) * 4 * N + t];
     w0 = v0 ? gload4(pipe_now) : EMPTY;
     w1 = v1 ? gload4(pipe_now + N) : EMPTY;
@@ -362,7 +363,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int4 k2 = gload4(&C.core[2 * N + t]);  // miss_head, miss_tail, bg_pending, force_line
   const int4 k3 = gload4(&C.core[3 * N + t]);  // force_dst, reply flits received, held op
   int fdst = k3.x, rcv = k3.y, hline = k3.z, hissue = k3.w;
-  const bool aged = C.variants & SIM_FLAG_AGE_DEFLECT;
+  const bool aged = VAR && (C.variants & SIM_FLAG_AGE_DEFLECT);
+  const int rdelay = VAR ? C.rdelay : 1, inj_delay = VAR ? C.inj_delay : 0;
   const uint32_t a0 = aged && v0 ? slot_age(w0) : 0u, a1 = aged && v1 ? slot_age(w1) : 0u;
   const uint32_t a2 = aged && v2 ? slot_age(w2) : 0u, a3 = aged && v3 ? slot_age(w3) : 0u;
 
@@ -391,8 +393,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, rcv, 0);    // reply flits received; the node's sent count is the home's
     h = mix_pair(h, hline, hissue);
     if (aged) mix_ages(a0w, a1w, a2w, a3w);
-    for (int st = 1; st < C.rdelay; ++st) {  // stage st: the flits arbitrated in cycle c-1+st
-      const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)(C.rdelay - 1)) * 4 * N + t];
+    for (int st = 1; st < rdelay; ++st) {  // stage st: the flits arbitrated in cycle c-1+st
+      const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)(rdelay - 1)) * 4 * N + t];
       const int4 x0 = v0 ? gload4(pp) : EMPTY, x1 = v1 ? gload4(pp + N) : EMPTY;
       const int4 x2 = v2 ? gload4(pp + 2 * N) : EMPTY, x3 = v3 ? gload4(pp + 3 * N) : EMPTY;
       mix_slots(x0, x1, x2, x3);
@@ -422,12 +424,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const bool fill = k0.x == CORE_FILL && wake;
   const bool missed = k0.x == CORE_L1MISS && wake;
   const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
-  const bool retry = k0.x == CORE_IDLE && hline >= 0;  // the op held back by the last miss
+  const bool retry = VAR && k0.x == CORE_IDLE && hline >= 0;  // the op held back by the last miss
   const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
   const bool drawn_idle = k0.x == CORE_IDLE && !retry && !forced && r.x < C.op_thr;
   // hit under miss (Sec. 3.5): a core with a miss outstanding still draws, unless the L1 is busy
   // with the fill or an op is already held
-  const bool drawn_hum = (C.variants & SIM_FLAG_HIT_UNDER_MISS) && k0.x != CORE_IDLE && !fill && hline < 0 &&
+  const bool drawn_hum = VAR && (C.variants & SIM_FLAG_HIT_UNDER_MISS) && k0.x != CORE_IDLE && !fill && hline < 0 &&
                          r.x < C.op_thr;
   const bool drawn = drawn_idle || drawn_hum;
   int* setR = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1))) * C.w2;
@@ -455,7 +457,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
     lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
     node_rq = rq;
-    node_ready = (hit ? c : c + C.mem_lat) + C.inj_delay;
+    node_ready = (hit ? c : c + C.mem_lat) + inj_delay;
     node_line = line;
     const int4 fresh = make_int4(-1, node_ready, line, 0);
     if (hit) {
@@ -553,7 +555,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int cls = -1;
   if (k2.x >= 0 && nm.y <= c) cls = 0;
   else if (k1.z >= 0 && nh.y <= c) cls = 1;
-  else if (k0.x == CORE_SEND && k0.y + C.inj_delay <= c) cls = 2;
+  else if (k0.x == CORE_SEND && k0.y + inj_delay <= c) cls = 2;
   else if (fdst >= 0) cls = 3;
   else if (k2.z > 0) cls = 4;
   if (cls >= 0 && arrivals >= deg) {
@@ -617,9 +619,10 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   // deflection count the count comes first, most deflected first (key 0xFFFF - count).  Only
   // (key, dst, index) tuples are sorted; the port of flit i is packed at bits 3i..3i+2 of
   // `ports` (7 = none) and each flit is stored straight into its neighbour's slot.
-  uint32_t qa0 = f0.x < 0 ? ~0u : aged ? AGE_MAX - a0 : 0u, qa1 = f1.x < 0 ? ~0u : aged ? AGE_MAX - a1 : 0u;
-  uint32_t qa2 = f2.x < 0 ? ~0u : aged ? AGE_MAX - a2 : 0u, qa3 = f3.x < 0 ? ~0u : aged ? AGE_MAX - a3 : 0u;
-  uint32_t qa4 = fi.x < 0 ? ~0u : aged ? (uint32_t)AGE_MAX : 0u;
+  // (without the count, qa is 0 for every slot: the empty ones still sort last on qh)
+  uint32_t qa0 = !aged ? 0u : f0.x < 0 ? ~0u : AGE_MAX - a0, qa1 = !aged ? 0u : f1.x < 0 ? ~0u : AGE_MAX - a1;
+  uint32_t qa2 = !aged ? 0u : f2.x < 0 ? ~0u : AGE_MAX - a2, qa3 = !aged ? 0u : f3.x < 0 ? ~0u : AGE_MAX - a3;
+  uint32_t qa4 = !aged ? 0u : fi.x < 0 ? ~0u : (uint32_t)AGE_MAX;
   uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
   uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
   uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
@@ -814,7 +817,7 @@ __device__ __forceinline__ void flush_counters(const Acc& acc, LdsStats& L, cons
 // up to min(flag + chunk, stop): one barrier per cycle inside the patch; patch edges are
 // synchronised through the stamped slots.  digests (optional, single chip): digests[c -
 // digest_base] += this patch's share of the digest of cycle c.
-template <bool MULTI>
+template <bool MULTI, bool VAR>
 __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict__ table, int chunk,
                                                    unsigned long long* digests, int digest_base) {
   __shared__ LdsStats L;
@@ -844,7 +847,7 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
       const int lx = j % cols, ly = j / cols, x = x0 + lx, y = y0 + ly;
       const bool cross[4] = {ly == 0 && y > 0, ly == rows - 1 && y < C.H - 1, lx == cols - 1 && x < C.W - 1,
                              lx == 0 && x > 0};
-      ok = ok && tile_step<MULTI>(C, y * C.W + x, x, y, c, cross, step, dig, h, acc, L);
+      ok = ok && tile_step<MULTI, VAR>(C, y * C.W + x, x, y, c, cross, step, dig, h, acc, L);
     }
     if (dig) {
       h = wave_sum(h);
@@ -1462,6 +1465,7 @@ struct sim_group {
   int32_t block;
   bool multi, fast;
   bool packets;                      // some chip has multi-flit replies
+  bool var;                          // some chip runs a model variant or a router delay > 1
   hipStream_t stream;
   LaunchEntry* table_dev;
   LaunchEntry* table_host;
@@ -1568,8 +1572,9 @@ int device_cus() {
   return cus;
 }
 
-const void* multi_kernel(bool fast, bool digest = false, bool packets = false) {
-  if (!fast) return reinterpret_cast<const void*>(step_kernel<true>);
+const void* multi_kernel(bool fast, bool digest = false, bool packets = false, bool var = false) {
+  if (!fast) return var ? reinterpret_cast<const void*>(step_kernel<true, true>)
+                        : reinterpret_cast<const void*>(step_kernel<true, false>);
   if (packets)
     return digest ? reinterpret_cast<const void*>(step_fast<true, true, true>)
                   : reinterpret_cast<const void*>(step_fast<true, false, true>);
@@ -1577,9 +1582,15 @@ const void* multi_kernel(bool fast, bool digest = false, bool packets = false) {
                 : reinterpret_cast<const void*>(step_fast<true, false, false>);
 }
 // how many workgroups of `block` threads of the multi-patch kernel can be resident at once
-int resident_limit(int block, bool fast) {
-  int per_cu = 0;
+int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
+  int per_cu = 0, per_cu_var = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
+  if (!fast) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(false, false, false, true), block, 0) !=
+        hipSuccess)
+      return 0;
+    per_cu = std::min(per_cu, per_cu_var);
+  }
   return per_cu * device_cus();
 }
 
@@ -1639,11 +1650,11 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
 // packets: some chip of the table has multi-flit replies (the kernel then reads each chip's count)
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
-                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets) {
+                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets, bool var) {
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, packets), dim3((unsigned)n), dim3(block),
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, packets, var), dim3((unsigned)n), dim3(block),
                                         args, 0, s));
   } else if (fast) {
     const dim3 g((unsigned)n), b(block);
@@ -1653,7 +1664,8 @@ int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, i
     else hipLaunchKernelGGL((step_fast<false, false, false>), g, b, 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   } else {
-    hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    if (var) hipLaunchKernelGGL((step_kernel<false, true>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    else hipLaunchKernelGGL((step_kernel<false, false>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   }
   return SIM_OK;
@@ -1823,7 +1835,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
     int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
-                            h->hd.reply_flits > 1);
+                            h->hd.reply_flits > 1, h->hd.variants != 0 || h->hd.rdelay > 1);
     if (rc) return rc;
   }
   h->cycle += n;
@@ -2067,7 +2079,11 @@ int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, si
   g->multi = multi;
   g->fast = fast;
   g->packets = false;
-  for (int i = 0; i < n; ++i) g->packets = g->packets || chips[i]->hd.reply_flits > 1;
+  g->var = false;
+  for (int i = 0; i < n; ++i) {
+    g->packets = g->packets || chips[i]->hd.reply_flits > 1;
+    g->var = g->var || chips[i]->hd.variants != 0 || chips[i]->hd.rdelay > 1;
+  }
   g->groups = groups;
   g->stream = static_cast<hipStream_t>(stream);
   g->table_dev = static_cast<LaunchEntry*>(dev_mem);
@@ -2107,7 +2123,7 @@ int simb_step(simb_t* g, const int64_t* cycles) {
     const int launches = (int)((lg_longest + chunk - 1) / chunk);
     for (int k = 0; k < launches; ++k) {
       int rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
-                              g->stream, g->packets);
+                              g->stream, g->packets, g->var);
       if (rc) return rc;
     }
   }
