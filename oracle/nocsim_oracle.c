@@ -24,7 +24,9 @@
  * by (seed; cycle, tile, stream)).  Three more literal readings can be switched
  * on as variants (ORACLE_FLAG_*): priority by deflection count, hits served
  * under an outstanding miss, and injection through the router's injection
- * register one cycle after a flit is made.  Every function below names the
+ * register one cycle after a flit is made; a router delay stretches every hop;
+ * and the paper's own L2 model, the LSPD cache with a directory (Sec. 3.2,
+ * 3.4, 6.2.2), replaces the static homes.  Every function below names the
  * passage it follows.
  *
  * Parity pins: the Philox generator is pinned to published known-answer
@@ -41,8 +43,17 @@
 #include <string.h>
 
 /* ---- fixed encodings --------------------------------------------------------------- */
-enum { K_REQ = 0, K_REPLY = 1, K_BG = 2 };                              /* flit kinds */
-enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4 }; /* core states */
+/* flit kinds; with the LSPD directory a request-class flit of kind K_DIR is a directory access
+   or an eviction notice, and a K_REPLY flit with the control bit set is a directory reply or a
+   trap (the control bit is bit 31 of the injection-cycle word, which cycles < 2^31 leave free) */
+enum { K_REQ = 0, K_REPLY = 1, K_BG = 2, K_DIR = 3 };
+enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4, /* core states */
+       ST_SEND_DA = 5, ST_SEND_RA = 6, ST_FILL_MEM = 7 };                   /* LSPD only */
+#define CTL_BIT 0x80000000u
+/* codes of the directory's and an owner's one-flit answers (queue node line word) */
+enum { CODE_TRAP = -2, CODE_NACK = -1 };
+/* request types at a slice's service input (the high byte of C_L2Q) */
+enum { Q_RA = 0, Q_DA = 1, Q_EV = 2 };
 enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
 /* per-tile core record (20 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
    node as a requester, written by its home while it waits there */
@@ -54,7 +65,10 @@ enum {
   C_NSENT = 17, /* flits of this tile's reply already injected by its home */
   C_DLINE = 18, /* hit under miss: line of the op waiting for the outstanding miss, -1 = none */
   C_DISSUE = 19,/* hit under miss: the waiting op's issue cycle */
-  C_WORDS = 20
+  C_TARGET = 20,/* LSPD: the owner a remote-access request goes to */
+  C_EV = 21,    /* LSPD: line whose eviction notice waits for injection, -1 = none */
+  C_DSUM_LO = 22, C_DSUM_HI = 23, /* LSPD: checksum of the directory entries this tile keeps */
+  C_WORDS = 24
 };
 /* flit record: destination, injection cycle, source, kind<<30 | line, and the number of times
    the flit has been deflected (kept for the AGE_DEFLECT variant, 0 otherwise); the first four
@@ -71,6 +85,10 @@ struct oracle_sim {
   int32_t W, H, N;
   int32_t reply_flits;   /* flits per reply packet */
   int32_t delay;         /* router delay D >= 1: cycles per hop */
+  int32_t lspd;          /* 0 static homes; 1 directory interleaved by line; 2 central directory */
+  int32_t dir_center;    /* the central directory's tile */
+  int64_t lines;         /* size of the line space (location array entries) */
+  int32_t* loc;          /* LSPD location array: [lines] owner tile or -1 */
   int32_t* scratch;      /* [2N], invariant checks */
   int64_t cycle;
   int32_t zk;
@@ -116,6 +134,12 @@ static void draw(const oracle_sim* s, int64_t cycle, int32_t tile, uint32_t stre
   uint32_t ctr[4] = {(uint32_t)cycle, (uint32_t)tile, stream, 0u};
   uint32_t key[2] = {s->cfg.seed_lo, s->cfg.seed_hi};
   oracle_philox4x32_10(ctr, key, out);
+}
+
+static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 2014) */
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
 }
 
 /* Zipf rank from a quantile table: bucket = high 16 bits, linear position inside it from
@@ -186,7 +210,8 @@ static int32_t* l1_set(oracle_sim* s, int32_t t, int32_t line) {
   return s->l1 + ((size_t)t * s->cfg.l1_sets + set) * s->cfg.l1_ways;
 }
 static int32_t* l2_set(oracle_sim* s, int32_t t, int32_t line) {
-  int32_t set = (line / s->N) & (s->cfg.l2_sets - 1);
+  /* a static home holds only its own lines: index by line / N; an LSPD slice holds any line */
+  int32_t set = (s->lspd ? line : line / s->N) & (s->cfg.l2_sets - 1);
   return s->l2 + ((size_t)t * s->cfg.l2_sets + set) * s->cfg.l2_ways;
 }
 
@@ -235,6 +260,32 @@ static int32_t drawn_line(const oracle_sim* s, int32_t t, const uint32_t* r) {
    router's injection register sits in between (INJECT_DELAY), else 0. */
 static int32_t inject_delay(const oracle_sim* s) { return (s->cfg.flags & ORACLE_FLAG_INJECT_DELAY) ? 1 : 0; }
 
+/* ---- LSPD directory (Sec. 3.2, Sec. 6.2.2): the location array ------------------------ */
+static int32_t dir_of(const oracle_sim* s, int32_t line) { return s->lspd == 2 ? s->dir_center : line % s->N; }
+static uint64_t dir_term(int32_t line, int32_t owner) {
+  return mix64(((uint64_t)(uint32_t)line << 32) | (uint32_t)owner);
+}
+/* Sets the directory entry of `line`, keeping the directory tile's checksum of its entries
+   (the sum of dir_term over the entries that name an owner). */
+static void dir_set(oracle_sim* s, int32_t line, int32_t owner) {
+  int32_t* k = s->core + (size_t)dir_of(s, line) * C_WORDS;
+  uint64_t sum = ((uint64_t)(uint32_t)k[C_DSUM_HI] << 32) | (uint32_t)k[C_DSUM_LO];
+  if (s->loc[line] >= 0) sum -= dir_term(line, s->loc[line]);
+  if (owner >= 0) sum += dir_term(line, owner);
+  s->loc[line] = owner;
+  k[C_DSUM_LO] = (int32_t)(uint32_t)sum;
+  k[C_DSUM_HI] = (int32_t)(uint32_t)(sum >> 32);
+}
+/* The directory's answer to tile `rq` asking for `line`: the owner, or a negative reply, in
+   which case the entry now names rq, which brings the block from memory into its slice. */
+static int32_t dir_lookup(oracle_sim* s, int32_t line, int32_t rq) {
+  s->stats[OS_DIR_ACCESS]++;
+  if (s->loc[line] >= 0) return s->loc[line];
+  dir_set(s, line, rq);
+  s->stats[OS_DIR_NACK]++;
+  return CODE_NACK;
+}
+
 /* ---- phase one: memory access (Sec. 7.1, work in phase one; Sec. 3.5) -------------- */
 static void phase_memory(oracle_sim* s, int32_t t) {
   const int64_t c = s->cycle;
@@ -244,10 +295,40 @@ static void phase_memory(oracle_sim* s, int32_t t) {
 
   /* home L2 slice serves the request that was ejected here in the previous cycle; the reply
      can leave once the block is there (at once on a hit, after mem_lat on a miss) */
-  if (k[C_L2Q] >= 0) {
+  if (k[C_L2Q] >= 0 && !s->lspd) {
     int32_t rq = k[C_L2Q], line = k[C_L2Q_LINE];
     if (l2_lookup(s, t, line)) list_append(s, t, C_HIT_H, C_HIT_T, rq, (int32_t)(c + delay), line);
     else list_append(s, t, C_MISS_H, C_MISS_T, rq, (int32_t)(c + s->cfg.mem_lat + delay), line);
+    k[C_L2Q] = -1;
+    k[C_L2Q_LINE] = -1;
+  }
+  /* LSPD: the message ejected here last cycle.  A remote access is served from this slice (the
+     block goes back in reply_flits flits) or trapped if the slice no longer holds the line; a
+     directory access is answered with the owner or a negative reply; an eviction notice clears
+     the entry (which names the sender until then).  One-flit answers wait in the miss queue, which an
+     LSPD slice does not otherwise use (Sec. 3.2, Sec. 6.2.2, Table 1). */
+  if (k[C_L2Q] >= 0 && s->lspd) {
+    int32_t type = k[C_L2Q] >> 24, who = k[C_L2Q] & 0xFFFFFF, line = k[C_L2Q_LINE];
+    if (type == Q_RA) {
+      if (cache_touch(l2_set(s, t, line), s->cfg.l2_ways, line, 0)) {
+        s->stats[OS_L2_HIT]++;
+        list_append(s, t, C_HIT_H, C_HIT_T, who, (int32_t)(c + delay), line);
+      } else {
+        s->stats[OS_TRAP]++;
+        list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), CODE_TRAP);
+      }
+    } else if (type == Q_DA) {
+      list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), dir_lookup(s, line, who));
+    } else {
+      /* the entry still names the evicting slice: only that slice's own notice changes an
+         entry that names an owner */
+      if (s->check && s->loc[line] != who && !s->bad) {
+        s->bad = 1;
+        snprintf(s->msg, sizeof s->msg, "eviction notice of %d for line %d named %d", who, line, s->loc[line]);
+      }
+      dir_set(s, line, -1);
+      s->stats[OS_DIR_EVICT]++;
+    }
     k[C_L2Q] = -1;
     k[C_L2Q_LINE] = -1;
   }
@@ -268,8 +349,62 @@ static void phase_memory(oracle_sim* s, int32_t t) {
         k[C_STATE] = ST_IDLE;
       }
       break;
+    case ST_FILL_MEM:
+      if (k[C_WAKE] == (int32_t)c) {            /* LSPD: block from memory into the local slice and L1 */
+        l1_used = 1;
+        int32_t line = k[C_LINE];
+        int32_t* set2 = l2_set(s, t, line);
+        int32_t victim = set2[s->cfg.l2_ways - 1];
+        cache_touch(set2, s->cfg.l2_ways, line, 1);
+        if (s->check) check_set(s, set2, s->cfg.l2_ways, "L2", t);
+        if (victim >= 0 && victim != line) {    /* the evicted block leaves the directory */
+          if (dir_of(s, victim) == t) {
+            dir_set(s, victim, -1);
+            s->stats[OS_DIR_EVICT]++;
+          } else {
+            k[C_EV] = victim;
+          }
+        }
+        int32_t* set = l1_set(s, t, line);
+        cache_touch(set, s->cfg.l1_ways, line, 1);
+        if (s->check) check_set(s, set, s->cfg.l1_ways, "L1", t);
+        int64_t lat = c - k[C_ISSUE];
+        s->stats[OS_OPS_DONE]++;
+        s->stats[OS_OP_LAT] += lat;
+        if (lat > s->stats[OS_OP_LAT_MAX]) s->stats[OS_OP_LAT_MAX] = lat;
+        k[C_STATE] = ST_IDLE;
+      }
+      break;
     case ST_L1MISS:
-      if (k[C_WAKE] == (int32_t)c) {            /* L1 miss penalty over: go to the home slice */
+      if (k[C_WAKE] == (int32_t)c && s->lspd) {
+        /* LSPD: the core's own slice, then the directory (at once when this tile keeps the
+           entry).  A pending eviction notice goes out first, so that a core has at most one. */
+        int32_t line = k[C_LINE];
+        if (k[C_EV] >= 0) {
+          k[C_WAKE] = (int32_t)(c + 1);
+        } else if (cache_touch(l2_set(s, t, line), s->cfg.l2_ways, line, 0)) {
+          s->stats[OS_L2_HIT]++;
+          k[C_STATE] = ST_FILL;
+          k[C_WAKE] = (int32_t)(c + 1);
+        } else {
+          s->stats[OS_L2_MISS]++;
+          if (dir_of(s, line) == t) {
+            int32_t o = dir_lookup(s, line, t);
+            if (o == CODE_NACK) {
+              k[C_STATE] = ST_FILL_MEM;
+              k[C_WAKE] = (int32_t)(c + s->cfg.mem_lat);
+            } else {                            /* a local entry never names this tile here */
+              k[C_STATE] = ST_SEND_RA;
+              k[C_TARGET] = o;
+              k[C_WAKE] = (int32_t)(c + delay);
+              s->stats[OS_REQ_MADE]++;
+            }
+          } else {
+            k[C_STATE] = ST_SEND_DA;
+            k[C_WAKE] = (int32_t)(c + delay);
+          }
+        }
+      } else if (k[C_WAKE] == (int32_t)c) {     /* L1 miss penalty over: go to the home slice */
         int32_t line = k[C_LINE];
         if (line % s->N == t) {
           int hit = l2_lookup(s, t, line);
@@ -438,10 +573,15 @@ static void phase_route(oracle_sim* s, int32_t t) {
 
   /* injection candidate: ready miss reply, ready hit reply, own request (made at least
      inject_delay cycles ago), test flit, background */
+  /* (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
+     eviction notice, a directory access or a remote-access request) */
   int cls = -1;
+  const int own = s->lspd ? (k[C_EV] >= 0 || ((k[C_STATE] == ST_SEND_DA || k[C_STATE] == ST_SEND_RA) &&
+                                              k[C_WAKE] <= (int32_t)c))
+                          : (k[C_STATE] == ST_SEND && k[C_WAKE] + inject_delay(s) <= (int32_t)c);
   if (k[C_MISS_H] >= 0 && s->core[(size_t)k[C_MISS_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 0;
   else if (k[C_HIT_H] >= 0 && s->core[(size_t)k[C_HIT_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 1;
-  else if (k[C_STATE] == ST_SEND && k[C_WAKE] + inject_delay(s) <= (int32_t)c) cls = 2;
+  else if (own) cls = 2;
   else if (k[C_FDST] >= 0) cls = 3;
   else if (k[C_BG] > 0) cls = 4;
   if (cls >= 0 && arrivals >= deg) {
@@ -453,7 +593,31 @@ static void phase_route(oracle_sim* s, int32_t t) {
     f[F_INJ] = (int32_t)c;
     f[F_SRC] = t;
     f[F_AGE] = 0;
-    if (cls == 0 || cls == 1) {
+    if (cls == 0 && s->lspd) {                 /* directory reply or trap: one flit */
+      int32_t rq = list_pop(s, t, C_MISS_H, C_MISS_T);
+      f[F_DST] = rq;
+      f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
+      f[F_INFO] = (K_REPLY << 30) | (s->core[(size_t)rq * C_WORDS + C_NLINE] + 2);
+      s->stats[OS_INJ_REPLY]++;
+    } else if (cls == 2 && s->lspd) {
+      const int32_t line = k[C_LINE];
+      if (k[C_EV] >= 0) {                       /* eviction notice to the block's directory */
+        f[F_DST] = dir_of(s, k[C_EV]);
+        f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
+        f[F_INFO] = (K_DIR << 30) | k[C_EV];
+        k[C_EV] = -1;
+      } else if (k[C_STATE] == ST_SEND_DA) {    /* directory access */
+        f[F_DST] = dir_of(s, line);
+        f[F_INFO] = (K_DIR << 30) | line;
+        k[C_STATE] = ST_WAIT;
+      } else {                                  /* remote access at the owner */
+        f[F_DST] = k[C_TARGET];
+        f[F_INFO] = (K_REQ << 30) | line;
+        k[C_TARGET] = -1;
+        k[C_STATE] = ST_WAIT;
+      }
+      s->stats[OS_INJ_REQ]++;
+    } else if (cls == 0 || cls == 1) {
       int32_t rq = k[cls == 0 ? C_MISS_H : C_HIT_H];
       int32_t* node = s->core + (size_t)rq * C_WORDS;
       f[F_DST] = rq;
@@ -490,7 +654,8 @@ static void phase_route(oracle_sim* s, int32_t t) {
   const int aged = (s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT) != 0;
   int32_t dst[5], inj[5], src[5], age[5], port[5], defl[5];
   for (int i = 0; i < n; ++i) {
-    dst[i] = fl[i][F_DST]; inj[i] = fl[i][F_INJ]; src[i] = fl[i][F_SRC]; age[i] = fl[i][F_AGE];
+    dst[i] = fl[i][F_DST]; inj[i] = (int32_t)((uint32_t)fl[i][F_INJ] & ~CTL_BIT); src[i] = fl[i][F_SRC];
+    age[i] = fl[i][F_AGE];
   }
   int rc = arbitrate_router(s->W, s->H, t, n, dst, inj, src, aged ? age : NULL, port, defl);
   if (rc != ORACLE_OK && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "router %d: no port", t); }
@@ -531,9 +696,11 @@ static void phase_move(oracle_sim* s, int32_t t) {
   const int32_t* ej = s->ej + (size_t)t * F_WORDS;
   if (ej[F_DST] >= 0) {
     int kind = (int)((uint32_t)ej[F_INFO] >> 30);
-    int64_t lat = c - ej[F_INJ];
-    s->stats[OS_EJ_REQ + kind]++;
-    s->stats[OS_LAT_REQ + kind] += lat;
+    const int ctl = ((uint32_t)ej[F_INJ] & CTL_BIT) != 0;
+    const int cl = kind == K_DIR ? K_REQ : kind;  /* directory messages count as requests */
+    int64_t lat = c - (int32_t)((uint32_t)ej[F_INJ] & ~CTL_BIT);
+    s->stats[OS_EJ_REQ + cl]++;
+    s->stats[OS_LAT_REQ + cl] += lat;
     if (lat > s->stats[OS_LAT_MAX]) s->stats[OS_LAT_MAX] = lat;
     int bin = 0;
     while (bin < 15 && (lat >> (bin + 1)) > 0) bin++;
@@ -546,10 +713,30 @@ static void phase_move(oracle_sim* s, int32_t t) {
         snprintf(s->msg, sizeof s->msg, "flit latency %lld over %lld hops at %d", (long long)lat, (long long)man, t);
       }
     }
-    if (kind == K_REQ) {                       /* request reaches its home slice */
+    if (kind == K_REQ) {                       /* request reaches its home slice (LSPD: the owner) */
       s->stats[OS_REQ_RECV]++;
       k[C_L2Q] = ej[F_SRC];
       k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
+    } else if (kind == K_DIR) {                /* LSPD: directory access or eviction notice */
+      k[C_L2Q] = ej[F_SRC] | ((ctl ? Q_EV : Q_DA) << 24);
+      k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
+    } else if (kind == K_REPLY && ctl) {       /* LSPD: directory reply or trap */
+      if (k[C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "answer at idle tile %d", t); }
+      int32_t code = (ej[F_INFO] & LINE_MASK) - 2;
+      k[C_WAKE] = (int32_t)(c + 1);
+      if (code == CODE_NACK) {                 /* not on chip: from memory into the local slice */
+        k[C_STATE] = ST_FILL_MEM;
+        k[C_WAKE] = (int32_t)(c + s->cfg.mem_lat);
+      } else if (code == CODE_TRAP || code == t) {
+        /* ask the directory again: its entry was stale (the owner had evicted the block, or
+           this tile's own eviction notice has not reached the directory yet) */
+        if (code == t) s->stats[OS_TRAP]++;
+        k[C_STATE] = ST_SEND_DA;
+      } else {
+        k[C_STATE] = ST_SEND_RA;
+        k[C_TARGET] = code;
+        s->stats[OS_REQ_MADE]++;
+      }
     } else if (kind == K_REPLY) {              /* a flit of the block reaches the requester */
       if (k[C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "reply at idle tile %d", t); }
       if (++k[C_RCV] == s->reply_flits) {      /* all flits in: the block is complete */
@@ -567,11 +754,6 @@ static void phase_move(oracle_sim* s, int32_t t) {
 }
 
 /* ---- per-cycle state digest --------------------------------------------------------- */
-static uint64_t mix64(uint64_t z) { /* SplitMix64 finalizer (Steele, Lea, Flood 2014) */
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
 /* Digest of the words tile t owns after cycle c: the four words of each of its input slots
    for the next cycle and its core record, then, in the AGE_DEFLECT variant, the deflection
    counts of those slots' flits packed in pairs (16 bits each, 0 for an empty slot).  The
@@ -617,7 +799,7 @@ static uint64_t tile_digest(const oracle_sim* s, int64_t c, int32_t t) {
 static void check_cycle(oracle_sim* s) {
   const int64_t c = s->cycle;
   const int32_t* nxt = s->link[(c + 1) & 1];
-  int64_t occupied = 0, req_fl = 0;
+  int64_t occupied = 0, req_fl = 0, ans_fl = 0;
   int32_t* rep_to = s->scratch;              /* reply flits in flight, per requester */
   int32_t* queued_at = s->scratch + s->N;    /* 1 while the requester sits in a home's queue */
   memset(s->scratch, 0, (size_t)s->N * 2 * sizeof(int32_t));
@@ -629,8 +811,10 @@ static void check_cycle(oracle_sim* s) {
         if (f[F_DST] < 0) continue;
         occupied++;
         int kind = (int)((uint32_t)f[F_INFO] >> 30);
-        if (kind == K_REQ) req_fl++;
-        if (kind == K_REPLY) rep_to[f[F_DST]]++;
+        const int ctl = ((uint32_t)f[F_INJ] & CTL_BIT) != 0;
+        if (kind == K_REQ || (kind == K_DIR && !ctl)) req_fl++;   /* remote or directory access */
+        if (kind == K_REPLY && ctl) ans_fl++;                    /* directory reply or trap */
+        if (kind == K_REPLY && !ctl) rep_to[f[F_DST]]++;
         if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
       }
     }
@@ -648,7 +832,7 @@ static void check_cycle(oracle_sim* s) {
   for (int32_t t = 0; t < s->N; ++t) {
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] == ST_WAIT) waiting++;
-    if (k[C_L2Q] >= 0) at_home++;
+    if (k[C_L2Q] >= 0 && (k[C_L2Q] >> 24) != Q_EV) at_home++;
     for (int which = 0; which < 2; ++which) {
       int32_t r = k[which ? C_MISS_H : C_HIT_H], last = -1;
       int64_t len = 0;
@@ -680,10 +864,24 @@ static void check_cycle(oracle_sim* s) {
       }
     }
   }
-  if (waiting != req_fl + rep_pk + queued + at_home && !s->bad) {
+  if (waiting != req_fl + ans_fl + rep_pk + queued + at_home && !s->bad) {
     s->bad = 1;
-    snprintf(s->msg, sizeof s->msg, "requester accounting: waiting=%lld req=%lld reply=%lld queued=%lld at_home=%lld",
-             (long long)waiting, (long long)req_fl, (long long)rep_pk, (long long)queued, (long long)at_home);
+    snprintf(s->msg, sizeof s->msg, "requester accounting: waiting=%lld req=%lld answers=%lld reply=%lld queued=%lld at_home=%lld",
+             (long long)waiting, (long long)req_fl, (long long)ans_fl, (long long)rep_pk, (long long)queued,
+             (long long)at_home);
+  }
+  /* LSPD: one copy of a block on chip, and the directory names the slice that holds it */
+  if (s->lspd) {
+    const int32_t S2 = s->cfg.l2_sets, W2 = s->cfg.l2_ways;
+    for (int32_t t = 0; t < s->N && !s->bad; ++t)
+      for (int32_t i = 0; i < S2 * W2; ++i) {
+        const int32_t line = s->l2[(size_t)t * S2 * W2 + i];
+        if (line >= 0 && s->loc[line] != t) {
+          s->bad = 1;
+          snprintf(s->msg, sizeof s->msg, "slice %d holds line %d, directory names %d", t, line, s->loc[line]);
+          break;
+        }
+      }
   }
 }
 
@@ -724,8 +922,11 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   if ((int64_t)cfg->shared_lines + N * cfg->private_lines > (int64_t)LINE_MASK + 1) return ORACLE_EINVAL;
   if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
   if (cfg->reply_flits < 0 || cfg->reply_flits > 16) return ORACLE_EINVAL;
-  if (cfg->flags & ~(ORACLE_FLAG_AGE_DEFLECT | ORACLE_FLAG_HIT_UNDER_MISS | ORACLE_FLAG_INJECT_DELAY)) return ORACLE_EINVAL;
+  if (cfg->flags & ~(ORACLE_FLAG_AGE_DEFLECT | ORACLE_FLAG_HIT_UNDER_MISS | ORACLE_FLAG_INJECT_DELAY | ORACLE_FLAG_LSPD |
+                     ORACLE_FLAG_LSPD_CENTRAL))
+    return ORACLE_EINVAL;
   if (cfg->router_delay < 0 || cfg->router_delay > 8) return ORACLE_EINVAL;
+  if ((cfg->flags & ORACLE_FLAG_LSPD_CENTRAL) && !(cfg->flags & ORACLE_FLAG_LSPD)) return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
   s->cfg = *cfg;
@@ -734,6 +935,9 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->N = (int32_t)N;
   s->reply_flits = cfg->reply_flits > 0 ? cfg->reply_flits : 1;
   s->delay = cfg->router_delay > 0 ? cfg->router_delay : 1;
+  s->lspd = (cfg->flags & ORACLE_FLAG_LSPD) ? ((cfg->flags & ORACLE_FLAG_LSPD_CENTRAL) ? 2 : 1) : 0;
+  s->dir_center = (cfg->height / 2) * cfg->width + cfg->width / 2;
+  s->lines = (int64_t)cfg->shared_lines + N * cfg->private_lines;
   s->zk = zk;
   s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
   s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
@@ -748,8 +952,9 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
   s->scratch = (int32_t*)malloc((size_t)N * 2 * 4);
   s->pipe = (int32_t*)malloc((size_t)(s->delay - 1) * N * SLOT_WORDS * 4 + 4);
+  s->loc = (int32_t*)malloc((size_t)(s->lspd ? s->lines : 0) * 4 + 4);
   if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
-      !s->oldest_ok || !s->scratch || !s->pipe) {
+      !s->oldest_ok || !s->scratch || !s->pipe || !s->loc) {
     oracle_destroy(s);
     return ORACLE_ENOMEM;
   }
@@ -759,6 +964,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   memset(s->link[0], 0xFF, (size_t)N * SLOT_WORDS * 4);
   memset(s->link[1], 0xFF, (size_t)N * SLOT_WORDS * 4);
   memset(s->pipe, 0xFF, (size_t)(s->delay - 1) * N * SLOT_WORDS * 4);
+  if (s->lspd) memset(s->loc, 0xFF, (size_t)s->lines * 4);
   memset(s->core, 0xFF, (size_t)N * C_WORDS * 4);
   for (int64_t t = 0; t < N; ++t) {
     s->core[t * C_WORDS + C_STATE] = ST_IDLE;
@@ -766,6 +972,8 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
     s->core[t * C_WORDS + C_RCV] = 0;
     s->core[t * C_WORDS + C_NSENT] = 0;
     s->core[t * C_WORDS + C_DISSUE] = 0;
+    s->core[t * C_WORDS + C_DSUM_LO] = 0;
+    s->core[t * C_WORDS + C_DSUM_HI] = 0;
   }
   memset(s->l1, 0xFF, (size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
   memset(s->l2, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
@@ -776,7 +984,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
 void oracle_destroy(oracle_sim* s) {
   if (!s) return;
   free(s->zs); free(s->zp); free(s->link[0]); free(s->link[1]); free(s->core); free(s->l1); free(s->l2);
-  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch); free(s->pipe);
+  free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch); free(s->pipe); free(s->loc);
   free(s);
 }
 
@@ -791,7 +999,7 @@ int64_t oracle_cycle(const oracle_sim* s) { return s ? s->cycle : -1; }
 size_t oracle_dump_words(const oracle_sim* s) {
   size_t N = (size_t)s->N;
   return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways +
-         2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20;
+         2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20 + (size_t)(s->lspd ? s->lines : 0);
 }
 
 /* Canonical state (format version 3): header {magic, 3, W, H, cycle (low, high), L1 sets,
@@ -801,13 +1009,14 @@ size_t oracle_dump_words(const oracle_sim* s) {
    flit (0 for an empty slot and outside the AGE_DEFLECT variant), and with a router delay
    D > 1 (header word 13) the routers' pipelines: stages 1..D-1, stage k holding the flits
    arbitrated k-1 cycles after the dump's cycle, four words per slot, then their deflection
-   counts. */
+   counts, and with the LSPD directory (header word 14: 1 interleaved, 2 central) the location
+   array, one word per line. */
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
   int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 3, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
                               s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
-                              C_WORDS, s->cfg.flags, s->delay, 0, 0};
+                              C_WORDS, s->cfg.flags, s->delay, s->lspd, 0};
   memcpy(buf, hdr, sizeof hdr);
   o += DUMP_HEADER;
   const int32_t* slots = s->link[s->cycle & 1];
@@ -835,6 +1044,7 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
     const int32_t* f = pipe_stage(s, s->cycle + st - 1, 0);
     for (size_t i = 0; i < N * 4; ++i) buf[o++] = f[i * F_WORDS + F_DST] >= 0 ? f[i * F_WORDS + F_AGE] : 0;
   }
+  if (s->lspd) memcpy(buf + o, s->loc, (size_t)s->lines * 4);
   return ORACLE_OK;
 }
 
@@ -842,7 +1052,7 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   if (buf[0] != DUMP_MAGIC || buf[1] != 3 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
       buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
-      buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay)
+      buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay || buf[14] != s->lspd)
     return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = DUMP_HEADER;
   s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
@@ -873,6 +1083,12 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
       if (ages[i] != 0 && !(s->cfg.flags & ORACLE_FLAG_AGE_DEFLECT)) return ORACLE_EINVAL;
       f[i * F_WORDS + F_AGE] = f[i * F_WORDS + F_DST] >= 0 ? ages[i] : -1;
     }
+  }
+  o += (size_t)(s->delay - 1) * N * 20;
+  if (s->lspd) {
+    for (int64_t i = 0; i < s->lines; ++i)
+      if (buf[o + i] < -1 || buf[o + i] >= s->N) return ORACLE_EINVAL;
+    memcpy(s->loc, buf + o, (size_t)s->lines * 4);
   }
   for (size_t t = 0; t < N; ++t)
     if (s->core[t * C_WORDS + C_DLINE] >= 0 && !(s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS)) return ORACLE_EINVAL;
@@ -907,7 +1123,7 @@ int oracle_quiescent(const oracle_sim* s) {
       if (cur[(size_t)t * SLOT_WORDS + p * F_WORDS] >= 0) return 0;
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
-        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0)
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0 || k[C_EV] >= 0)
       return 0;
   }
   return 1;

@@ -50,8 +50,21 @@ typedef struct {
      (Sec. 3.5).  The base model's core issues nothing while a miss is outstanding.
    INJECT_DELAY: a request or reply made in a cycle can enter the network from the next cycle
      on (the router's injection register, filled in phase three: Sec. 6.2.1, Sec. 7.1).  The
-     base model injects it in the cycle it is made. */
-enum { ORACLE_FLAG_AGE_DEFLECT = 1, ORACLE_FLAG_HIT_UNDER_MISS = 2, ORACLE_FLAG_INJECT_DELAY = 4 };
+     base model injects it in the cycle it is made.
+   LSPD: the logically shared, physically distributed L2 with a directory (Sec. 3.2, 3.4,
+     6.2.2, Table 1): a block lives in the slice of the core that brought it from memory (local
+     placement); an L1 miss looks in the core's own slice, then asks the directory (DA), which
+     answers with the owner or a negative reply (DR); on a negative reply the block comes from
+     memory into the local slice, otherwise the core asks the owner (RA) for it.  An owner that
+     no longer holds the block answers with a trap and the core asks the directory again; a
+     slice that evicts a block sends the directory an eviction notice.  Directory entries are
+     kept in a location array indexed by line; the entry of a line belongs to the line's
+     directory slice, line mod N, or with LSPD_CENTRAL to the one tile at the mesh centre.
+     The base model homes each line statically at slice line mod N. */
+enum {
+  ORACLE_FLAG_AGE_DEFLECT = 1, ORACLE_FLAG_HIT_UNDER_MISS = 2, ORACLE_FLAG_INJECT_DELAY = 4,
+  ORACLE_FLAG_LSPD = 8, ORACLE_FLAG_LSPD_CENTRAL = 16
+};
 
 enum {
   ORACLE_OK = 0,
@@ -72,6 +85,7 @@ enum {
   OS_L1_HIT = 16, OS_L1_MISS = 17, OS_L2_HIT = 18, OS_L2_MISS = 19,
   OS_REQ_MADE = 20, OS_REQ_RECV = 21, OS_REPLY_SENT = 22, OS_REPLY_RECV = 23,
   OS_INJ_BLOCKED = 24, OS_BG_GEN = 25, OS_OP_LAT_MAX = 26,
+  OS_DIR_ACCESS = 27, OS_DIR_NACK = 28, OS_TRAP = 29, OS_DIR_EVICT = 30, /* LSPD directory */
   OS_HIST = 32, /* 16 bins: floor(log2(latency)), last bin open */
   OS_COUNT = 48
 };

@@ -23,6 +23,7 @@ STAT_NAMES = {
     "l1_hit": 16, "l1_miss": 17, "l2_hit": 18, "l2_miss": 19, "req_made": 20,
     "req_received": 21, "reply_sent": 22, "reply_received": 23, "inj_blocked": 24,
     "bg_generated": 25, "op_lat_max": 26,
+    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30,
 }
 HIST = 32
 

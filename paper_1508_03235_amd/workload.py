@@ -35,6 +35,11 @@ FIELDS = (
 AGE_DEFLECT = 1
 HIT_UNDER_MISS = 2
 INJECT_DELAY = 4
+# The paper's logically shared, physically distributed L2 with a directory (local placement,
+# directory access / reply, remote access, traps, eviction notices); the directory is
+# interleaved over the tiles by line, or with LSPD_CENTRAL kept by the tile at the mesh centre.
+LSPD = 8
+LSPD_CENTRAL = 16
 
 
 def thr(p: float) -> int:
@@ -78,7 +83,7 @@ class SimParams:
     zipf_shared_s: float = 0.8
     zipf_private_s: float = 0.9
     reply_flits: int = 1      # flits per reply packet (the paper's Table 1: 4 for a remote L2 access)
-    flags: int = 0            # model variants: AGE_DEFLECT | HIT_UNDER_MISS | INJECT_DELAY
+    flags: int = 0            # model variants: AGE_DEFLECT | HIT_UNDER_MISS | INJECT_DELAY | LSPD [| LSPD_CENTRAL]
     router_delay: int = 1     # cycles per hop (a flit waits router_delay - 1 cycles in each router)
 
     @property

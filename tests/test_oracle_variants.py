@@ -416,7 +416,9 @@ def test_variants_change_the_run():
 
 def test_unknown_flags_are_refused():
     with pytest.raises(ValueError):
-        O.OracleSim(quiet_params(2, 2, flags=8))
+        O.OracleSim(quiet_params(2, 2, flags=32))
+    with pytest.raises(ValueError):
+        O.OracleSim(quiet_params(2, 2, flags=W.LSPD_CENTRAL))   # central needs the directory
 
 
 # ---- router delay: every hop takes D cycles ----------------------------------------------------
