@@ -78,8 +78,21 @@ typedef struct {
      its latency counted from its first issue (Sec. 3.5).
    INJECT_DELAY: requests and replies pass through the router's injection register and can
      enter the network only from the cycle after they are made (Sec. 6.2.1, Sec. 7.1 phase
-     three). */
-enum { SIM_FLAG_AGE_DEFLECT = 1, SIM_FLAG_HIT_UNDER_MISS = 2, SIM_FLAG_INJECT_DELAY = 4 };
+     three).
+   LSPD: the paper's logically shared, physically distributed L2 with a directory (Sec. 3.2,
+     3.4, 6.2.2, Table 1) instead of static homes.  A block lives in the slice of the core that
+     brought it from memory; an L1 miss looks in the core's own slice, then sends a directory
+     access (1 flit) to the line's directory slice (line mod N, or with LSPD_CENTRAL the tile
+     at (width/2, height/2)); the directory answers (1 flit) with the owner, or negatively and
+     records the asker as owner, which then brings the block from memory into its slice (after
+     mem_lat); an owner answers a remote access with reply_flits flits, or with a trap (1 flit)
+     if it has evicted the block, and the core asks the directory again; a slice that evicts a
+     block sends an eviction notice (1 flit) that clears the entry.  Directory entries live in
+     a location array of one int32 per line (shared_lines + N * private_lines entries). */
+enum {
+  SIM_FLAG_AGE_DEFLECT = 1, SIM_FLAG_HIT_UNDER_MISS = 2, SIM_FLAG_INJECT_DELAY = 4, SIM_FLAG_LSPD = 8,
+  SIM_FLAG_LSPD_CENTRAL = 16
+};
 
 /* Statistics: 48 int64 counters (index = position in `v`).  Latencies are in cycles from
    injection to ejection; op latency from issue to L1 fill. */
@@ -96,6 +109,10 @@ enum {
   SIM_ST_REQ_MADE = 20, SIM_ST_REQ_RECV = 21, SIM_ST_REPLY_SENT = 22, SIM_ST_REPLY_RECV = 23,
   SIM_ST_INJ_BLOCKED = 24,  /* tile-cycles with a flit to inject but no free input */
   SIM_ST_BG_GEN = 25, SIM_ST_OP_LAT_MAX = 26,
+  SIM_ST_DIR_ACCESS = 27,   /* LSPD: directory look-ups (remote and local) */
+  SIM_ST_DIR_NACK = 28,     /* LSPD: negative directory answers = blocks brought from memory */
+  SIM_ST_TRAP = 29,         /* LSPD: stale directory answers (owner without the block) */
+  SIM_ST_DIR_EVICT = 30,    /* LSPD: directory entries cleared by evictions */
   SIM_ST_HIST = 32,         /* 16 bins of floor(log2(latency)); the last bin is open */
   SIM_ST_COUNT = 48
 };
@@ -133,16 +150,19 @@ int sim_stats(sim_t* h, sim_stats_t* out);
 
 /* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 3, width,
    height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, reply_flits (>= 1),
-   core-record words (20), flags, 0...}, then per tile the 4 input slots of the next cycle
-   ({dst (-1 = empty), inject cycle, source, kind<<30 | line}), then per tile 20 core words
-   {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail, miss_head, miss_tail,
-   bg_pending, node_next, node_ready, node_line, force_line, force_dst, reply flits received,
-   node flits sent, held line (-1 = none), held issue cycle}, then L1 and L2 tags per tile per
+   core-record words (24), flags, router delay, LSPD mode (0 static homes, 1 interleaved
+   directory, 2 central), 0}, then per tile the 4 input slots of the next cycle ({dst (-1 =
+   empty), inject cycle (bit 31: LSPD control flit), source, kind<<30 | line}), then per tile
+   24 core words {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail, miss_head,
+   miss_tail, bg_pending, node_next, node_ready, node_line, force_line, force_dst, reply flits
+   received, node flits sent, held line (-1 = none), held issue cycle, remote-access target,
+   pending eviction line, directory checksum lo, hi}, then L1 and L2 tags per tile per
    set (most recently used first, -1 invalid), then the 48 statistics as (low, high) word
    pairs, then per tile the deflection counts of the 4 input slots' flits (0 when empty or
    without AGE_DEFLECT), then, when router_delay D > 1 (header word 13 = D), the routers'
    pipelines: stages k = 1..D-1 (stage k holds the flits arbitrated k-1 cycles after the
-   dump's cycle), each as per tile 4 slots of 4 words, then the stages' deflection counts.
+   dump's cycle), each as per tile 4 slots of 4 words, then the stages' deflection counts,
+   then with LSPD the location array (owner tile per line, -1 = not on chip).
    sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);

@@ -29,16 +29,25 @@
 namespace {
 
 // ---- encodings ---------------------------------------------------------------------------
-constexpr int KIND_REQ = 0, KIND_REPLY = 1, KIND_BG = 2;
+// With the LSPD directory, KIND_DIR flits are directory accesses or (control bit) eviction
+// notices, and KIND_REPLY flits with the control bit are directory answers or traps; the control
+// bit is bit 31 of the inject-cycle word (cycles stay below 2^31).
+constexpr int KIND_REQ = 0, KIND_REPLY = 1, KIND_BG = 2, KIND_DIR = 3;
 constexpr int CORE_IDLE = 0, CORE_L1MISS = 1, CORE_SEND = 2, CORE_WAIT = 3, CORE_FILL = 4;
+constexpr int CORE_SEND_DA = 5, CORE_SEND_RA = 6, CORE_FILL_MEM = 7;  // LSPD
+constexpr uint32_t CTL_BIT = 0x80000000u;
+constexpr int CODE_TRAP = -2, CODE_NACK = -1;  // one-flit answers (queue node line word)
+constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2;    // message types at a slice's service input (l2q >> 24)
 constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // words of a tile's record in the canonical dump: state, wake, line, issue, l2q, l2q_line,
 // hit head/tail, miss head/tail, bg_pending, node next/ready/line, force_line, force_dst,
-// reply flits received, node flits sent, held line, held issue cycle
-constexpr int CORE_RECORD = 20;
+// reply flits received, node flits sent, held line, held issue cycle, remote-access target,
+// pending eviction line, directory checksum (low, high)
+constexpr int CORE_RECORD = 24;
 constexpr int DUMP_VERSION = 3;
 // model variants (sim_config.flags); the one-tile-per-thread kernel runs the base model only
-constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
+constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY | SIM_FLAG_LSPD |
+                                  SIM_FLAG_LSPD_CENTRAL;
 constexpr int AGE_MAX = 0xFFFF;  // deflections a flit may take; one more stops the run (livelock)
 constexpr int ZIPF_K = 65536;
 constexpr int MAX_PATCHES = 4096;
@@ -59,12 +68,17 @@ struct ChipDev {
   int32_t variants;          // SIM_FLAG_* model variants
   int32_t inj_delay;         // 1 when a flit can enter the network only the cycle after it is made
   int32_t rdelay;            // router delay D >= 1: cycles per hop
+  int32_t lspd;              // 0 static homes; 1 LSPD, directory interleaved by line; 2 central directory
+  int32_t dir_center;        // the central directory's tile
+  int32_t lines;             // line space: shared_lines + N * private_lines
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int4* link;                // [2 parity][4 port][N]
   int4* pipe;                // [D-1][4 port][N]: raw slot words of flits waiting in the routers'
                              // pipelines; entry (a mod (D-1)) holds those arbitrated in cycle a
-  int4* core;                // [4][N]; word group 3: force_dst, reply flits received, held line, held issue
+  int4* core;                // [5][N]; group 3: force_dst, reply flits received, held line, held issue;
+                             // group 4 (LSPD): remote-access target, pending eviction, directory checksum lo, hi
+  int32_t* loc;              // LSPD location array [lines]: owner tile or -1; entry L belongs to L's directory tile
   int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
   int32_t* l2;               // [N][s2][w2]
@@ -365,6 +379,10 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int fdst = k3.x, rcv = k3.y, hline = k3.z, hissue = k3.w;
   const bool aged = VAR && (C.variants & SIM_FLAG_AGE_DEFLECT);
   const int rdelay = VAR ? C.rdelay : 1, inj_delay = VAR ? C.inj_delay : 0;
+  const bool lspd = VAR && C.lspd != 0;
+  // LSPD core words: remote-access target, pending eviction, directory checksum (constant
+  // -1, -1, 0, 0 without the directory)
+  int4 k4 = lspd ? gload4(&C.core[4 * N + t]) : make_int4(-1, -1, 0, 0);
   const uint32_t a0 = aged && v0 ? slot_age(w0) : 0u, a1 = aged && v1 ? slot_age(w1) : 0u;
   const uint32_t a2 = aged && v2 ? slot_age(w2) : 0u, a3 = aged && v3 ? slot_age(w3) : 0u;
 
@@ -392,6 +410,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, k2.w, fdst);
     h = mix_pair(h, rcv, 0);    // reply flits received; the node's sent count is the home's
     h = mix_pair(h, hline, hissue);
+    h = mix_pair(h, k4.x, k4.y);
+    h = mix_pair(h, k4.z, k4.w);
     if (aged) mix_ages(a0w, a1w, a2w, a3w);
     for (int st = 1; st < rdelay; ++st) {  // stage st: the flits arbitrated in cycle c-1+st
       const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)(rdelay - 1)) * 4 * N + t];
@@ -414,16 +434,34 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     st_coh(C.err, 2);                                              \
     return false;                                                  \
   }
+#define GUARD_LINE(l)                                              \
+  if ((unsigned)(l) >= (unsigned)C.lines) {                        \
+    st_coh(C.err, 2);                                              \
+    return false;                                                  \
+  }
   const bool svc = k1.x >= 0;  // a request was ejected here last cycle: home-slice lookup
-  if (svc) { GUARD(k1.x) }
+  const int svc_type = lspd ? (k1.x >> 24) : Q_RA, svc_who = lspd ? (k1.x & 0xFFFFFF) : k1.x;
+  if (svc) { GUARD(svc_who) }
+  if (lspd && svc) { GUARD_LINE(k1.y) }
+  if (lspd && k4.x >= 0) { GUARD(k4.x) }
+  if (lspd && k4.y >= 0) { GUARD_LINE(k4.y) }
   if (k1.z >= 0) { GUARD(k1.z) }
   if (k1.w >= 0) { GUARD(k1.w) }
   if (k2.x >= 0) { GUARD(k2.x) }
   if (k2.y >= 0) { GUARD(k2.y) }
   const bool wake = k0.y == c;
-  const bool fill = k0.x == CORE_FILL && wake;
+  const bool fill_mem = lspd && k0.x == CORE_FILL_MEM && wake;  // LSPD: block from memory
+  const bool fill = (k0.x == CORE_FILL && wake) || fill_mem;
   const bool missed = k0.x == CORE_L1MISS && wake;
-  const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  const bool local = !lspd && missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  // LSPD: the core's own slice (after an L1 miss, unless an eviction notice is still pending,
+  // and when a block from memory is installed) and the directory entries this cycle touches
+  auto dir_of = [&](int line) -> int { return C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)line); };
+  const bool slice_look = lspd && missed && k4.y < 0;
+  if (slice_look || fill_mem) { GUARD_LINE(k0.z) }
+  const bool dir_core = slice_look && dir_of(k0.z) == t;
+  const int loc_svc = lspd && svc && svc_type == Q_DA ? *gp(&C.loc[k1.y]) : -1;
+  const int loc_core = dir_core ? *gp(&C.loc[k0.z]) : -1;
   const bool retry = VAR && k0.x == CORE_IDLE && hline >= 0;  // the op held back by the last miss
   const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
   const bool drawn_idle = k0.x == CORE_IDLE && !retry && !forced && r.x < C.op_thr;
@@ -432,11 +470,13 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const bool drawn_hum = VAR && (C.variants & SIM_FLAG_HIT_UNDER_MISS) && k0.x != CORE_IDLE && !fill && hline < 0 &&
                          r.x < C.op_thr;
   const bool drawn = drawn_idle || drawn_hum;
-  int* setR = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1))) * C.w2;
-  int* setL = C.l2 + ((size_t)t * C.s2 + (div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1))) * C.w2;
+  // L2 set: a static home holds only its own lines (index line / N); an LSPD slice any line
+  const uint32_t ixR = lspd ? (uint32_t)k1.y : div_n(C, (uint32_t)k1.y), ixL = lspd ? (uint32_t)k0.z : div_n(C, (uint32_t)k0.z);
+  int* setR = C.l2 + ((size_t)t * C.s2 + (ixR & (uint32_t)(C.s2 - 1))) * C.w2;
+  int* setL = C.l2 + ((size_t)t * C.s2 + (ixL & (uint32_t)(C.s2 - 1))) * C.w2;
   int vR[8], vL[8], u[8];
-  if (svc) set_load(setR, C.w2, vR);
-  if (local) set_load(setL, C.w2, vL);
+  if (svc && svc_type == Q_RA) set_load(setR, C.w2, vR);
+  if (local || slice_look || fill_mem) set_load(setL, C.w2, vL);
   int4 nh = EMPTY, nm = EMPTY;  // nodes at the hit-queue and miss-queue heads: next, ready, line
   if (k1.z >= 0) nh = ld_node<MULTI>(&C.node[k1.z]);
   if (k2.x >= 0) nm = ld_node<MULTI>(&C.node[k2.x]);
@@ -450,17 +490,16 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (fill || retry || forced || drawn) set_load(set1, C.w1, u);
 
   // ---- phase one: home L2 service, then the core (Sec. 7.1, phase one; Sec. 3.5) ----------
-  bool dirtyR = false, dirtyL = false, dirty1 = false;
+  bool dirtyR = false, dirtyL = false, dirty1 = false, d4 = false;
   int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0, node_w = 0;
-  if (svc) {
-    const int rq = k1.x, line = k1.y;
-    const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
-    lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
+  // appends requester rq to this tile's hit queue (replies with the block) or miss queue (a
+  // static home's memory misses; an LSPD slice's one-flit answers); its node is written below
+  auto enqueue = [&](bool hitq, int rq, int ready, int word) {
     node_rq = rq;
-    node_ready = (hit ? c : c + C.mem_lat) + inj_delay;
-    node_line = line;
-    const int4 fresh = make_int4(-1, node_ready, line, 0);
-    if (hit) {
+    node_ready = ready;
+    node_line = word;
+    const int4 fresh = make_int4(-1, ready, word, 0);
+    if (hitq) {
       if (k1.w >= 0) {
         node_tail = k1.w;
         if (k1.w == k1.z) nh.x = rq;
@@ -479,18 +518,102 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       }
       k2.y = rq;
     }
+  };
+  // LSPD directory entries of this tile: each write also moves the tile's checksum
+  unsigned long long dsum_dir = (unsigned long long)(uint32_t)k4.z | ((unsigned long long)(uint32_t)k4.w << 32);
+  int fwd_line = -1, fwd_val = 0;  // the entry written by the service, read again by the core
+  auto dir_write = [&](int line, int old_owner, int owner) {
+    if (old_owner >= 0) dsum_dir -= mix64(((unsigned long long)(uint32_t)line << 32) | (uint32_t)old_owner);
+    if (owner >= 0) dsum_dir += mix64(((unsigned long long)(uint32_t)line << 32) | (uint32_t)owner);
+    *gp(&C.loc[line]) = owner;
+    fwd_line = line;
+    fwd_val = owner;
+    d4 = true;
+  };
+  if (svc && !lspd) {
+    const int rq = k1.x, line = k1.y;
+    const bool hit = set_touch(vR, C.w2, line, true, dirtyR);
+    lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_L2_MISS, 1);
+    enqueue(hit, rq, (hit ? c : c + C.mem_lat) + inj_delay, line);
+    k1.x = -1;
+    k1.y = -1;
+    d1 = true;
+    d2 = true;
+  } else if (svc) {  // LSPD (Sec. 3.2, Sec. 6.2.2): remote access, directory access, eviction notice
+    const int who = svc_who, line = k1.y;
+    if (svc_type == Q_RA) {
+      const bool hit = set_touch(vR, C.w2, line, false, dirtyR);
+      lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_TRAP, 1);
+      enqueue(hit, who, c + inj_delay, hit ? line : CODE_TRAP);
+    } else if (svc_type == Q_DA) {
+      lds_add(L, SIM_ST_DIR_ACCESS, 1);
+      int code = loc_svc;
+      if (loc_svc < 0) {  // not on chip: the asker will bring it from memory
+        dir_write(line, -1, who);
+        lds_add(L, SIM_ST_DIR_NACK, 1);
+        code = CODE_NACK;
+      }
+      enqueue(false, who, c + inj_delay, code);
+    } else {  // the entry names the evicting slice until its notice arrives
+      dir_write(line, who, -1);
+      lds_add(L, SIM_ST_DIR_EVICT, 1);
+    }
     k1.x = -1;
     k1.y = -1;
     d1 = true;
     d2 = true;
   }
   if (fill) {  // the block arrived: fill L1, the op completes
+    if (fill_mem) {  // LSPD: into the local slice too; an evicted block leaves the directory
+      const int victim = vL[C.w2 - 1];
+      set_touch(vL, C.w2, k0.z, true, dirtyL);
+      if (victim >= 0 && victim != k0.z) {
+        GUARD_LINE(victim)
+        if (dir_of(victim) == t) {
+          dir_write(victim, t, -1);
+          lds_add(L, SIM_ST_DIR_EVICT, 1);
+        } else {
+          k4.y = victim;
+          d4 = true;
+        }
+      }
+    }
     set_touch(u, C.w1, line_op, true, dirty1);
     const unsigned long long lat = (unsigned long long)(c - k0.w);
     lds_add(L, SIM_ST_OPS_DONE, 1);
     lds_add(L, SIM_ST_OP_LAT, lat);
     atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
     k0.x = CORE_IDLE;
+    d0 = true;
+  } else if (missed && lspd) {  // LSPD: own slice, then the directory (Sec. 3.2)
+    if (k4.y >= 0) {
+      k0.y = c + 1;  // the pending eviction notice goes out first
+    } else if (set_touch(vL, C.w2, k0.z, false, dirtyL)) {
+      lds_add(L, SIM_ST_L2_HIT, 1);
+      k0.x = CORE_FILL;
+      k0.y = c + 1;
+    } else {
+      lds_add(L, SIM_ST_L2_MISS, 1);
+      if (dir_core) {  // this tile keeps the entry: look it up at once
+        lds_add(L, SIM_ST_DIR_ACCESS, 1);
+        const int o = fwd_line == k0.z ? fwd_val : loc_core;
+        if (o < 0) {
+          dir_write(k0.z, -1, t);
+          lds_add(L, SIM_ST_DIR_NACK, 1);
+          k0.x = CORE_FILL_MEM;
+          k0.y = c + C.mem_lat;
+        } else {
+          k0.x = CORE_SEND_RA;
+          k4.x = o;
+          d4 = true;
+          k0.y = c + inj_delay;
+          lds_add(L, SIM_ST_REQ_MADE, 1);
+        }
+      } else {
+        k0.x = CORE_SEND_DA;
+        k0.y = c + inj_delay;
+      }
+    }
     d0 = true;
   } else if (missed) {  // L1 miss penalty over: local home slice, or a request flit
     if (local) {
@@ -552,10 +675,14 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   // ---- phase two: injection into a free input, then oldest-first arbitration ----------------
   const int arrivals = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0);
   const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
+  // (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
+  // eviction notice, a directory access or a remote-access request)
+  const bool own = lspd ? (k4.y >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
+                        : (k0.x == CORE_SEND && k0.y + inj_delay <= c);
   int cls = -1;
   if (k2.x >= 0 && nm.y <= c) cls = 0;
   else if (k1.z >= 0 && nh.y <= c) cls = 1;
-  else if (k0.x == CORE_SEND && k0.y + inj_delay <= c) cls = 2;
+  else if (own) cls = 2;
   else if (fdst >= 0) cls = 3;
   else if (k2.z > 0) cls = 4;
   if (cls >= 0 && arrivals >= deg) {
@@ -566,7 +693,36 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (cls >= 0) {
     fi.y = c;
     fi.z = t;
-    if (cls <= 1) {  // a flit of the head's reply; the head is popped with the packet's last flit
+    if (cls == 0 && lspd) {  // directory answer or trap: one flit, control bit set
+      fi.x = k2.x;
+      fi.y = (int)((uint32_t)c | CTL_BIT);
+      fi.w = (KIND_REPLY << 30) | (nm.z + 2);
+      k2.x = nm.x;
+      if (nm.x < 0) k2.y = -1;
+      acc.inj_reply++;
+      d2 = true;
+    } else if (cls == 2 && lspd) {
+      if (k4.y >= 0) {  // eviction notice to the block's directory tile
+        fi.x = dir_of(k4.y);
+        fi.y = (int)((uint32_t)c | CTL_BIT);
+        fi.w = (KIND_DIR << 30) | k4.y;
+        k4.y = -1;
+        d4 = true;
+      } else if (k0.x == CORE_SEND_DA) {  // directory access
+        fi.x = dir_of(k0.z);
+        fi.w = (KIND_DIR << 30) | k0.z;
+        k0.x = CORE_WAIT;
+        d0 = true;
+      } else {  // remote access at the owner
+        fi.x = k4.x;
+        fi.w = (KIND_REQ << 30) | k0.z;
+        k4.x = -1;
+        d4 = true;
+        k0.x = CORE_WAIT;
+        d0 = true;
+      }
+      acc.inj_req++;
+    } else if (cls <= 1) {  // a flit of the head's reply; the head is popped with the packet's last flit
       const int4 hd = cls == 0 ? nm : nh;
       const int rq = cls == 0 ? k2.x : k1.z;
       const int sent = hd.w + 1;
@@ -623,11 +779,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   uint32_t qa0 = !aged ? 0u : f0.x < 0 ? ~0u : AGE_MAX - a0, qa1 = !aged ? 0u : f1.x < 0 ? ~0u : AGE_MAX - a1;
   uint32_t qa2 = !aged ? 0u : f2.x < 0 ? ~0u : AGE_MAX - a2, qa3 = !aged ? 0u : f3.x < 0 ? ~0u : AGE_MAX - a3;
   uint32_t qa4 = !aged ? 0u : fi.x < 0 ? ~0u : (uint32_t)AGE_MAX;
-  uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
-  uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
-  uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
-  uint32_t qh3 = f3.x < 0 ? ~0u : (uint32_t)f3.y, ql3 = f3.x < 0 ? ~0u : (uint32_t)f3.z;
-  uint32_t qh4 = fi.x < 0 ? ~0u : (uint32_t)fi.y, ql4 = fi.x < 0 ? ~0u : (uint32_t)fi.z;
+  const uint32_t ym = lspd ? ~CTL_BIT : ~0u;  // the inject cycle without the LSPD control bit
+  uint32_t qh0 = f0.x < 0 ? ~0u : (uint32_t)f0.y & ym, ql0 = f0.x < 0 ? ~0u : (uint32_t)f0.z;
+  uint32_t qh1 = f1.x < 0 ? ~0u : (uint32_t)f1.y & ym, ql1 = f1.x < 0 ? ~0u : (uint32_t)f1.z;
+  uint32_t qh2 = f2.x < 0 ? ~0u : (uint32_t)f2.y & ym, ql2 = f2.x < 0 ? ~0u : (uint32_t)f2.z;
+  uint32_t qh3 = f3.x < 0 ? ~0u : (uint32_t)f3.y & ym, ql3 = f3.x < 0 ? ~0u : (uint32_t)f3.z;
+  uint32_t qh4 = fi.x < 0 ? ~0u : (uint32_t)fi.y & ym, ql4 = fi.x < 0 ? ~0u : (uint32_t)fi.z;
   int sd0 = f0.x, sd1 = f1.x, sd2 = f2.x, sd3 = f3.x, sd4 = fi.x;
   int si0 = 0, si1 = 1, si2 = 2, si3 = 3, si4 = 4;
 #define CSWAP(a, b)                                                                              \
@@ -720,12 +877,14 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
 
   if (oe.x >= 0) {
     const int kind = (int)((uint32_t)oe.w >> 30);
-    const int lat = c - oe.y;
+    const bool ctl = lspd && ((uint32_t)oe.y & CTL_BIT);
+    const int lat = c - (int)((uint32_t)oe.y & ym);
     const unsigned long long ulat = (unsigned long long)lat;
-    acc.ej_req += kind == KIND_REQ;
+    const bool as_req = kind == KIND_REQ || kind == KIND_DIR;  // directory messages count as requests
+    acc.ej_req += as_req;
     acc.ej_reply += kind == KIND_REPLY;
     acc.ej_bg += kind == KIND_BG;
-    acc.lat_req += kind == KIND_REQ ? ulat : 0ull;
+    acc.lat_req += as_req ? ulat : 0ull;
     acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
     acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
     atomicMax(&L.v[SIM_ST_LAT_MAX], (unsigned long long)lat);
@@ -735,6 +894,27 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       k1.x = oe.z;
       k1.y = oe.w & LINE_MASK;
       d1 = true;
+    } else if (kind == KIND_DIR) {  // LSPD: directory access or (control bit) eviction notice
+      k1.x = oe.z | ((ctl ? Q_EV : Q_DA) << 24);
+      k1.y = oe.w & LINE_MASK;
+      d1 = true;
+    } else if (kind == KIND_REPLY && ctl) {  // LSPD: the directory's answer or a trap
+      const int code = (oe.w & LINE_MASK) - 2;
+      if (code == CODE_NACK) {  // not on chip: from memory into the local slice
+        k0.x = CORE_FILL_MEM;
+        k0.y = c + C.mem_lat;
+      } else if (code == CODE_TRAP || code == t) {  // stale entry: ask the directory again
+        if (code == t) lds_add(L, SIM_ST_TRAP, 1);
+        k0.x = CORE_SEND_DA;
+        k0.y = c + 1;
+      } else {
+        k0.x = CORE_SEND_RA;
+        k0.y = c + 1;
+        k4.x = code;
+        d4 = true;
+        lds_add(L, SIM_ST_REQ_MADE, 1);
+      }
+      d0 = true;
     } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
       rcv += 1;
       d3 = true;
@@ -756,7 +936,13 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (d1) gstore4(&C.core[N + t], k1);
   if (d2) gstore4(&C.core[2 * N + t], k2);
   if (d3) gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, hline, hissue));
+  if (d4) {
+    k4.z = (int)(uint32_t)dsum_dir;
+    k4.w = (int)(uint32_t)(dsum_dir >> 32);
+    gstore4(&C.core[4 * N + t], k4);
+  }
 #undef GUARD
+#undef GUARD_LINE
   return true;
 }
 
@@ -1233,6 +1419,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, d2.w, dfd);
         h = mix_pair(h, drcv, 0);
         h = mix_pair(h, -1, 0);  // no op is held in the base model
+        h = mix_pair(h, -1, -1);  // nor a remote-access target or eviction notice,
+        h = mix_pair(h, 0, 0);    // and no directory entry
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1425,6 +1613,7 @@ __global__ void init_core(int4* core, int4* node, int N) {
     core[N + t] = make_int4(-1, -1, -1, -1);
     core[2 * N + t] = make_int4(-1, -1, 0, -1);
     core[3 * N + t] = make_int4(-1, 0, -1, 0);  // forced background destination, reply flits received, held op
+    core[4 * N + t] = make_int4(-1, -1, 0, 0);  // remote-access target, pending eviction, directory checksum
     node[t] = make_int4(-1, -1, -1, 0);
   }
 }
@@ -1496,13 +1685,17 @@ bool config_ok(const sim_config* c) {
   if (c->reply_flits < 0 || c->reply_flits > 16) return false;
   if (c->flags & ~VARIANT_FLAGS) return false;
   if (c->router_delay < 0 || c->router_delay > 8) return false;
+  if ((c->flags & SIM_FLAG_LSPD_CENTRAL) && !(c->flags & SIM_FLAG_LSPD)) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
 
 struct Layout {
-  size_t desc, link, pipe, core, node, l1, l2, zs, zp, flags, table, stats, err, total;
+  size_t desc, link, pipe, core, node, loc, l1, l2, zs, zp, flags, table, stats, err, total;
 };
+size_t lspd_lines(const sim_config* c) {  // location-array entries (0 without the directory)
+  return (c->flags & SIM_FLAG_LSPD) ? (size_t)c->shared_lines + (size_t)c->width * c->height * c->private_lines : 0;
+}
 int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_delay : 1; }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
@@ -1516,7 +1709,8 @@ Layout layout(const sim_config* c) {
   L.desc = take(sizeof(ChipDev));
   L.link = take(2 * 4 * N * sizeof(int4));
   L.pipe = take((size_t)(router_delay(c) - 1) * 4 * N * sizeof(int4));
-  L.core = take(4 * N * sizeof(int4));
+  L.core = take(5 * N * sizeof(int4));
+  L.loc = take(lspd_lines(c) * sizeof(int32_t));
   L.node = take(N * sizeof(int4));
   L.l1 = take(N * c->l1_sets * c->l1_ways * sizeof(int32_t));
   L.l2 = take(N * c->l2_sets * c->l2_ways * sizeof(int32_t));
@@ -1743,12 +1937,16 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.variants = cfg->flags;
   d.inj_delay = (cfg->flags & SIM_FLAG_INJECT_DELAY) ? 1 : 0;
   d.rdelay = router_delay(cfg);
+  d.lspd = (cfg->flags & SIM_FLAG_LSPD) ? ((cfg->flags & SIM_FLAG_LSPD_CENTRAL) ? 2 : 1) : 0;
+  d.dir_center = (cfg->height / 2) * cfg->width + cfg->width / 2;
+  d.lines = (int32_t)lspd_lines(cfg);
   d.shared_lines = cfg->shared_lines;
   d.private_lines = cfg->private_lines;
   d.stop = 0;
   d.max_patches = max_patches(cfg);
   d.link = reinterpret_cast<int4*>(h->base + Lo.link);
   d.pipe = reinterpret_cast<int4*>(h->base + Lo.pipe);
+  d.loc = reinterpret_cast<int32_t*>(h->base + Lo.loc);
   d.core = reinterpret_cast<int4*>(h->base + Lo.core);
   d.node = reinterpret_cast<int4*>(h->base + Lo.node);
   d.l1 = reinterpret_cast<int32_t*>(h->base + Lo.l1);
@@ -1772,6 +1970,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
   if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.pipe), -1, (size_t)(d.rdelay - 1) * 4 * N * 4, h->stream)))
     return fail(rc);
+  if ((rc = launch_grid_fill_i32(d.loc, -1, lspd_lines(cfg), h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l1, -1, (size_t)N * cfg->l1_sets * cfg->l1_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l2, -1, (size_t)N * cfg->l2_sets * cfg->l2_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_u64(d.stats, 0, NSTAT, h->stream))) return fail(rc);
@@ -1857,16 +2056,16 @@ size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
   return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4 +
-         (size_t)(h->hd.rdelay - 1) * N * 20;
+         (size_t)(h->hd.rdelay - 1) * N * 20 + (size_t)h->hd.lines;
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   if (!h || !buf || words < sim_dump_words(h)) return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const int par = (int)(h->cycle & 1);
-  std::vector<int4> link(4 * N), core(4 * N), node(N);
+  std::vector<int4> link(4 * N), core(5 * N), node(N);
   HIPCHECK(hipMemcpyAsync(link.data(), h->hd.link + (size_t)par * 4 * N, 4 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
-  HIPCHECK(hipMemcpyAsync(core.data(), h->hd.core, 4 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(core.data(), h->hd.core, 5 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipMemcpyAsync(node.data(), h->hd.node, N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
   size_t o = 16;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
@@ -1879,16 +2078,17 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   HIPCHECK(hipStreamSynchronize(h->stream));
   const int32_t hdr[16] = {0x4E4F4353, DUMP_VERSION, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle,
                            (int32_t)(h->cycle >> 32), h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits,
-                           CORE_RECORD, h->hd.variants, h->hd.rdelay, 0, 0};
+                           CORE_RECORD, h->hd.variants, h->hd.rdelay, h->hd.lspd, 0};
   std::memcpy(buf, hdr, sizeof hdr);
   int32_t* ages = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT;
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) host_decode(link[p * N + t], buf + o + t * 16 + p * 4, ages + t * 4 + p);
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
-    const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], nd = node[t];
-    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y,
-                                      k2.z, nd.x, nd.y, nd.z, k2.w, k3.x, k3.y, nd.w, k3.z, k3.w};
+    const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], k4 = core[4 * N + t];
+    const int4 nd = node[t];
+    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y, k2.z, nd.x,
+                                      nd.y, nd.z, k2.w, k3.x, k3.y, nd.w, k3.z, k3.w, k4.x, k4.y, k4.z, k4.w};
     std::memcpy(buf + o + t * CORE_RECORD, rec, sizeof rec);
   }
   o += N * CORE_RECORD + n1 + n2;
@@ -1911,6 +2111,11 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
                       pa + ((size_t)(k - 1) * N + t) * 4 + p);
     }
   }
+  o += (size_t)(D - 1) * N * 20;
+  if (h->hd.lines) {  // LSPD location array
+    HIPCHECK(hipMemcpyAsync(buf + o, h->hd.loc, (size_t)h->hd.lines * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  }
   return SIM_OK;
 }
 
@@ -1919,7 +2124,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (buf[0] != 0x4E4F4353 || buf[1] != DUMP_VERSION || buf[2] != h->hd.W || buf[3] != h->hd.H ||
       buf[6] != h->hd.s1 || buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 ||
       buf[10] != h->hd.reply_flits || buf[11] != CORE_RECORD || buf[12] != h->hd.variants ||
-      buf[13] != h->hd.rdelay)
+      buf[13] != h->hd.rdelay || buf[14] != h->hd.lspd)
     return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
@@ -1927,7 +2132,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   const bool aged = h->hd.variants & SIM_FLAG_AGE_DEFLECT;
   const int64_t cyc = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
   if (cyc < 0 || cyc > 0x7FFFFFFF) return SIM_EINVAL;
-  std::vector<int4> link(4 * N), core(4 * N), node(N);
+  std::vector<int4> link(4 * N), core(5 * N), node(N);
   size_t o = 16;
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) {
@@ -1945,7 +2150,11 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     core[2 * N + t] = make_int4(r[8], r[9], r[10], r[14]);
     // a held op exists only with hit under miss (the base kernel keeps none)
     if (r[18] >= 0 && !(h->hd.variants & SIM_FLAG_HIT_UNDER_MISS)) return SIM_EINVAL;
+    // the directory's words: a target and a pending eviction only with LSPD
+    if (!h->hd.lspd && (r[20] != -1 || r[21] != -1 || r[22] != 0 || r[23] != 0)) return SIM_EINVAL;
+    if (r[20] < -1 || r[20] >= (int32_t)N || r[21] < -1 || r[21] >= h->hd.lines) return SIM_EINVAL;
     core[3 * N + t] = make_int4(r[15], r[16], r[18], r[19]);
+    core[4 * N + t] = make_int4(r[20], r[21], r[22], r[23]);
     node[t] = make_int4(r[11], r[12], r[13], r[17]);
   }
   o += N * CORE_RECORD;
@@ -1968,6 +2177,10 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
         }
     }
   }
+  // LSPD location array: owners in range
+  const int32_t* locw = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT + N * 4 + (size_t)(D - 1) * N * 20;
+  for (int32_t i = 0; i < h->hd.lines; ++i)
+    if (locw[i] < -1 || locw[i] >= (int32_t)N) return SIM_EINVAL;
   const int par = (int)(cyc & 1);
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)par * 4 * N, link.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   // the other parity: empty, stamped cyc-1 (it is rewritten during cycle cyc)
@@ -1975,7 +2188,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)(par ^ 1) * 4 * N, other.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   int rc = SIM_OK;
-  HIPCHECK(hipMemcpyAsync(h->hd.core, core.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->hd.core, core.data(), 5 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.node, node.data(), N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.l1, buf + o, n1 * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.l2, buf + o + n1, n2 * 4, hipMemcpyHostToDevice, h->stream));
@@ -1984,6 +2197,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   for (int i = 0; i < NSTAT; ++i) st[i] = (unsigned long long)(uint32_t)buf[o + 2 * i] | ((unsigned long long)(uint32_t)buf[o + 2 * i + 1] << 32);
   HIPCHECK(hipMemcpyAsync(h->hd.stats, st, sizeof st, hipMemcpyHostToDevice, h->stream));
   if (D > 1) HIPCHECK(hipMemcpyAsync(h->hd.pipe, pipe.data(), pipe.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+  if (h->hd.lines) HIPCHECK(hipMemcpyAsync(h->hd.loc, locw, (size_t)h->hd.lines * 4, hipMemcpyHostToDevice, h->stream));
   h->cycle = cyc;
   if ((rc = launch_grid_fill_i32(h->hd.flags, (int32_t)cyc, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream))) return rc;
   HIPCHECK(hipStreamSynchronize(h->stream));
