@@ -314,8 +314,9 @@ __device__ __forceinline__ unsigned long long mix_pair(unsigned long long h, int
   return mix64(h ^ (((unsigned long long)(uint32_t)a << 32) | (uint32_t)b));
 }
 
-// VAR: the chip may run a model variant or a router delay > 1 (compiled out otherwise)
-template <bool MULTI, bool VAR>
+// VAR: 0 = the base model only; 1 = model variants and router delay; 2 = also the LSPD
+// directory (the paths a level does not need are compiled out)
+template <bool MULTI, int VAR>
 __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y, int c, const bool cross[4], bool step,
                                           bool digest, unsigned long long& dsum, Acc& acc, LdsStats& L) {
   const int N = C.N;
@@ -379,7 +380,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int fdst = k3.x, rcv = k3.y, hline = k3.z, hissue = k3.w;
   const bool aged = VAR && (C.variants & SIM_FLAG_AGE_DEFLECT);
   const int rdelay = VAR ? C.rdelay : 1, inj_delay = VAR ? C.inj_delay : 0;
-  const bool lspd = VAR && C.lspd != 0;
+  const bool lspd = VAR == 2 && C.lspd != 0;
   // LSPD core words: remote-access target, pending eviction, directory checksum (constant
   // -1, -1, 0, 0 without the directory)
   int4 k4 = lspd ? gload4(&C.core[4 * N + t]) : make_int4(-1, -1, 0, 0);
@@ -1003,7 +1004,7 @@ __device__ __forceinline__ void flush_counters(const Acc& acc, LdsStats& L, cons
 // up to min(flag + chunk, stop): one barrier per cycle inside the patch; patch edges are
 // synchronised through the stamped slots.  digests (optional, single chip): digests[c -
 // digest_base] += this patch's share of the digest of cycle c.
-template <bool MULTI, bool VAR>
+template <bool MULTI, int VAR>
 __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict__ table, int chunk,
                                                    unsigned long long* digests, int digest_base) {
   __shared__ LdsStats L;
@@ -1654,7 +1655,7 @@ struct sim_group {
   int32_t block;
   bool multi, fast;
   bool packets;                      // some chip has multi-flit replies
-  bool var;                          // some chip runs a model variant or a router delay > 1
+  int var;                           // general-kernel build: 1 a variant or router delay > 1, 2 the directory
   hipStream_t stream;
   LaunchEntry* table_dev;
   LaunchEntry* table_host;
@@ -1697,6 +1698,8 @@ size_t lspd_lines(const sim_config* c) {  // location-array entries (0 without t
   return (c->flags & SIM_FLAG_LSPD) ? (size_t)c->shared_lines + (size_t)c->width * c->height * c->private_lines : 0;
 }
 int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_delay : 1; }
+// which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
+int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
 
@@ -1766,9 +1769,10 @@ int device_cus() {
   return cus;
 }
 
-const void* multi_kernel(bool fast, bool digest = false, bool packets = false, bool var = false) {
-  if (!fast) return var ? reinterpret_cast<const void*>(step_kernel<true, true>)
-                        : reinterpret_cast<const void*>(step_kernel<true, false>);
+const void* multi_kernel(bool fast, bool digest = false, bool packets = false, int var = 0) {
+  if (!fast) return var == 2 ? reinterpret_cast<const void*>(step_kernel<true, 2>)
+                    : var == 1 ? reinterpret_cast<const void*>(step_kernel<true, 1>)
+                               : reinterpret_cast<const void*>(step_kernel<true, 0>);
   if (packets)
     return digest ? reinterpret_cast<const void*>(step_fast<true, true, true>)
                   : reinterpret_cast<const void*>(step_fast<true, false, true>);
@@ -1779,8 +1783,8 @@ const void* multi_kernel(bool fast, bool digest = false, bool packets = false, b
 int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
   int per_cu = 0, per_cu_var = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
-  if (!fast) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(false, false, false, true), block, 0) !=
+  for (int v = 1; !fast && v <= 2; ++v) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(false, false, false, v), block, 0) !=
         hipSuccess)
       return 0;
     per_cu = std::min(per_cu, per_cu_var);
@@ -1844,7 +1848,7 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
 // packets: some chip of the table has multi-flit replies (the kernel then reads each chip's count)
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
-                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets, bool var) {
+                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets, int var) {
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
@@ -1858,8 +1862,10 @@ int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, i
     else hipLaunchKernelGGL((step_fast<false, false, false>), g, b, 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   } else {
-    if (var) hipLaunchKernelGGL((step_kernel<false, true>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
-    else hipLaunchKernelGGL((step_kernel<false, false>), dim3((unsigned)n), dim3(block), 0, s, table, chunk, digests, digest_base);
+    const dim3 g((unsigned)n), b(block);
+    if (var == 2) hipLaunchKernelGGL((step_kernel<false, 2>), g, b, 0, s, table, chunk, digests, digest_base);
+    else if (var == 1) hipLaunchKernelGGL((step_kernel<false, 1>), g, b, 0, s, table, chunk, digests, digest_base);
+    else hipLaunchKernelGGL((step_kernel<false, 0>), g, b, 0, s, table, chunk, digests, digest_base);
     HIPCHECK(hipGetLastError());
   }
   return SIM_OK;
@@ -2034,7 +2040,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
     int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
-                            h->hd.reply_flits > 1, h->hd.variants != 0 || h->hd.rdelay > 1);
+                            h->hd.reply_flits > 1, kernel_level(h->hd));
     if (rc) return rc;
   }
   h->cycle += n;
@@ -2293,10 +2299,10 @@ int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, si
   g->multi = multi;
   g->fast = fast;
   g->packets = false;
-  g->var = false;
+  g->var = 0;
   for (int i = 0; i < n; ++i) {
     g->packets = g->packets || chips[i]->hd.reply_flits > 1;
-    g->var = g->var || chips[i]->hd.variants != 0 || chips[i]->hd.rdelay > 1;
+    g->var = std::max(g->var, kernel_level(chips[i]->hd));
   }
   g->groups = groups;
   g->stream = static_cast<hipStream_t>(stream);
