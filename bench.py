@@ -44,7 +44,7 @@ CYCLES_PER_STEP = 1000
 
 
 def algorithmic_bytes(p, st_delta, cycles):
-    """Bytes a cycle sweep must move, from the event counts of the run:
+    """Bytes a cycle sweep must move at least, from the event counts of the run:
     every directed link's destination word read and written; 12 payload bytes written and
     read per flit hop; the 13-word core record read; a 16-byte core word written per
     injection, ejection and op event; the L1 set (16 B) read and written per op issue and
@@ -293,8 +293,8 @@ def main():
         print(json.dumps({"copy_bytes": n, "copies": 3}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: every box in this setup has one GPU, and the simulator "
-              "shards a chip across GPUs only by design (see DESIGN.md); run with --gpus 1.",
+        print("bench.py measures one GPU: the simulator runs a chip on one GPU (sharding a chip "
+              "across GPUs is a design, not built); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -885,7 +885,7 @@ static void check_cycle(oracle_sim* s) {
   }
 }
 
-/* ---- driver (Sec. 7.1: the serial main loop) ----------------------------------------- */
+/* ---- the serial main loop (Sec. 7.1) --------------------------------------------------- */
 int oracle_step(oracle_sim* s, int64_t n, uint64_t* digests, int32_t check) {
   if (!s || n < 0) return ORACLE_EINVAL;
   s->check = check;
