@@ -26,8 +26,8 @@
  * under an outstanding miss, and injection through the router's injection
  * register one cycle after a flit is made; a router delay stretches every hop;
  * and the paper's own L2 model, the LSPD cache with a directory (Sec. 3.2,
- * 3.4, 6.2.2), replaces the static homes.  Every function below names the
- * passage it follows.
+ * 3.4, 6.2.2), replaces the static homes, optionally with block migration and
+ * redirection (Sec. 3.3).  Every function below names the passage it follows.
  *
  * Parity pins: the Philox generator is pinned to published known-answer
  * vectors; routing to closed-form zero-load latencies and hand traces; the
@@ -48,12 +48,24 @@
    trap (the control bit is bit 31 of the injection-cycle word, which cycles < 2^31 leave free) */
 enum { K_REQ = 0, K_REPLY = 1, K_BG = 2, K_DIR = 3 };
 enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4, /* core states */
-       ST_SEND_DA = 5, ST_SEND_RA = 6, ST_FILL_MEM = 7 };                   /* LSPD only */
+       ST_SEND_DA = 5, ST_SEND_RA = 6, ST_FILL_MEM = 7,                     /* LSPD only */
+       ST_FILL_MIG = 8 };                                                   /* a migrated block */
 #define CTL_BIT 0x80000000u
-/* codes of the directory's and an owner's one-flit answers (queue node line word) */
-enum { CODE_TRAP = -2, CODE_NACK = -1 };
+/* codes of the directory's and an owner's answers (queue node line word; sent as code + 4):
+   the directory's acknowledgement of an ownership claim, a flit of a migrating block, a trap,
+   a negative directory answer, or an owner tile >= 0 */
+enum { CODE_ACK = -4, CODE_MIG = -3, CODE_TRAP = -2, CODE_NACK = -1 };
+#define CODE_BASE 4
 /* request types at a slice's service input (the high byte of C_L2Q) */
-enum { Q_RA = 0, Q_DA = 1, Q_EV = 2 };
+enum { Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3 };
+/* migration (Sec. 3.3): a block moves as 16 flits (Table 1, L2 block migration); a queued reply
+   carries this bit on its line word when it is a migration; an L2 way's access record packs the
+   last accessor (20 bits) and how many accesses in a row came from it (12 bits) */
+#define MIG_FLITS 16
+#define MIG_MARK 0x40000000
+#define REC(who, run) ((int32_t)(((uint32_t)(run) << 20) | (uint32_t)(who)))
+#define REC_WHO(r) ((int32_t)((uint32_t)(r) & 0xFFFFFu))
+#define REC_RUN(r) ((int32_t)((uint32_t)(r) >> 20))
 enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
 /* per-tile core record (20 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
    node as a requester, written by its home while it waits there */
@@ -68,7 +80,10 @@ enum {
   C_TARGET = 20,/* LSPD: the owner a remote-access request goes to */
   C_EV = 21,    /* LSPD: line whose eviction notice waits for injection, -1 = none */
   C_DSUM_LO = 22, C_DSUM_HI = 23, /* LSPD: checksum of the directory entries this tile keeps */
-  C_WORDS = 24
+  C_CLAIM = 24, /* migration: line whose ownership claim waits for injection, -1 = none */
+  C_FWD_LINE = 25, C_FWD_DST = 26, /* migration: the last block this slice gave away, and to whom */
+  C_PAD = 27,
+  C_WORDS = 28
 };
 /* flit record: destination, injection cycle, source, kind<<30 | line, and the number of times
    the flit has been deflected (kept for the AGE_DEFLECT variant, 0 otherwise); the first four
@@ -89,6 +104,9 @@ struct oracle_sim {
   int32_t dir_center;    /* the central directory's tile */
   int64_t lines;         /* size of the line space (location array entries) */
   int32_t* loc;          /* LSPD location array: [lines] owner tile or -1 */
+  int32_t* l2h;          /* migration: [N][S2][W2] access record of each L2 way (REC) */
+  int32_t mig;           /* migration threshold: accesses in a row from one remote tile (0 = off) */
+  int32_t* seen;         /* [lines] scratch of the one-copy check */
   int32_t* scratch;      /* [2N], invariant checks */
   int64_t cycle;
   int32_t zk;
@@ -276,6 +294,57 @@ static void dir_set(oracle_sim* s, int32_t line, int32_t owner) {
   k[C_DSUM_LO] = (int32_t)(uint32_t)sum;
   k[C_DSUM_HI] = (int32_t)(uint32_t)(sum >> 32);
 }
+/* A slice evicted `line` (its eviction notice, or at once when it keeps the entry itself): the
+   entry names that slice until then (a slice that received a block by migration evicts nothing
+   before the directory has acknowledged its claim). */
+static void dir_evicted(oracle_sim* s, int32_t line, int32_t who) {
+  if (s->check && s->loc[line] != who && !s->bad) {
+    s->bad = 1;
+    snprintf(s->msg, sizeof s->msg, "eviction notice of %d for line %d named %d", who, line, s->loc[line]);
+  }
+  dir_set(s, line, -1);
+  s->stats[OS_DIR_EVICT]++;
+}
+
+/* L2 ways of an LSPD slice with their access records (rec = NULL without migration): find,
+   move to the front, remove, insert at the front (returns the dropped last way). */
+static int32_t* l2_rec(oracle_sim* s, int32_t t, int32_t line) {
+  if (!s->mig) return NULL;
+  return s->l2h + ((size_t)t * s->cfg.l2_sets + (line & (s->cfg.l2_sets - 1))) * s->cfg.l2_ways;
+}
+static int l2_find(const int32_t* set, int ways, int32_t line) {
+  for (int i = 0; i < ways; ++i)
+    if (set[i] == line) return i;
+  return -1;
+}
+static void l2_front(int32_t* set, int32_t* rec, int i) {
+  int32_t tag = set[i], r = rec ? rec[i] : 0;
+  for (int j = i; j > 0; --j) {
+    set[j] = set[j - 1];
+    if (rec) rec[j] = rec[j - 1];
+  }
+  set[0] = tag;
+  if (rec) rec[0] = r;
+}
+static void l2_remove(int32_t* set, int32_t* rec, int ways, int i) {
+  for (int j = i; j < ways - 1; ++j) {
+    set[j] = set[j + 1];
+    if (rec) rec[j] = rec[j + 1];
+  }
+  set[ways - 1] = -1;
+  if (rec) rec[ways - 1] = 0;
+}
+static int32_t l2_insert(int32_t* set, int32_t* rec, int ways, int32_t line, int32_t r) {
+  int32_t victim = set[ways - 1];
+  for (int j = ways - 1; j > 0; --j) {
+    set[j] = set[j - 1];
+    if (rec) rec[j] = rec[j - 1];
+  }
+  set[0] = line;
+  if (rec) rec[0] = r;
+  return victim;
+}
+
 /* The directory's answer to tile `rq` asking for `line`: the owner, or a negative reply, in
    which case the entry now names rq, which brings the block from memory into its slice. */
 static int32_t dir_lookup(oracle_sim* s, int32_t line, int32_t rq) {
@@ -310,24 +379,45 @@ static void phase_memory(oracle_sim* s, int32_t t) {
   if (k[C_L2Q] >= 0 && s->lspd) {
     int32_t type = k[C_L2Q] >> 24, who = k[C_L2Q] & 0xFFFFFF, line = k[C_L2Q_LINE];
     if (type == Q_RA) {
-      if (cache_touch(l2_set(s, t, line), s->cfg.l2_ways, line, 0)) {
+      int32_t* set = l2_set(s, t, line);
+      int32_t* rec = l2_rec(s, t, line);
+      int i = l2_find(set, s->cfg.l2_ways, line);
+      if (i >= 0) {
         s->stats[OS_L2_HIT]++;
-        list_append(s, t, C_HIT_H, C_HIT_T, who, (int32_t)(c + delay), line);
+        int32_t run = 1;
+        if (rec) {  /* Sec. 3.3: the block's record of its latest accessors */
+          run = REC_WHO(rec[i]) == who ? REC_RUN(rec[i]) + 1 : 1;
+          if (run > 4095) run = 4095;
+          rec[i] = REC(who, run);
+        }
+        l2_front(set, rec, i);
+        /* a remote tile uses it most: the block moves there, unless it has just moved here and
+           the directory has not yet acknowledged this slice's claim (so one claim per block is
+           in flight at a time) */
+        const int claiming = k[C_STATE] == ST_WAIT && k[C_LINE] == line;
+        if (s->mig && run >= s->mig && !claiming) {
+          l2_remove(set, rec, s->cfg.l2_ways, 0);
+          k[C_FWD_LINE] = line;
+          k[C_FWD_DST] = who;
+          s->stats[OS_MIGRATE]++;
+          list_append(s, t, C_HIT_H, C_HIT_T, who, (int32_t)(c + delay), line | MIG_MARK);
+        } else {
+          list_append(s, t, C_HIT_H, C_HIT_T, who, (int32_t)(c + delay), line);
+        }
+      } else if (s->mig && k[C_FWD_LINE] == line) {  /* Sec. 3.3: redirect to where it went */
+        s->stats[OS_REDIRECT]++;
+        list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), k[C_FWD_DST]);
       } else {
         s->stats[OS_TRAP]++;
         list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), CODE_TRAP);
       }
     } else if (type == Q_DA) {
       list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), dir_lookup(s, line, who));
-    } else {
-      /* the entry still names the evicting slice: only that slice's own notice changes an
-         entry that names an owner */
-      if (s->check && s->loc[line] != who && !s->bad) {
-        s->bad = 1;
-        snprintf(s->msg, sizeof s->msg, "eviction notice of %d for line %d named %d", who, line, s->loc[line]);
-      }
-      dir_set(s, line, -1);
-      s->stats[OS_DIR_EVICT]++;
+    } else if (type == Q_EV) {
+      dir_evicted(s, line, who);
+    } else {  /* Sec. 3.3: the directory is updated to the block's new owner, which is told */
+      dir_set(s, line, who);
+      list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), CODE_ACK);
     }
     k[C_L2Q] = -1;
     k[C_L2Q_LINE] = -1;
@@ -350,20 +440,27 @@ static void phase_memory(oracle_sim* s, int32_t t) {
       }
       break;
     case ST_FILL_MEM:
-      if (k[C_WAKE] == (int32_t)c) {            /* LSPD: block from memory into the local slice and L1 */
+    case ST_FILL_MIG:
+      if (k[C_WAKE] == (int32_t)c) {            /* LSPD: block from memory (or migrated here) into
+                                                   the local slice and L1 */
         l1_used = 1;
         int32_t line = k[C_LINE];
         int32_t* set2 = l2_set(s, t, line);
-        int32_t victim = set2[s->cfg.l2_ways - 1];
-        cache_touch(set2, s->cfg.l2_ways, line, 1);
+        int32_t victim = l2_insert(set2, l2_rec(s, t, line), s->cfg.l2_ways, line, REC(t, 0));
         if (s->check) check_set(s, set2, s->cfg.l2_ways, "L2", t);
-        if (victim >= 0 && victim != line) {    /* the evicted block leaves the directory */
-          if (dir_of(s, victim) == t) {
-            dir_set(s, victim, -1);
-            s->stats[OS_DIR_EVICT]++;
-          } else {
-            k[C_EV] = victim;
-          }
+        if (victim >= 0) {                      /* the evicted block leaves the directory */
+          if (dir_of(s, victim) == t) dir_evicted(s, victim, t);
+          else k[C_EV] = victim;
+        }
+        int claim = 0;
+        if (state == ST_FILL_MIG) {             /* Sec. 3.3: the directory learns the new owner; */
+          if (dir_of(s, line) == t) dir_set(s, line, t);  /* the op completes when it has */
+          else claim = 1;
+        }
+        if (claim) {
+          k[C_CLAIM] = line;
+          k[C_STATE] = ST_WAIT;
+          break;
         }
         int32_t* set = l1_set(s, t, line);
         cache_touch(set, s->cfg.l1_ways, line, 1);
@@ -380,29 +477,42 @@ static void phase_memory(oracle_sim* s, int32_t t) {
         /* LSPD: the core's own slice, then the directory (at once when this tile keeps the
            entry).  A pending eviction notice goes out first, so that a core has at most one. */
         int32_t line = k[C_LINE];
-        if (k[C_EV] >= 0) {
+        int32_t* set2 = l2_set(s, t, line);
+        int32_t* rec = l2_rec(s, t, line);
+        int i = l2_find(set2, s->cfg.l2_ways, line);
+        if (k[C_EV] >= 0 || k[C_CLAIM] >= 0) {  /* notices first */
           k[C_WAKE] = (int32_t)(c + 1);
-        } else if (cache_touch(l2_set(s, t, line), s->cfg.l2_ways, line, 0)) {
+        } else if (i >= 0) {
           s->stats[OS_L2_HIT]++;
+          if (rec) rec[i] = REC(t, REC_WHO(rec[i]) == t && REC_RUN(rec[i]) < 4095 ? REC_RUN(rec[i]) + 1 : 1);
+          l2_front(set2, rec, i);
           k[C_STATE] = ST_FILL;
           k[C_WAKE] = (int32_t)(c + 1);
-        } else {
-          s->stats[OS_L2_MISS]++;
-          if (dir_of(s, line) == t) {
-            int32_t o = dir_lookup(s, line, t);
+        } else if (dir_of(s, line) == t) {
+          int32_t o = dir_lookup(s, line, t);
+          if (o == t && k[C_FWD_LINE] == line) {  /* this slice gave the block away and its new */
+            o = k[C_FWD_DST];                       /* owner's claim is still on the way */
+            s->stats[OS_REDIRECT]++;
+          }
+          if (o == t) {                         /* stale (an older migration): look again */
+            s->stats[OS_TRAP]++;
+            k[C_WAKE] = (int32_t)(c + 1);
+          } else {
+            s->stats[OS_L2_MISS]++;
             if (o == CODE_NACK) {
               k[C_STATE] = ST_FILL_MEM;
               k[C_WAKE] = (int32_t)(c + s->cfg.mem_lat);
-            } else {                            /* a local entry never names this tile here */
+            } else {
               k[C_STATE] = ST_SEND_RA;
               k[C_TARGET] = o;
               k[C_WAKE] = (int32_t)(c + delay);
               s->stats[OS_REQ_MADE]++;
             }
-          } else {
-            k[C_STATE] = ST_SEND_DA;
-            k[C_WAKE] = (int32_t)(c + delay);
           }
+        } else {
+          s->stats[OS_L2_MISS]++;
+          k[C_STATE] = ST_SEND_DA;
+          k[C_WAKE] = (int32_t)(c + delay);
         }
       } else if (k[C_WAKE] == (int32_t)c) {     /* L1 miss penalty over: go to the home slice */
         int32_t line = k[C_LINE];
@@ -576,7 +686,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
   /* (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
      eviction notice, a directory access or a remote-access request) */
   int cls = -1;
-  const int own = s->lspd ? (k[C_EV] >= 0 || ((k[C_STATE] == ST_SEND_DA || k[C_STATE] == ST_SEND_RA) &&
+  const int own = s->lspd ? (k[C_EV] >= 0 || k[C_CLAIM] >= 0 || ((k[C_STATE] == ST_SEND_DA || k[C_STATE] == ST_SEND_RA) &&
                                               k[C_WAKE] <= (int32_t)c))
                           : (k[C_STATE] == ST_SEND && k[C_WAKE] + inject_delay(s) <= (int32_t)c);
   if (k[C_MISS_H] >= 0 && s->core[(size_t)k[C_MISS_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 0;
@@ -597,7 +707,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
       int32_t rq = list_pop(s, t, C_MISS_H, C_MISS_T);
       f[F_DST] = rq;
       f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-      f[F_INFO] = (K_REPLY << 30) | (s->core[(size_t)rq * C_WORDS + C_NLINE] + 2);
+      f[F_INFO] = (K_REPLY << 30) | (s->core[(size_t)rq * C_WORDS + C_NLINE] + CODE_BASE);
       s->stats[OS_INJ_REPLY]++;
     } else if (cls == 2 && s->lspd) {
       const int32_t line = k[C_LINE];
@@ -606,6 +716,11 @@ static void phase_route(oracle_sim* s, int32_t t) {
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
         f[F_INFO] = (K_DIR << 30) | k[C_EV];
         k[C_EV] = -1;
+      } else if (k[C_CLAIM] >= 0) {             /* a migrated block's new owner, to the directory */
+        f[F_DST] = dir_of(s, k[C_CLAIM]);
+        f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
+        f[F_INFO] = (K_BG << 30) | k[C_CLAIM];
+        k[C_CLAIM] = -1;
       } else if (k[C_STATE] == ST_SEND_DA) {    /* directory access */
         f[F_DST] = dir_of(s, line);
         f[F_INFO] = (K_DIR << 30) | line;
@@ -620,14 +735,21 @@ static void phase_route(oracle_sim* s, int32_t t) {
     } else if (cls == 0 || cls == 1) {
       int32_t rq = k[cls == 0 ? C_MISS_H : C_HIT_H];
       int32_t* node = s->core + (size_t)rq * C_WORDS;
+      /* a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits */
+      const int mig_pk = s->lspd && (node[C_NLINE] & MIG_MARK);
       f[F_DST] = rq;
-      f[F_INFO] = (K_REPLY << 30) | node[C_NLINE];
+      if (mig_pk) {
+        f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
+        f[F_INFO] = (K_REPLY << 30) | (CODE_MIG + CODE_BASE);
+      } else {
+        f[F_INFO] = (K_REPLY << 30) | node[C_NLINE];
+      }
       s->stats[OS_INJ_REPLY]++;
-      if (++node[C_NSENT] == s->reply_flits) {  /* the packet's last flit */
+      if (++node[C_NSENT] == (mig_pk ? MIG_FLITS : s->reply_flits)) {  /* the packet's last flit */
         node[C_NSENT] = 0;
         if (cls == 0) list_pop(s, t, C_MISS_H, C_MISS_T);
         else list_pop(s, t, C_HIT_H, C_HIT_T);
-        s->stats[OS_REPLY_SENT]++;
+        if (!mig_pk) s->stats[OS_REPLY_SENT]++;
       }
     } else if (cls == 2) {
       f[F_DST] = k[C_LINE] % s->N;
@@ -697,7 +819,8 @@ static void phase_move(oracle_sim* s, int32_t t) {
   if (ej[F_DST] >= 0) {
     int kind = (int)((uint32_t)ej[F_INFO] >> 30);
     const int ctl = ((uint32_t)ej[F_INJ] & CTL_BIT) != 0;
-    const int cl = kind == K_DIR ? K_REQ : kind;  /* directory messages count as requests */
+    const int cl = (kind == K_DIR || (kind == K_BG && ctl)) ? K_REQ : kind;  /* directory messages
+                                                                               count as requests */
     int64_t lat = c - (int32_t)((uint32_t)ej[F_INJ] & ~CTL_BIT);
     s->stats[OS_EJ_REQ + cl]++;
     s->stats[OS_LAT_REQ + cl] += lat;
@@ -720,18 +843,29 @@ static void phase_move(oracle_sim* s, int32_t t) {
     } else if (kind == K_DIR) {                /* LSPD: directory access or eviction notice */
       k[C_L2Q] = ej[F_SRC] | ((ctl ? Q_EV : Q_DA) << 24);
       k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
+    } else if (kind == K_BG && ctl) {          /* migration: the new owner's claim */
+      k[C_L2Q] = ej[F_SRC] | (Q_CLAIM << 24);
+      k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
     } else if (kind == K_REPLY && ctl) {       /* LSPD: directory reply or trap */
       if (k[C_STATE] != ST_WAIT && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "answer at idle tile %d", t); }
-      int32_t code = (ej[F_INFO] & LINE_MASK) - 2;
-      k[C_WAKE] = (int32_t)(c + 1);
-      if (code == CODE_NACK) {                 /* not on chip: from memory into the local slice */
+      int32_t code = (ej[F_INFO] & LINE_MASK) - CODE_BASE;
+      if (code != CODE_MIG) k[C_WAKE] = (int32_t)(c + 1);
+      if (code == CODE_MIG) {                  /* a flit of the block migrating here; with the */
+        if (++k[C_RCV] == MIG_FLITS) {         /* last one it goes into the slice and L1 */
+          k[C_RCV] = 0;
+          k[C_STATE] = ST_FILL_MIG;
+          k[C_WAKE] = (int32_t)(c + 1);
+        }
+      } else if (code == CODE_ACK) {           /* the directory names this slice: the migrated */
+        k[C_STATE] = ST_FILL;                  /* block fills L1 and the op completes */
+      } else if (code == CODE_NACK) {          /* not on chip: from memory into the local slice */
         k[C_STATE] = ST_FILL_MEM;
         k[C_WAKE] = (int32_t)(c + s->cfg.mem_lat);
       } else if (code == CODE_TRAP || code == t) {
         /* ask the directory again: its entry was stale (the owner had evicted the block, or
            this tile's own eviction notice has not reached the directory yet) */
         if (code == t) s->stats[OS_TRAP]++;
-        k[C_STATE] = ST_SEND_DA;
+        k[C_STATE] = ST_SEND_DA;          /* (a redirection to this tile itself is stale too) */
       } else {
         k[C_STATE] = ST_SEND_RA;
         k[C_TARGET] = code;
@@ -802,7 +936,8 @@ static void check_cycle(oracle_sim* s) {
   int64_t occupied = 0, req_fl = 0, ans_fl = 0;
   int32_t* rep_to = s->scratch;              /* reply flits in flight, per requester */
   int32_t* queued_at = s->scratch + s->N;    /* 1 while the requester sits in a home's queue */
-  memset(s->scratch, 0, (size_t)s->N * 2 * sizeof(int32_t));
+  int32_t* mig_to = s->scratch + 2 * s->N;   /* flits of a migrating block in flight, per receiver */
+  memset(s->scratch, 0, (size_t)s->N * 3 * sizeof(int32_t));
   for (int32_t t = 0; t < s->N; ++t) {
     for (int st = 0; st < s->delay; ++st) {    /* the link slots, then the pipeline stages */
       const int32_t* sl = st == 0 ? nxt + (size_t)t * SLOT_WORDS : pipe_stage(s, c + st, t);
@@ -812,8 +947,11 @@ static void check_cycle(oracle_sim* s) {
         occupied++;
         int kind = (int)((uint32_t)f[F_INFO] >> 30);
         const int ctl = ((uint32_t)f[F_INJ] & CTL_BIT) != 0;
-        if (kind == K_REQ || (kind == K_DIR && !ctl)) req_fl++;   /* remote or directory access */
-        if (kind == K_REPLY && ctl) ans_fl++;                    /* directory reply or trap */
+        const int mig_flit = kind == K_REPLY && ctl && (f[F_INFO] & LINE_MASK) == CODE_MIG + CODE_BASE;
+        if (kind == K_REQ || (kind == K_DIR && !ctl) || (kind == K_BG && ctl)) req_fl++;  /* remote or
+                                                           directory access, ownership claim */
+        if (kind == K_REPLY && ctl && !mig_flit) ans_fl++;       /* directory answer, trap, redirection */
+        if (mig_flit) mig_to[f[F_DST]]++;
         if (kind == K_REPLY && !ctl) rep_to[f[F_DST]]++;
         if (!port_valid(s, t, p) && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "flit on a missing link at %d", t); }
       }
@@ -833,6 +971,7 @@ static void check_cycle(oracle_sim* s) {
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] == ST_WAIT) waiting++;
     if (k[C_L2Q] >= 0 && (k[C_L2Q] >> 24) != Q_EV) at_home++;
+    if (k[C_CLAIM] >= 0) at_home++;   /* a claim waiting for injection */
     for (int which = 0; which < 2; ++which) {
       int32_t r = k[which ? C_MISS_H : C_HIT_H], last = -1;
       int64_t len = 0;
@@ -853,12 +992,13 @@ static void check_cycle(oracle_sim* s) {
   int64_t rep_pk = 0;
   for (int32_t r = 0; r < s->N; ++r) {
     const int32_t* k = s->core + (size_t)r * C_WORDS;
-    const int32_t in_flight = rep_to[r];
+    const int32_t in_flight = rep_to[r] + mig_to[r];
     if (queued_at[r]) {
       if (in_flight != k[C_NSENT] - k[C_RCV] && !s->bad) { s->bad = 1; snprintf(s->msg, sizeof s->msg, "reply flits of queued tile %d", r); }
     } else if (in_flight > 0) {
       rep_pk++;
-      if ((k[C_STATE] != ST_WAIT || in_flight != s->reply_flits - k[C_RCV]) && !s->bad) {
+      const int32_t len = mig_to[r] ? MIG_FLITS : s->reply_flits;
+      if ((k[C_STATE] != ST_WAIT || (rep_to[r] && mig_to[r]) || in_flight != len - k[C_RCV]) && !s->bad) {
         s->bad = 1;
         snprintf(s->msg, sizeof s->msg, "reply flits in flight to tile %d", r);
       }
@@ -870,18 +1010,24 @@ static void check_cycle(oracle_sim* s) {
              (long long)waiting, (long long)req_fl, (long long)ans_fl, (long long)rep_pk, (long long)queued,
              (long long)at_home);
   }
-  /* LSPD: one copy of a block on chip, and the directory names the slice that holds it */
+  /* LSPD: one copy of a block on chip, and the directory names the slice that holds it (with
+     migration: or the slice waits for the acknowledgement of its claim of it) */
   if (s->lspd) {
     const int32_t S2 = s->cfg.l2_sets, W2 = s->cfg.l2_ways;
-    for (int32_t t = 0; t < s->N && !s->bad; ++t)
+    memset(s->seen, 0, (size_t)s->lines * sizeof(int32_t));
+    for (int32_t t = 0; t < s->N && !s->bad; ++t) {
+      const int32_t* k = s->core + (size_t)t * C_WORDS;
       for (int32_t i = 0; i < S2 * W2; ++i) {
         const int32_t line = s->l2[(size_t)t * S2 * W2 + i];
-        if (line >= 0 && s->loc[line] != t) {
+        if (line < 0) continue;
+        const int claiming = s->mig && k[C_STATE] == ST_WAIT && k[C_LINE] == line;
+        if (s->seen[line]++ || (s->loc[line] != t && !claiming)) {
           s->bad = 1;
           snprintf(s->msg, sizeof s->msg, "slice %d holds line %d, directory names %d", t, line, s->loc[line]);
           break;
         }
       }
+    }
   }
 }
 
@@ -927,6 +1073,8 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
     return ORACLE_EINVAL;
   if (cfg->router_delay < 0 || cfg->router_delay > 8) return ORACLE_EINVAL;
   if ((cfg->flags & ORACLE_FLAG_LSPD_CENTRAL) && !(cfg->flags & ORACLE_FLAG_LSPD)) return ORACLE_EINVAL;
+  if (cfg->mig_threshold < 0 || cfg->mig_threshold > 4095 || (cfg->mig_threshold && !(cfg->flags & ORACLE_FLAG_LSPD)))
+    return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
   s->cfg = *cfg;
@@ -938,6 +1086,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->lspd = (cfg->flags & ORACLE_FLAG_LSPD) ? ((cfg->flags & ORACLE_FLAG_LSPD_CENTRAL) ? 2 : 1) : 0;
   s->dir_center = (cfg->height / 2) * cfg->width + cfg->width / 2;
   s->lines = (int64_t)cfg->shared_lines + N * cfg->private_lines;
+  s->mig = cfg->mig_threshold;
   s->zk = zk;
   s->zs = (uint32_t*)malloc((size_t)(zk + 1) * 4);
   s->zp = (uint32_t*)malloc((size_t)(zk + 1) * 4);
@@ -950,11 +1099,13 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->outp = (int32_t*)malloc((size_t)N * SLOT_WORDS * 4);
   s->ej = (int32_t*)malloc((size_t)N * F_WORDS * 4);
   s->oldest_ok = (int32_t*)malloc((size_t)N * 4);
-  s->scratch = (int32_t*)malloc((size_t)N * 2 * 4);
+  s->scratch = (int32_t*)malloc((size_t)N * 3 * 4);
   s->pipe = (int32_t*)malloc((size_t)(s->delay - 1) * N * SLOT_WORDS * 4 + 4);
   s->loc = (int32_t*)malloc((size_t)(s->lspd ? s->lines : 0) * 4 + 4);
+  s->seen = (int32_t*)malloc((size_t)(s->lspd ? s->lines : 0) * 4 + 4);
+  s->l2h = (int32_t*)calloc((size_t)(s->mig ? N * cfg->l2_sets * cfg->l2_ways : 0) + 1, 4);
   if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
-      !s->oldest_ok || !s->scratch || !s->pipe || !s->loc) {
+      !s->oldest_ok || !s->scratch || !s->pipe || !s->loc || !s->seen || !s->l2h) {
     oracle_destroy(s);
     return ORACLE_ENOMEM;
   }
@@ -985,6 +1136,7 @@ void oracle_destroy(oracle_sim* s) {
   if (!s) return;
   free(s->zs); free(s->zp); free(s->link[0]); free(s->link[1]); free(s->core); free(s->l1); free(s->l2);
   free(s->rnd); free(s->outp); free(s->ej); free(s->oldest_ok); free(s->scratch); free(s->pipe); free(s->loc);
+  free(s->seen); free(s->l2h);
   free(s);
 }
 
@@ -999,7 +1151,8 @@ int64_t oracle_cycle(const oracle_sim* s) { return s ? s->cycle : -1; }
 size_t oracle_dump_words(const oracle_sim* s) {
   size_t N = (size_t)s->N;
   return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways +
-         2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20 + (size_t)(s->lspd ? s->lines : 0);
+         2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20 + (size_t)(s->lspd ? s->lines : 0) +
+         (size_t)(s->mig ? N * s->cfg.l2_sets * s->cfg.l2_ways : 0);
 }
 
 /* Canonical state (format version 3): header {magic, 3, W, H, cycle (low, high), L1 sets,
@@ -1009,14 +1162,15 @@ size_t oracle_dump_words(const oracle_sim* s) {
    flit (0 for an empty slot and outside the AGE_DEFLECT variant), and with a router delay
    D > 1 (header word 13) the routers' pipelines: stages 1..D-1, stage k holding the flits
    arbitrated k-1 cycles after the dump's cycle, four words per slot, then their deflection
-   counts, and with the LSPD directory (header word 14: 1 interleaved, 2 central) the location
-   array, one word per line. */
+   counts, with the LSPD directory (header word 14: 1 interleaved, 2 central) the location
+   array, one word per line, and with migration (header word 15: the threshold) the access
+   record of every L2 way. */
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
   int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 3, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
                               s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
-                              C_WORDS, s->cfg.flags, s->delay, s->lspd, 0};
+                              C_WORDS, s->cfg.flags, s->delay, s->lspd, s->mig};
   memcpy(buf, hdr, sizeof hdr);
   o += DUMP_HEADER;
   const int32_t* slots = s->link[s->cycle & 1];
@@ -1044,7 +1198,11 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
     const int32_t* f = pipe_stage(s, s->cycle + st - 1, 0);
     for (size_t i = 0; i < N * 4; ++i) buf[o++] = f[i * F_WORDS + F_DST] >= 0 ? f[i * F_WORDS + F_AGE] : 0;
   }
-  if (s->lspd) memcpy(buf + o, s->loc, (size_t)s->lines * 4);
+  if (s->lspd) {
+    memcpy(buf + o, s->loc, (size_t)s->lines * 4);
+    o += (size_t)s->lines;
+  }
+  if (s->mig) memcpy(buf + o, s->l2h, N * s->cfg.l2_sets * s->cfg.l2_ways * 4);
   return ORACLE_OK;
 }
 
@@ -1052,7 +1210,8 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   if (buf[0] != DUMP_MAGIC || buf[1] != 3 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
       buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
-      buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay || buf[14] != s->lspd)
+      buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay || buf[14] != s->lspd ||
+      buf[15] != s->mig)
     return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = DUMP_HEADER;
   s->cycle = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
@@ -1089,7 +1248,9 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
     for (int64_t i = 0; i < s->lines; ++i)
       if (buf[o + i] < -1 || buf[o + i] >= s->N) return ORACLE_EINVAL;
     memcpy(s->loc, buf + o, (size_t)s->lines * 4);
+    o += (size_t)s->lines;
   }
+  if (s->mig) memcpy(s->l2h, buf + o, N * s->cfg.l2_sets * s->cfg.l2_ways * 4);
   for (size_t t = 0; t < N; ++t)
     if (s->core[t * C_WORDS + C_DLINE] >= 0 && !(s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS)) return ORACLE_EINVAL;
   return ORACLE_OK;
@@ -1123,7 +1284,7 @@ int oracle_quiescent(const oracle_sim* s) {
       if (cur[(size_t)t * SLOT_WORDS + p * F_WORDS] >= 0) return 0;
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
-        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0 || k[C_EV] >= 0)
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0 || k[C_EV] >= 0 || k[C_CLAIM] >= 0)
       return 0;
   }
   return 1;

@@ -39,6 +39,8 @@ typedef struct {
   int32_t router_delay;        /* cycles a flit takes per hop, 1..8 (0 counts as 1): a flit that
                                   arrives at a router waits router_delay - 1 cycles in its
                                   pipeline before it is arbitrated */
+  int32_t mig_threshold;       /* LSPD migration (Sec. 3.3): a block moves to a remote tile whose
+                                  accesses to it, in a row, reach this count (0 = never, <= 4095) */
 } oracle_config;
 
 /* Model variants: each bit replaces one reading of the base model by a more literal one.
@@ -60,7 +62,12 @@ typedef struct {
      slice that evicts a block sends the directory an eviction notice.  Directory entries are
      kept in a location array indexed by line; the entry of a line belongs to the line's
      directory slice, line mod N, or with LSPD_CENTRAL to the one tile at the mesh centre.
-     The base model homes each line statically at slice line mod N. */
+     The base model homes each line statically at slice line mod N.  With mig_threshold > 0 a
+     block migrates (Sec. 3.3): each L2 way records its last accessor and how many accesses in a
+     row came from it; when a remote tile's run reaches the threshold the owner sends it the
+     block (16 flits, Table 1) and keeps a forwarding pointer, answering a request that still
+     reaches it with a redirection (1 flit); the receiver claims the directory entry and its op
+     completes with the directory's acknowledgement (a block under claim does not move on). */
 enum {
   ORACLE_FLAG_AGE_DEFLECT = 1, ORACLE_FLAG_HIT_UNDER_MISS = 2, ORACLE_FLAG_INJECT_DELAY = 4,
   ORACLE_FLAG_LSPD = 8, ORACLE_FLAG_LSPD_CENTRAL = 16
@@ -87,7 +94,8 @@ enum {
   OS_INJ_BLOCKED = 24, OS_BG_GEN = 25, OS_OP_LAT_MAX = 26,
   OS_DIR_ACCESS = 27, OS_DIR_NACK = 28, OS_TRAP = 29, OS_DIR_EVICT = 30, /* LSPD directory */
   OS_HIST = 32, /* 16 bins: floor(log2(latency)), last bin open */
-  OS_COUNT = 48
+  OS_MIGRATE = 48, OS_REDIRECT = 49, /* LSPD migration: blocks moved, requests redirected */
+  OS_COUNT = 64
 };
 
 typedef struct oracle_sim oracle_sim;

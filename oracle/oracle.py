@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "nocsim_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-N_STATS = 48
+N_STATS = 64
 STAT_NAMES = {
     "cycles": 0, "inj_req": 1, "inj_reply": 2, "inj_bg": 3, "ej_req": 4, "ej_reply": 5,
     "ej_bg": 6, "lat_req": 7, "lat_reply": 8, "lat_bg": 9, "lat_max": 10,
@@ -23,7 +23,7 @@ STAT_NAMES = {
     "l1_hit": 16, "l1_miss": 17, "l2_hit": 18, "l2_miss": 19, "req_made": 20,
     "req_received": 21, "reply_sent": 22, "reply_received": 23, "inj_blocked": 24,
     "bg_generated": 25, "op_lat_max": 26,
-    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30,
+    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30, "migrations": 48, "redirects": 49,
 }
 HIST = 32
 
@@ -48,7 +48,7 @@ class OracleConfig(C.Structure):
         ("l1_lat", C.c_int32), ("mem_lat", C.c_int32),
         ("op_thr", C.c_uint32), ("shared_thr", C.c_uint32), ("bg_thr", C.c_uint32),
         ("shared_lines", C.c_int32), ("private_lines", C.c_int32), ("flags", C.c_int32),
-        ("reply_flits", C.c_int32), ("router_delay", C.c_int32),
+        ("reply_flits", C.c_int32), ("router_delay", C.c_int32), ("mig_threshold", C.c_int32),
     ]
 
 
@@ -139,7 +139,8 @@ class OracleSim:
             l1_lat=params.l1_lat, mem_lat=params.mem_lat,
             op_thr=params.op_thr, shared_thr=params.shared_thr, bg_thr=params.bg_thr,
             shared_lines=params.shared_lines, private_lines=params.private_lines, flags=params.flags,
-            reply_flits=params.reply_flits, router_delay=params.router_delay)
+            reply_flits=params.reply_flits, router_delay=params.router_delay,
+            mig_threshold=params.mig_threshold)
         h = C.c_void_p()
         rc = lib().oracle_create(C.byref(cfg), _ptr(self._zs), _ptr(self._zp), len(self._zs) - 1, C.byref(h))
         if rc != 0:

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnocsim.so")
 
-N_STATS = 48
+N_STATS = 64
 STAT = {
     "cycles": 0, "inj_req": 1, "inj_reply": 2, "inj_bg": 3, "ej_req": 4, "ej_reply": 5,
     "ej_bg": 6, "lat_req": 7, "lat_reply": 8, "lat_bg": 9, "lat_max": 10,
@@ -22,7 +22,7 @@ STAT = {
     "l1_hit": 16, "l1_miss": 17, "l2_hit": 18, "l2_miss": 19, "req_made": 20,
     "req_received": 21, "reply_sent": 22, "reply_received": 23, "inj_blocked": 24,
     "bg_generated": 25, "op_lat_max": 26,
-    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30,
+    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30, "migrations": 48, "redirects": 49,
 }
 ERRORS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINVARIANT", -5: "EBUSY", -6: "EHANG"}
 
@@ -45,7 +45,7 @@ class SimConfig(C.Structure):
         ("l1_lat", C.c_int32), ("mem_lat", C.c_int32),
         ("op_thr", C.c_uint32), ("shared_thr", C.c_uint32), ("bg_thr", C.c_uint32),
         ("shared_lines", C.c_int32), ("private_lines", C.c_int32), ("flags", C.c_int32),
-        ("reply_flits", C.c_int32), ("router_delay", C.c_int32),
+        ("reply_flits", C.c_int32), ("router_delay", C.c_int32), ("mig_threshold", C.c_int32),
     ]
 
     @classmethod
@@ -55,7 +55,7 @@ class SimConfig(C.Structure):
                    l2_sets=p.l2_sets, l2_ways=p.l2_ways, l1_lat=p.l1_lat, mem_lat=p.mem_lat,
                    op_thr=p.op_thr, shared_thr=p.shared_thr, bg_thr=p.bg_thr,
                    shared_lines=p.shared_lines, private_lines=p.private_lines, flags=p.flags,
-                   reply_flits=p.reply_flits, router_delay=p.router_delay)
+                   reply_flits=p.reply_flits, router_delay=p.router_delay, mig_threshold=p.mig_threshold)
 
 
 _L = None

@@ -25,7 +25,7 @@ ZIPF_K = 65536
 FIELDS = (
     "width", "height", "seed", "l1_sets", "l1_ways", "l2_sets", "l2_ways", "l1_lat",
     "mem_lat", "op_thr", "shared_thr", "bg_thr", "shared_lines", "private_lines",
-    "zipf_shared_s", "zipf_private_s", "reply_flits", "flags", "router_delay",
+    "zipf_shared_s", "zipf_private_s", "reply_flits", "flags", "router_delay", "mig_threshold",
 )
 
 # Model variants (bits of SimParams.flags), each a more literal reading of one passage of the
@@ -85,6 +85,7 @@ class SimParams:
     reply_flits: int = 1      # flits per reply packet (the paper's Table 1: 4 for a remote L2 access)
     flags: int = 0            # model variants: AGE_DEFLECT | HIT_UNDER_MISS | INJECT_DELAY | LSPD [| LSPD_CENTRAL]
     router_delay: int = 1     # cycles per hop (a flit waits router_delay - 1 cycles in each router)
+    mig_threshold: int = 0    # LSPD: migrate a block to a remote tile after this many accesses in a row
 
     @property
     def tiles(self) -> int:

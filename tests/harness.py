@@ -18,13 +18,14 @@ STAT = {
     "l1_hit": 16, "l1_miss": 17, "l2_hit": 18, "l2_miss": 19, "req_made": 20,
     "req_received": 21, "reply_sent": 22, "reply_received": 23, "inj_blocked": 24,
     "bg_generated": 25, "op_lat_max": 26,
-    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30,
+    "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30, "migrations": 48, "redirects": 49,
 }
 CORE = {"state": 0, "wake": 1, "line": 2, "issue": 3, "l2q": 4, "l2q_line": 5, "hit_head": 6,
         "hit_tail": 7, "miss_head": 8, "miss_tail": 9, "bg_pending": 10, "node_next": 11,
         "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15, "reply_flits_received": 16,
         "node_flits_sent": 17, "deferred_line": 18, "deferred_issue": 19, "target": 20, "pending_ev": 21,
-        "dir_sum_lo": 22, "dir_sum_hi": 23}
+        "dir_sum_lo": 22, "dir_sum_hi": 23, "claim": 24, "fwd_line": 25, "fwd_dst": 26}
+N_STATS = 64
 
 
 def load_golden(name):
@@ -43,13 +44,15 @@ def split_dump(buf, params):
     out["l1"] = buf[o:o + n1].reshape(N, params.l1_sets, params.l1_ways); o += n1
     n2 = N * params.l2_sets * params.l2_ways
     out["l2"] = buf[o:o + n2].reshape(N, params.l2_sets, params.l2_ways); o += n2
-    out["stats"] = buf[o:o + 96].copy().view(np.int64); o += 96
+    out["stats"] = buf[o:o + 2 * N_STATS].copy().view(np.int64); o += 2 * N_STATS
     out["ages"] = buf[o:o + N * 4].reshape(N, 4); o += N * 4   # deflection count of each input slot's flit
     D = max(1, int(buf[13]))   # router delay: stages 1..D-1 of the routers' pipelines follow
     out["pipe"] = buf[o:o + (D - 1) * N * 16].reshape(D - 1, N, 4, 4); o += (D - 1) * N * 16
     out["pipe_ages"] = buf[o:o + (D - 1) * N * 4].reshape(D - 1, N, 4); o += (D - 1) * N * 4
     lines = params.shared_lines + N * params.private_lines if int(buf[14]) else 0
-    out["loc"] = buf[o:o + lines]   # LSPD directory: owner of each line, -1 = not on chip
+    out["loc"] = buf[o:o + lines]; o += lines   # LSPD directory: owner of each line, -1 = not on chip
+    ways = N * params.l2_sets * params.l2_ways if int(buf[15]) else 0
+    out["l2rec"] = buf[o:o + ways].reshape(-1, params.l2_sets, params.l2_ways) if ways else buf[o:o]
     return out
 
 
