@@ -65,6 +65,13 @@ typedef struct {
   int32_t router_delay;       /* cycles per hop, 1..8 (0 counts as 1): a flit that arrives at a
                                  router waits router_delay - 1 cycles in the router's pipeline
                                  before it is arbitrated; > 1 runs on the general kernel */
+  int32_t mig_threshold;      /* with LSPD: block migration (Sec. 3.3).  Each L2 way records its
+                                 last accessor and how many accesses in a row came from it; when a
+                                 remote tile's run reaches this count the owner sends it the block
+                                 (16 flits, Table 1), keeps a forwarding pointer and answers later
+                                 requests with a redirection (1 flit); the receiver claims the
+                                 directory entry (1 flit) and its op completes with the directory's
+                                 acknowledgement (1 flit).  0 = no migration, at most 4095 */
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
@@ -94,7 +101,7 @@ enum {
   SIM_FLAG_LSPD_CENTRAL = 16
 };
 
-/* Statistics: 48 int64 counters (index = position in `v`).  Latencies are in cycles from
+/* Statistics: 64 int64 counters (index = position in `v`).  Latencies are in cycles from
    injection to ejection; op latency from issue to L1 fill. */
 enum {
   SIM_ST_CYCLES = 0,
@@ -114,7 +121,9 @@ enum {
   SIM_ST_TRAP = 29,         /* LSPD: stale directory answers (owner without the block) */
   SIM_ST_DIR_EVICT = 30,    /* LSPD: directory entries cleared by evictions */
   SIM_ST_HIST = 32,         /* 16 bins of floor(log2(latency)); the last bin is open */
-  SIM_ST_COUNT = 48
+  SIM_ST_MIGRATE = 48,      /* blocks migrated (Sec. 3.3) */
+  SIM_ST_REDIRECT = 49,     /* requests redirected by a block's previous owner */
+  SIM_ST_COUNT = 64
 };
 typedef struct { int64_t v[SIM_ST_COUNT]; } sim_stats_t;
 
@@ -150,19 +159,21 @@ int sim_stats(sim_t* h, sim_stats_t* out);
 
 /* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 3, width,
    height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, reply_flits (>= 1),
-   core-record words (24), flags, router delay, LSPD mode (0 static homes, 1 interleaved
-   directory, 2 central), 0}, then per tile the 4 input slots of the next cycle ({dst (-1 =
-   empty), inject cycle (bit 31: LSPD control flit), source, kind<<30 | line}), then per tile
-   24 core words {state, wake, line, issue, l2q, l2q_line, hit_head, hit_tail, miss_head,
-   miss_tail, bg_pending, node_next, node_ready, node_line, force_line, force_dst, reply flits
-   received, node flits sent, held line (-1 = none), held issue cycle, remote-access target,
-   pending eviction line, directory checksum lo, hi}, then L1 and L2 tags per tile per
-   set (most recently used first, -1 invalid), then the 48 statistics as (low, high) word
+   core-record words (28), flags, router delay, LSPD mode (0 static homes, 1 interleaved
+   directory, 2 central), migration threshold}, then per tile the 4 input slots of the next
+   cycle ({dst (-1 = empty), inject cycle (bit 31: LSPD control flit), source, kind<<30 |
+   line}), then per tile 28 core words {state, wake, line, issue, l2q, l2q_line, hit_head,
+   hit_tail, miss_head, miss_tail, bg_pending, node_next, node_ready, node_line, force_line,
+   force_dst, reply flits received, node flits sent, held line (-1 = none), held issue cycle,
+   remote-access target, pending eviction line, directory checksum lo, hi, pending claim,
+   forwarded line, its destination, spare}, then L1 and L2 tags per tile per
+   set (most recently used first, -1 invalid), then the 64 statistics as (low, high) word
    pairs, then per tile the deflection counts of the 4 input slots' flits (0 when empty or
    without AGE_DEFLECT), then, when router_delay D > 1 (header word 13 = D), the routers'
    pipelines: stages k = 1..D-1 (stage k holds the flits arbitrated k-1 cycles after the
    dump's cycle), each as per tile 4 slots of 4 words, then the stages' deflection counts,
-   then with LSPD the location array (owner tile per line, -1 = not on chip).
+   then with LSPD the location array (owner tile per line, -1 = not on chip), then with
+   migration the access record of every L2 way (last accessor | run << 20).
    sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);

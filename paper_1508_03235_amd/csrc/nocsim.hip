@@ -34,16 +34,24 @@ namespace {
 // bit is bit 31 of the inject-cycle word (cycles stay below 2^31).
 constexpr int KIND_REQ = 0, KIND_REPLY = 1, KIND_BG = 2, KIND_DIR = 3;
 constexpr int CORE_IDLE = 0, CORE_L1MISS = 1, CORE_SEND = 2, CORE_WAIT = 3, CORE_FILL = 4;
-constexpr int CORE_SEND_DA = 5, CORE_SEND_RA = 6, CORE_FILL_MEM = 7;  // LSPD
+constexpr int CORE_SEND_DA = 5, CORE_SEND_RA = 6, CORE_FILL_MEM = 7, CORE_FILL_MIG = 8;  // LSPD
 constexpr uint32_t CTL_BIT = 0x80000000u;
-constexpr int CODE_TRAP = -2, CODE_NACK = -1;  // one-flit answers (queue node line word)
-constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2;    // message types at a slice's service input (l2q >> 24)
+// answers (queue node line word, sent as code + CODE_BASE): claim acknowledged, a flit of a
+// migrating block, trap, negative directory answer, or an owner tile >= 0
+constexpr int CODE_ACK = -4, CODE_MIG = -3, CODE_TRAP = -2, CODE_NACK = -1, CODE_BASE = 4;
+constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3;  // message types at a slice's service input (l2q >> 24)
+// migration (Sec. 3.3): a block moves as 16 flits (Table 1); a queued reply that is a migration
+// carries MIG_MARK on its line word; an L2 way's access record packs the last accessor (20 bits)
+// and how many accesses in a row came from it (12 bits)
+constexpr int MIG_FLITS = 16;
+constexpr int MIG_MARK = 0x40000000;
 constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // words of a tile's record in the canonical dump: state, wake, line, issue, l2q, l2q_line,
 // hit head/tail, miss head/tail, bg_pending, node next/ready/line, force_line, force_dst,
 // reply flits received, node flits sent, held line, held issue cycle, remote-access target,
-// pending eviction line, directory checksum (low, high)
-constexpr int CORE_RECORD = 24;
+// pending eviction line, directory checksum (low, high), pending claim, forwarded line, its
+// destination, a spare word
+constexpr int CORE_RECORD = 28;
 constexpr int DUMP_VERSION = 3;
 // model variants (sim_config.flags); the one-tile-per-thread kernel runs the base model only
 constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY | SIM_FLAG_LSPD |
@@ -71,13 +79,16 @@ struct ChipDev {
   int32_t lspd;              // 0 static homes; 1 LSPD, directory interleaved by line; 2 central directory
   int32_t dir_center;        // the central directory's tile
   int32_t lines;             // line space: shared_lines + N * private_lines
+  int32_t mig;               // migration threshold (0 = none)
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int4* link;                // [2 parity][4 port][N]
   int4* pipe;                // [D-1][4 port][N]: raw slot words of flits waiting in the routers'
                              // pipelines; entry (a mod (D-1)) holds those arbitrated in cycle a
-  int4* core;                // [5][N]; group 3: force_dst, reply flits received, held line, held issue;
-                             // group 4 (LSPD): remote-access target, pending eviction, directory checksum lo, hi
+  int4* core;                // [6][N]; group 3: force_dst, reply flits received, held line, held issue;
+                             // group 4 (LSPD): remote-access target, pending eviction, directory checksum lo, hi;
+                             // group 5 (migration): pending claim, forwarded line, its destination, spare
+  int32_t* l2h;              // migration: [N][s2][w2] access record of each L2 way
   int32_t* loc;              // LSPD location array [lines]: owner tile or -1; entry L belongs to L's directory tile
   int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
@@ -280,6 +291,63 @@ __device__ __forceinline__ bool set_touch(int (&v)[8], int ways, int line, bool 
   return hit;
 }
 
+// LSPD slice ways with their access records (h, moved along when `rec`); positions are handled
+// with unrolled selects so that the arrays stay in registers.
+__device__ __forceinline__ int way_of(const int (&v)[8], int line) {
+  int pos = -1;
+#pragma unroll
+  for (int i = 7; i >= 0; --i)
+    if (v[i] == line) pos = i;
+  return pos;
+}
+__device__ __forceinline__ int way_pick(const int (&v)[8], int i) {
+  int x = v[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k)
+    if (i == k) x = v[k];
+  return x;
+}
+__device__ __forceinline__ void way_front(int (&v)[8], int (&h)[8], int i, bool rec) {
+  const int tag = way_pick(v, i), r = way_pick(h, i);
+#pragma unroll
+  for (int k = 7; k >= 1; --k)
+    if (k <= i) {
+      v[k] = v[k - 1];
+      if (rec) h[k] = h[k - 1];
+    }
+  v[0] = tag;
+  if (rec) h[0] = r;
+}
+__device__ __forceinline__ void way_remove(int (&v)[8], int (&h)[8], int ways, int i, bool rec) {
+  ways = __builtin_amdgcn_readfirstlane(ways);
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+    if (k >= i && k < ways - 1) {
+      v[k] = v[k + 1];
+      if (rec) h[k] = h[k + 1];
+    }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k == ways - 1) {
+      v[k] = -1;
+      if (rec) h[k] = 0;
+    }
+}
+// inserts `line` at the front with record r; returns the way it pushed out (or -1)
+__device__ __forceinline__ int way_insert(int (&v)[8], int (&h)[8], int ways, int line, int r, bool rec) {
+  ways = __builtin_amdgcn_readfirstlane(ways);
+  const int victim = way_pick(v, ways - 1);
+#pragma unroll
+  for (int k = 7; k >= 1; --k)
+    if (k <= ways - 1) {
+      v[k] = v[k - 1];
+      if (rec) h[k] = h[k - 1];
+    }
+  v[0] = line;
+  if (rec) h[0] = r;
+  return victim;
+}
+
 // Queue nodes {next, ready, line, 0}: device-scope atomics when several workgroups share a chip.
 template <bool COH> __device__ __forceinline__ int4 ld_node(const int4* p) { return ld_slot(p, COH); }
 template <bool COH> __device__ __forceinline__ void st_node(int4* p, int4 v) { st_slot(p, v, COH); }
@@ -384,6 +452,9 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   // LSPD core words: remote-access target, pending eviction, directory checksum (constant
   // -1, -1, 0, 0 without the directory)
   int4 k4 = lspd ? gload4(&C.core[4 * N + t]) : make_int4(-1, -1, 0, 0);
+  // migration words: pending claim, forwarded line, its destination, spare (all -1 without)
+  int4 k5 = lspd ? gload4(&C.core[5 * N + t]) : make_int4(-1, -1, -1, -1);
+  const bool mig = lspd && C.mig > 0;
   const uint32_t a0 = aged && v0 ? slot_age(w0) : 0u, a1 = aged && v1 ? slot_age(w1) : 0u;
   const uint32_t a2 = aged && v2 ? slot_age(w2) : 0u, a3 = aged && v3 ? slot_age(w3) : 0u;
 
@@ -413,9 +484,11 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     h = mix_pair(h, hline, hissue);
     h = mix_pair(h, k4.x, k4.y);
     h = mix_pair(h, k4.z, k4.w);
+    h = mix_pair(h, k5.x, k5.y);
+    h = mix_pair(h, k5.z, k5.w);
     if (aged) mix_ages(a0w, a1w, a2w, a3w);
     for (int st = 1; st < rdelay; ++st) {  // stage st: the flits arbitrated in cycle c-1+st
-      const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)(rdelay - 1)) * 4 * N + t];
+      const int4* pp = &C.pipe[(size_t)(((uint32_t)c + (uint32_t)(st - 1)) % (uint32_t)max(rdelay - 1, 1)) * 4 * N + t];
       const int4 x0 = v0 ? gload4(pp) : EMPTY, x1 = v1 ? gload4(pp + N) : EMPTY;
       const int4 x2 = v2 ? gload4(pp + 2 * N) : EMPTY, x3 = v3 ? gload4(pp + 3 * N) : EMPTY;
       mix_slots(x0, x1, x2, x3);
@@ -446,22 +519,26 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (lspd && svc) { GUARD_LINE(k1.y) }
   if (lspd && k4.x >= 0) { GUARD(k4.x) }
   if (lspd && k4.y >= 0) { GUARD_LINE(k4.y) }
+  if (lspd && k5.x >= 0) { GUARD_LINE(k5.x) }
+  if (lspd && k5.z >= 0) { GUARD(k5.z) }
   if (k1.z >= 0) { GUARD(k1.z) }
   if (k1.w >= 0) { GUARD(k1.w) }
   if (k2.x >= 0) { GUARD(k2.x) }
   if (k2.y >= 0) { GUARD(k2.y) }
   const bool wake = k0.y == c;
-  const bool fill_mem = lspd && k0.x == CORE_FILL_MEM && wake;  // LSPD: block from memory
+  // LSPD: a block from memory, or one that migrated here, goes into the slice
+  const bool fill_mem = lspd && (k0.x == CORE_FILL_MEM || k0.x == CORE_FILL_MIG) && wake;
+  const bool fill_mig = fill_mem && k0.x == CORE_FILL_MIG;
   const bool fill = (k0.x == CORE_FILL && wake) || fill_mem;
   const bool missed = k0.x == CORE_L1MISS && wake;
   const bool local = !lspd && missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
   // LSPD: the core's own slice (after an L1 miss, unless an eviction notice is still pending,
   // and when a block from memory is installed) and the directory entries this cycle touches
   auto dir_of = [&](int line) -> int { return C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)line); };
-  const bool slice_look = lspd && missed && k4.y < 0;
+  const bool slice_look = lspd && missed && k4.y < 0 && k5.x < 0;
   if (slice_look || fill_mem) { GUARD_LINE(k0.z) }
-  const bool dir_core = slice_look && dir_of(k0.z) == t;
-  const int loc_svc = lspd && svc && svc_type == Q_DA ? *gp(&C.loc[k1.y]) : -1;
+  const bool dir_core = (slice_look || fill_mig) && dir_of(k0.z) == t;
+  const int loc_svc = lspd && svc && (svc_type == Q_DA || svc_type == Q_CLAIM) ? *gp(&C.loc[k1.y]) : -1;
   const int loc_core = dir_core ? *gp(&C.loc[k0.z]) : -1;
   const bool retry = VAR && k0.x == CORE_IDLE && hline >= 0;  // the op held back by the last miss
   const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
@@ -478,6 +555,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int vR[8], vL[8], u[8];
   if (svc && svc_type == Q_RA) set_load(setR, C.w2, vR);
   if (local || slice_look || fill_mem) set_load(setL, C.w2, vL);
+  // migration: the access records of those two sets (same layout as the tags)
+  int* recR = mig ? C.l2h + (setR - C.l2) : nullptr;
+  int* recL = mig ? C.l2h + (setL - C.l2) : nullptr;
+  int hR[8] = {0, 0, 0, 0, 0, 0, 0, 0}, hL[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (mig && svc && svc_type == Q_RA) set_load(recR, C.w2, hR);
+  if (mig && (slice_look || fill_mem)) set_load(recL, C.w2, hL);
   int4 nh = EMPTY, nm = EMPTY;  // nodes at the hit-queue and miss-queue heads: next, ready, line
   if (k1.z >= 0) nh = ld_node<MULTI>(&C.node[k1.z]);
   if (k2.x >= 0) nm = ld_node<MULTI>(&C.node[k2.x]);
@@ -491,7 +574,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (fill || retry || forced || drawn) set_load(set1, C.w1, u);
 
   // ---- phase one: home L2 service, then the core (Sec. 7.1, phase one; Sec. 3.5) ----------
-  bool dirtyR = false, dirtyL = false, dirty1 = false, d4 = false;
+  bool dirtyR = false, dirtyL = false, dirty1 = false, d4 = false, d5 = false;
   int node_tail = -1, node_rq = -1, node_ready = 0, node_line = 0, node_w = 0;
   // appends requester rq to this tile's hit queue (replies with the block) or miss queue (a
   // static home's memory misses; an LSPD slice's one-flit answers); its node is written below
@@ -543,9 +626,39 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   } else if (svc) {  // LSPD (Sec. 3.2, Sec. 6.2.2): remote access, directory access, eviction notice
     const int who = svc_who, line = k1.y;
     if (svc_type == Q_RA) {
-      const bool hit = set_touch(vR, C.w2, line, false, dirtyR);
-      lds_add(L, hit ? SIM_ST_L2_HIT : SIM_ST_TRAP, 1);
-      enqueue(hit, who, c + inj_delay, hit ? line : CODE_TRAP);
+      const int i = way_of(vR, line);
+      if (i >= 0) {
+        lds_add(L, SIM_ST_L2_HIT, 1);
+        int run = 1;
+        if (mig) {  // Sec. 3.3: the block's record of its latest accessors
+          run = (hR[i] & 0xFFFFF) == who ? min(((uint32_t)hR[i] >> 20) + 1, 4095u) : 1;
+          hR[i] = (int)(((uint32_t)run << 20) | (uint32_t)who);
+        }
+        way_front(vR, hR, i, mig);
+        dirtyR = true;
+        // a remote tile uses it most: the block moves there, unless it has just moved here and
+        // this slice still waits for the directory to acknowledge its claim
+        const bool claiming = k0.x == CORE_WAIT && k0.z == line;
+        if (mig && run >= C.mig && !claiming) {
+          way_remove(vR, hR, C.w2, 0, mig);
+          k5.y = line;
+          k5.z = who;
+          d5 = true;
+          lds_add(L, SIM_ST_MIGRATE, 1);
+          enqueue(true, who, c + inj_delay, line | MIG_MARK);
+        } else {
+          enqueue(true, who, c + inj_delay, line);
+        }
+      } else if (mig && k5.y == line) {  // Sec. 3.3: redirected to where the block went
+        lds_add(L, SIM_ST_REDIRECT, 1);
+        enqueue(false, who, c + inj_delay, k5.z);
+      } else {
+        lds_add(L, SIM_ST_TRAP, 1);
+        enqueue(false, who, c + inj_delay, CODE_TRAP);
+      }
+    } else if (svc_type == Q_CLAIM) {  // the directory names the block's new owner and tells it
+      dir_write(line, loc_svc, who);
+      enqueue(false, who, c + inj_delay, CODE_ACK);
     } else if (svc_type == Q_DA) {
       lds_add(L, SIM_ST_DIR_ACCESS, 1);
       int code = loc_svc;
@@ -564,11 +677,22 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     d1 = true;
     d2 = true;
   }
+  // the core's slice access below sees the service's changes when both touch one set
+  if (lspd && svc && svc_type == Q_RA && (slice_look || fill_mem) && setL == setR) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      vL[i] = vR[i];
+      hL[i] = hR[i];
+    }
+    dirtyL = dirtyL || dirtyR;
+    dirtyR = false;
+  }
   if (fill) {  // the block arrived: fill L1, the op completes
+    bool claim = false;
     if (fill_mem) {  // LSPD: into the local slice too; an evicted block leaves the directory
-      const int victim = vL[C.w2 - 1];
-      set_touch(vL, C.w2, k0.z, true, dirtyL);
-      if (victim >= 0 && victim != k0.z) {
+      const int victim = way_insert(vL, hL, C.w2, k0.z, t, mig);  // record: this tile, run 0
+      dirtyL = true;
+      if (victim >= 0) {
         GUARD_LINE(victim)
         if (dir_of(victim) == t) {
           dir_write(victim, t, -1);
@@ -578,26 +702,53 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
           d4 = true;
         }
       }
+      if (fill_mig) {  // Sec. 3.3: the directory learns the new owner; the op completes when it has
+        if (dir_of(k0.z) == t) {
+          dir_write(k0.z, fwd_line == k0.z ? fwd_val : loc_core, t);
+        } else {
+          claim = true;
+          k5.x = k0.z;
+          d5 = true;
+          k0.x = CORE_WAIT;
+          d0 = true;
+        }
+      }
     }
-    set_touch(u, C.w1, line_op, true, dirty1);
-    const unsigned long long lat = (unsigned long long)(c - k0.w);
-    lds_add(L, SIM_ST_OPS_DONE, 1);
-    lds_add(L, SIM_ST_OP_LAT, lat);
-    atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
-    k0.x = CORE_IDLE;
-    d0 = true;
+    if (!claim) {
+      set_touch(u, C.w1, line_op, true, dirty1);
+      const unsigned long long lat = (unsigned long long)(c - k0.w);
+      lds_add(L, SIM_ST_OPS_DONE, 1);
+      lds_add(L, SIM_ST_OP_LAT, lat);
+      atomicMax(&L.v[SIM_ST_OP_LAT_MAX], lat);
+      k0.x = CORE_IDLE;
+      d0 = true;
+    }
   } else if (missed && lspd) {  // LSPD: own slice, then the directory (Sec. 3.2)
-    if (k4.y >= 0) {
-      k0.y = c + 1;  // the pending eviction notice goes out first
-    } else if (set_touch(vL, C.w2, k0.z, false, dirtyL)) {
+    const int i = way_of(vL, k0.z);
+    if (k4.y >= 0 || k5.x >= 0) {
+      k0.y = c + 1;  // a pending eviction notice or claim goes out first
+    } else if (i >= 0) {
       lds_add(L, SIM_ST_L2_HIT, 1);
+      if (mig) {
+        const uint32_t run = (hL[i] & 0xFFFFF) == t ? min(((uint32_t)hL[i] >> 20) + 1, 4095u) : 1u;
+        hL[i] = (int)((run << 20) | (uint32_t)t);
+      }
+      way_front(vL, hL, i, mig);
+      dirtyL = true;
       k0.x = CORE_FILL;
       k0.y = c + 1;
-    } else {
-      lds_add(L, SIM_ST_L2_MISS, 1);
-      if (dir_core) {  // this tile keeps the entry: look it up at once
-        lds_add(L, SIM_ST_DIR_ACCESS, 1);
-        const int o = fwd_line == k0.z ? fwd_val : loc_core;
+    } else if (dir_core) {  // this tile keeps the entry: look it up at once
+      lds_add(L, SIM_ST_DIR_ACCESS, 1);
+      int o = fwd_line == k0.z ? fwd_val : loc_core;
+      if (o == t && k5.y == k0.z) {  // this slice gave the block away; the new owner's claim
+        o = k5.z;                    // is still on the way
+        lds_add(L, SIM_ST_REDIRECT, 1);
+      }
+      if (o == t) {  // stale (an older migration): look again next cycle
+        lds_add(L, SIM_ST_TRAP, 1);
+        k0.y = c + 1;
+      } else {
+        lds_add(L, SIM_ST_L2_MISS, 1);
         if (o < 0) {
           dir_write(k0.z, -1, t);
           lds_add(L, SIM_ST_DIR_NACK, 1);
@@ -610,10 +761,11 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
           k0.y = c + inj_delay;
           lds_add(L, SIM_ST_REQ_MADE, 1);
         }
-      } else {
-        k0.x = CORE_SEND_DA;
-        k0.y = c + inj_delay;
       }
+    } else {
+      lds_add(L, SIM_ST_L2_MISS, 1);
+      k0.x = CORE_SEND_DA;
+      k0.y = c + inj_delay;
     }
     d0 = true;
   } else if (missed) {  // L1 miss penalty over: local home slice, or a request flit
@@ -678,7 +830,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
   // (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
   // eviction notice, a directory access or a remote-access request)
-  const bool own = lspd ? (k4.y >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
+  const bool own = lspd ? (k4.y >= 0 || k5.x >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
                         : (k0.x == CORE_SEND && k0.y + inj_delay <= c);
   int cls = -1;
   if (k2.x >= 0 && nm.y <= c) cls = 0;
@@ -697,7 +849,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     if (cls == 0 && lspd) {  // directory answer or trap: one flit, control bit set
       fi.x = k2.x;
       fi.y = (int)((uint32_t)c | CTL_BIT);
-      fi.w = (KIND_REPLY << 30) | (nm.z + 2);
+      fi.w = (KIND_REPLY << 30) | (nm.z + CODE_BASE);
       k2.x = nm.x;
       if (nm.x < 0) k2.y = -1;
       acc.inj_reply++;
@@ -709,6 +861,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
         fi.w = (KIND_DIR << 30) | k4.y;
         k4.y = -1;
         d4 = true;
+      } else if (k5.x >= 0) {  // a migrated block's new owner, to its directory tile
+        fi.x = dir_of(k5.x);
+        fi.y = (int)((uint32_t)c | CTL_BIT);
+        fi.w = (KIND_BG << 30) | k5.x;
+        k5.x = -1;
+        d5 = true;
       } else if (k0.x == CORE_SEND_DA) {  // directory access
         fi.x = dir_of(k0.z);
         fi.w = (KIND_DIR << 30) | k0.z;
@@ -727,7 +885,10 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       const int4 hd = cls == 0 ? nm : nh;
       const int rq = cls == 0 ? k2.x : k1.z;
       const int sent = hd.w + 1;
-      const bool last = sent >= C.reply_flits;
+      // a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits
+      const bool mig_pk = lspd && (hd.z & MIG_MARK);
+      const int len = mig_pk ? MIG_FLITS : C.reply_flits;
+      const bool last = sent >= len;
       if (last) {
         if (cls == 0) {
           k2.x = hd.x;
@@ -736,16 +897,17 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
           k1.z = hd.x;
           if (hd.x < 0) k1.w = -1;
         }
-        lds_add(L, SIM_ST_REPLY_SENT, 1);
+        if (!mig_pk) lds_add(L, SIM_ST_REPLY_SENT, 1);
       }
       // the sent count goes to the head's node; a node appended this cycle is written whole
       // below, so its count rides with that store
-      if (C.reply_flits > 1) {
+      if (len > 1) {
         if (rq == node_rq) node_w = last ? 0 : sent;
         else st_i<MULTI>(reinterpret_cast<int*>(&C.node[rq]) + 3, last ? 0 : sent);
       }
       fi.x = rq;
-      fi.w = (KIND_REPLY << 30) | hd.z;
+      fi.w = mig_pk ? (KIND_REPLY << 30) | (CODE_MIG + CODE_BASE) : (KIND_REPLY << 30) | hd.z;
+      if (mig_pk) fi.y = (int)((uint32_t)c | CTL_BIT);
       acc.inj_reply++;
       d1 = true;
       d2 = true;
@@ -839,6 +1001,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   }
   if (dirtyR) set_store(setR, C.w2, vR);
   if (dirtyL) set_store(setL, C.w2, vL);
+  if (mig && dirtyR) set_store(recR, C.w2, hR);
+  if (mig && dirtyL) set_store(recL, C.w2, hL);
   if (dirty1) set_store(set1, C.w1, u);
   if (node_rq >= 0) {
     st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, node_w));
@@ -881,13 +1045,15 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     const bool ctl = lspd && ((uint32_t)oe.y & CTL_BIT);
     const int lat = c - (int)((uint32_t)oe.y & ym);
     const unsigned long long ulat = (unsigned long long)lat;
-    const bool as_req = kind == KIND_REQ || kind == KIND_DIR;  // directory messages count as requests
+    // directory messages and ownership claims count as requests
+    const bool as_req = kind == KIND_REQ || kind == KIND_DIR || (kind == KIND_BG && ctl);
+    const bool as_bg = kind == KIND_BG && !ctl;
     acc.ej_req += as_req;
     acc.ej_reply += kind == KIND_REPLY;
-    acc.ej_bg += kind == KIND_BG;
+    acc.ej_bg += as_bg;
     acc.lat_req += as_req ? ulat : 0ull;
     acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
-    acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
+    acc.lat_bg += as_bg ? ulat : 0ull;
     atomicMax(&L.v[SIM_ST_LAT_MAX], (unsigned long long)lat);
     lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
     if (kind == KIND_REQ) {
@@ -899,9 +1065,24 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       k1.x = oe.z | ((ctl ? Q_EV : Q_DA) << 24);
       k1.y = oe.w & LINE_MASK;
       d1 = true;
-    } else if (kind == KIND_REPLY && ctl) {  // LSPD: the directory's answer or a trap
-      const int code = (oe.w & LINE_MASK) - 2;
-      if (code == CODE_NACK) {  // not on chip: from memory into the local slice
+    } else if (kind == KIND_BG && ctl) {  // migration: the new owner's claim
+      k1.x = oe.z | (Q_CLAIM << 24);
+      k1.y = oe.w & LINE_MASK;
+      d1 = true;
+    } else if (kind == KIND_REPLY && ctl) {  // LSPD: the directory's answer, a trap, a redirection
+      const int code = (oe.w & LINE_MASK) - CODE_BASE;
+      if (code == CODE_MIG) {  // a flit of the block migrating here; the last one fills it in
+        rcv += 1;
+        d3 = true;
+        if (rcv >= MIG_FLITS) {
+          rcv = 0;
+          k0.x = CORE_FILL_MIG;
+          k0.y = c + 1;
+        }
+      } else if (code == CODE_ACK) {  // the directory names this slice: L1 fill, op complete
+        k0.x = CORE_FILL;
+        k0.y = c + 1;
+      } else if (code == CODE_NACK) {  // not on chip: from memory into the local slice
         k0.x = CORE_FILL_MEM;
         k0.y = c + C.mem_lat;
       } else if (code == CODE_TRAP || code == t) {  // stale entry: ask the directory again
@@ -942,6 +1123,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     k4.w = (int)(uint32_t)(dsum_dir >> 32);
     gstore4(&C.core[4 * N + t], k4);
   }
+  if (d5) gstore4(&C.core[5 * N + t], k5);
 #undef GUARD
 #undef GUARD_LINE
   return true;
@@ -1421,7 +1603,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, drcv, 0);
         h = mix_pair(h, -1, 0);  // no op is held in the base model
         h = mix_pair(h, -1, -1);  // nor a remote-access target or eviction notice,
-        h = mix_pair(h, 0, 0);    // and no directory entry
+        h = mix_pair(h, 0, 0);    // no directory entry,
+        h = mix_pair(h, -1, -1);  // no claim, forwarded block
+        h = mix_pair(h, -1, -1);  // or its destination
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1615,6 +1799,7 @@ __global__ void init_core(int4* core, int4* node, int N) {
     core[2 * N + t] = make_int4(-1, -1, 0, -1);
     core[3 * N + t] = make_int4(-1, 0, -1, 0);  // forced background destination, reply flits received, held op
     core[4 * N + t] = make_int4(-1, -1, 0, 0);  // remote-access target, pending eviction, directory checksum
+    core[5 * N + t] = make_int4(-1, -1, -1, -1);  // pending claim, forwarded line and destination, spare
     node[t] = make_int4(-1, -1, -1, 0);
   }
 }
@@ -1687,12 +1872,13 @@ bool config_ok(const sim_config* c) {
   if (c->flags & ~VARIANT_FLAGS) return false;
   if (c->router_delay < 0 || c->router_delay > 8) return false;
   if ((c->flags & SIM_FLAG_LSPD_CENTRAL) && !(c->flags & SIM_FLAG_LSPD)) return false;
+  if (c->mig_threshold < 0 || c->mig_threshold > 4095 || (c->mig_threshold && !(c->flags & SIM_FLAG_LSPD))) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
 
 struct Layout {
-  size_t desc, link, pipe, core, node, loc, l1, l2, zs, zp, flags, table, stats, err, total;
+  size_t desc, link, pipe, core, node, loc, l1, l2, l2h, zs, zp, flags, table, stats, err, total;
 };
 size_t lspd_lines(const sim_config* c) {  // location-array entries (0 without the directory)
   return (c->flags & SIM_FLAG_LSPD) ? (size_t)c->shared_lines + (size_t)c->width * c->height * c->private_lines : 0;
@@ -1712,11 +1898,12 @@ Layout layout(const sim_config* c) {
   L.desc = take(sizeof(ChipDev));
   L.link = take(2 * 4 * N * sizeof(int4));
   L.pipe = take((size_t)(router_delay(c) - 1) * 4 * N * sizeof(int4));
-  L.core = take(5 * N * sizeof(int4));
+  L.core = take(6 * N * sizeof(int4));
   L.loc = take(lspd_lines(c) * sizeof(int32_t));
   L.node = take(N * sizeof(int4));
   L.l1 = take(N * c->l1_sets * c->l1_ways * sizeof(int32_t));
   L.l2 = take(N * c->l2_sets * c->l2_ways * sizeof(int32_t));
+  L.l2h = take(c->mig_threshold > 0 ? N * c->l2_sets * c->l2_ways * sizeof(int32_t) : 0);
   L.zs = take((ZIPF_K + 1) * sizeof(uint32_t));
   L.zp = take((ZIPF_K + 1) * sizeof(uint32_t));
   L.flags = take(maxp * FLAG_STRIDE * sizeof(int32_t));
@@ -1946,6 +2133,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.lspd = (cfg->flags & SIM_FLAG_LSPD) ? ((cfg->flags & SIM_FLAG_LSPD_CENTRAL) ? 2 : 1) : 0;
   d.dir_center = (cfg->height / 2) * cfg->width + cfg->width / 2;
   d.lines = (int32_t)lspd_lines(cfg);
+  d.mig = cfg->mig_threshold;
   d.shared_lines = cfg->shared_lines;
   d.private_lines = cfg->private_lines;
   d.stop = 0;
@@ -1953,6 +2141,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.link = reinterpret_cast<int4*>(h->base + Lo.link);
   d.pipe = reinterpret_cast<int4*>(h->base + Lo.pipe);
   d.loc = reinterpret_cast<int32_t*>(h->base + Lo.loc);
+  d.l2h = reinterpret_cast<int32_t*>(h->base + Lo.l2h);
   d.core = reinterpret_cast<int4*>(h->base + Lo.core);
   d.node = reinterpret_cast<int4*>(h->base + Lo.node);
   d.l1 = reinterpret_cast<int32_t*>(h->base + Lo.l1);
@@ -1977,6 +2166,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.pipe), -1, (size_t)(d.rdelay - 1) * 4 * N * 4, h->stream)))
     return fail(rc);
   if ((rc = launch_grid_fill_i32(d.loc, -1, lspd_lines(cfg), h->stream))) return fail(rc);
+  if ((rc = launch_grid_fill_i32(d.l2h, 0, cfg->mig_threshold > 0 ? (size_t)N * cfg->l2_sets * cfg->l2_ways : 0, h->stream)))
+    return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l1, -1, (size_t)N * cfg->l1_sets * cfg->l1_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l2, -1, (size_t)N * cfg->l2_sets * cfg->l2_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_u64(d.stats, 0, NSTAT, h->stream))) return fail(rc);
@@ -2062,16 +2253,16 @@ size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
   return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4 +
-         (size_t)(h->hd.rdelay - 1) * N * 20 + (size_t)h->hd.lines;
+         (size_t)(h->hd.rdelay - 1) * N * 20 + (size_t)h->hd.lines + (h->hd.mig ? N * h->hd.s2 * h->hd.w2 : 0);
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   if (!h || !buf || words < sim_dump_words(h)) return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const int par = (int)(h->cycle & 1);
-  std::vector<int4> link(4 * N), core(5 * N), node(N);
+  std::vector<int4> link(4 * N), core(6 * N), node(N);
   HIPCHECK(hipMemcpyAsync(link.data(), h->hd.link + (size_t)par * 4 * N, 4 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
-  HIPCHECK(hipMemcpyAsync(core.data(), h->hd.core, 5 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(core.data(), h->hd.core, 6 * N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipMemcpyAsync(node.data(), h->hd.node, N * sizeof(int4), hipMemcpyDeviceToHost, h->stream));
   size_t o = 16;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
@@ -2084,7 +2275,7 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   HIPCHECK(hipStreamSynchronize(h->stream));
   const int32_t hdr[16] = {0x4E4F4353, DUMP_VERSION, h->hd.W, h->hd.H, (int32_t)(uint32_t)h->cycle,
                            (int32_t)(h->cycle >> 32), h->hd.s1, h->hd.w1, h->hd.s2, h->hd.w2, h->hd.reply_flits,
-                           CORE_RECORD, h->hd.variants, h->hd.rdelay, h->hd.lspd, 0};
+                           CORE_RECORD, h->hd.variants, h->hd.rdelay, h->hd.lspd, h->hd.mig};
   std::memcpy(buf, hdr, sizeof hdr);
   int32_t* ages = buf + 16 + N * (16 + CORE_RECORD) + n1 + n2 + 2 * NSTAT;
   for (size_t t = 0; t < N; ++t)
@@ -2092,9 +2283,9 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   o += N * 16;
   for (size_t t = 0; t < N; ++t) {
     const int4 k0 = core[t], k1 = core[N + t], k2 = core[2 * N + t], k3 = core[3 * N + t], k4 = core[4 * N + t];
-    const int4 nd = node[t];
-    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y, k2.z, nd.x,
-                                      nd.y, nd.z, k2.w, k3.x, k3.y, nd.w, k3.z, k3.w, k4.x, k4.y, k4.z, k4.w};
+    const int4 k5 = core[5 * N + t], nd = node[t];
+    const int32_t rec[CORE_RECORD] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w, k2.x, k2.y, k2.z, nd.x, nd.y, nd.z,
+                                      k2.w, k3.x, k3.y, nd.w, k3.z, k3.w, k4.x, k4.y, k4.z, k4.w, k5.x, k5.y, k5.z, k5.w};
     std::memcpy(buf + o + t * CORE_RECORD, rec, sizeof rec);
   }
   o += N * CORE_RECORD + n1 + n2;
@@ -2120,8 +2311,11 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
   o += (size_t)(D - 1) * N * 20;
   if (h->hd.lines) {  // LSPD location array
     HIPCHECK(hipMemcpyAsync(buf + o, h->hd.loc, (size_t)h->hd.lines * 4, hipMemcpyDeviceToHost, h->stream));
-    HIPCHECK(hipStreamSynchronize(h->stream));
+    o += (size_t)h->hd.lines;
   }
+  if (h->hd.mig)  // migration: the access record of every L2 way
+    HIPCHECK(hipMemcpyAsync(buf + o, h->hd.l2h, N * h->hd.s2 * h->hd.w2 * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
   return SIM_OK;
 }
 
@@ -2130,7 +2324,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (buf[0] != 0x4E4F4353 || buf[1] != DUMP_VERSION || buf[2] != h->hd.W || buf[3] != h->hd.H ||
       buf[6] != h->hd.s1 || buf[7] != h->hd.w1 || buf[8] != h->hd.s2 || buf[9] != h->hd.w2 ||
       buf[10] != h->hd.reply_flits || buf[11] != CORE_RECORD || buf[12] != h->hd.variants ||
-      buf[13] != h->hd.rdelay || buf[14] != h->hd.lspd)
+      buf[13] != h->hd.rdelay || buf[14] != h->hd.lspd || buf[15] != h->hd.mig)
     return SIM_EINVAL;
   const size_t N = (size_t)h->hd.N;
   const size_t n1 = N * h->hd.s1 * h->hd.w1, n2 = N * h->hd.s2 * h->hd.w2;
@@ -2138,7 +2332,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   const bool aged = h->hd.variants & SIM_FLAG_AGE_DEFLECT;
   const int64_t cyc = (int64_t)(((uint64_t)(uint32_t)buf[5] << 32) | (uint32_t)buf[4]);
   if (cyc < 0 || cyc > 0x7FFFFFFF) return SIM_EINVAL;
-  std::vector<int4> link(4 * N), core(5 * N), node(N);
+  std::vector<int4> link(4 * N), core(6 * N), node(N);
   size_t o = 16;
   for (size_t t = 0; t < N; ++t)
     for (int p = 0; p < 4; ++p) {
@@ -2159,8 +2353,14 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     // the directory's words: a target and a pending eviction only with LSPD
     if (!h->hd.lspd && (r[20] != -1 || r[21] != -1 || r[22] != 0 || r[23] != 0)) return SIM_EINVAL;
     if (r[20] < -1 || r[20] >= (int32_t)N || r[21] < -1 || r[21] >= h->hd.lines) return SIM_EINVAL;
+    // migration words: a claim and a forwarding pointer only with migration
+    if (!h->hd.mig && (r[24] != -1 || r[25] != -1 || r[26] != -1 || r[27] != -1)) return SIM_EINVAL;
+    if (r[24] < -1 || r[24] >= h->hd.lines || r[25] < -1 || r[25] >= h->hd.lines || r[26] < -1 ||
+        r[26] >= (int32_t)N)
+      return SIM_EINVAL;
     core[3 * N + t] = make_int4(r[15], r[16], r[18], r[19]);
     core[4 * N + t] = make_int4(r[20], r[21], r[22], r[23]);
+    core[5 * N + t] = make_int4(r[24], r[25], r[26], r[27]);
     node[t] = make_int4(r[11], r[12], r[13], r[17]);
   }
   o += N * CORE_RECORD;
@@ -2194,7 +2394,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   HIPCHECK(hipMemcpyAsync(h->hd.link + (size_t)(par ^ 1) * 4 * N, other.data(), 4 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   int rc = SIM_OK;
-  HIPCHECK(hipMemcpyAsync(h->hd.core, core.data(), 5 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipMemcpyAsync(h->hd.core, core.data(), 6 * N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.node, node.data(), N * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.l1, buf + o, n1 * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipMemcpyAsync(h->hd.l2, buf + o + n1, n2 * 4, hipMemcpyHostToDevice, h->stream));
@@ -2204,6 +2404,8 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   HIPCHECK(hipMemcpyAsync(h->hd.stats, st, sizeof st, hipMemcpyHostToDevice, h->stream));
   if (D > 1) HIPCHECK(hipMemcpyAsync(h->hd.pipe, pipe.data(), pipe.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   if (h->hd.lines) HIPCHECK(hipMemcpyAsync(h->hd.loc, locw, (size_t)h->hd.lines * 4, hipMemcpyHostToDevice, h->stream));
+  if (h->hd.mig)
+    HIPCHECK(hipMemcpyAsync(h->hd.l2h, locw + h->hd.lines, N * h->hd.s2 * h->hd.w2 * 4, hipMemcpyHostToDevice, h->stream));
   h->cycle = cyc;
   if ((rc = launch_grid_fill_i32(h->hd.flags, (int32_t)cyc, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream))) return rc;
   HIPCHECK(hipStreamSynchronize(h->stream));

@@ -1,0 +1,101 @@
+"""Parity of block migration and redirection (Sec. 3.3) on the GPU with the serial oracle."""
+import pytest
+
+from oracle import oracle as O
+from paper_1508_03235_amd import workload as W
+from tests.harness import CORE, STAT, quiet_params, split_dump
+from tests.test_gpu_parity import assert_same_run, gpu_sim
+from tests.test_oracle_lspd import M, _run_ops
+
+pytestmark = pytest.mark.gpu
+
+LSPD, CENTRAL = W.LSPD, W.LSPD_CENTRAL
+
+
+def test_gpu_hand_trace_migration_and_redirection():
+    """The oracle's hand trace on the GPU: M + 4, 11, 1 + M, then the migration (30) and the
+    redirected request (15)."""
+    p = quiet_params(2, 2, l1_lat=1, mem_lat=M, flags=LSPD, mig_threshold=2, l1_sets=1, l1_ways=1)
+    sim = gpu_sim(p)
+    assert _run_ops(sim, [(0, 0, 5)]) == {0: M + 4}
+    assert _run_ops(sim, [(sim.cycle + 2, 3, 5)]) == {0: 11}
+    assert _run_ops(sim, [(sim.cycle + 2, 3, 7)]) == {0: 1 + M}
+    c0 = sim.cycle + 2
+    assert _run_ops(sim, [(c0, 3, 5), (c0 + 20, 2, 5)]) == {0: 30, 1: 15}
+    st = sim.stats()
+    assert st[STAT["migrations"]] == 1 and st[STAT["redirects"]] == 1
+
+
+@pytest.mark.parametrize("thr", [1, 2, 4])
+@pytest.mark.parametrize("flags", [LSPD, LSPD | CENTRAL], ids=["interleaved", "central"])
+def test_migration_config0_run(flags, thr):
+    p = W.config0().with_(flags=flags, mig_threshold=thr, op_thr=W.thr(0.5), l1_sets=2, l1_ways=1, l2_sets=8,
+                          l2_ways=2, shared_lines=256, reply_flits=4)
+    assert_same_run(p, 6000, step_sizes=[1, 999, 5000])
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (5, 5), (13, 7)])
+@pytest.mark.parametrize("flags", [LSPD, LSPD | W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY],
+                         ids=["lspd", "with_variants"])
+def test_migration_small_shapes(w, h, flags):
+    p = W.config1().with_(width=w, height=h, seed=w * 100 + h + flags, bg_thr=W.thr(0.1) if w * h > 1 else 0,
+                          op_thr=W.thr(0.6), l1_sets=2, l1_ways=1, l2_sets=8, l2_ways=2, shared_lines=256,
+                          private_lines=32, flags=flags, mig_threshold=1, reply_flits=2, router_delay=2)
+    assert_same_run(p, 3000)
+
+
+@pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
+def test_migration_patch_mappings(launch):
+    p = W.config1().with_(width=20, height=13, seed=12, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l1_sets=2, l1_ways=1,
+                          l2_sets=8, l2_ways=2, shared_lines=512, private_lines=32, flags=LSPD, mig_threshold=2)
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+
+
+def test_migration_208x208_prefix():
+    p = W.config2(0.05).with_(flags=LSPD, private_lines=2**10, mig_threshold=2)
+    assert_same_run(p, 80, step_sizes=[30, 50])
+
+
+def test_migration_checkpoint_mid_claim_and_drain():
+    p = W.config1().with_(width=6, height=6, seed=61, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l1_sets=2, l1_ways=1,
+                          l2_sets=8, l2_ways=2, shared_lines=128, private_lines=16, flags=LSPD, mig_threshold=1,
+                          reply_flits=4)
+    b = gpu_sim(p)
+    for _ in range(3000):
+        b.step(1)
+        core = split_dump(b.dump(), p)["core"]
+        if ((core[:, CORE["state"]] == 3) & (core[:, CORE["claim"]] >= 0)).any():
+            break
+    else:
+        raise AssertionError("no pending claim seen")
+    k = b.cycle
+    snap = b.dump()
+    a = gpu_sim(p)
+    da = a.step(k + 700, digests=True)
+    c = gpu_sim(p)
+    c.load(snap)
+    assert (c.step(700, digests=True) == da[k:]).all()
+    o = O.OracleSim(p)
+    o.load(snap)
+    o.step(700)
+    assert (c.dump() == o.dump()).all()
+    for s in (a, o):
+        s.set_rates(0, 0)
+        s.step(3000)
+    assert (a.dump() == o.dump()).all()
+    assert o.quiescent()
+    assert a.stats()[STAT["migrations"]] > 0
+
+
+def test_migration_batch_with_other_chips():
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=7000 + i, bg_thr=W.thr(0.1), l1_sets=2, l1_ways=1,
+                                l2_sets=16, shared_lines=2048, private_lines=64, flags=f, mig_threshold=m)
+              for i, (s, f, m) in enumerate([(8, 0, 0), (16, LSPD, 2), (8, LSPD | CENTRAL, 1), (24, LSPD, 0)])]
+    sims = [gpu_sim(p) for p in params]
+    b = nocsim.Batch(sims)
+    b.step([300, 250, 300, 123])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123]):
+        o = O.OracleSim(p)
+        o.step(n)
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags} mig {p.mig_threshold}"

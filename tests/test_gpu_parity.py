@@ -35,7 +35,7 @@ def assert_same_run(p, cycles, launch=None, step_sizes=None, generic=False):
     a, b = g.dump(), o.dump()
     if not (a == b).all():
         da, db = split_dump(a, p), split_dump(b, p)
-        for k in ("links", "core", "l1", "l2", "stats", "ages", "pipe", "loc"):
+        for k in ("links", "core", "l1", "l2", "stats", "ages", "pipe", "loc", "l2rec"):
             if not np.array_equal(da[k], db[k]):
                 idx = np.argwhere(da[k] != db[k])[:5]
                 raise AssertionError(f"dump section {k} differs at {idx.tolist()}")
