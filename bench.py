@@ -19,7 +19,8 @@ Besides the headline line the JSON carries:
                  digests of a prefix against the oracle (--no-packets);
   variants     - the same chip under each model variant (priority by deflection count, hit
                  under miss, injection register, all three; router delay 2; the LSPD directory,
-                 interleaved and central) on the general kernel, beside the
+                 interleaved and central, and with migration after 2 accesses) on the general
+                 kernel, beside the
                  base model on that kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
   batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
@@ -170,10 +171,12 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
     out = {}
     cases = [("base", 0), ("age_deflect", W.AGE_DEFLECT), ("hit_under_miss", W.HIT_UNDER_MISS),
              ("inject_delay", W.INJECT_DELAY), ("all", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
-             ("router_delay_2", 0), ("lspd", W.LSPD), ("lspd_central", W.LSPD | W.LSPD_CENTRAL)]
+             ("router_delay_2", 0), ("lspd", W.LSPD), ("lspd_central", W.LSPD | W.LSPD_CENTRAL),
+             ("lspd_migration_2", W.LSPD)]
     S = nocsim.STAT
     for name, flags in cases:
-        p = W.config2(0.05).with_(flags=flags, router_delay=2 if name == "router_delay_2" else 1)
+        p = W.config2(0.05).with_(flags=flags, router_delay=2 if name == "router_delay_2" else 1,
+                                  mig_threshold=2 if name == "lspd_migration_2" else 0)
         sim = nocsim.Sim(p)
         sim.set_kernel(True)
         sim.step(300)
@@ -192,7 +195,8 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
              "avg_op_latency": float(st[S["op_lat"]] / max(1, st[S["ops_done"]])),
              "ops_per_tile_cycle": float(st[S["ops_done"]] / (p.tiles * cycles))}
         if flags & W.LSPD:
-            r["directory"] = {k: int(st[S[k]]) for k in ("dir_access", "dir_nack", "trap", "dir_evict", "l2_hit", "l2_miss")}
+            r["directory"] = {k: int(st[S[k]]) for k in ("dir_access", "dir_nack", "trap", "dir_evict", "l2_hit", "l2_miss",
+                                                         "migrations", "redirects")}
         del sim
         if O is not None:
             g = nocsim.Sim(p)
