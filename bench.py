@@ -19,7 +19,7 @@ Besides the headline line the JSON carries:
                  digests of a prefix against the oracle (--no-packets);
   variants     - the same chip under each model variant (priority by deflection count, hit
                  under miss, injection register, all three; router delay 2; the LSPD directory,
-                 interleaved and central, and with migration after 2 accesses) on the general
+                 interleaved and central, and migrating a block on every remote access) on the general
                  kernel, beside the
                  base model on that kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
@@ -172,11 +172,11 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
     cases = [("base", 0), ("age_deflect", W.AGE_DEFLECT), ("hit_under_miss", W.HIT_UNDER_MISS),
              ("inject_delay", W.INJECT_DELAY), ("all", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
              ("router_delay_2", 0), ("lspd", W.LSPD), ("lspd_central", W.LSPD | W.LSPD_CENTRAL),
-             ("lspd_migration_2", W.LSPD)]
+             ("lspd_migration_1", W.LSPD)]
     S = nocsim.STAT
     for name, flags in cases:
         p = W.config2(0.05).with_(flags=flags, router_delay=2 if name == "router_delay_2" else 1,
-                                  mig_threshold=2 if name == "lspd_migration_2" else 0)
+                                  mig_threshold=1 if name == "lspd_migration_1" else 0)
         sim = nocsim.Sim(p)
         sim.set_kernel(True)
         sim.step(300)
