@@ -100,7 +100,7 @@ class OracleBackend(Backend):
 
     def state_bytes(self, params) -> int:
         N = params.tiles
-        return N * (128 + 64 + 16 + 4 * (params.l1_sets * params.l1_ways + params.l2_sets * params.l2_ways))
+        return N * (128 + 96 + 16 + 4 * (params.l1_sets * params.l1_ways + params.l2_sets * params.l2_ways))
 
     def create(self, params):
         return self.O.OracleSim(params)
