@@ -99,3 +99,12 @@ def test_migration_batch_with_other_chips():
         o = O.OracleSim(p)
         o.step(n)
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags} mig {p.mig_threshold}"
+
+
+def test_full_size_long_prefix_every_option():
+    """208x208 with the directory, migration on every remote access, multi-flit replies, the
+    three variants and a router delay: 400 cycles, every digest equal to the oracle's, then the
+    whole canonical state (location array and way records included)."""
+    p = W.config2(0.1).with_(flags=LSPD | W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY, private_lines=2**10,
+                             mig_threshold=1, reply_flits=4, router_delay=2, l1_sets=4, l1_ways=1)
+    assert_same_run(p, 400, step_sizes=[150, 250])

@@ -172,3 +172,25 @@ def test_router_delay_batch_mixed():
         o = O.OracleSim(p)
         o.step(n)
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} router_delay {p.router_delay}"
+
+
+def test_serving_mixed_model_options_equal_solo_runs():
+    """Jobs with different model options share the scheduler's batched launches; each job's
+    statistics equal those of the oracle run of the same job."""
+    from paper_1508_03235_amd import serve
+    import random
+    rng = random.Random(5)
+    opts = [dict(), dict(flags=AGE), dict(flags=HUM | DELAY, reply_flits=4), dict(router_delay=3),
+            dict(flags=W.LSPD, mig_threshold=2, private_lines=64), dict(flags=W.LSPD | W.LSPD_CENTRAL, private_lines=64)]
+    jobs = []
+    for i, o in enumerate(opts * 2):
+        side = rng.choice([8, 12, 16])
+        p = W.config1().with_(width=side, height=side, seed=9000 + i, bg_thr=W.thr(0.1), l2_sets=16, **o)
+        jobs.append(W.Job(i, 0.001 * i, rng.choice([300, 500, 700]), p))
+    srv = serve.Server(serve.GpuBackend(), budget_bytes=8 << 30, tick_cycles=200)
+    rep = srv.run(jobs)
+    for r, j in zip(rep.results, jobs):
+        assert r.error is None, r.error
+        o = O.OracleSim(j.params)
+        o.step(j.cycles)
+        assert (r.stats == o.stats()).all(), f"job {j.index} {j.params.flags}"
