@@ -307,6 +307,11 @@ __device__ __forceinline__ int way_pick(const int (&v)[8], int i) {
     if (i == k) x = v[k];
   return x;
 }
+__device__ __forceinline__ void way_put(int (&v)[8], int i, int x) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (i == k) v[k] = x;
+}
 __device__ __forceinline__ void way_front(int (&v)[8], int (&h)[8], int i, bool rec) {
   const int tag = way_pick(v, i), r = way_pick(h, i);
 #pragma unroll
@@ -631,8 +636,9 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
         lds_add(L, SIM_ST_L2_HIT, 1);
         int run = 1;
         if (mig) {  // Sec. 3.3: the block's record of its latest accessors
-          run = (hR[i] & 0xFFFFF) == who ? min(((uint32_t)hR[i] >> 20) + 1, 4095u) : 1;
-          hR[i] = (int)(((uint32_t)run << 20) | (uint32_t)who);
+          const int hr = way_pick(hR, i);
+          run = (hr & 0xFFFFF) == who ? min(((uint32_t)hr >> 20) + 1, 4095u) : 1;
+          way_put(hR, i, (int)(((uint32_t)run << 20) | (uint32_t)who));
         }
         way_front(vR, hR, i, mig);
         dirtyR = true;
@@ -730,8 +736,9 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     } else if (i >= 0) {
       lds_add(L, SIM_ST_L2_HIT, 1);
       if (mig) {
-        const uint32_t run = (hL[i] & 0xFFFFF) == t ? min(((uint32_t)hL[i] >> 20) + 1, 4095u) : 1u;
-        hL[i] = (int)((run << 20) | (uint32_t)t);
+        const int hl = way_pick(hL, i);
+        const uint32_t run = (hl & 0xFFFFF) == t ? min(((uint32_t)hl >> 20) + 1, 4095u) : 1u;
+        way_put(hL, i, (int)((run << 20) | (uint32_t)t));
       }
       way_front(vL, hL, i, mig);
       dirtyL = true;
@@ -882,7 +889,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       }
       acc.inj_req++;
     } else if (cls <= 1) {  // a flit of the head's reply; the head is popped with the packet's last flit
-      const int4 hd = cls == 0 ? nm : nh;
+      const int4 hd = sel4(cls == 0, nm, nh);  // word by word (a struct select can go through scratch)
       const int rq = cls == 0 ? k2.x : k1.z;
       const int sent = hd.w + 1;
       // a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits
