@@ -1263,32 +1263,9 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
 //    finishes cycle c+1, while its next writer is at least three cycles of flit traffic away.
 constexpr int FAST_MAX = 256;
 
-// Port of one flit, oldest first: eject if destined here and free, else the first free
-// productive port (X before Y), else the lowest free port; packs it at bits 3*idx of `ports`.
-__device__ __forceinline__ void arb_assign(int dst, int idx, int t, int x, int y, const ChipDev& C, unsigned valid,
-                                           unsigned& used, uint32_t& ports, Acc& acc) {
-  if (dst < 0) return;
-  unsigned port;
-  if (dst == t && !(used & 16u)) {
-    port = 4;
-  } else {
-    const int drow = C.W > 1 ? (int)__umulhi((uint32_t)dst, C.w_magic) : dst;
-    const int dx = (dst - drow * C.W) - x, dy = drow - y;
-    const int px = dx > 0 ? 2 : (dx < 0 ? 3 : -1);
-    const int py = dy > 0 ? 1 : (dy < 0 ? 0 : -1);
-    if (px >= 0 && !(used & (1u << px))) port = (unsigned)px;
-    else if (py >= 0 && !(used & (1u << py))) port = (unsigned)py;
-    else {
-      port = (unsigned)__builtin_ctz(valid & ~used & 15u);
-      acc.defl++;
-    }
-    acc.trav++;
-  }
-  used |= 1u << port;
-  ports = (ports & ~(7u << (3 * idx))) | (port << (3 * idx));
-}
-
-// The same choice without branches, for the one-tile-per-thread kernel: `key` is the flit's
+// Port of one flit, oldest first, without branches (the one-tile-per-thread kernel): eject if
+// destined here and free, else the first free productive port (X before Y), else the lowest
+// free port.  `key` is the flit's
 // priority key (inject cycle, then source, then its input index in the low 3 bits; all ones for
 // an empty input), `dst` its destination (negative when empty).  Records the flit's input index
 // at bits 3*port of `inv` (the flit each output port carries; 7 = none).
