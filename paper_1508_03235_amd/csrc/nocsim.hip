@@ -1962,6 +1962,18 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
   }
   return per_cu * device_cus();
 }
+// the same over every build a chip may be launched with (with or without digests and packets,
+// or on the general kernel)
+int resident_limit_any(int block) {
+  int lo = resident_limit(block, false);
+  for (int k = 0; k < 4; ++k) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k & 2), block, 0) != hipSuccess)
+      return 0;
+    lo = std::min(lo, per_cu * device_cus());
+  }
+  return lo;
+}
 
 int upload_desc(sim_chip* h) {
   HIPCHECK(hipMemcpyAsync(h->dd, &h->hd, sizeof(ChipDev), hipMemcpyHostToDevice, h->stream));
@@ -1969,8 +1981,12 @@ int upload_desc(sim_chip* h) {
   return SIM_OK;
 }
 
-// Default mapping: one workgroup for small chips; strips of whole rows (up to 256 tiles) for
-// chips up to 256 columns wide; otherwise square-ish patches, about one per compute unit.
+static int block_for(int tiles) { return tiles <= 64 ? 64 : tiles <= 128 ? 128 : tiles <= 192 ? 192 : 256; }
+
+// Default mapping: one workgroup for small chips; for chips up to 256 columns, one tile per
+// thread in strips of one row per workgroup of one or two waves (half a row above 128 columns;
+// up to 256 tiles of whole rows below 64 columns), as long as every strip can be resident at
+// once; otherwise square-ish patches, about one per compute unit.
 void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* block) {
   const int N = c->width * c->height;
   if (N <= 1024) {
@@ -1979,18 +1995,23 @@ void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* blo
     *block = N <= 64 ? 64 : 256;
     return;
   }
-  if (c->width <= 256) {  // strips of whole rows, up to 256 tiles each (measured fastest)
-    *pw = c->width;
-    *ph = std::max(1, 256 / c->width);
-  } else {
-    const int target = device_cus();
-    int side = 1;
-    while ((int64_t)((c->width + side - 1) / side) * ((c->height + side - 1) / side) > target) side++;
-    *pw = std::min(side, c->width);
-    *ph = std::min(side, c->height);
+  if (c->width <= 256) {
+    const int w = c->width > 128 ? (c->width + 1) / 2 : c->width;
+    const int h = c->width < 64 ? std::min(c->height, 256 / c->width) : 1;
+    const int np = ((c->width + w - 1) / w) * ((c->height + h - 1) / h);
+    if (np <= resident_limit_any(block_for(w * h))) {
+      *pw = w;
+      *ph = h;
+      *block = block_for(w * h);
+      return;
+    }
   }
-  const int tiles = (*pw) * std::min(*ph, c->height);
-  *block = tiles <= 64 ? 64 : tiles <= 128 ? 128 : tiles <= 192 ? 192 : 256;
+  const int target = device_cus();
+  int side = 1;
+  while ((int64_t)((c->width + side - 1) / side) * ((c->height + side - 1) / side) > target) side++;
+  *pw = std::min(side, c->width);
+  *ph = std::min(side, c->height);
+  *block = block_for((*pw) * (*ph));
 }
 
 int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
