@@ -158,7 +158,6 @@ __device__ __forceinline__ void st_slot(int4* p, int4 v, bool coh) {
   __hip_atomic_store(gp(q), (unsigned long long)(uint32_t)v.x | ((unsigned long long)(uint32_t)v.y << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(gp(q + 1), (unsigned long long)(uint32_t)v.z | ((unsigned long long)(uint32_t)v.w << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-template <bool COH> __device__ __forceinline__ int ld_i(const int* p) { return COH ? ld_coh(p) : *gp(p); }
 template <bool COH> __device__ __forceinline__ void st_i(int* p, int v) { if (COH) st_coh(p, v); else *gp(p) = v; }
 
 // ---- link-slot encoding -------------------------------------------------------------------------
@@ -1287,18 +1286,6 @@ __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, 
   acc.defl += moved && !okx && !oky;
   used |= live ? (1u << port) : 0u;
   inv = live ? ((inv & ~(7u << (3 * port))) | (idx << (3 * port))) : inv;
-}
-
-// The flit leaving through port p (0..3, or 4 = eject), or an empty slot.
-__device__ __forceinline__ int4 flit_on_port(uint32_t ports, unsigned p, const int4& f0, const int4& f1, const int4& f2,
-                                             const int4& f3, const int4& f4) {
-  int4 o = make_int4(-1, -1, -1, -1);
-  if ((ports & 7u) == p) o = f0;
-  if (((ports >> 3) & 7u) == p) o = f1;
-  if (((ports >> 6) & 7u) == p) o = f2;
-  if (((ports >> 9) & 7u) == p) o = f3;
-  if (((ports >> 12) & 7u) == p) o = f4;
-  return o;
 }
 
 constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;

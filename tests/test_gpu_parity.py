@@ -174,6 +174,19 @@ def test_wide_and_tall_chips(w, h):
     assert_same_run(p, 150, step_sizes=[60, 90])
 
 
+@pytest.mark.parametrize("w,h", [(100, 2048), (256, 300)])
+def test_default_mapping_of_tall_chips(w, h):
+    """Strips of one row per workgroup would outnumber the workgroups some build of the kernel
+    can hold at once on these chips: the default mapping falls back to square-ish patches."""
+    p = W.config0().with_(width=w, height=h, seed=w + h, bg_thr=W.thr(0.1), op_thr=W.thr(0.3),
+                          l1_sets=16, l2_sets=32)
+    g = gpu_sim(p)
+    pw, ph, block, _ = g.get_launch()
+    assert -(-w // pw) * -(-h // ph) <= 512
+    del g
+    assert_same_run(p, 40, step_sizes=[15, 25])
+
+
 def test_largest_line_numbers():
     """252x256 tiles with 2^14 private lines each: the top private line is 2^30 - 1, the
     largest line the flit format holds."""
