@@ -20,8 +20,8 @@ Besides the headline line the JSON carries:
   variants     - the same chip under each model variant (priority by deflection count, hit
                  under miss, injection register, all three; router delay 2; the LSPD directory,
                  interleaved and central, and migrating a block on every remote access) on the general
-                 kernel, beside the
-                 base model on that kernel: throughput, deflection rate, latencies, ops per
+                 kernel, beside the base model on that kernel, and the injection register also on
+                 the one-tile-per-thread kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
   batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
   serving      - Poisson-arriving simulation jobs under continuous batching: p50/p99 job
@@ -167,18 +167,20 @@ def run_packets(nocsim, W, torch, O, cycles, parity_cycles=200, flits=4):
 
 
 def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
-    """The 208x208 chip at background 0.05 under each model variant (general kernel)."""
+    """The 208x208 chip at background 0.05 under each model variant (general kernel; the
+    injection register also on the one-tile-per-thread kernel)."""
     out = {}
     cases = [("base", 0), ("age_deflect", W.AGE_DEFLECT), ("hit_under_miss", W.HIT_UNDER_MISS),
              ("inject_delay", W.INJECT_DELAY), ("all", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
              ("router_delay_2", 0), ("lspd", W.LSPD), ("lspd_central", W.LSPD | W.LSPD_CENTRAL),
-             ("lspd_migration_1", W.LSPD)]
+             ("lspd_migration_1", W.LSPD), ("inject_delay_fast", W.INJECT_DELAY)]
     S = nocsim.STAT
     for name, flags in cases:
+        generic = not name.endswith("_fast")
         p = W.config2(0.05).with_(flags=flags, router_delay=2 if name == "router_delay_2" else 1,
                                   mig_threshold=1 if name == "lspd_migration_1" else 0)
         sim = nocsim.Sim(p)
-        sim.set_kernel(True)
+        sim.set_kernel(generic)
         sim.step(300)
         st0 = sim.stats()
         torch.cuda.synchronize()
@@ -188,7 +190,8 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
         st = sim.stats() - st0
         ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
         lat = st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]
-        r = {"flags": flags, "router_delay": p.router_delay, "tile_cycles_per_s": p.tiles * cycles / dt,
+        r = {"flags": flags, "router_delay": p.router_delay, "kernel": "general" if generic else "one tile per thread",
+             "tile_cycles_per_s": p.tiles * cycles / dt,
              "deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
              "avg_flit_latency": float(lat / max(1, ej)),
              "max_flit_latency": int(sim.stats()[S["lat_max"]]),
@@ -200,7 +203,7 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
         del sim
         if O is not None:
             g = nocsim.Sim(p)
-            g.set_kernel(True)
+            g.set_kernel(generic)
             r["parity"] = {"cycles": parity_cycles, "digests_equal": bool(
                 (g.step(parity_cycles, digests=True) == O.OracleSim(p).step(parity_cycles, digests=True)).all())}
             del g

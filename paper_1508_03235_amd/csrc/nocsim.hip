@@ -1348,11 +1348,16 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   draw_ahead(C, t, c + 1, P);
 }
 
-// PACKETS: replies may have several flits (the chip's reply_flits); without it the kernel is
-// the single-flit model, compiled without the per-flit counts.
-template <bool MULTI, bool DIGEST, bool PACKETS>
+// OPT bit 0 (FAST_PACKETS): replies may have several flits (the chip's reply_flits); without it
+// the kernel is the single-flit model, compiled without the per-flit counts.  OPT bit 1
+// (FAST_INJ_REG): the chip may have the injection register (a flit made in a cycle enters the
+// network from the next one on, Sec. 6.2.1); without it that variant is compiled out.
+constexpr int FAST_PACKETS = 1, FAST_INJ_REG = 2;
+template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
+  constexpr bool PACKETS = (OPT & FAST_PACKETS) != 0;
+  constexpr bool INJ_REG = (OPT & FAST_INJ_REG) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1362,6 +1367,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const LaunchEntry e = table[blockIdx.x];
   const ChipDev C = *e.chip;
   const int N = C.N;
+  const int D = INJ_REG ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1476,7 +1482,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           acc.l2_hit += hit;
           acc.l2_miss += !hit;
           node_rq = rq;
-          node_ready = hit ? c : c + C.mem_lat;
+          node_ready = (hit ? c : c + C.mem_lat) + D;
           node_line = line;
           const int4 fresh = make_int4(-1, node_ready, line, 0);
           if (hit) {
@@ -1584,8 +1590,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
         int cls = -1;
         if (k2.x >= 0 && nm.y <= c) cls = 0;
-        else if (k1.z >= 0) cls = 1;
-        else if (k0.x == CORE_SEND) cls = 2;
+        else if (k1.z >= 0 && (!INJ_REG || nh.y <= c)) cls = 1;
+        else if (k0.x == CORE_SEND && (!INJ_REG || k0.y + D <= c)) cls = 2;
         else if (fdst >= 0) cls = 3;
         else if (k2.z > 0) cls = 4;
         if (cls >= 0 && arrivals >= deg) {
@@ -1810,7 +1816,7 @@ struct sim_group {
   std::vector<sim_launch_group> groups;
   int32_t block;
   bool multi, fast;
-  bool packets;                      // some chip has multi-flit replies
+  int opt;                           // FAST_* bits some chip needs (multi-flit replies, injection register)
   int var;                           // general-kernel build: 1 a variant or router delay > 1, 2 the directory
   hipStream_t stream;
   LaunchEntry* table_dev;
@@ -1857,6 +1863,8 @@ size_t lspd_lines(const sim_config* c) {  // location-array entries (0 without t
 int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_delay : 1; }
 // which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
 int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
+// OPT bits of the one-tile-per-thread kernel a chip needs
+int fast_opt(const ChipDev& d) { return (d.reply_flits > 1 ? FAST_PACKETS : 0) | (d.inj_delay ? FAST_INJ_REG : 0); }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
 
@@ -1927,15 +1935,21 @@ int device_cus() {
   return cus;
 }
 
-const void* multi_kernel(bool fast, bool digest = false, bool packets = false, int var = 0) {
+// the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
+template <bool MULTI, bool DIGEST>
+const void* fast_build(int opt) {
+  switch (opt & 3) {
+    case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
+    case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
+    case 2: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 2>);
+    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
+  }
+}
+const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 0) {
   if (!fast) return var == 2 ? reinterpret_cast<const void*>(step_kernel<true, 2>)
                     : var == 1 ? reinterpret_cast<const void*>(step_kernel<true, 1>)
                                : reinterpret_cast<const void*>(step_kernel<true, 0>);
-  if (packets)
-    return digest ? reinterpret_cast<const void*>(step_fast<true, true, true>)
-                  : reinterpret_cast<const void*>(step_fast<true, false, true>);
-  return digest ? reinterpret_cast<const void*>(step_fast<true, true, false>)
-                : reinterpret_cast<const void*>(step_fast<true, false, false>);
+  return digest ? fast_build<true, true>(opt) : fast_build<true, false>(opt);
 }
 // how many workgroups of `block` threads of the multi-patch kernel can be resident at once
 int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
@@ -1949,13 +1963,13 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
   }
   return per_cu * device_cus();
 }
-// the same over every build a chip may be launched with (with or without digests and packets,
-// or on the general kernel)
+// the same over every build a chip may be launched with (with or without digests, with any
+// OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < 8; ++k) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k & 2), block, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
     lo = std::min(lo, per_cu * device_cus());
   }
@@ -2025,21 +2039,19 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 }
 
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
-// packets: some chip of the table has multi-flit replies (the kernel then reads each chip's count)
+// opt: FAST_PACKETS when some chip of the table has multi-flit replies (the kernel then reads
+// each chip's count), FAST_INJ_REG when some chip has the injection register
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
-                   unsigned long long* digests, int digest_base, hipStream_t s, bool packets, int var) {
+                   unsigned long long* digests, int digest_base, hipStream_t s, int opt, int var) {
   if (n <= 0) return SIM_OK;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, packets, var), dim3((unsigned)n), dim3(block),
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, opt, var), dim3((unsigned)n), dim3(block),
                                         args, 0, s));
   } else if (fast) {
-    const dim3 g((unsigned)n), b(block);
-    if (digests && packets) hipLaunchKernelGGL((step_fast<false, true, true>), g, b, 0, s, table, chunk, digests, digest_base);
-    else if (digests) hipLaunchKernelGGL((step_fast<false, true, false>), g, b, 0, s, table, chunk, digests, digest_base);
-    else if (packets) hipLaunchKernelGGL((step_fast<false, false, true>), g, b, 0, s, table, chunk, digests, digest_base);
-    else hipLaunchKernelGGL((step_fast<false, false, false>), g, b, 0, s, table, chunk, digests, digest_base);
-    HIPCHECK(hipGetLastError());
+    void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
+    HIPCHECK(hipLaunchKernel(digests ? fast_build<false, true>(opt) : fast_build<false, false>(opt), dim3((unsigned)n),
+                             dim3(block), args, 0, s));
   } else {
     const dim3 g((unsigned)n), b(block);
     if (var == 2) hipLaunchKernelGGL((step_kernel<false, 2>), g, b, 0, s, table, chunk, digests, digest_base);
@@ -2090,7 +2102,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  h->use_fast = (cfg->flags & VARIANT_FLAGS) == 0 && router_delay(cfg) == 1;  // variants: general kernel
+  // variants other than the injection register, and D > 1: general kernel
+  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~SIM_FLAG_INJECT_DELAY) == 0 && router_delay(cfg) == 1;
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -2186,7 +2199,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS) == 0 && h->hd.rdelay == 1;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~SIM_FLAG_INJECT_DELAY) == 0 && h->hd.rdelay == 1;
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;
@@ -2223,7 +2236,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
     int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
-                            h->hd.reply_flits > 1, kernel_level(h->hd));
+                            fast_opt(h->hd), kernel_level(h->hd));
     if (rc) return rc;
   }
   h->cycle += n;
@@ -2492,10 +2505,10 @@ int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, si
   g->block = blk;
   g->multi = multi;
   g->fast = fast;
-  g->packets = false;
+  g->opt = 0;
   g->var = 0;
   for (int i = 0; i < n; ++i) {
-    g->packets = g->packets || chips[i]->hd.reply_flits > 1;
+    g->opt |= fast_opt(chips[i]->hd);
     g->var = std::max(g->var, kernel_level(chips[i]->hd));
   }
   g->groups = groups;
@@ -2537,7 +2550,7 @@ int simb_step(simb_t* g, const int64_t* cycles) {
     const int launches = (int)((lg_longest + chunk - 1) / chunk);
     for (int k = 0; k < launches; ++k) {
       int rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
-                              g->stream, g->packets, g->var);
+                              g->stream, g->opt, g->var);
       if (rc) return rc;
     }
   }

@@ -1,6 +1,7 @@
 """Parity of the model variants (SimParams.flags) on the GPU with the serial oracle.
 
-The variants run on the general kernel.  Bar: bit-exact, as for the base model: every
+The injection register runs on the one-tile-per-thread kernel as well as on the general one;
+the other variants run on the general kernel.  Bar: bit-exact, as for the base model: every
 per-cycle digest and the final canonical dump, including each in-flight flit's deflection
 count and each core's held op.
 """
@@ -33,7 +34,7 @@ def test_variants_small_shapes(w, h, flags):
     assert_same_run(p, 3000)
 
 
-@pytest.mark.parametrize("flags", [AGE, AGE | HUM | DELAY], ids=["age", "all"])
+@pytest.mark.parametrize("flags", [AGE, DELAY, AGE | HUM | DELAY], ids=["age", "delay", "all"])
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
 def test_variants_patch_mappings(launch, flags):
     """Deflection counts travel in the link slots across patch edges (stamped halves), and
@@ -46,6 +47,34 @@ def test_variants_patch_mappings(launch, flags):
 def test_variants_config2_full_size_prefix(flags):
     """208x208 (43,264 tiles) in the default launch configuration."""
     assert_same_run(W.config2(0.1).with_(flags=flags), 100, step_sizes=[40, 60])
+
+
+@pytest.mark.parametrize("reply_flits", [1, 3])
+def test_injection_register_on_both_kernels(reply_flits):
+    """The injection register on the one-tile-per-thread kernel equals the general kernel and
+    the oracle, with single- and multi-flit replies, across launch boundaries."""
+    p = W.config0().with_(width=24, height=9, seed=55 + reply_flits, bg_thr=W.thr(0.2), op_thr=W.thr(0.6),
+                          flags=DELAY, reply_flits=reply_flits)
+    a = gpu_sim(p)
+    b = gpu_sim(p, generic=True)
+    assert (a.step(777, digests=True) == b.step(777, digests=True)).all()
+    assert (a.dump() == b.dump()).all()
+    assert_same_run(p, 1200, step_sizes=[500, 700])
+
+
+def test_injection_register_batch_on_the_fast_kernel():
+    """One launch of the one-tile-per-thread kernel over base chips and chips with the
+    injection register (some with multi-flit replies): each equals its own oracle run."""
+    from paper_1508_03235_amd import nocsim
+    params = [W.config1().with_(width=s, height=s, seed=5000 + i, bg_thr=W.thr(0.15), flags=f, reply_flits=r)
+              for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, DELAY, 4), (12, 0, 2), (16, DELAY, 2)])]
+    sims = [gpu_sim(p, launch=(p.width, 256 // p.width, 256, 0)) for p in params]
+    b = nocsim.Batch(sims)
+    b.step([300, 250, 300, 123, 200])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200]):
+        o = O.OracleSim(p)
+        o.step(n)
+        assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags} reply_flits {p.reply_flits}"
 
 
 def test_variants_refuse_the_base_kernel():
