@@ -198,6 +198,23 @@ __device__ __forceinline__ int4 slot_decode(const int4& w) {
   if (d == TILE_BITS_MASK) return make_int4(-1, -1, -1, -1);
   return make_int4((int)d, w.y, (int)((uint32_t)w.z & TILE_BITS_MASK), w.w);
 }
+// The same, keeping the deflection count in bits 20-27 of the dst and src words (the
+// one-tile-per-thread kernel's flit rows under priority by deflection count).
+constexpr uint32_t STAMP_OFF = ~(STAMP_MASK << STAMP_SHIFT);
+__device__ __forceinline__ int4 slot_decode_aged(const int4& w) {
+  if (((uint32_t)w.x & TILE_BITS_MASK) == TILE_BITS_MASK) return make_int4(-1, -1, -1, -1);
+  return make_int4((int)((uint32_t)w.x & STAMP_OFF), w.y, (int)((uint32_t)w.z & STAMP_OFF), w.w);
+}
+// deflection count of such a row (0 when empty)
+__device__ __forceinline__ uint32_t row_age(const int4& f) {
+  if (f.x < 0) return 0u;
+  return (((uint32_t)f.x >> AGE_SHIFT) & 0xFFu) | ((((uint32_t)f.z >> AGE_SHIFT) & 0xFFu) << 8);
+}
+// the row without its count
+__device__ __forceinline__ int4 row_clean(const int4& f) {
+  if (f.x < 0) return f;
+  return make_int4((int)((uint32_t)f.x & TILE_BITS_MASK), f.y, (int)((uint32_t)f.z & TILE_BITS_MASK), f.w);
+}
 __device__ __forceinline__ int4 sel4(bool p, const int4& a, const int4& b) {  // p ? a : b, per word
   return make_int4(p ? a.x : b.x, p ? a.y : b.y, p ? a.z : b.z, p ? a.w : b.w);
 }
@@ -1268,8 +1285,9 @@ constexpr int FAST_MAX = 256;
 // priority key (inject cycle, then source, then its input index in the low 3 bits; all ones for
 // an empty input), `dst` its destination (negative when empty).  Records the flit's input index
 // at bits 3*port of `inv` (the flit each output port carries; 7 = none).
+template <bool DEFL_MASK>  // also record the deflected flits in `dm`
 __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, int t, int x, int y, const ChipDev& C,
-                                               unsigned valid, unsigned& used, uint32_t& inv, Acc& acc) {
+                                               unsigned valid, unsigned& used, uint32_t& inv, unsigned& dm, Acc& acc) {
   const bool live = dst >= 0;
   const unsigned idx = (unsigned)key & 7u;
   const unsigned fr = ~used;
@@ -1284,6 +1302,7 @@ __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, 
   const bool moved = live && !ej;
   acc.trav += moved;
   acc.defl += moved && !okx && !oky;
+  if (DEFL_MASK) dm |= (moved && !okx && !oky) ? (1u << idx) : 0u;  // deflected: bit of its input index
   used |= live ? (1u << port) : 0u;
   inv = live ? ((inv & ~(7u << (3 * port))) | (idx << (3 * port))) : inv;
 }
@@ -1351,13 +1370,16 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // OPT bit 0 (FAST_PACKETS): replies may have several flits (the chip's reply_flits); without it
 // the kernel is the single-flit model, compiled without the per-flit counts.  OPT bit 1
 // (FAST_INJ_REG): the chip may have the injection register (a flit made in a cycle enters the
-// network from the next one on, Sec. 6.2.1); without it that variant is compiled out.
-constexpr int FAST_PACKETS = 1, FAST_INJ_REG = 2;
+// network from the next one on, Sec. 6.2.1); without it that variant is compiled out.  OPT bit 2
+// (FAST_AGE): the chip may rank flits by deflection count (Sec. 4.2, Sec. 6.2.1); the flit rows
+// then keep the count in bits 20-27 of their dst and src words, as the link slots do.
+constexpr int FAST_PACKETS = 1, FAST_INJ_REG = 2, FAST_AGE = 4;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   constexpr bool PACKETS = (OPT & FAST_PACKETS) != 0;
   constexpr bool INJ_REG = (OPT & FAST_INJ_REG) != 0;
+  constexpr bool AGE = (OPT & FAST_AGE) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1368,6 +1390,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const ChipDev C = *e.chip;
   const int N = C.N;
   const int D = INJ_REG ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
+  const bool aged = AGE && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1412,10 +1435,22 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     fdst = k3.x;
     rcv = k3.y;
     const int par = c0 & 1;
-    if (i0) s_link[par][0][j] = slot_decode(gload4(&C.link[(par * 4 + 0) * N + t]));
-    if (i1) s_link[par][1][j] = slot_decode(gload4(&C.link[(par * 4 + 1) * N + t]));
-    if (i2) s_link[par][2][j] = slot_decode(gload4(&C.link[(par * 4 + 2) * N + t]));
-    if (i3) s_link[par][3][j] = slot_decode(gload4(&C.link[(par * 4 + 3) * N + t]));
+    if (i0) {
+      const int4 w = gload4(&C.link[(par * 4 + 0) * N + t]);
+      s_link[par][0][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+    }
+    if (i1) {
+      const int4 w = gload4(&C.link[(par * 4 + 1) * N + t]);
+      s_link[par][1][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+    }
+    if (i2) {
+      const int4 w = gload4(&C.link[(par * 4 + 2) * N + t]);
+      s_link[par][2][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+    }
+    if (i3) {
+      const int4 w = gload4(&C.link[(par * 4 + 3) * N + t]);
+      s_link[par][3][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+    }
   }
   // this tile's cache arrays
   int* const l1_base = C.l1 + (size_t)(active ? t : 0) * (size_t)C.s1 * (size_t)C.w1;
@@ -1554,10 +1589,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
-      const int4 f0 = sel4(i0, l0, e0 ? slot_decode(w0) : EMPTY);
-      const int4 f1 = sel4(i1, l1, e1 ? slot_decode(w1) : EMPTY);
-      const int4 f2 = sel4(i2, l2, e2 ? slot_decode(w2) : EMPTY);
-      const int4 f3 = sel4(i3, l3, e3 ? slot_decode(w3) : EMPTY);
+      const int4 f0 = sel4(i0, l0, e0 ? (AGE ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
+      const int4 f1 = sel4(i1, l1, e1 ? (AGE ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
+      const int4 f2 = sel4(i2, l2, e2 ? (AGE ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
+      const int4 f3 = sel4(i3, l3, e3 ? (AGE ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
       // every input row now holds this cycle's input (a patch-edge flit, or empty where there
       // is no link; an in-patch row is rewritten with what it held)
       s_link[cur][0][j] = f0;
@@ -1566,11 +1601,13 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       s_link[cur][3][j] = f3;
 
       if (dig) {  // state owned by t after cycle c-1
+        const int4 g0 = AGE ? row_clean(f0) : f0, g1 = AGE ? row_clean(f1) : f1;
+        const int4 g2 = AGE ? row_clean(f2) : f2, g3 = AGE ? row_clean(f3) : f3;
         h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
-        h = mix_pair(h, f0.x, f0.y); h = mix_pair(h, f0.z, f0.w);
-        h = mix_pair(h, f1.x, f1.y); h = mix_pair(h, f1.z, f1.w);
-        h = mix_pair(h, f2.x, f2.y); h = mix_pair(h, f2.z, f2.w);
-        h = mix_pair(h, f3.x, f3.y); h = mix_pair(h, f3.z, f3.w);
+        h = mix_pair(h, g0.x, g0.y); h = mix_pair(h, g0.z, g0.w);
+        h = mix_pair(h, g1.x, g1.y); h = mix_pair(h, g1.z, g1.w);
+        h = mix_pair(h, g2.x, g2.y); h = mix_pair(h, g2.z, g2.w);
+        h = mix_pair(h, g3.x, g3.y); h = mix_pair(h, g3.z, g3.w);
         h = mix_pair(h, d0.x, d0.y); h = mix_pair(h, d0.z, d0.w);
         h = mix_pair(h, d1.x, d1.y); h = mix_pair(h, d1.z, d1.w);
         h = mix_pair(h, d2.x, d2.y);
@@ -1583,6 +1620,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, 0, 0);    // no directory entry,
         h = mix_pair(h, -1, -1);  // no claim, forwarded block
         h = mix_pair(h, -1, -1);  // or its destination
+        if (aged)  // the inputs' deflection counts
+          h = mix_pair(h, (int)(row_age(f0) | (row_age(f1) << 16)), (int)(row_age(f2) | (row_age(f3) << 16)));
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1642,34 +1681,64 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         // sort keys: (inject cycle, source) with the input index in the low 3 bits (sources
         // take 20 bits), all ones for an empty input; the destination rides along
         typedef unsigned long long u64;
-#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)(uint32_t)(f).z << 3) | (i##ull)))
+        // (with deflection counts, the source and destination words carry the count in bits
+        // 20-27, masked off here; the count itself is a first key word, most deflected first)
+#define SRCW(f) (AGE ? ((uint32_t)(f).z & TILE_BITS_MASK) : (uint32_t)(f).z)
+#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)SRCW(f) << 3) | (i##ull)))
         u64 q0 = SKEY(f0, 0), q1 = SKEY(f1, 1), q2 = SKEY(f2, 2), q3 = SKEY(f3, 3), q4 = SKEY(fi, 4);
 #undef SKEY
-        int sd0 = f0.x, sd1 = f1.x, sd2 = f2.x, sd3 = f3.x, sd4 = fi.x;
+#undef SRCW
+#define DSTW(f) (AGE && (f).x >= 0 ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
+        int sd0 = DSTW(f0), sd1 = DSTW(f1), sd2 = DSTW(f2), sd3 = DSTW(f3), sd4 = fi.x;
+#undef DSTW
+#define AKEY(f) ((f).x < 0 ? ~0u : (uint32_t)AGE_MAX - row_age(f))
+        uint32_t ak0 = 0, ak1 = 0, ak2 = 0, ak3 = 0, ak4 = 0;
+        if (aged) { ak0 = AKEY(f0); ak1 = AKEY(f1); ak2 = AKEY(f2); ak3 = AKEY(f3); ak4 = AKEY(fi); }
+#undef AKEY
 #define CSWAP(a, b)                                                            \
   {                                                                            \
-    const bool sw = q##b < q##a;                                               \
+    const bool sw = AGE ? (ak##b < ak##a || (ak##b == ak##a && q##b < q##a)) : q##b < q##a; \
     const u64 qa = sw ? q##b : q##a, qb = sw ? q##a : q##b;                    \
     const int da = sw ? sd##b : sd##a, db = sw ? sd##a : sd##b;                \
     q##a = qa; q##b = qb; sd##a = da; sd##b = db;                              \
+    if (AGE) { const uint32_t xa = sw ? ak##b : ak##a, xb = sw ? ak##a : ak##b; ak##a = xa; ak##b = xb; } \
   }
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
 #undef CSWAP
         s_link[cur][4][j] = fi;
         const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
-        unsigned used = 0;
+        unsigned used = 0, dm = 0;
         uint32_t inv = 0x7FFFu;
-        arb_assign_sel(q0, sd0, t, x, y, C, valid, used, inv, acc);
-        arb_assign_sel(q1, sd1, t, x, y, C, valid, used, inv, acc);
-        arb_assign_sel(q2, sd2, t, x, y, C, valid, used, inv, acc);
-        arb_assign_sel(q3, sd3, t, x, y, C, valid, used, inv, acc);
-        arb_assign_sel(q4, sd4, t, x, y, C, valid, used, inv, acc);
+        arb_assign_sel<AGE>(q0, sd0, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<AGE>(q1, sd1, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<AGE>(q2, sd2, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<AGE>(q3, sd3, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<AGE>(q4, sd4, t, x, y, C, valid, used, inv, dm, acc);
 
         // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
         // then the next cycle's loads
 #define out_for(p) s_link[cur][min((inv >> (3 * (p))) & 7u, 5u)][j]
         // the five gathers first (one LDS round trip), then the stores
-        const int4 o0 = out_for(0), o1 = out_for(1), o2 = out_for(2), o3 = out_for(3), oe = out_for(4);
+        int4 o0 = out_for(0), o1 = out_for(1), o2 = out_for(2), o3 = out_for(3);
+        const int4 oe = out_for(4);
+        if (aged && dm) {  // a deflected flit leaves with one more deflection (Sec. 6.2.1)
+          auto bump = [&](int4& o, unsigned p) {
+            const unsigned i = (inv >> (3 * p)) & 7u;
+            if (i > 4u || !((dm >> i) & 1u)) return;
+            uint32_t a = row_age(o) + 1u;
+            if (a > (uint32_t)AGE_MAX) {
+              st_coh(C.err, 4);  // a flit deflected 65,536 times: reported as an invariant failure
+              a = (uint32_t)AGE_MAX;
+            }
+            const uint32_t keep = ~(0xFFu << AGE_SHIFT);
+            o.x = (int)(((uint32_t)o.x & keep) | ((a & 0xFFu) << AGE_SHIFT));
+            o.z = (int)(((uint32_t)o.z & keep) | ((a >> 8) << AGE_SHIFT));
+          };
+          bump(o0, 0);
+          bump(o1, 1);
+          bump(o2, 2);
+          bump(o3, 3);
+        }
         const uint32_t ns = (uint32_t)(c + 1);
         if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(o0, ns), MULTI);
         if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(o1, ns), MULTI);
@@ -1702,7 +1771,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
           if (kind == KIND_REQ) {
             acc.req_recv++;
-            k1.x = oe.z;
+            k1.x = AGE ? (int)((uint32_t)oe.z & TILE_BITS_MASK) : oe.z;
             k1.y = oe.w & LINE_MASK;
           } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
             rcv += PACKETS ? 1 : 0;
@@ -1864,7 +1933,12 @@ int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_d
 // which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
 int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
 // OPT bits of the one-tile-per-thread kernel a chip needs
-int fast_opt(const ChipDev& d) { return (d.reply_flits > 1 ? FAST_PACKETS : 0) | (d.inj_delay ? FAST_INJ_REG : 0); }
+int fast_opt(const ChipDev& d) {
+  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | (d.inj_delay ? FAST_INJ_REG : 0) |
+         ((d.variants & SIM_FLAG_AGE_DEFLECT) ? FAST_AGE : 0);
+}
+// variants the one-tile-per-thread kernel carries (the others, and D > 1, need the general one)
+constexpr int32_t FAST_VARIANTS = SIM_FLAG_INJECT_DELAY | SIM_FLAG_AGE_DEFLECT;
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
 
@@ -1938,11 +2012,15 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
-  switch (opt & 3) {
+  switch (opt & 7) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
     case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
     case 2: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 2>);
-    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
+    case 3: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
+    case 4: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 4>);
+    case 5: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 5>);
+    case 6: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 6>);
+    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 7>);
   }
 }
 const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 0) {
@@ -1967,7 +2045,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 16; ++k) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2102,8 +2180,9 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  // variants other than the injection register, and D > 1: general kernel
-  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~SIM_FLAG_INJECT_DELAY) == 0 && router_delay(cfg) == 1;
+  // variants other than the injection register and priority by deflection count, and D > 1:
+  // general kernel
+  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_VARIANTS) == 0 && router_delay(cfg) == 1;
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -2199,7 +2278,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~SIM_FLAG_INJECT_DELAY) == 0 && h->hd.rdelay == 1;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_VARIANTS) == 0 && h->hd.rdelay == 1;
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;

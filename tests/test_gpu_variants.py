@@ -1,7 +1,8 @@
 """Parity of the model variants (SimParams.flags) on the GPU with the serial oracle.
 
-The injection register runs on the one-tile-per-thread kernel as well as on the general one;
-the other variants run on the general kernel.  Bar: bit-exact, as for the base model: every
+Priority by deflection count and the injection register run on the one-tile-per-thread
+kernel as well as on the general one; hit under miss, the router delay and the directory run
+on the general kernel.  Bar: bit-exact, as for the base model: every
 per-cycle digest and the final canonical dump, including each in-flight flit's deflection
 count and each core's held op.
 """
@@ -34,7 +35,7 @@ def test_variants_small_shapes(w, h, flags):
     assert_same_run(p, 3000)
 
 
-@pytest.mark.parametrize("flags", [AGE, DELAY, AGE | HUM | DELAY], ids=["age", "delay", "all"])
+@pytest.mark.parametrize("flags", [AGE, DELAY, AGE | DELAY, AGE | HUM | DELAY], ids=["age", "delay", "age_delay", "all"])
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
 def test_variants_patch_mappings(launch, flags):
     """Deflection counts travel in the link slots across patch edges (stamped halves), and
@@ -49,12 +50,14 @@ def test_variants_config2_full_size_prefix(flags):
     assert_same_run(W.config2(0.1).with_(flags=flags), 100, step_sizes=[40, 60])
 
 
+@pytest.mark.parametrize("flags", [DELAY, AGE, AGE | DELAY], ids=["delay", "age", "age_delay"])
 @pytest.mark.parametrize("reply_flits", [1, 3])
-def test_injection_register_on_both_kernels(reply_flits):
-    """The injection register on the one-tile-per-thread kernel equals the general kernel and
-    the oracle, with single- and multi-flit replies, across launch boundaries."""
-    p = W.config0().with_(width=24, height=9, seed=55 + reply_flits, bg_thr=W.thr(0.2), op_thr=W.thr(0.6),
-                          flags=DELAY, reply_flits=reply_flits)
+def test_fast_kernel_variants_on_both_kernels(reply_flits, flags):
+    """Priority by deflection count and the injection register on the one-tile-per-thread
+    kernel equal the general kernel and the oracle, with single- and multi-flit replies,
+    across launch boundaries."""
+    p = W.config0().with_(width=24, height=9, seed=55 + reply_flits + flags, bg_thr=W.thr(0.2), op_thr=W.thr(0.6),
+                          flags=flags, reply_flits=reply_flits)
     a = gpu_sim(p)
     b = gpu_sim(p, generic=True)
     assert (a.step(777, digests=True) == b.step(777, digests=True)).all()
@@ -62,12 +65,13 @@ def test_injection_register_on_both_kernels(reply_flits):
     assert_same_run(p, 1200, step_sizes=[500, 700])
 
 
-def test_injection_register_batch_on_the_fast_kernel():
+def test_fast_kernel_variants_batch():
     """One launch of the one-tile-per-thread kernel over base chips and chips with the
-    injection register (some with multi-flit replies): each equals its own oracle run."""
+    injection register or priority by deflection count (some with multi-flit replies): each
+    equals its own oracle run."""
     from paper_1508_03235_amd import nocsim
     params = [W.config1().with_(width=s, height=s, seed=5000 + i, bg_thr=W.thr(0.15), flags=f, reply_flits=r)
-              for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, DELAY, 4), (12, 0, 2), (16, DELAY, 2)])]
+              for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, AGE, 4), (12, 0, 2), (16, AGE | DELAY, 2)])]
     sims = [gpu_sim(p, launch=(p.width, 256 // p.width, 256, 0)) for p in params]
     b = nocsim.Batch(sims)
     b.step([300, 250, 300, 123, 200])
@@ -78,7 +82,8 @@ def test_injection_register_batch_on_the_fast_kernel():
 
 
 def test_variants_refuse_the_base_kernel():
-    """Asking for the one-tile-per-thread kernel keeps a variant chip on the general kernel."""
+    """Asking for the one-tile-per-thread kernel keeps a chip with hit under miss on the
+    general kernel."""
     p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM)
     a = gpu_sim(p)
     a.set_kernel(False)
