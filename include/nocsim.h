@@ -75,9 +75,8 @@ typedef struct {
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
-   more literal reading of the paper.  Chips with hit under miss, the directory or a router
-   delay above 1 run on the general kernel; priority by deflection count and the injection
-   register also run on the one-tile-per-thread kernel.
+   more literal reading of the paper.  Chips with the directory or a router delay above 1 run
+   on the general kernel; the other variants also run on the one-tile-per-thread kernel.
    AGE_DEFLECT: a flit's priority is the number of times it has been deflected (more first,
      0 at injection; Sec. 4.2, Sec. 6.2.1, Sec. 7.1 phase two), ties by (injection cycle,
      source).  The base model ranks by (injection cycle, source) alone.  A flit deflected

@@ -1308,6 +1308,7 @@ __device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, 
 }
 
 constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;
+constexpr uint32_t PF_RETRY = 32, PF_HUM = 64;  // hit under miss: the held op again; an op drawn under a miss
 
 struct Prefetch {            // loads of one cycle issued ahead of it
   uint4 r;                   // the tile's random words of the cycle
@@ -1334,9 +1335,10 @@ __device__ __forceinline__ void draw_ahead(const ChipDev& C, int t, int c, Prefe
 
 // Issues every load of cycle c that does not depend on its link inputs.  The random words of c
 // and their Zipf words were drawn one cycle earlier (draw_ahead); this draws those of c+1.
-template <bool MULTI>
+// VARS: `hline` is the op held by hit under miss (-1 for none), `hum` whether the chip has it.
+template <bool MULTI, bool VARS>
 __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
-                                         int* l1_base, int* l2_base, Prefetch& P) {
+                                         int hline, bool hum, int* l1_base, int* l2_base, Prefetch& P) {
   const int N = C.N;
   P.r = P.r1;
   const bool svc = k1.x >= 0;
@@ -1344,10 +1346,14 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const bool fill = k0.x == CORE_FILL && wake;
   const bool missed = k0.x == CORE_L1MISS && wake;
   const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
-  const bool forced = k0.x == CORE_IDLE && k2.w >= 0;
-  const bool drawn = k0.x == CORE_IDLE && !forced && P.r.x < C.op_thr;
+  const bool retry = VARS && k0.x == CORE_IDLE && hline >= 0;
+  const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
+  const bool drawn = k0.x == CORE_IDLE && !retry && !forced && P.r.x < C.op_thr;
+  // hit under miss (Sec. 3.5): a core with a miss outstanding still draws, unless the L1 is busy
+  // with the fill or an op is already held
+  const bool drawn_hum = VARS && hum && k0.x != CORE_IDLE && !fill && hline < 0 && P.r.x < C.op_thr;
   P.flags = (svc ? PF_SVC : 0u) | (local ? PF_LOCAL : 0u) | (fill ? PF_FILL : 0u) | (forced ? PF_FORCED : 0u) |
-            (drawn ? PF_DRAWN : 0u);
+            (drawn ? PF_DRAWN : 0u) | (retry ? PF_RETRY : 0u) | (drawn_hum ? PF_HUM : 0u);
   P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
   P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
   if (svc) set_load(P.setR, C.w2, P.vR);
@@ -1361,25 +1367,26 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const bool priv = C.private_lines > 0 && P.r.y >= C.shared_thr;
   const int rank = (int)(P.z_lo + (uint32_t)(((unsigned long long)(P.r.z & 0xFFFFu) * (P.z_hi - P.z_lo)) >> 16));
   const int drawn_line = (priv ? C.shared_lines + t * C.private_lines : 0) + rank;
-  P.line_op = forced ? k2.w : (drawn ? drawn_line : k0.z);
+  P.line_op = retry ? hline : forced ? k2.w : ((drawn || drawn_hum) ? drawn_line : k0.z);
   P.set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
-  if (fill || forced || drawn) set_load(P.set1, C.w1, P.u);
+  if (fill || retry || forced || drawn || drawn_hum) set_load(P.set1, C.w1, P.u);
   draw_ahead(C, t, c + 1, P);
 }
 
 // OPT bit 0 (FAST_PACKETS): replies may have several flits (the chip's reply_flits); without it
 // the kernel is the single-flit model, compiled without the per-flit counts.  OPT bit 1
-// (FAST_INJ_REG): the chip may have the injection register (a flit made in a cycle enters the
-// network from the next one on, Sec. 6.2.1); without it that variant is compiled out.  OPT bit 2
-// (FAST_AGE): the chip may rank flits by deflection count (Sec. 4.2, Sec. 6.2.1); the flit rows
-// then keep the count in bits 20-27 of their dst and src words, as the link slots do.
-constexpr int FAST_PACKETS = 1, FAST_INJ_REG = 2, FAST_AGE = 4;
+// (FAST_VARIANTS): the chip may have any of three variants, each read from the chip at run
+// time: priority by deflection count (Sec. 4.2, Sec. 6.2.1; the flit rows then keep the count
+// in bits 20-27 of their dst and src words, as the link slots do), hit under miss (Sec. 3.5;
+// the held op rides in two more registers) and the injection register (a flit made in a
+// cycle enters the network from the next one on, Sec. 6.2.1).  Without the bit they are
+// compiled out.
+constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   constexpr bool PACKETS = (OPT & FAST_PACKETS) != 0;
-  constexpr bool INJ_REG = (OPT & FAST_INJ_REG) != 0;
-  constexpr bool AGE = (OPT & FAST_AGE) != 0;
+  constexpr bool VARS = (OPT & FAST_VARIANTS) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1389,8 +1396,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const LaunchEntry e = table[blockIdx.x];
   const ChipDev C = *e.chip;
   const int N = C.N;
-  const int D = INJ_REG ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
-  const bool aged = AGE && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
+  const int D = VARS ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
+  const bool aged = VARS && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
+  const bool hum = VARS && (C.variants & SIM_FLAG_HIT_UNDER_MISS) != 0;  // ops drawn under a miss
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1425,6 +1433,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 
   int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
   int fdst = -1, rcv = 0;  // forced background destination; flits of the awaited reply received
+  int hline = -1, hissue = 0;  // hit under miss: the held op's line and issue cycle (none: -1, 0)
   uint32_t geo = geo0;
   const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
   if (active) {
@@ -1434,22 +1443,26 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     const int4 k3 = gload4(&C.core[3 * N + t]);
     fdst = k3.x;
     rcv = k3.y;
+    if (VARS) {
+      hline = k3.z;
+      hissue = k3.w;
+    }
     const int par = c0 & 1;
     if (i0) {
       const int4 w = gload4(&C.link[(par * 4 + 0) * N + t]);
-      s_link[par][0][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+      s_link[par][0][j] = VARS ? slot_decode_aged(w) : slot_decode(w);
     }
     if (i1) {
       const int4 w = gload4(&C.link[(par * 4 + 1) * N + t]);
-      s_link[par][1][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+      s_link[par][1][j] = VARS ? slot_decode_aged(w) : slot_decode(w);
     }
     if (i2) {
       const int4 w = gload4(&C.link[(par * 4 + 2) * N + t]);
-      s_link[par][2][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+      s_link[par][2][j] = VARS ? slot_decode_aged(w) : slot_decode(w);
     }
     if (i3) {
       const int4 w = gload4(&C.link[(par * 4 + 3) * N + t]);
-      s_link[par][3][j] = AGE ? slot_decode_aged(w) : slot_decode(w);
+      s_link[par][3][j] = VARS ? slot_decode_aged(w) : slot_decode(w);
     }
   }
   // this tile's cache arrays
@@ -1458,7 +1471,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   Prefetch P;
   if (active) {
     draw_ahead(C, t, c0, P);
-    prefetch<MULTI>(C, t, c0, k0, k1, k2, l1_base, l2_base, P);
+    prefetch<MULTI, VARS>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P);
   }
   __syncthreads();
 
@@ -1494,8 +1507,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       asm volatile("" : "+v"(pf));
       const bool p_svc = (pf & PF_SVC) != 0, p_local = (pf & PF_LOCAL) != 0, p_fill = (pf & PF_FILL) != 0;
       const bool p_forced = (pf & PF_FORCED) != 0, p_drawn = (pf & PF_DRAWN) != 0;
+      const bool p_retry = VARS && (pf & PF_RETRY) != 0, p_hum = VARS && (pf & PF_HUM) != 0;
       // the core words as they stand after cycle c-1 (the digest hashes them after the links)
       const int4 d0 = k0, d1 = k1, d2 = k2;
+      const int dhl = hline, dhi = hissue;
       const int dfd = fdst, drcv = rcv;
       if (step) {
         if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
@@ -1554,18 +1569,38 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             k0.x = CORE_SEND;
             acc.req_made++;
           }
-        } else if (p_forced || p_drawn) {
+        } else if (p_retry || p_forced || p_drawn) {
+          const int issued = p_retry ? hissue : c;  // a held op counts from its first issue
+          if (p_retry) {
+            hline = -1;
+            hissue = 0;
+          } else {
+            acc.ops_issued++;
+          }
           if (p_forced) k2.w = -1;
-          acc.ops_issued++;
           k0.z = P.line_op;
-          k0.w = c;
+          k0.w = issued;
           if (set_touch(P.u, C.w1, P.line_op, false, dirty1)) {
             acc.l1_hit++;
             acc.ops_done++;
+            if (p_retry) {
+              acc.op_lat += (unsigned long long)(c - issued);
+              acc.op_lat_max = max(acc.op_lat_max, c - issued);
+            }
           } else {
             acc.l1_miss++;
             k0.x = CORE_L1MISS;
             k0.y = c + C.l1_lat;
+          }
+        }
+        if (p_hum) {  // a hit completes under the miss; a miss is held until the fill (Sec. 3.5)
+          acc.ops_issued++;
+          if (set_touch(P.u, C.w1, P.line_op, false, dirty1)) {
+            acc.l1_hit++;
+            acc.ops_done++;
+          } else {
+            hline = P.line_op;
+            hissue = c;
           }
         }
 
@@ -1589,10 +1624,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
-      const int4 f0 = sel4(i0, l0, e0 ? (AGE ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
-      const int4 f1 = sel4(i1, l1, e1 ? (AGE ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
-      const int4 f2 = sel4(i2, l2, e2 ? (AGE ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
-      const int4 f3 = sel4(i3, l3, e3 ? (AGE ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
+      const int4 f0 = sel4(i0, l0, e0 ? (VARS ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
+      const int4 f1 = sel4(i1, l1, e1 ? (VARS ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
+      const int4 f2 = sel4(i2, l2, e2 ? (VARS ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
+      const int4 f3 = sel4(i3, l3, e3 ? (VARS ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
       // every input row now holds this cycle's input (a patch-edge flit, or empty where there
       // is no link; an in-patch row is rewritten with what it held)
       s_link[cur][0][j] = f0;
@@ -1601,8 +1636,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       s_link[cur][3][j] = f3;
 
       if (dig) {  // state owned by t after cycle c-1
-        const int4 g0 = AGE ? row_clean(f0) : f0, g1 = AGE ? row_clean(f1) : f1;
-        const int4 g2 = AGE ? row_clean(f2) : f2, g3 = AGE ? row_clean(f3) : f3;
+        const int4 g0 = VARS ? row_clean(f0) : f0, g1 = VARS ? row_clean(f1) : f1;
+        const int4 g2 = VARS ? row_clean(f2) : f2, g3 = VARS ? row_clean(f3) : f3;
         h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
         h = mix_pair(h, g0.x, g0.y); h = mix_pair(h, g0.z, g0.w);
         h = mix_pair(h, g1.x, g1.y); h = mix_pair(h, g1.z, g1.w);
@@ -1615,7 +1650,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, 0, 0);
         h = mix_pair(h, d2.w, dfd);
         h = mix_pair(h, drcv, 0);
-        h = mix_pair(h, -1, 0);  // no op is held in the base model
+        h = mix_pair(h, dhl, dhi);  // the op held by hit under miss (-1, 0: none)
         h = mix_pair(h, -1, -1);  // nor a remote-access target or eviction notice,
         h = mix_pair(h, 0, 0);    // no directory entry,
         h = mix_pair(h, -1, -1);  // no claim, forwarded block
@@ -1629,8 +1664,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
         int cls = -1;
         if (k2.x >= 0 && nm.y <= c) cls = 0;
-        else if (k1.z >= 0 && (!INJ_REG || nh.y <= c)) cls = 1;
-        else if (k0.x == CORE_SEND && (!INJ_REG || k0.y + D <= c)) cls = 2;
+        else if (k1.z >= 0 && (!VARS || nh.y <= c)) cls = 1;
+        else if (k0.x == CORE_SEND && (!VARS || k0.y + D <= c)) cls = 2;
         else if (fdst >= 0) cls = 3;
         else if (k2.z > 0) cls = 4;
         if (cls >= 0 && arrivals >= deg) {
@@ -1683,12 +1718,12 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         typedef unsigned long long u64;
         // (with deflection counts, the source and destination words carry the count in bits
         // 20-27, masked off here; the count itself is a first key word, most deflected first)
-#define SRCW(f) (AGE ? ((uint32_t)(f).z & TILE_BITS_MASK) : (uint32_t)(f).z)
+#define SRCW(f) (VARS ? ((uint32_t)(f).z & TILE_BITS_MASK) : (uint32_t)(f).z)
 #define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)SRCW(f) << 3) | (i##ull)))
         u64 q0 = SKEY(f0, 0), q1 = SKEY(f1, 1), q2 = SKEY(f2, 2), q3 = SKEY(f3, 3), q4 = SKEY(fi, 4);
 #undef SKEY
 #undef SRCW
-#define DSTW(f) (AGE && (f).x >= 0 ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
+#define DSTW(f) (VARS && (f).x >= 0 ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
         int sd0 = DSTW(f0), sd1 = DSTW(f1), sd2 = DSTW(f2), sd3 = DSTW(f3), sd4 = fi.x;
 #undef DSTW
 #define AKEY(f) ((f).x < 0 ? ~0u : (uint32_t)AGE_MAX - row_age(f))
@@ -1697,11 +1732,11 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 #undef AKEY
 #define CSWAP(a, b)                                                            \
   {                                                                            \
-    const bool sw = AGE ? (ak##b < ak##a || (ak##b == ak##a && q##b < q##a)) : q##b < q##a; \
+    const bool sw = VARS ? (ak##b < ak##a || (ak##b == ak##a && q##b < q##a)) : q##b < q##a; \
     const u64 qa = sw ? q##b : q##a, qb = sw ? q##a : q##b;                    \
     const int da = sw ? sd##b : sd##a, db = sw ? sd##a : sd##b;                \
     q##a = qa; q##b = qb; sd##a = da; sd##b = db;                              \
-    if (AGE) { const uint32_t xa = sw ? ak##b : ak##a, xb = sw ? ak##a : ak##b; ak##a = xa; ak##b = xb; } \
+    if (VARS) { const uint32_t xa = sw ? ak##b : ak##a, xb = sw ? ak##a : ak##b; ak##a = xa; ak##b = xb; } \
   }
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
 #undef CSWAP
@@ -1709,11 +1744,11 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
         unsigned used = 0, dm = 0;
         uint32_t inv = 0x7FFFu;
-        arb_assign_sel<AGE>(q0, sd0, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<AGE>(q1, sd1, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<AGE>(q2, sd2, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<AGE>(q3, sd3, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<AGE>(q4, sd4, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<VARS>(q0, sd0, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<VARS>(q1, sd1, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<VARS>(q2, sd2, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<VARS>(q3, sd3, t, x, y, C, valid, used, inv, dm, acc);
+        arb_assign_sel<VARS>(q4, sd4, t, x, y, C, valid, used, inv, dm, acc);
 
         // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
         // then the next cycle's loads
@@ -1771,7 +1806,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
           if (kind == KIND_REQ) {
             acc.req_recv++;
-            k1.x = AGE ? (int)((uint32_t)oe.z & TILE_BITS_MASK) : oe.z;
+            k1.x = VARS ? (int)((uint32_t)oe.z & TILE_BITS_MASK) : oe.z;
             k1.y = oe.w & LINE_MASK;
           } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
             rcv += PACKETS ? 1 : 0;
@@ -1787,7 +1822,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k2.z += 1;
           acc.bg_gen++;
         }
-        if (c + 1 < c_end) prefetch<MULTI>(C, t, c + 1, k0, k1, k2, l1_base, l2_base, P);
+        if (c + 1 < c_end) prefetch<MULTI, VARS>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P);
 #undef out_for
       }
     }
@@ -1809,7 +1844,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     gstore4(&C.core[t], k0);
     gstore4(&C.core[N + t], k1);
     gstore4(&C.core[2 * N + t], k2);
-    gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, -1, 0));
+    gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, hline, hissue));
     const int par = c_done & 1;
     if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
     if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
@@ -1933,12 +1968,11 @@ int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_d
 // which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
 int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
 // OPT bits of the one-tile-per-thread kernel a chip needs
+// variants the one-tile-per-thread kernel carries (the directory, and D > 1, need the general one)
+constexpr int32_t FAST_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
 int fast_opt(const ChipDev& d) {
-  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | (d.inj_delay ? FAST_INJ_REG : 0) |
-         ((d.variants & SIM_FLAG_AGE_DEFLECT) ? FAST_AGE : 0);
+  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0);
 }
-// variants the one-tile-per-thread kernel carries (the others, and D > 1, need the general one)
-constexpr int32_t FAST_VARIANTS = SIM_FLAG_INJECT_DELAY | SIM_FLAG_AGE_DEFLECT;
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
 
@@ -2012,15 +2046,11 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
-  switch (opt & 7) {
+  switch (opt & 3) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
     case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
     case 2: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 2>);
-    case 3: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
-    case 4: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 4>);
-    case 5: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 5>);
-    case 6: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 6>);
-    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 7>);
+    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
   }
 }
 const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 0) {
@@ -2045,7 +2075,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 16; ++k) {
+  for (int k = 0; k < 8; ++k) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2118,7 +2148,7 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
 // opt: FAST_PACKETS when some chip of the table has multi-flit replies (the kernel then reads
-// each chip's count), FAST_INJ_REG when some chip has the injection register
+// each chip's count), FAST_VARIANTS when some chip has a variant the kernel carries
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
                    unsigned long long* digests, int digest_base, hipStream_t s, int opt, int var) {
   if (n <= 0) return SIM_OK;
@@ -2180,9 +2210,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  // variants other than the injection register and priority by deflection count, and D > 1:
-  // general kernel
-  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_VARIANTS) == 0 && router_delay(cfg) == 1;
+  // the directory, and D > 1: general kernel
+  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0 && router_delay(cfg) == 1;
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -2278,7 +2307,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_VARIANTS) == 0 && h->hd.rdelay == 1;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0 && h->hd.rdelay == 1;
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;

@@ -1,8 +1,8 @@
 """Parity of the model variants (SimParams.flags) on the GPU with the serial oracle.
 
-Priority by deflection count and the injection register run on the one-tile-per-thread
-kernel as well as on the general one; hit under miss, the router delay and the directory run
-on the general kernel.  Bar: bit-exact, as for the base model: every
+Priority by deflection count, hit under miss and the injection register run on the
+one-tile-per-thread kernel as well as on the general one; the router delay and the directory
+run on the general kernel.  Bar: bit-exact, as for the base model: every
 per-cycle digest and the final canonical dump, including each in-flight flit's deflection
 count and each core's held op.
 """
@@ -50,12 +50,12 @@ def test_variants_config2_full_size_prefix(flags):
     assert_same_run(W.config2(0.1).with_(flags=flags), 100, step_sizes=[40, 60])
 
 
-@pytest.mark.parametrize("flags", [DELAY, AGE, AGE | DELAY], ids=["delay", "age", "age_delay"])
+@pytest.mark.parametrize("flags", [DELAY, AGE, HUM, AGE | DELAY, AGE | HUM | DELAY],
+                         ids=["delay", "age", "hum", "age_delay", "all"])
 @pytest.mark.parametrize("reply_flits", [1, 3])
 def test_fast_kernel_variants_on_both_kernels(reply_flits, flags):
-    """Priority by deflection count and the injection register on the one-tile-per-thread
-    kernel equal the general kernel and the oracle, with single- and multi-flit replies,
-    across launch boundaries."""
+    """The variants on the one-tile-per-thread kernel equal the general kernel and the oracle,
+    with single- and multi-flit replies, across launch boundaries."""
     p = W.config0().with_(width=24, height=9, seed=55 + reply_flits + flags, bg_thr=W.thr(0.2), op_thr=W.thr(0.6),
                           flags=flags, reply_flits=reply_flits)
     a = gpu_sim(p)
@@ -66,25 +66,25 @@ def test_fast_kernel_variants_on_both_kernels(reply_flits, flags):
 
 
 def test_fast_kernel_variants_batch():
-    """One launch of the one-tile-per-thread kernel over base chips and chips with the
-    injection register or priority by deflection count (some with multi-flit replies): each
-    equals its own oracle run."""
+    """One launch of the one-tile-per-thread kernel over base chips and chips with variants
+    (some with multi-flit replies): each equals its own oracle run."""
     from paper_1508_03235_amd import nocsim
     params = [W.config1().with_(width=s, height=s, seed=5000 + i, bg_thr=W.thr(0.15), flags=f, reply_flits=r)
-              for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, AGE, 4), (12, 0, 2), (16, AGE | DELAY, 2)])]
+              for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, AGE, 4), (12, 0, 2), (16, AGE | DELAY, 2),
+                                             (12, HUM, 1), (8, AGE | HUM | DELAY, 3)])]
     sims = [gpu_sim(p, launch=(p.width, 256 // p.width, 256, 0)) for p in params]
     b = nocsim.Batch(sims)
-    b.step([300, 250, 300, 123, 200])
-    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200]):
+    b.step([300, 250, 300, 123, 200, 280, 333])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200, 280, 333]):
         o = O.OracleSim(p)
         o.step(n)
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags} reply_flits {p.reply_flits}"
 
 
 def test_variants_refuse_the_base_kernel():
-    """Asking for the one-tile-per-thread kernel keeps a chip with hit under miss on the
+    """Asking for the one-tile-per-thread kernel keeps a chip with a router delay on the
     general kernel."""
-    p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM)
+    p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM, router_delay=2)
     a = gpu_sim(p)
     a.set_kernel(False)
     b = gpu_sim(p, generic=True)
