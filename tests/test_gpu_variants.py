@@ -228,3 +228,24 @@ def test_serving_mixed_model_options_equal_solo_runs():
         o = O.OracleSim(j.params)
         o.step(j.cycles)
         assert (r.stats == o.stats()).all(), f"job {j.index} {j.params.flags}"
+
+
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "general"])
+def test_deflection_count_limit_on_gpu(generic):
+    """A flit one below the 16-bit deflection limit leaves with the limit, as in the oracle; at
+    the limit one more deflection stops the run with an invariant failure on both kernels."""
+    from paper_1508_03235_amd import nocsim
+    from tests.test_oracle_variants import contended_pair_at_centre
+    p, snap = contended_pair_at_centre(0xFFFE)
+    g = gpu_sim(p, generic=generic)
+    g.load(snap)
+    g.step(1)
+    o = O.OracleSim(p)
+    o.load(snap)
+    o.step(1)
+    assert (g.dump() == o.dump()).all()
+    p, snap = contended_pair_at_centre(0xFFFF)
+    g = gpu_sim(p, generic=generic)
+    g.load(snap)
+    with pytest.raises(nocsim.SimError, match="EINVARIANT"):
+        g.step(1)

@@ -543,3 +543,38 @@ def test_router_delay_one_is_the_default():
             O.OracleSim(p.with_(router_delay=0)).step(600, digests=True)).all()
     with pytest.raises(ValueError):
         O.OracleSim(p.with_(router_delay=9))
+
+
+def contended_pair_at_centre(age):
+    """3x1 chip with priority by deflection count, at cycle 1: two background flits for the
+    centre tile wait at its west and east inputs, both with the given deflection count.  In
+    cycle 1 the one from tile 0 (same count and cycle, lower source) ejects and the one from
+    tile 2 is deflected (Sec. 4.3, Sec. 6.2.1)."""
+    p = W.config0().with_(width=3, height=1, seed=1, bg_thr=0, op_thr=0, flags=AGE)
+    o = O.OracleSim(p)
+    o.force_bg(0, 1)
+    o.force_bg(2, 1)
+    o.step(1)
+    snap = o.dump()
+    d = split_dump(snap, p)
+    assert d["links"][1, 3, 0] == 1 and d["links"][1, 3, 2] == 0   # from tile 0, at the west input
+    assert d["links"][1, 2, 0] == 1 and d["links"][1, 2, 2] == 2   # from tile 2, at the east input
+    d["ages"][1, 2] = d["ages"][1, 3] = age                         # (views into the dump)
+    return p, snap
+
+
+def test_deflection_count_increments_and_overflow_is_reported():
+    """One below the 16-bit limit the deflected flit leaves with the limit; at the limit one
+    more deflection is reported as an invariant failure rather than wrapped."""
+    p, snap = contended_pair_at_centre(0xFFFE)
+    o = O.OracleSim(p)
+    o.load(snap)
+    o.step(1)
+    d = split_dump(o.dump(), p)
+    assert d["links"][2, 3, 2] == 2 and d["ages"][2, 3] == 0xFFFF    # back to tile 2, one more deflection
+    assert o.stat("deflections") == 1 and o.stat("ej_bg") == 1
+    p, snap = contended_pair_at_centre(0xFFFF)
+    o = O.OracleSim(p)
+    o.load(snap)
+    with pytest.raises(AssertionError, match="deflection count overflow"):
+        o.step(1)
