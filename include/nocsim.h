@@ -64,7 +64,7 @@ typedef struct {
                                  background flits are one flit */
   int32_t router_delay;       /* cycles per hop, 1..8 (0 counts as 1): a flit that arrives at a
                                  router waits router_delay - 1 cycles in the router's pipeline
-                                 before it is arbitrated; > 1 runs on the general kernel */
+                                 before it is arbitrated */
   int32_t mig_threshold;      /* with LSPD: block migration (Sec. 3.3).  Each L2 way records its
                                  last accessor and how many accesses in a row came from it; when a
                                  remote tile's run reaches this count the owner sends it the block
@@ -75,8 +75,8 @@ typedef struct {
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
-   more literal reading of the paper.  Chips with the directory or a router delay above 1 run
-   on the general kernel; the other variants also run on the one-tile-per-thread kernel.
+   more literal reading of the paper.  Chips with the directory run on the general kernel; the
+   other variants, and a router delay above 1, also run on the one-tile-per-thread kernel.
    AGE_DEFLECT: a flit's priority is the number of times it has been deflected (more first,
      0 at injection; Sec. 4.2, Sec. 6.2.1, Sec. 7.1 phase two), ties by (injection cycle,
      source).  The base model ranks by (injection cycle, source) alone.  A flit deflected

@@ -1380,13 +1380,15 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // in bits 20-27 of their dst and src words, as the link slots do), hit under miss (Sec. 3.5;
 // the held op rides in two more registers) and the injection register (a flit made in a
 // cycle enters the network from the next one on, Sec. 6.2.1).  Without the bit they are
-// compiled out.
-constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2;
+// compiled out.  OPT bit 2 (FAST_PIPE): the chip may have a router delay D > 1 (arrivals wait
+// D-1 cycles in a per-tile pipeline in HBM before they are arbitrated).
+constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   constexpr bool PACKETS = (OPT & FAST_PACKETS) != 0;
   constexpr bool VARS = (OPT & FAST_VARIANTS) != 0;
+  constexpr bool PIPE = (OPT & FAST_PIPE) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1399,6 +1401,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const int D = VARS ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
   const bool aged = VARS && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
   const bool hum = VARS && (C.variants & SIM_FLAG_HIT_UNDER_MISS) != 0;  // ops drawn under a miss
+  const int rd = PIPE ? C.rdelay : 1;  // router delay D: arrivals wait D-1 cycles in a pipeline
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1430,6 +1433,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
   const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
   int c_done = c0;
+  // pipeline entry of the current cycle (cycle mod (D-1)): the flits it holds leave this cycle,
+  // and this cycle's arrivals take their place
+  int pe = (PIPE && rd > 1) ? (int)((uint32_t)c0 % (uint32_t)(rd - 1)) : 0;
 
   int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
   int fdst = -1, rcv = 0;  // forced background destination; flits of the awaited reply received
@@ -1493,6 +1499,15 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       // an edge on port p reads one shared slot instead): a fixed number of loads lets the
       // compiler wait for the prefetched words in phase one without waiting for these.
       int4 w0 = EMPTY, w1 = EMPTY, w2 = EMPTY, w3 = EMPTY;
+      // with D > 1, the pipeline entry leaving this cycle (raw slot words), read ahead as well
+      int4 pp0 = EMPTY, pp1 = EMPTY, pp2 = EMPTY, pp3 = EMPTY;
+      if (PIPE && rd > 1 && step) {
+        const int4* pq = &C.pipe[(size_t)pe * 4 * N + t];
+        if (v0) pp0 = gload4(pq);
+        if (v1) pp1 = gload4(pq + N);
+        if (v2) pp2 = gload4(pq + 2 * N);
+        if (v3) pp3 = gload4(pq + 3 * N);
+      }
       if (MULTI) {
         const int4* shared_slot = C.link;
         w0 = ld_slot(e0 ? &C.link[(cur * 4 + 0) * N + t] : shared_slot, true);
@@ -1624,20 +1639,29 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
-      const int4 f0 = sel4(i0, l0, e0 ? (VARS ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
-      const int4 f1 = sel4(i1, l1, e1 ? (VARS ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
-      const int4 f2 = sel4(i2, l2, e2 ? (VARS ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
-      const int4 f3 = sel4(i3, l3, e3 ? (VARS ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
+      // this cycle's arrivals
+      const int4 a0 = sel4(i0, l0, e0 ? (VARS ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
+      const int4 a1 = sel4(i1, l1, e1 ? (VARS ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
+      const int4 a2 = sel4(i2, l2, e2 ? (VARS ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
+      const int4 a3 = sel4(i3, l3, e3 ? (VARS ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
+      // this cycle's arbitration inputs: the arrivals, or with D > 1 the flits that arrived D-1
+      // cycles ago, leaving the pipeline now
+      const bool piped = PIPE && rd > 1 && step;
+      const int4 f0 = piped ? (v0 ? slot_decode_aged(pp0) : EMPTY) : a0;
+      const int4 f1 = piped ? (v1 ? slot_decode_aged(pp1) : EMPTY) : a1;
+      const int4 f2 = piped ? (v2 ? slot_decode_aged(pp2) : EMPTY) : a2;
+      const int4 f3 = piped ? (v3 ? slot_decode_aged(pp3) : EMPTY) : a3;
       // every input row now holds this cycle's input (a patch-edge flit, or empty where there
-      // is no link; an in-patch row is rewritten with what it held)
+      // is no link; an in-patch row is rewritten with what it held, or with D > 1 with the
+      // pipeline's output)
       s_link[cur][0][j] = f0;
       s_link[cur][1][j] = f1;
       s_link[cur][2][j] = f2;
       s_link[cur][3][j] = f3;
 
-      if (dig) {  // state owned by t after cycle c-1
-        const int4 g0 = VARS ? row_clean(f0) : f0, g1 = VARS ? row_clean(f1) : f1;
-        const int4 g2 = VARS ? row_clean(f2) : f2, g3 = VARS ? row_clean(f3) : f3;
+      if (dig) {  // state owned by t after cycle c-1: its arrivals, core words and pipeline
+        const int4 g0 = VARS ? row_clean(a0) : a0, g1 = VARS ? row_clean(a1) : a1;
+        const int4 g2 = VARS ? row_clean(a2) : a2, g3 = VARS ? row_clean(a3) : a3;
         h = mix64(((unsigned long long)(uint32_t)(c - 1) << 32) | (uint32_t)t);
         h = mix_pair(h, g0.x, g0.y); h = mix_pair(h, g0.z, g0.w);
         h = mix_pair(h, g1.x, g1.y); h = mix_pair(h, g1.z, g1.w);
@@ -1655,8 +1679,28 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, 0, 0);    // no directory entry,
         h = mix_pair(h, -1, -1);  // no claim, forwarded block
         h = mix_pair(h, -1, -1);  // or its destination
-        if (aged)  // the inputs' deflection counts
-          h = mix_pair(h, (int)(row_age(f0) | (row_age(f1) << 16)), (int)(row_age(f2) | (row_age(f3) << 16)));
+        if (aged)  // the arrivals' deflection counts
+          h = mix_pair(h, (int)(row_age(a0) | (row_age(a1) << 16)), (int)(row_age(a2) | (row_age(a3) << 16)));
+        if (PIPE && rd > 1) {  // stage st: the flits that leave the pipeline in cycle c-1+st
+          int pst = pe;
+          for (int st = 1; st < rd; ++st) {
+            const int4* pq = &C.pipe[(size_t)pst * 4 * N + t];
+            const int4 x0 = v0 ? gload4(pq) : EMPTY, x1 = v1 ? gload4(pq + N) : EMPTY;
+            const int4 x2 = v2 ? gload4(pq + 2 * N) : EMPTY, x3 = v3 ? gload4(pq + 3 * N) : EMPTY;
+            const int4 y0 = v0 ? slot_decode(x0) : EMPTY, y1 = v1 ? slot_decode(x1) : EMPTY;
+            const int4 y2 = v2 ? slot_decode(x2) : EMPTY, y3 = v3 ? slot_decode(x3) : EMPTY;
+            h = mix_pair(h, y0.x, y0.y); h = mix_pair(h, y0.z, y0.w);
+            h = mix_pair(h, y1.x, y1.y); h = mix_pair(h, y1.z, y1.w);
+            h = mix_pair(h, y2.x, y2.y); h = mix_pair(h, y2.z, y2.w);
+            h = mix_pair(h, y3.x, y3.y); h = mix_pair(h, y3.z, y3.w);
+            if (aged) {
+              const uint32_t b0 = v0 ? slot_age(x0) : 0u, b1 = v1 ? slot_age(x1) : 0u;
+              const uint32_t b2 = v2 ? slot_age(x2) : 0u, b3 = v3 ? slot_age(x3) : 0u;
+              h = mix_pair(h, (int)(b0 | (b1 << 16)), (int)(b2 | (b3 << 16)));
+            }
+            pst = pst + 1 == rd - 1 ? 0 : pst + 1;
+          }
+        }
       }
       if (step && ok) {
         // ---- phase two: injection, then oldest-first arbitration ----------------------------
@@ -1750,6 +1794,13 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         arb_assign_sel<VARS>(q3, sd3, t, x, y, C, valid, used, inv, dm, acc);
         arb_assign_sel<VARS>(q4, sd4, t, x, y, C, valid, used, inv, dm, acc);
 
+        if (PIPE && rd > 1) {  // this cycle's arrivals enter the pipeline (stamped, as on the links)
+          int4* pq = &C.pipe[(size_t)pe * 4 * N + t];
+          if (v0) gstore4(pq, slot_encode(a0, (uint32_t)c));
+          if (v1) gstore4(pq + N, slot_encode(a1, (uint32_t)c));
+          if (v2) gstore4(pq + 2 * N, slot_encode(a2, (uint32_t)c));
+          if (v3) gstore4(pq + 3 * N, slot_encode(a3, (uint32_t)c));
+        }
         // ---- phase three: link outputs (patch edges first: neighbours poll for them), ejection,
         // then the next cycle's loads
 #define out_for(p) s_link[cur][min((inv >> (3 * (p))) & 7u, 5u)][j]
@@ -1836,7 +1887,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     __builtin_amdgcn_s_barrier();
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (s_fail) break;
-    if (step) c_done = c + 1;
+    if (step) {
+      c_done = c + 1;
+      if (PIPE && rd > 1) pe = pe + 1 == rd - 1 ? 0 : pe + 1;
+    }
   }
 
   // ---- write back: core words, interior slots of cycle c_done (stamped), flag, counters ----
@@ -1968,10 +2022,12 @@ int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_d
 // which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
 int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
 // OPT bits of the one-tile-per-thread kernel a chip needs
-// variants the one-tile-per-thread kernel carries (the directory, and D > 1, need the general one)
+// variants the one-tile-per-thread kernel carries, with any router delay (the directory needs
+// the general kernel)
 constexpr int32_t FAST_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
 int fast_opt(const ChipDev& d) {
-  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0);
+  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
+         (d.rdelay > 1 ? FAST_PIPE : 0);
 }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
@@ -2046,11 +2102,15 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
-  switch (opt & 3) {
+  switch (opt & 7) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
     case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
     case 2: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 2>);
-    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
+    case 3: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 3>);
+    case 4: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 4>);
+    case 5: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 5>);
+    case 6: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 6>);
+    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 7>);
   }
 }
 const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 0) {
@@ -2075,7 +2135,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 16; ++k) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2148,7 +2208,8 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
 // opt: FAST_PACKETS when some chip of the table has multi-flit replies (the kernel then reads
-// each chip's count), FAST_VARIANTS when some chip has a variant the kernel carries
+// each chip's count), FAST_VARIANTS when some chip has a variant the kernel carries, FAST_PIPE
+// when some chip has a router delay
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
                    unsigned long long* digests, int digest_base, hipStream_t s, int opt, int var) {
   if (n <= 0) return SIM_OK;
@@ -2210,8 +2271,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  // the directory, and D > 1: general kernel
-  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0 && router_delay(cfg) == 1;
+  // the directory: general kernel
+  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0;
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -2307,7 +2368,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0 && h->hd.rdelay == 1;
+  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0;
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;

@@ -1,8 +1,8 @@
 """Parity of the model variants (SimParams.flags) on the GPU with the serial oracle.
 
-Priority by deflection count, hit under miss and the injection register run on the
-one-tile-per-thread kernel as well as on the general one; the router delay and the directory
-run on the general kernel.  Bar: bit-exact, as for the base model: every
+Priority by deflection count, hit under miss, the injection register and the router delay
+run on the one-tile-per-thread kernel as well as on the general one; the directory runs on
+the general kernel.  Bar: bit-exact, as for the base model: every
 per-cycle digest and the final canonical dump, including each in-flight flit's deflection
 count and each core's held op.
 """
@@ -65,6 +65,20 @@ def test_fast_kernel_variants_on_both_kernels(reply_flits, flags):
     assert_same_run(p, 1200, step_sizes=[500, 700])
 
 
+@pytest.mark.parametrize("flags", [0, AGE | HUM | DELAY], ids=["base", "all"])
+@pytest.mark.parametrize("D", [2, 3, 8])
+def test_fast_kernel_router_delay_on_both_kernels(D, flags):
+    """Router pipelines on the one-tile-per-thread kernel equal the general kernel and the
+    oracle, alone and with every other flag, across launch boundaries."""
+    p = W.config0().with_(width=17, height=11, seed=70 + D + flags, bg_thr=W.thr(0.25), op_thr=W.thr(0.5),
+                          flags=flags, router_delay=D, reply_flits=2)
+    a = gpu_sim(p)
+    b = gpu_sim(p, generic=True)
+    assert (a.step(555, digests=True) == b.step(555, digests=True)).all()
+    assert (a.dump() == b.dump()).all()
+    assert_same_run(p, 900, launch=(17, 4, 128, 0), step_sizes=[400, 500])
+
+
 def test_fast_kernel_variants_batch():
     """One launch of the one-tile-per-thread kernel over base chips and chips with variants
     (some with multi-flit replies): each equals its own oracle run."""
@@ -72,19 +86,21 @@ def test_fast_kernel_variants_batch():
     params = [W.config1().with_(width=s, height=s, seed=5000 + i, bg_thr=W.thr(0.15), flags=f, reply_flits=r)
               for i, (s, f, r) in enumerate([(8, 0, 1), (16, DELAY, 1), (8, AGE, 4), (12, 0, 2), (16, AGE | DELAY, 2),
                                              (12, HUM, 1), (8, AGE | HUM | DELAY, 3)])]
+    params += [W.config1().with_(width=10, height=10, seed=5100, bg_thr=W.thr(0.2), router_delay=2),
+               W.config1().with_(width=9, height=12, seed=5101, bg_thr=W.thr(0.2), router_delay=5, flags=AGE | HUM)]
     sims = [gpu_sim(p, launch=(p.width, 256 // p.width, 256, 0)) for p in params]
     b = nocsim.Batch(sims)
-    b.step([300, 250, 300, 123, 200, 280, 333])
-    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200, 280, 333]):
+    b.step([300, 250, 300, 123, 200, 280, 333, 310, 290])
+    for p, s, n in zip(params, sims, [300, 250, 300, 123, 200, 280, 333, 310, 290]):
         o = O.OracleSim(p)
         o.step(n)
         assert (s.dump() == o.dump()).all(), f"chip {p.width}x{p.height} flags {p.flags} reply_flits {p.reply_flits}"
 
 
 def test_variants_refuse_the_base_kernel():
-    """Asking for the one-tile-per-thread kernel keeps a chip with a router delay on the
+    """Asking for the one-tile-per-thread kernel keeps a chip with the directory on the
     general kernel."""
-    p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM, router_delay=2)
+    p = W.config0().with_(width=8, height=8, seed=4, bg_thr=W.thr(0.3), flags=AGE | HUM | W.LSPD, router_delay=2)
     a = gpu_sim(p)
     a.set_kernel(False)
     b = gpu_sim(p, generic=True)
