@@ -145,6 +145,12 @@ __device__ __forceinline__ int ld_coh(const int* p) {
 __device__ __forceinline__ void st_coh(int* p, int v) {
   __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A wait that gave up: records a hang unless another workgroup already recorded an error (a
+// workgroup that stops on an invariant failure leaves its neighbours waiting; its code is kept).
+__device__ __forceinline__ void note_hang(int* err) {
+  int none = 0;
+  __hip_atomic_compare_exchange_strong(gp(err), &none, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int4 ld_slot(const int4* p, bool coh) {
   if (!coh) return gload4(p);
   unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<int4*>(p));
@@ -432,7 +438,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
       if (!(p0 | p1 | p2 | p3)) break;
       if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
-        st_coh(C.err, 1);
+        note_hang(C.err);
         return false;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -1627,7 +1633,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
           if (!(p0 | p1 | p2 | p3)) break;
           if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
-            st_coh(C.err, 1);
+            note_hang(C.err);
             ok = false;
             break;
           }
