@@ -83,18 +83,17 @@ def kernel_events_ms(sim, n_cycles, torch):
 
 def profiled_traffic(kernel_tag):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a copy
-    calibration) for this exact kernel source, or None when the source changed since."""
-    import hashlib
+    calibration) for this exact kernel build (source and compiler flags), or None when either
+    changed since."""
     import re
-    src = os.path.join(ROOT, "paper_1508_03235_amd", "csrc", "nocsim.hip")
+    from __graft_entry__ import build_signature
     prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_208x208_bg0.05_counters.md")
     if not os.path.exists(prof):
         return None
     text = open(prof).read()
-    m_sha = re.search(r"kernel source sha256 \(first 16 hex\): ([0-9a-f]{16})", text)
+    m_sha = re.search(r"kernel build sha256 \(source and compiler flags, first 16 hex\): ([0-9a-f]{16})", text)
     m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if not m_sha or not m_b or m_sha.group(1) != sha:
+    if not m_sha or not m_b or m_sha.group(1) != build_signature():
         return None
     return int(m_b.group(1))
 
