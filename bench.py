@@ -357,7 +357,7 @@ def main():
             "kernel": kernel, "launch_ms": ms_launch, "cycles_per_launch": chunk,
             "algorithmic_bytes_per_tile_cycle": abytes_per_launch / chunk / p.tiles,
             "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 "
-                            "(profiles/, same kernel source hash), null if the source changed"}
+                            "(profiles/, same hash of kernel source and compiler flags), null if either changed"}
 
     S = nocsim.STAT
     ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
