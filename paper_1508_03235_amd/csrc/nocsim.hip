@@ -1637,7 +1637,6 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             ok = false;
             break;
           }
-          __builtin_amdgcn_s_sleep(1);
           if (p0) w0 = ld_slot(&C.link[(cur * 4 + 0) * N + t], true);
           if (p1) w1 = ld_slot(&C.link[(cur * 4 + 1) * N + t], true);
           if (p2) w2 = ld_slot(&C.link[(cur * 4 + 2) * N + t], true);
