@@ -193,7 +193,11 @@ int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr);
 /* Launch mapping: patch_w x patch_h tiles per workgroup (the chip is cut into patches that
    exchange boundary links through per-patch cycle flags), `block` threads per workgroup (64..256, a multiple of 64),
    `chunk` cycles per launch.  0 keeps the current value.  EINVAL if the patch grid cannot
-   be resident on the device at once. */
+   be resident on the device at once.  sim_create's default: one workgroup for chips of at
+   most 1,024 tiles; for chips up to 256 columns one row per workgroup of 64 or 128 threads
+   (half a row above 128 columns, whole rows up to 256 tiles below 64 columns) when every
+   build of the step kernel can hold all of them at once; otherwise square-ish patches, about
+   one per compute unit; chunk 1,000. */
 int sim_set_launch(sim_t* h, int32_t patch_w, int32_t patch_h, int32_t block, int32_t chunk);
 int sim_get_launch(const sim_t* h, int32_t* patch_w, int32_t* patch_h, int32_t* block, int32_t* chunk);
 /* Kernel choice: when every patch has at most `block` tiles the library runs a kernel that keeps
