@@ -1404,7 +1404,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const LaunchEntry e = table[blockIdx.x];
   const ChipDev C = *e.chip;
   const int N = C.N;
-  const int D = VARS ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
+  const int idl = VARS ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
   const bool aged = VARS && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
   const bool hum = VARS && (C.variants & SIM_FLAG_HIT_UNDER_MISS) != 0;  // ops drawn under a miss
   const int rd = PIPE ? C.rdelay : 1;  // router delay D: arrivals wait D-1 cycles in a pipeline
@@ -1553,7 +1553,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           acc.l2_hit += hit;
           acc.l2_miss += !hit;
           node_rq = rq;
-          node_ready = (hit ? c : c + C.mem_lat) + D;
+          node_ready = (hit ? c : c + C.mem_lat) + idl;
           node_line = line;
           const int4 fresh = make_int4(-1, node_ready, line, 0);
           if (hit) {
@@ -1714,7 +1714,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         int cls = -1;
         if (k2.x >= 0 && nm.y <= c) cls = 0;
         else if (k1.z >= 0 && (!VARS || nh.y <= c)) cls = 1;
-        else if (k0.x == CORE_SEND && (!VARS || k0.y + D <= c)) cls = 2;
+        else if (k0.x == CORE_SEND && (!VARS || k0.y + idl <= c)) cls = 2;
         else if (fdst >= 0) cls = 3;
         else if (k2.z > 0) cls = 4;
         if (cls >= 0 && arrivals >= deg) {
