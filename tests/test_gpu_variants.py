@@ -265,3 +265,11 @@ def test_deflection_count_limit_on_gpu(generic):
     g.load(snap)
     with pytest.raises(nocsim.SimError, match="EINVARIANT"):
         g.step(1)
+
+
+def test_fast_kernel_every_option_full_size():
+    """208x208 in the default launch configuration with every option the one-tile-per-thread
+    kernel carries: deflection-count priority, hit under miss, the injection register, a
+    router delay of 3 and 4-flit replies, against the oracle cycle by cycle."""
+    p = W.config2(0.1).with_(flags=AGE | HUM | DELAY, router_delay=3, reply_flits=4)
+    assert_same_run(p, 90, step_sizes=[35, 55])
