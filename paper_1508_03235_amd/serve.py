@@ -11,7 +11,7 @@ next tick, so their work overlaps on the device.  Because every chip's randomnes
 by its own (seed; cycle, tile), a job's result does not depend on what it ran beside.
 
 The scheduler is written against a small backend interface so that its admission, memory
-accounting and completion logic can be tested on the CPU with the oracle behind it.
+accounting and completion logic can be tested on the CPU with a stand-in backend.
 """
 from __future__ import annotations
 
@@ -89,41 +89,6 @@ class GpuBackend(Backend):
     def release(self, chip):
         chip.close()
         del chip.mem
-
-
-class OracleBackend(Backend):
-    """The serial oracle behind the same interface (test double for the scheduler)."""
-
-    def __init__(self):
-        from oracle import oracle as O
-        self.O = O
-
-    def state_bytes(self, params) -> int:
-        N = params.tiles
-        return N * (128 + 96 + 16 + 4 * (params.l1_sets * params.l1_ways + params.l2_sets * params.l2_ways))
-
-    def create(self, params):
-        return self.O.OracleSim(params)
-
-    def step(self, chips, cycles):
-        for c, n in zip(chips, cycles):
-            self.step_one(c, n)
-
-    def step_one(self, chip, cycles):
-        if cycles:
-            chip.step(int(cycles))
-
-    def cycle(self, chip):
-        return chip.cycle
-
-    def check(self, chip):
-        pass
-
-    def stats(self, chip):
-        return chip.stats()
-
-    def release(self, chip):
-        chip.close()
 
 
 @dataclass

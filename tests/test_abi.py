@@ -80,3 +80,20 @@ def test_model_options_validation():
     ways = p.tiles * p.l2_sets * p.l2_ways
     assert size(p.with_(flags=W.LSPD, mig_threshold=2)) >= size(p.with_(flags=W.LSPD)) + 4 * ways  # way records
     assert size(p.with_(router_delay=3)) >= base + 2 * 4 * 16 * p.tiles    # two pipeline stages
+
+
+def test_product_package_never_loads_the_oracle():
+    """Only the tests, the smoke check and the benchmark's CPU-baseline leg may load oracle/."""
+    import ast
+    import pathlib
+    pkg = pathlib.Path(__file__).resolve().parent.parent / "paper_1508_03235_amd"
+    for f in pkg.rglob("*.py"):
+        tree = ast.parse(f.read_text())
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                names = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                names = [node.module or ""]
+            else:
+                continue
+            assert not any(n == "oracle" or n.startswith("oracle.") for n in names), f"{f} imports {names}"

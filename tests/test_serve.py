@@ -5,7 +5,8 @@ import pytest
 
 from oracle import oracle as O
 from paper_1508_03235_amd import workload as W
-from paper_1508_03235_amd.serve import GpuBackend, OracleBackend, Server
+from paper_1508_03235_amd.serve import GpuBackend, Server
+from fake_backend import OracleBackend
 
 
 def small_jobs(n, seed=4):
