@@ -209,20 +209,45 @@ int sim_destroy(sim_t* h);
 const char* sim_strerror(int code);
 int sim_last_hip_error(void);
 
-/* ---- batches: many independent chips advanced by one persistent launch ---------------- */
-/* A batch groups chips created with sim_create (each in its own buffer) so that one launch
-   advances all of them: workgroup w runs one patch of one chip, and chips never wait on each
-   other.  The launch table lives in a caller-owned device buffer of simb_state_bytes().  The
-   batch launches on its own stream; the caller orders any per-chip call with it.  Chips keep
-   their own launch mapping, except the workgroup size, which is the batch's `block` (0 =
-   largest of the chips').  A chip cut into several patches needs all of its workgroups
-   resident at once: simb_create returns SIM_EINVAL when the batch grid cannot be. */
-size_t simb_state_bytes(int32_t n_chips, int64_t n_patches);
-int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, size_t bytes,
-                void* stream, simb_t** out);
-/* Advances chip i by cycles[i] >= 0 cycles (host array of n), all in one persistent launch
-   per `chunk` cycles; chips that need fewer cycles stop early.  Asynchronous. */
+/* ---- batches: many independent chips advanced by one persistent launch ----------------
+   The batched step of many independent simulations (each chip is the paper's whole simulated
+   system, Sec. 7.1; chips share nothing).  A batch groups chips created with sim_create (each
+   in its own buffer) so that one launch advances all of them: workgroup w runs one patch of
+   one chip, and chips never wait on each other.  The batch keeps a launch table and one error
+   word per chip in a caller-owned device workspace of simb_state_bytes(max_chips,
+   max_patches) bytes (256-byte aligned), sized for the most chips and patches it will ever
+   hold.  The batch launches on its own stream; the caller orders any per-chip call with it.
+   Chips keep their own launch mapping, except the workgroup size, which is the batch's
+   `block`.  A chip cut into several patches needs all of its workgroups resident at once.
+   Chips are identified by slot numbers 0 .. simb_slots()-1; a slot freed by simb_remove is
+   reused by the next simb_add.  A chip belongs to at most one batch; the batch never frees a
+   chip.  Not thread safe. */
+size_t simb_state_bytes(int32_t max_chips, int64_t max_patches);  /* 0 if invalid */
+/* Creates a batch of n >= 0 chips in slots 0..n-1.  block: threads per workgroup (64..256, a
+   multiple of 64; 0 = the largest of the chips', which needs n > 0).  max_chips / max_patches:
+   capacity of the workspace (0 = exactly the n chips given).  EINVAL when a chip of several
+   patches cannot be resident under the batch's kernel, ENOMEM when `bytes` is too small. */
+int simb_create(sim_t* const* chips, int32_t n, int32_t block, int32_t max_chips, int64_t max_patches,
+                void* dev_mem, size_t bytes, void* stream, simb_t** out);
+/* Continuous batching (a served job joins or leaves between steps).  simb_add puts `chip` in
+   the lowest free slot (*slot); EBUSY when the workspace cannot hold it, EINVAL when it is
+   already in the batch or cannot be resident.  simb_remove takes the chip in `slot` out (the
+   chip itself stays valid and keeps its state). */
+int simb_add(simb_t* b, sim_t* chip, int32_t* slot);
+int simb_remove(simb_t* b, int32_t slot);
+int32_t simb_slots(const simb_t* b);  /* number of slot numbers in use (free ones included) */
+/* Statistics of the chip in `slot` (as sim_stats; synchronises). */
+int simb_stats(simb_t* b, int32_t slot, sim_stats_t* out);
+/* Advances the chip in slot i by cycles[i] >= 0 cycles (host array of simb_slots() entries;
+   free slots' entries are ignored), one persistent launch per launch group per `chunk` cycles
+   (the smallest chunk of the members); chips that need fewer cycles stop early.  Returns once
+   the step has finished, with SIM_EHANG / SIM_EINVARIANT if a chip reported one. */
 int simb_step(simb_t* b, const int64_t* cycles);
+/* on = 1: simb_step replays one chunk of every launch group as a HIP graph (one kernel node
+   per launch group, chained; groups of multi-patch chips are cooperative nodes), built on the
+   first step and rebuilt after a membership or chunk change, instead of launching the chunks
+   one by one.  Results are identical either way. */
+int simb_set_graph(simb_t* b, int32_t on);
 int simb_destroy(simb_t* b);
 
 #ifdef __cplusplus

@@ -29,11 +29,11 @@ HIST = 32
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain C11, -O2)."""
+    """Compile liboracle.so with gcc (plain C11, -O3)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "nocsim_oracle.h"))):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-Wall", "-Wextra",
+        subprocess.check_call(["gcc", "-std=c11", "-O3", "-fPIC", "-shared", "-Wall", "-Wextra",
                                "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB

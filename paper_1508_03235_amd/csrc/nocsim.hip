@@ -1923,6 +1923,28 @@ __global__ void fill_u64(unsigned long long* p, unsigned long long v, size_t n) 
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 __global__ void set_stop(ChipDev* d, int stop) { d->stop = stop; }
+// Launch tables are written on the device from a list of chips passed by value (no host
+// staging buffer; a table upload is then one small kernel, also inside a captured graph).
+constexpr int LIST_CHIPS = 96;  // chips per list (kernel arguments stay well under 4 KB)
+struct ChipList {
+  int32_t count;
+  int32_t first[LIST_CHIPS];  // first table entry of each chip
+  int32_t stop[LIST_CHIPS];   // cycle each chip stops at (-1: the chip's own descriptor says)
+  ChipDev* chip[LIST_CHIPS];
+};
+// workgroup k writes the entries of chip k: one per patch, in patch order
+__global__ void fill_table(LaunchEntry* table, ChipList L) {
+  const int k = blockIdx.x;
+  if (k >= L.count) return;
+  ChipDev* d = L.chip[k];
+  const int np = d->n_patches;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) table[L.first[k] + p] = LaunchEntry{d, p, L.stop[k]};
+}
+// out[base + k] = error word of chip k
+__global__ void gather_errors(int32_t* out, int base, ChipList L) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < L.count) out[base + k] = *L.chip[k]->err;
+}
 // link slots of a fresh (or reloaded) chip at cycle c: every slot empty; parity c&1 holds the
 // inputs of cycle c, the other parity is stamped c-1 so that it cannot pass for cycle c+1
 __global__ void init_links(int4* link, int N, int c) {
@@ -1960,8 +1982,7 @@ struct sim_chip {
   int32_t block, chunk;
   bool fast;               // every patch fits its workgroup: one tile per thread (step_fast)
   bool use_fast;           // allow step_fast (tests compare both kernels)
-  LaunchEntry* table_dev;  // MAX_PATCHES entries
-  LaunchEntry* table_host; // pinned staging
+  LaunchEntry* table_dev;  // max_patches entries
 };
 
 // A launch group: consecutive chips whose workgroups are launched together.  Chips cut into
@@ -1974,17 +1995,27 @@ struct sim_launch_group {
 };
 
 struct sim_group {
-  std::vector<sim_chip*> chips;
-  std::vector<int32_t> first_entry;  // first table entry of chip i
-  std::vector<sim_launch_group> groups;
-  int32_t block;
-  bool multi, fast;
-  int opt;                           // FAST_* bits some chip needs (multi-flit replies, injection register)
-  int var;                           // general-kernel build: 1 a variant or router delay > 1, 2 the directory
+  std::vector<sim_chip*> slots;      // chip of each slot; nullptr = free
+  int32_t block;                     // threads per workgroup of every launch
+  int32_t max_chips;                 // capacity of the caller's workspace
+  int64_t max_entries;
   hipStream_t stream;
-  LaunchEntry* table_dev;
-  LaunchEntry* table_host;
+  LaunchEntry* table_dev;            // workspace: [max_entries] launch entries
+  int32_t* err_dev;                  // workspace: [max_chips] error words gathered after a step
+  // derived from the members, rebuilt after simb_add / simb_remove
+  bool dirty;
+  std::vector<int32_t> members;      // occupied slots in table order
+  std::vector<int32_t> first_entry;  // first table entry of each member
+  std::vector<sim_launch_group> groups;
+  bool fast;
+  int opt;                           // FAST_* bits some member needs (multi-flit replies, variants, router delay)
+  int var;                           // general-kernel build: 1 a variant or router delay > 1, 2 the directory
   int64_t n_entries;
+  // one chunk of every launch group, as a graph of kernel nodes (simb_set_graph)
+  bool use_graph;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int32_t graph_chunk;
 };
 
 namespace {
@@ -2206,9 +2237,16 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   // every patch's flag records the chip's cycle
   int rc = launch_grid_fill_i32(h->hd.flags, (int32_t)h->cycle, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream);
   if (rc) return rc;
-  for (int p = 0; p < np; ++p) h->table_host[p] = LaunchEntry{h->dd, p, -1};
-  HIPCHECK(hipMemcpyAsync(h->table_dev, h->table_host, np * sizeof(LaunchEntry), hipMemcpyHostToDevice, h->stream));
-  return upload_desc(h);
+  HIPCHECK(hipMemcpyAsync(h->dd, &h->hd, sizeof(ChipDev), hipMemcpyHostToDevice, h->stream));
+  ChipList one{};
+  one.count = 1;
+  one.first[0] = 0;
+  one.stop[0] = -1;
+  one.chip[0] = h->dd;
+  hipLaunchKernelGGL(fill_table, dim3(1), dim3(256), 0, h->stream, h->table_dev, one);
+  HIPCHECK(hipGetLastError());
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return SIM_OK;
 }
 
 // fast: every patch has at most `block` tiles (one tile per thread: step_fast)
@@ -2332,12 +2370,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.err = reinterpret_cast<int32_t*>(h->base + Lo.err);
   h->dd = reinterpret_cast<ChipDev*>(h->base + Lo.desc);
   h->table_dev = reinterpret_cast<LaunchEntry*>(h->base + Lo.table);
-  if (hipHostMalloc(reinterpret_cast<void**>(&h->table_host), d.max_patches * sizeof(LaunchEntry), hipHostMallocDefault) != hipSuccess) {
-    delete h;
-    return SIM_EHIP;
-  }
   int rc = SIM_OK;
-  auto fail = [&](int code) { (void)hipHostFree(h->table_host); delete h; return code; };
+  auto fail = [&](int code) { delete h; return code; };
   hipLaunchKernelGGL(init_links, dim3(std::min((8 * N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.link, N, 0);
   if (hipGetLastError() != hipSuccess) return fail(SIM_EHIP);
   hipLaunchKernelGGL(init_core, dim3(std::min((N + 255) / 256, 4096)), dim3(256), 0, h->stream, d.core, d.node, N);
@@ -2623,127 +2657,331 @@ int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr) {
 int sim_destroy(sim_t* h) {
   if (!h) return SIM_EINVAL;
   (void)hipStreamSynchronize(h->stream);
-  (void)hipHostFree(h->table_host);
   delete h;
   return SIM_OK;
 }
 
 // ---- batches ------------------------------------------------------------------------------------
-size_t simb_state_bytes(int32_t n_chips, int64_t n_patches) {
-  if (n_chips < 1 || n_patches < n_chips) return 0;
-  return align_up((size_t)n_patches * sizeof(LaunchEntry), 256);
+size_t simb_state_bytes(int32_t max_chips, int64_t max_patches) {
+  if (max_chips < 1 || max_patches < max_chips || max_patches > 0x7FFFFFFF) return 0;
+  return align_up((size_t)max_patches * sizeof(LaunchEntry), 256) + align_up((size_t)max_chips * sizeof(int32_t), 256);
 }
 
-int simb_create(sim_t* const* chips, int32_t n, int32_t block, void* dev_mem, size_t bytes, void* stream, simb_t** out) {
-  if (!out || !chips || n < 1 || !dev_mem || block < 0 || block > 256 || block % 64) return SIM_EINVAL;
-  *out = nullptr;
-  int64_t entries = 0;
-  int32_t bmax = 0, tmax = 0;
-  bool multi = false, use_fast = true;
+}  // extern "C"
+
+namespace {
+
+// The kernel that runs a launch group of a batch.
+const void* batch_kernel(bool multi, bool fast, int opt, int var) {
+  if (multi) return multi_kernel(fast, false, opt, var);
+  if (fast) return fast_build<false, false>(opt);
+  return var == 2 ? reinterpret_cast<const void*>(step_kernel<false, 2>)
+         : var == 1 ? reinterpret_cast<const void*>(step_kernel<false, 1>)
+                    : reinterpret_cast<const void*>(step_kernel<false, 0>);
+}
+
+// Which kernel a set of chips runs on in a batch of `block`-thread workgroups.
+struct BatchKind {
+  bool fast, multi;
+  int opt, var;
+};
+template <class ChipAt>
+BatchKind batch_kind(ChipAt chip_at, int n, int block) {
+  BatchKind k{true, false, 0, 0};
   for (int i = 0; i < n; ++i) {
-    if (!chips[i]) return SIM_EINVAL;
-    entries += chips[i]->hd.n_patches;
-    bmax = std::max(bmax, chips[i]->block);
-    tmax = std::max(tmax, chips[i]->hd.pw * chips[i]->hd.ph);
-    multi = multi || chips[i]->hd.n_patches > 1;
-    use_fast = use_fast && chips[i]->use_fast;
+    const sim_chip* h = chip_at(i);
+    k.fast = k.fast && h->use_fast && h->hd.pw * h->hd.ph <= block;
+    k.multi = k.multi || h->hd.n_patches > 1;
+    k.opt |= fast_opt(h->hd);
+    k.var = std::max(k.var, kernel_level(h->hd));
   }
-  if (bytes < simb_state_bytes(n, entries)) return SIM_ENOMEM;
-  if (entries > 0x7FFFFFFF) return SIM_EINVAL;
-  const int32_t blk = block ? block : bmax;
-  const bool fast = use_fast && tmax <= blk;
-  const int limit = multi ? resident_limit(blk, fast) : 0;
-  // split into launch groups: a group with a multi-patch chip stays within `limit` workgroups
-  std::vector<sim_launch_group> groups;
-  {
-    sim_launch_group cur{0, 0, 0, 0, false};
-    int64_t e = 0;
-    for (int i = 0; i < n; ++i) {
-      const int np = chips[i]->hd.n_patches;
-      if (np > 1 && np > limit) return SIM_EINVAL;  // this chip alone cannot be resident
-      const bool m = cur.multi || np > 1;
-      if (cur.n_chips > 0 && m && cur.n_entries + np > limit) {
-        groups.push_back(cur);
-        cur = sim_launch_group{i, 0, e, 0, false};
-      }
-      cur.n_chips++;
-      cur.n_entries += np;
-      cur.multi = cur.multi || np > 1;
-      e += np;
+  return k;
+}
+
+// Cuts chips 0..n-1 (in order) into launch groups: a group that holds a chip of several
+// patches stays within `limit` workgroups, the number the device holds at once.  Calls
+// emit(group) for each group; returns SIM_EINVAL if one chip alone exceeds the limit.
+template <class ChipAt, class Emit>
+int plan_groups(ChipAt chip_at, int n, int limit, Emit emit) {
+  sim_launch_group cur{0, 0, 0, 0, false};
+  int64_t e = 0;
+  for (int i = 0; i < n; ++i) {
+    const int np = chip_at(i)->hd.n_patches;
+    if (np > 1 && np > limit) return SIM_EINVAL;
+    const bool m = cur.multi || np > 1;
+    if (cur.n_chips > 0 && m && cur.n_entries + np > limit) {
+      emit(cur);
+      cur = sim_launch_group{i, 0, e, 0, false};
     }
-    groups.push_back(cur);
+    cur.n_chips++;
+    cur.n_entries += np;
+    cur.multi = cur.multi || np > 1;
+    e += np;
   }
-  sim_group* g = new (std::nothrow) sim_group();
-  if (!g) return SIM_ENOMEM;
-  g->chips.assign(chips, chips + n);
-  g->block = blk;
-  g->multi = multi;
-  g->fast = fast;
-  g->opt = 0;
-  g->var = 0;
+  if (cur.n_chips > 0) emit(cur);
+  return SIM_OK;
+}
+
+// Writes the launch-table entries of chips [k0, k0 + count) (first entries first[], stop
+// cycles stop[]) on the stream, LIST_CHIPS chips per kernel.
+template <class ChipAt, class FirstAt, class StopAt>
+int write_table(LaunchEntry* table, ChipAt chip_at, FirstAt first_at, StopAt stop_at, int n, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += LIST_CHIPS) {
+    ChipList L{};
+    L.count = std::min(LIST_CHIPS, n - k0);
+    for (int k = 0; k < L.count; ++k) {
+      L.chip[k] = chip_at(k0 + k)->dd;
+      L.first[k] = first_at(k0 + k);
+      L.stop[k] = stop_at(k0 + k);
+    }
+    hipLaunchKernelGGL(fill_table, dim3(L.count), dim3(64), 0, s, table, L);
+    HIPCHECK(hipGetLastError());
+  }
+  return SIM_OK;
+}
+
+// Gathers the error words of chips 0..n-1 into err_dev, copies them to err_host and returns
+// the worst status (synchronises the stream).
+template <class ChipAt>
+int gather_status(int32_t* err_dev, int32_t* err_host, ChipAt chip_at, int n, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += LIST_CHIPS) {
+    ChipList L{};
+    L.count = std::min(LIST_CHIPS, n - k0);
+    for (int k = 0; k < L.count; ++k) L.chip[k] = chip_at(k0 + k)->dd;
+    hipLaunchKernelGGL(gather_errors, dim3(1), dim3(LIST_CHIPS < 64 ? 64 : 128), 0, s, err_dev, k0, L);
+    HIPCHECK(hipGetLastError());
+  }
+  HIPCHECK(hipMemcpyAsync(err_host, err_dev, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  int worst = SIM_OK;
   for (int i = 0; i < n; ++i) {
-    g->opt |= fast_opt(chips[i]->hd);
-    g->var = std::max(g->var, kernel_level(chips[i]->hd));
+    if (err_host[i] == 1) worst = SIM_EHANG;
+    else if (err_host[i] && worst == SIM_OK) worst = SIM_EINVARIANT;
   }
-  g->groups = groups;
-  g->stream = static_cast<hipStream_t>(stream);
-  g->table_dev = static_cast<LaunchEntry*>(dev_mem);
-  g->n_entries = entries;
-  if (hipHostMalloc(reinterpret_cast<void**>(&g->table_host), (size_t)entries * sizeof(LaunchEntry), hipHostMallocDefault) != hipSuccess) {
-    delete g;
-    return SIM_EHIP;
-  }
+  return worst;
+}
+
+void drop_graph(sim_group* g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->exec = nullptr;
+  g->graph = nullptr;
+  g->graph_chunk = 0;
+}
+
+// Recomputes the members' table layout, launch groups and kernel after a membership change.
+int rebuild(sim_group* g) {
+  g->members.clear();
+  g->first_entry.clear();
+  g->groups.clear();
+  for (size_t i = 0; i < g->slots.size(); ++i)
+    if (g->slots[i]) g->members.push_back((int32_t)i);
+  const int n = (int)g->members.size();
+  auto chip_at = [g](int k) { return g->slots[g->members[k]]; };
+  const BatchKind k = batch_kind(chip_at, n, g->block);
+  g->fast = k.fast;
+  g->opt = k.opt;
+  g->var = k.var;
+  const int limit = k.multi ? resident_limit(g->block, k.fast) : 0;
   int64_t e = 0;
   for (int i = 0; i < n; ++i) {
     g->first_entry.push_back((int32_t)e);
-    for (int p = 0; p < chips[i]->hd.n_patches; ++p) g->table_host[e++] = LaunchEntry{chips[i]->dd, p, 0};
+    e += chip_at(i)->hd.n_patches;
+  }
+  g->n_entries = e;
+  int rc = plan_groups(chip_at, n, limit, [g](const sim_launch_group& lg) { g->groups.push_back(lg); });
+  if (rc) return rc;
+  drop_graph(g);
+  g->dirty = false;
+  return SIM_OK;
+}
+
+// Builds the graph of one chunk: one kernel node per launch group, in order.
+int build_graph(sim_group* g, int chunk) {
+  drop_graph(g);
+  HIPCHECK(hipGraphCreate(&g->graph, 0));
+  hipGraphNode_t prev = nullptr;
+  static unsigned long long* const no_digests = nullptr;
+  static const int zero = 0;
+  for (const sim_launch_group& lg : g->groups) {
+    const LaunchEntry* table = g->table_dev + lg.first_entry;
+    void* args[] = {(void*)&table, (void*)&chunk, (void*)&no_digests, (void*)&zero};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(batch_kernel(lg.multi, g->fast, g->opt, g->var));
+    kp.gridDim = dim3((unsigned)lg.n_entries);
+    kp.blockDim = dim3((unsigned)g->block);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    HIPCHECK(hipGraphAddKernelNode(&node, g->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    if (lg.multi) {
+      // the patches of a chip wait on each other: ask for co-residency as a cooperative launch does
+      hipKernelNodeAttrValue v{};
+      v.cooperative = 1;
+      HIPCHECK(hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &v));
+    }
+    prev = node;
+  }
+  HIPCHECK(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  g->graph_chunk = chunk;
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int simb_create(sim_t* const* chips, int32_t n, int32_t block, int32_t max_chips, int64_t max_patches, void* dev_mem,
+                size_t bytes, void* stream, simb_t** out) {
+  if (!out) return SIM_EINVAL;
+  *out = nullptr;
+  if (n < 0 || (n > 0 && !chips) || !dev_mem || block < 0 || block > 256 || block % 64) return SIM_EINVAL;
+  if (reinterpret_cast<uintptr_t>(dev_mem) % 256) return SIM_EINVAL;
+  int64_t entries = 0;
+  int32_t bmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!chips[i]) return SIM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (chips[j] == chips[i]) return SIM_EINVAL;
+    entries += chips[i]->hd.n_patches;
+    bmax = std::max(bmax, chips[i]->block);
+  }
+  if (!max_chips) max_chips = n;
+  if (!max_patches) max_patches = entries;
+  if (max_chips < n || max_patches < entries) return SIM_EINVAL;
+  const size_t need = simb_state_bytes(max_chips, max_patches);
+  if (!need) return SIM_EINVAL;
+  if (bytes < need) return SIM_ENOMEM;
+  const int32_t blk = block ? block : bmax;
+  if (!blk) return SIM_EINVAL;
+  sim_group* g = new (std::nothrow) sim_group();
+  if (!g) return SIM_ENOMEM;
+  g->slots.assign(chips, chips + n);
+  g->block = blk;
+  g->max_chips = max_chips;
+  g->max_entries = max_patches;
+  g->stream = static_cast<hipStream_t>(stream);
+  g->table_dev = static_cast<LaunchEntry*>(dev_mem);
+  g->err_dev = reinterpret_cast<int32_t*>(static_cast<char*>(dev_mem) +
+                                          align_up((size_t)max_patches * sizeof(LaunchEntry), 256));
+  g->use_graph = false;
+  g->graph = nullptr;
+  g->exec = nullptr;
+  g->graph_chunk = 0;
+  g->dirty = true;
+  const int rc = rebuild(g);
+  if (rc) {
+    delete g;
+    return rc;
   }
   *out = g;
   return SIM_OK;
 }
 
-int simb_step(simb_t* g, const int64_t* cycles) {
-  if (!g || !cycles) return SIM_EINVAL;
-  int64_t longest = 0;
-  int chunk = 1 << 30;
-  for (size_t i = 0; i < g->chips.size(); ++i) {
-    if (cycles[i] < 0 || g->chips[i]->cycle + cycles[i] > 0x7FFFFFFFll) return SIM_EINVAL;
-    longest = std::max(longest, cycles[i]);
-    chunk = std::min(chunk, g->chips[i]->chunk);
-  }
-  if (!longest) return SIM_OK;
-  for (size_t i = 0; i < g->chips.size(); ++i) {
-    sim_chip* h = g->chips[i];
-    const int stop = (int)(h->cycle + cycles[i]);
-    for (int p = 0; p < h->hd.n_patches; ++p) g->table_host[g->first_entry[i] + p].stop = stop;
-  }
-  HIPCHECK(hipMemcpyAsync(g->table_dev, g->table_host, (size_t)g->n_entries * sizeof(LaunchEntry), hipMemcpyHostToDevice, g->stream));
-  for (const sim_launch_group& lg : g->groups) {
-    int64_t lg_longest = 0;
-    for (int i = lg.first_chip; i < lg.first_chip + lg.n_chips; ++i) lg_longest = std::max(lg_longest, cycles[i]);
-    const int launches = (int)((lg_longest + chunk - 1) / chunk);
-    for (int k = 0; k < launches; ++k) {
-      int rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
-                              g->stream, g->opt, g->var);
-      if (rc) return rc;
+int simb_add(simb_t* g, sim_t* chip, int32_t* slot) {
+  if (!g || !chip || !slot) return SIM_EINVAL;
+  int free_slot = -1, members = 0;
+  int64_t entries = chip->hd.n_patches;
+  for (size_t i = 0; i < g->slots.size(); ++i) {
+    if (g->slots[i] == chip) return SIM_EINVAL;
+    if (!g->slots[i]) {
+      if (free_slot < 0) free_slot = (int)i;
+    } else {
+      members++;
+      entries += g->slots[i]->hd.n_patches;
     }
   }
-  for (size_t i = 0; i < g->chips.size(); ++i) g->chips[i]->cycle += cycles[i];
-  HIPCHECK(hipStreamSynchronize(g->stream));
-  int worst = SIM_OK;
-  for (size_t i = 0; i < g->chips.size(); ++i) {
-    int32_t err = 0;
-    HIPCHECK(hipMemcpy(&err, g->chips[i]->hd.err, sizeof err, hipMemcpyDeviceToHost));
-    if (err == 1) worst = SIM_EHANG;
-    else if (err && worst == SIM_OK) worst = SIM_EINVARIANT;
+  if (members + 1 > g->max_chips || entries > g->max_entries) return SIM_EBUSY;
+  // a chip of several patches must fit the device at once under the batch's kernel
+  if (chip->hd.n_patches > 1) {
+    bool fast = chip->use_fast && chip->hd.pw * chip->hd.ph <= g->block;
+    for (sim_chip* h : g->slots)
+      if (h) fast = fast && h->use_fast && h->hd.pw * h->hd.ph <= g->block;
+    if (chip->hd.n_patches > resident_limit(g->block, fast)) return SIM_EINVAL;
   }
-  return worst;
+  if (free_slot < 0) {
+    free_slot = (int)g->slots.size();
+    g->slots.push_back(chip);
+  } else {
+    g->slots[free_slot] = chip;
+  }
+  g->dirty = true;
+  *slot = free_slot;
+  return SIM_OK;
+}
+
+int simb_remove(simb_t* g, int32_t slot) {
+  if (!g || slot < 0 || slot >= (int32_t)g->slots.size() || !g->slots[slot]) return SIM_EINVAL;
+  g->slots[slot] = nullptr;
+  g->dirty = true;
+  return SIM_OK;
+}
+
+int32_t simb_slots(const simb_t* g) { return g ? (int32_t)g->slots.size() : -1; }
+
+int simb_stats(simb_t* g, int32_t slot, sim_stats_t* out) {
+  if (!g || slot < 0 || slot >= (int32_t)g->slots.size() || !g->slots[slot]) return SIM_EINVAL;
+  return sim_stats(g->slots[slot], out);
+}
+
+int simb_set_graph(simb_t* g, int32_t on) {
+  if (!g) return SIM_EINVAL;
+  g->use_graph = on != 0;
+  if (!g->use_graph) drop_graph(g);
+  return SIM_OK;
+}
+
+int simb_step(simb_t* g, const int64_t* cycles) {
+  if (!g || !cycles) return SIM_EINVAL;
+  if (g->dirty) {
+    const int rc = rebuild(g);
+    if (rc) return rc;
+  }
+  const int n = (int)g->members.size();
+  int64_t longest = 0;
+  int chunk = 1 << 30;
+  for (int k = 0; k < n; ++k) {
+    const sim_chip* h = g->slots[g->members[k]];
+    const int64_t c = cycles[g->members[k]];
+    if (c < 0 || h->cycle + c > 0x7FFFFFFFll) return SIM_EINVAL;
+    longest = std::max(longest, c);
+    chunk = std::min(chunk, h->chunk);
+  }
+  if (!longest) return SIM_OK;
+  auto chip_at = [g](int k) { return g->slots[g->members[k]]; };
+  int rc = write_table(
+      g->table_dev, chip_at, [g](int k) { return g->first_entry[k]; },
+      [g, cycles](int k) { return (int)(g->slots[g->members[k]]->cycle + cycles[g->members[k]]); }, n, g->stream);
+  if (rc) return rc;
+  if (g->use_graph) {
+    if (!g->exec || g->graph_chunk != chunk) {
+      if ((rc = build_graph(g, chunk))) return rc;
+    }
+    const int64_t launches = (longest + chunk - 1) / chunk;
+    for (int64_t k = 0; k < launches; ++k) HIPCHECK(hipGraphLaunch(g->exec, g->stream));
+  } else {
+    for (const sim_launch_group& lg : g->groups) {
+      int64_t lg_longest = 0;
+      for (int i = lg.first_chip; i < lg.first_chip + lg.n_chips; ++i)
+        lg_longest = std::max(lg_longest, cycles[g->members[i]]);
+      const int launches = (int)((lg_longest + chunk - 1) / chunk);
+      for (int k = 0; k < launches; ++k) {
+        rc = launch_entries(g->table_dev + lg.first_entry, lg.n_entries, lg.multi, g->fast, g->block, chunk, nullptr, 0,
+                            g->stream, g->opt, g->var);
+        if (rc) return rc;
+      }
+    }
+  }
+  for (int k = 0; k < n; ++k) g->slots[g->members[k]]->cycle += cycles[g->members[k]];
+  std::vector<int32_t> errs((size_t)n);
+  return gather_status(g->err_dev, errs.data(), chip_at, n, g->stream);
 }
 
 int simb_destroy(simb_t* g) {
   if (!g) return SIM_EINVAL;
   (void)hipStreamSynchronize(g->stream);
-  (void)hipHostFree(g->table_host);
+  drop_graph(g);
   delete g;
   return SIM_OK;
 }

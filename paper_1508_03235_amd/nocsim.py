@@ -88,7 +88,12 @@ def _lib():
             "sim_strerror": (C.c_char_p, [i32]),
             "sim_last_hip_error": (i32, []),
             "simb_state_bytes": (sz, [i32, i64]),
-            "simb_create": (i32, [p, i32, i32, p, sz, p, C.POINTER(p)]),
+            "simb_create": (i32, [p, i32, i32, i32, i64, p, sz, p, C.POINTER(p)]),
+            "simb_add": (i32, [p, p, C.POINTER(i32)]),
+            "simb_remove": (i32, [p, i32]),
+            "simb_slots": (i32, [p]),
+            "simb_stats": (i32, [p, i32, p]),
+            "simb_set_graph": (i32, [p, i32]),
             "simb_step": (i32, [p, p]),
             "simb_destroy": (i32, [p]),
         }
@@ -105,7 +110,8 @@ def exported_symbols():
     return ["sim_state_bytes", "sim_create", "sim_step", "sim_sync", "sim_cycle", "sim_stats",
             "sim_dump_words", "sim_dump", "sim_load", "sim_force_op", "sim_force_bg",
             "sim_set_rates", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
-            "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_step", "simb_destroy"]
+            "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_add", "simb_remove", "simb_slots",
+            "simb_stats", "simb_set_graph", "simb_step", "simb_destroy"]
 
 
 def _check(fn, rc):
@@ -228,30 +234,79 @@ class Sim:
         return tuple(int(x.value) for x in v)
 
 
-class Batch:
-    """Chips advanced together by one persistent launch per chunk of cycles."""
+def patches_of(sim) -> int:
+    """Workgroups (patches) the chip's current launch mapping cuts it into."""
+    pw, ph, _, _ = sim.get_launch()
+    return -(-sim.params.width // pw) * -(-sim.params.height // ph)
 
-    def __init__(self, sims, block: int = 0, stream=None):
+
+class Batch:
+    """Chips advanced together by one persistent launch per chunk of cycles.
+
+    `sims` fill slots 0..n-1; `max_chips` / `max_patches` size the launch table for chips added
+    later with add() (0 = exactly the chips given).  graph=True replays each chunk as a HIP
+    graph.  A chip's slot number is what step(), stats() and remove() take."""
+
+    def __init__(self, sims=(), block: int = 0, stream=None, max_chips: int = 0, max_patches: int = 0,
+                 graph: bool = False, device=None):
         import torch
         self.sims = list(sims)
         n = len(self.sims)
-        patches = 0
-        for s in self.sims:
-            pw, ph, _, _ = s.get_launch()
-            patches += -(-s.params.width // pw) * -(-s.params.height // ph)
-        nbytes = int(_lib().simb_state_bytes(n, patches))
+        patches = sum(patches_of(s) for s in self.sims)
+        self.max_chips = max_chips or n
+        self.max_patches = max_patches or patches
+        nbytes = int(_lib().simb_state_bytes(self.max_chips, self.max_patches))
         if nbytes == 0:
             raise SimError("simb_state_bytes", -1)
-        self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.sims[0].device)
+        dev = device if device is not None else (self.sims[0].device if self.sims else "cuda")
+        self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         base = (self.mem.data_ptr() + 255) // 256 * 256
-        arr = (C.c_void_p * n)(*[s.handle.value for s in self.sims])
+        arr = (C.c_void_p * max(n, 1))(*[s.handle.value for s in self.sims])
         h = C.c_void_p()
-        rc = _lib().simb_create(arr, n, block, C.c_void_p(base), nbytes, _stream_handle(stream), C.byref(h))
+        rc = _lib().simb_create(arr, n, block, max_chips, max_patches, C.c_void_p(base), nbytes,
+                                _stream_handle(stream), C.byref(h))
         _check("simb_create", rc)
         self._h = h
+        self.slot_of = {id(s): i for i, s in enumerate(self.sims)}
+        self.members = {i: s for i, s in enumerate(self.sims)}
+        if graph:
+            self.set_graph(True)
+
+    def add(self, sim) -> int:
+        slot = C.c_int32()
+        _check("simb_add", _lib().simb_add(self._h, sim.handle, C.byref(slot)))
+        self.members[slot.value] = sim
+        self.slot_of[id(sim)] = slot.value
+        return slot.value
+
+    def remove(self, sim_or_slot):
+        slot = sim_or_slot if isinstance(sim_or_slot, int) else self.slot_of[id(sim_or_slot)]
+        _check("simb_remove", _lib().simb_remove(self._h, slot))
+        sim = self.members.pop(slot)
+        self.slot_of.pop(id(sim), None)
+
+    @property
+    def slots(self) -> int:
+        return int(_lib().simb_slots(self._h))
+
+    def set_graph(self, on: bool):
+        _check("simb_set_graph", _lib().simb_set_graph(self._h, 1 if on else 0))
+
+    def stats(self, slot: int) -> np.ndarray:
+        out = np.zeros(N_STATS, dtype=np.int64)
+        _check("simb_stats", _lib().simb_stats(self._h, slot, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def step(self, cycles):
-        c = np.ascontiguousarray(np.broadcast_to(np.asarray(cycles, dtype=np.int64), (len(self.sims),)))
+        """cycles: one count for every member, a sequence in slot order (len == slots), or a
+        {slot: cycles} dict (missing slots advance 0)."""
+        n = self.slots
+        if isinstance(cycles, dict):
+            c = np.zeros(max(n, 1), dtype=np.int64)
+            for k, v in cycles.items():
+                c[k] = v
+        else:
+            c = np.ascontiguousarray(np.broadcast_to(np.asarray(cycles, dtype=np.int64), (max(n, 1),)))
         _check("simb_step", _lib().simb_step(self._h, c.ctypes.data_as(C.c_void_p)))
 
     def close(self):

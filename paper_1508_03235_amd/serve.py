@@ -1,11 +1,12 @@
 """Serving loop: simulation jobs admitted as they arrive, run with continuous batching.
 
 Each job is one chip (its own device buffer).  A job is admitted when its buffer fits the
-HBM state budget and a slot is free; every scheduler tick advances all resident jobs
-together (`simb_step`: the patches of all resident chips in one persistent launch, or a few
-launch groups when they do not fit the device at once, each chip with its own remaining
-cycle count), retires the jobs that finished, reads their statistics, frees their memory and
-admits new arrivals.  A job whose creation or step fails is retired with its error; the
+HBM state budget and a slot is free, and its chip joins one resident batch (`simb_add`);
+every scheduler tick advances all resident jobs together (`simb_step`: the patches of all
+resident chips in one persistent launch, or a few launch groups when they do not fit the
+device at once, each chip with its own remaining cycle count), retires the jobs that
+finished (`simb_remove`), reads their statistics, frees their memory and admits new
+arrivals.  A job whose creation or step fails is retired with its error; the
 others keep running.  Requests that arrive while others run join at the
 next tick, so their work overlaps on the device.  Because every chip's randomness is keyed
 by its own (seed; cycle, tile), a job's result does not depend on what it ran beside.
@@ -52,13 +53,27 @@ class Backend:
 
 
 class GpuBackend(Backend):
-    """Chips on the GPU through the C ABI; one batched launch per tick."""
+    """Chips on the GPU through the C ABI, all members of one resident batch: a job's chip joins
+    the batch when it is admitted (simb_add) and leaves when it retires (simb_remove); each
+    tick is one simb_step over the members.  The launch table is sized once for `max_chips`
+    chips of up to `max_patches` patches in all."""
 
-    def __init__(self, block: int = 256, chunk: int = 1000):
+    def __init__(self, block: int = 256, chunk: int = 1000, max_chips: int = 512, max_patches: int = 65536,
+                 graph: bool = False):
         from paper_1508_03235_amd import nocsim
         self.nocsim = nocsim
         self.block = block
         self.chunk = chunk
+        self.max_chips = max_chips
+        self.max_patches = max_patches
+        self.graph = graph
+        self.batch = None
+
+    def _batch(self):
+        if self.batch is None:
+            self.batch = self.nocsim.Batch((), block=self.block, max_chips=self.max_chips,
+                                           max_patches=self.max_patches, graph=self.graph)
+        return self.batch
 
     def state_bytes(self, params) -> int:
         return self.nocsim.state_bytes(params) + 256
@@ -66,13 +81,17 @@ class GpuBackend(Backend):
     def create(self, params):
         s = self.nocsim.Sim(params)
         side = 16 if params.tiles > self.block else max(params.width, params.height)
-        s.set_launch(min(side, params.width), min(side, params.height), self.block, self.chunk)
+        try:
+            s.set_launch(min(side, params.width), min(side, params.height), self.block, self.chunk)
+            self._batch().add(s)
+        except Exception:
+            s.close()
+            raise
         return s
 
     def step(self, chips, cycles):
-        b = self.nocsim.Batch(chips, block=self.block)
-        b.step(cycles)
-        b.close()
+        b = self._batch()
+        b.step({b.slot_of[id(c)]: int(n) for c, n in zip(chips, cycles)})
 
     def step_one(self, chip, cycles):
         chip.step(int(cycles))
@@ -87,8 +106,15 @@ class GpuBackend(Backend):
         return chip.stats()
 
     def release(self, chip):
+        if self.batch is not None and id(chip) in self.batch.slot_of:
+            self.batch.remove(chip)
         chip.close()
         del chip.mem
+
+    def close(self):
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
 
 
 @dataclass

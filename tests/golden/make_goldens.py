@@ -1,0 +1,130 @@
+"""Writes tests/golden/full_runs.json: expected results of full-length runs of the workload
+configurations, computed by the serial oracle alone.
+
+For each run the file holds the model parameters, the number of cycles, per-block hashes of
+the oracle's per-cycle state digests (one hash per 1,000 cycles) and hashes of the canonical
+state dump at the end (and, for the benchmark's 208x208 chip at background 0.05, after every
+1,000 cycles, so that a timed run of any whole number of 1,000-cycle steps can be checked).
+
+  config1   64x64, 100,000 cycles
+  config2   208x208 at each background rate, 50,000 cycles
+  config3   each of the 256 batch instances, 20,000 cycles
+  config4   a sample of the served jobs (the first ones whose tiles x cycles stay below a bound)
+
+Hashes are xxh3-128 of the little-endian bytes: the uint64 digests of a block of cycles, or
+the int32 dump words.  Nothing here reads a GPU result.  Run:
+    python tests/golden/make_goldens.py [--procs 8]
+(about 10 minutes on 8 cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+OUT = os.path.join(HERE, "full_runs.json")
+BLOCK = 1000
+CONFIG4_JOBS = 60            # the served job list the benchmark runs
+CONFIG4_MAX_WORK = 3.0e8     # tile-cycles per sampled job
+CONFIG4_SAMPLE = 8
+
+
+def _hash(a: np.ndarray) -> str:
+    import xxhash
+    return xxhash.xxh3_128_hexdigest(memoryview(np.ascontiguousarray(a)))
+
+
+def run_one(task):
+    """task = (key, params dict, cycles, dump_every) -> (key, result dict)."""
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as O
+    from paper_1508_03235_amd.workload import SimParams
+    key, pd, cycles, dump_every = task
+    p = SimParams(**pd)
+    t0 = time.perf_counter()
+    o = O.OracleSim(p)
+    blocks, dumps = [], {}
+    done = 0
+    while done < cycles:
+        n = min(BLOCK, cycles - done)
+        d = o.step(n, digests=True)
+        blocks.append(_hash(d.astype("<u8")))
+        done += n
+        if (dump_every and done % dump_every == 0) or done == cycles:
+            dumps[str(done)] = _hash(o.dump().astype("<i4"))
+    o.close()
+    return key, {"params": pd, "cycles": cycles, "digest_blocks": blocks, "dumps": dumps,
+                 "oracle_s": round(time.perf_counter() - t0, 1)}
+
+
+def config4_sample():
+    sys.path.insert(0, ROOT)
+    from paper_1508_03235_amd import workload as W
+    out = []
+    for j in W.config4(CONFIG4_JOBS):
+        if j.params.tiles * j.cycles <= CONFIG4_MAX_WORK:
+            out.append(j)
+        if len(out) == CONFIG4_SAMPLE:
+            break
+    return out
+
+
+def tasks():
+    sys.path.insert(0, ROOT)
+    from paper_1508_03235_amd import workload as W
+    t = [("config1", W.config1().as_dict(), 100_000, 0)]
+    for r in W.CONFIG2_RATES:
+        t.append((f"config2_{r}", W.config2(r).as_dict(), 50_000, BLOCK if r == 0.05 else 0))
+    for i, p in enumerate(W.config3()):
+        t.append((f"config3_{i}", p.as_dict(), 20_000, 0))
+    for j in config4_sample():
+        t.append((f"config4_{j.index}", j.params.as_dict(), j.cycles, 0))
+    # longest first, so the pool's tail is short
+    t.sort(key=lambda x: -x[1]["width"] * x[1]["height"] * x[2])
+    return t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--procs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--only", default="", help="comma-separated key prefixes to (re)compute")
+    args = ap.parse_args()
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as O
+    O.build()
+    todo = tasks()
+    old = {}
+    if args.only and os.path.exists(OUT):
+        old = json.load(open(OUT))["runs"]
+        pre = tuple(args.only.split(","))
+        todo = [t for t in todo if t[0].startswith(pre)]
+    runs = dict(old)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(args.procs) as pool:
+        for k, (key, res) in enumerate(pool.imap_unordered(run_one, todo)):
+            runs[key] = res
+            print(f"[{time.perf_counter() - t0:7.1f}s] {k + 1}/{len(todo)} {key} ({res['oracle_s']} s)", flush=True)
+    doc = {
+        "source": "serial oracle (oracle/nocsim_oracle.c) only; written by tests/golden/make_goldens.py",
+        "hash": "xxh3-128 of little-endian bytes",
+        "digest_block_cycles": BLOCK,
+        "config4_sample": {"jobs_listed": CONFIG4_JOBS, "max_tile_cycles": CONFIG4_MAX_WORK,
+                           "sample": CONFIG4_SAMPLE},
+        "runs": {k: runs[k] for k in sorted(runs)},
+    }
+    tmp = OUT + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(doc, f, indent=0, sort_keys=False)
+    os.replace(tmp, OUT)
+    print(f"wrote {OUT}: {len(runs)} runs in {time.perf_counter() - t0:.0f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -48,6 +48,10 @@ def test_state_bytes_and_validation():
         assert lib.sim_state_bytes(C.byref(cfg)) == 0, b
     assert lib.sim_strerror(-6) == b"cross-workgroup wait timed out"
     assert lib.simb_state_bytes(4, 3) == 0
+    assert lib.simb_state_bytes(0, 8) == 0
+    # launch table (16 B per patch) and one error word per chip, each 256-byte aligned
+    assert lib.simb_state_bytes(3, 20) == 512 + 256
+    assert lib.simb_state_bytes(100, 1000) == 16128 + 512
 
 
 def test_null_handles_rejected():
@@ -55,6 +59,17 @@ def test_null_handles_rejected():
     assert lib.sim_step(None, 1, None) == -1
     assert lib.sim_stats(None, None) == -1
     assert lib.simb_step(None, None) == -1
+    assert lib.simb_stats(None, 0, None) == -1
+    assert lib.simb_remove(None, 0) == -1
+    assert lib.simb_set_graph(None, 1) == -1
+    assert lib.simb_slots(None) == -1
+    slot = C.c_int32()
+    assert lib.simb_add(None, None, C.byref(slot)) == -1
+    out = C.c_void_p()
+    # a batch without chips needs an explicit workgroup size and a workspace
+    assert lib.simb_create(None, 0, 0, 4, 16, C.c_void_p(256), 4096, None, C.byref(out)) == -1
+    assert lib.simb_create(None, 0, 64, 4, 16, None, 4096, None, C.byref(out)) == -1
+    assert lib.simb_create(None, -1, 64, 4, 16, C.c_void_p(256), 4096, None, C.byref(out)) == -1
 
 
 def test_model_options_validation():
