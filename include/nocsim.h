@@ -250,6 +250,18 @@ int simb_step(simb_t* b, const int64_t* cycles);
 int simb_set_graph(simb_t* b, int32_t on);
 int simb_destroy(simb_t* b);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): the batched step of simb_create + simb_step in one
+   call, with the launch table and the per-chip error words in a static device array of the
+   library (about 516 KB per GPU, held until the process ends) instead of a caller workspace.
+   Advances chips[i] by cycles[i] >= 0 cycles (n chips, distinct, created with sim_create on the
+   current device); block as in simb_create.  Launches on `stream` and synchronises it; returns
+   SIM_EHANG / SIM_EINVARIANT as simb_step does.  At most 1024 chips and 32768 patches in total
+   per call: more is refused with SIM_ENOMEM before anything runs.  The call allocates nothing
+   (no hipMalloc, hipFree or library allocation).  Every call on one GPU shares that GPU's array:
+   calls that overlap on one GPU (other threads, other streams) race and are not allowed. */
+int simb_step_noalloc(sim_t* const* chips, int32_t n, int32_t block, const int64_t* cycles, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -2828,6 +2829,35 @@ int build_graph(sim_group* g, int chunk) {
   return SIM_OK;
 }
 
+// ---- batched step without a workspace argument ---------------------------------------------------
+// simb_step_noalloc keeps its launch table and error words in this array instead of a caller-owned
+// workspace.  Host code never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): each device's copy is looked up once with hipGetSymbolAddress.
+constexpr int NOALLOC_MAX_CHIPS = 1024;
+constexpr int NOALLOC_MAX_ENTRIES = 32768;
+constexpr size_t NOALLOC_TABLE_BYTES = (size_t)NOALLOC_MAX_ENTRIES * sizeof(LaunchEntry);
+constexpr size_t NOALLOC_BYTES = NOALLOC_TABLE_BYTES + (size_t)NOALLOC_MAX_CHIPS * sizeof(int32_t);
+static_assert(NOALLOC_TABLE_BYTES % 256 == 0, "error words start 256-byte aligned");
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::atomic<void*> g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's copy of `scratch` (looked up on first use).
+int scratch_of_current_device(char** out) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return SIM_EINVAL;
+  void* p = g_scratch_dev[dev].load(std::memory_order_acquire);
+  if (!p) {
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SIM_EHIP;
+    g_scratch_dev[dev].store(p, std::memory_order_release);
+  }
+  *out = static_cast<char*>(p);
+  return SIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2984,6 +3014,61 @@ int simb_destroy(simb_t* g) {
   drop_graph(g);
   delete g;
   return SIM_OK;
+}
+
+int simb_step_noalloc(sim_t* const* chips, int32_t n, int32_t block, const int64_t* cycles, void* stream) {
+  if (n < 0 || (n > 0 && (!chips || !cycles)) || block < 0 || block > 256 || block % 64) return SIM_EINVAL;
+  if (n > NOALLOC_MAX_CHIPS) return SIM_ENOMEM;
+  int32_t first[NOALLOC_MAX_CHIPS];
+  int64_t entries = 0, longest = 0;
+  int32_t bmax = 0;
+  int chunk = 1 << 30;
+  for (int i = 0; i < n; ++i) {
+    if (!chips[i]) return SIM_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (chips[j] == chips[i]) return SIM_EINVAL;
+    if (cycles[i] < 0 || chips[i]->cycle + cycles[i] > 0x7FFFFFFFll) return SIM_EINVAL;
+    first[i] = (int32_t)std::min<int64_t>(entries, NOALLOC_MAX_ENTRIES);
+    entries += chips[i]->hd.n_patches;
+    bmax = std::max(bmax, chips[i]->block);
+    longest = std::max(longest, cycles[i]);
+    chunk = std::min(chunk, chips[i]->chunk);
+  }
+  if (entries > NOALLOC_MAX_ENTRIES) return SIM_ENOMEM;
+  if (!longest) return SIM_OK;
+  const int32_t blk = block ? block : bmax;
+  char* ws = nullptr;
+  int rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  LaunchEntry* table = reinterpret_cast<LaunchEntry*>(ws);
+  int32_t* err_dev = reinterpret_cast<int32_t*>(ws + NOALLOC_TABLE_BYTES);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto chip_at = [chips](int k) { return chips[k]; };
+  const BatchKind k = batch_kind(chip_at, n, blk);
+  const int limit = k.multi ? resident_limit(blk, k.fast) : 0;
+  // a chip too large to be resident is refused before anything is launched
+  rc = plan_groups(chip_at, n, limit, [](const sim_launch_group&) {});
+  if (rc) return rc;
+  // every entry the launches read is written here; nothing in the array needs clearing
+  rc = write_table(
+      table, chip_at, [&first](int i) { return first[i]; },
+      [chips, cycles](int i) { return (int)(chips[i]->cycle + cycles[i]); }, n, s);
+  if (rc) return rc;
+  int launch_rc = SIM_OK;
+  rc = plan_groups(chip_at, n, limit, [&](const sim_launch_group& lg) {
+    if (launch_rc) return;
+    int64_t lg_longest = 0;
+    for (int i = lg.first_chip; i < lg.first_chip + lg.n_chips; ++i) lg_longest = std::max(lg_longest, cycles[i]);
+    const int launches = (int)((lg_longest + chunk - 1) / chunk);
+    for (int l = 0; l < launches && !launch_rc; ++l)
+      launch_rc = launch_entries(table + lg.first_entry, lg.n_entries, lg.multi, k.fast, blk, chunk, nullptr, 0, s, k.opt,
+                                 k.var);
+  });
+  if (rc) return rc;
+  if (launch_rc) return launch_rc;
+  for (int i = 0; i < n; ++i) chips[i]->cycle += cycles[i];
+  int32_t errs[NOALLOC_MAX_CHIPS];
+  return gather_status(err_dev, errs, chip_at, n, s);
 }
 
 }  // extern "C"

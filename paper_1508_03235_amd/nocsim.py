@@ -96,6 +96,7 @@ def _lib():
             "simb_set_graph": (i32, [p, i32]),
             "simb_step": (i32, [p, p]),
             "simb_destroy": (i32, [p]),
+            "simb_step_noalloc": (i32, [p, i32, i32, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -111,7 +112,7 @@ def exported_symbols():
             "sim_dump_words", "sim_dump", "sim_load", "sim_force_op", "sim_force_bg",
             "sim_set_rates", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
             "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_add", "simb_remove", "simb_slots",
-            "simb_stats", "simb_set_graph", "simb_step", "simb_destroy"]
+            "simb_stats", "simb_set_graph", "simb_step", "simb_destroy", "simb_step_noalloc"]
 
 
 def _check(fn, rc):
@@ -319,3 +320,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def step_noalloc(sims, cycles, block: int = 0, stream=None):
+    """Advances sims[i] by cycles[i] cycles in one batched step that allocates no device memory
+    (the library's static launch table; see simb_step_noalloc)."""
+    n = len(sims)
+    arr = (C.c_void_p * max(n, 1))(*[s.handle.value for s in sims])
+    c = np.ascontiguousarray(np.broadcast_to(np.asarray(cycles, dtype=np.int64), (max(n, 1),)))
+    _check("simb_step_noalloc", _lib().simb_step_noalloc(arr, n, block, c.ctypes.data_as(C.c_void_p),
+                                                         _stream_handle(stream)))
