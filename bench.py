@@ -10,8 +10,12 @@ Besides the headline line the JSON carries:
   roofline     - algorithmic bytes per launch of the step kernel / its measured duration,
                  against the 8 TB/s HBM peak;
   cpu_baseline - the serial oracle on the host, on a bounded prefix of the same workload;
-  parity       - per-cycle state digests of the GPU run compared with the oracle on that
-                 prefix;
+  parity       - per-cycle state digests of a GPU run compared with the oracle on that
+                 prefix, and the timed chip's own final state compared with the oracle's state
+                 after the same cycles (stored oracle runs); `checked` is true only when the
+                 latter matched;
+  oracle_configs - the serial oracle timed on every workload configuration (one pinned host
+                 thread each) and on all host CPUs at once for configs 2 and 3;
   sweep        - per-rate throughput and the sweep's outputs (deflection rate, average
                  latency, L2 hit rate) (skip with --no-sweep);
   packets      - the same chip with replies of 4 flits (the paper's Table 1, remote L2 access):
@@ -116,19 +120,122 @@ def profiled_traffic(kernel_tag):
     return int(m_b.group(1))
 
 
+def host_cpu():
+    """Host CPU description: logical CPUs the process may use, and the model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count(), "model": model}
+
+
+class pinned:
+    """Pins the calling thread to one host CPU for the duration of a with-block."""
+
+    def __init__(self, cpu=None):
+        self.cpu = cpu
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0)
+        cpu = self.cpu if self.cpu is not None else min(self.saved)
+        os.sched_setaffinity(0, {cpu})
+        return cpu
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.saved)
+
+
 def cpu_baseline(p, budget_s=12.0):
     from oracle import oracle as O
+    O.build()
+    o = O.OracleSim(p)
+    with pinned() as cpu:
+        t0 = time.perf_counter()
+        n = 0
+        digests = []
+        while time.perf_counter() - t0 < budget_s:
+            digests.append(o.step(50, digests=True))
+            n += 50
+        dt = time.perf_counter() - t0
+    o.close()
+    host = host_cpu()
+    return {"value": p.tiles * n / dt, "unit": "tile-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{p.width}x{p.height} chip, first {n} cycles of the benchmark workload, "
+                      f"serial C oracle (gcc -O3), one host thread pinned to CPU {cpu}, {dt:.1f} s",
+            "host": host}, np.concatenate(digests)
+
+
+def _oracle_worker(task):
+    """(params dict, seconds, cpu) -> (tile-cycles, seconds): the oracle on one pinned CPU."""
+    pd, budget, cpu = task
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as O
+    from paper_1508_03235_amd.workload import SimParams
+    if cpu is not None:
+        os.sched_setaffinity(0, {cpu})
+    p = SimParams(**pd)
     o = O.OracleSim(p)
     t0 = time.perf_counter()
     n = 0
-    digests = []
-    while time.perf_counter() - t0 < budget_s:
-        digests.append(o.step(50, digests=True))
-        n += 50
+    step = max(1, min(1000, int(2e6 // p.tiles)))
+    while time.perf_counter() - t0 < budget:
+        o.step(step)
+        n += step
     dt = time.perf_counter() - t0
-    return {"value": p.tiles * n / dt, "unit": "tile-cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{p.width}x{p.height} chip, first {n} cycles of the benchmark workload, "
-                      f"serial C oracle (gcc -O2), one host thread, {dt:.1f} s"}, np.concatenate(digests)
+    o.close()
+    return p.tiles * n, dt
+
+
+def oracle_configs(W, budget=2.0, max_procs=16):
+    """The serial oracle on every workload configuration: one pinned host thread per config
+    (bounded samples of `budget` seconds), and for the multi-run configurations (config 2's five
+    rates, config 3's instances) independent oracle processes on all host CPUs at once (at most
+    `max_procs`), reported as their aggregate tile-cycles/s."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.build()
+    cpus = sorted(os.sched_getaffinity(0))
+    procs = min(len(cpus), max_procs)
+    c3 = W.config3()
+    jobs = W.config4(60)
+    single = {"config0": W.config0(), "config1": W.config1(), "config2_0.05": W.config2(0.05),
+              "config3_instance0": c3[0], "config4_job0": jobs[0].params}
+    out = {"host": host_cpu(), "budget_s_per_sample": budget, "single_core": {}, "all_core": {}}
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        for name, p in single.items():
+            tc, dt = pool.apply(_oracle_worker, ((p.as_dict(), budget, cpus[0]),))
+            out["single_core"][name] = {"tiles": p.tiles, "tile_cycles_per_s": tc / dt}
+        for name, plist in (("config2_five_rates", [W.config2(r) for r in W.CONFIG2_RATES]),
+                            ("config3_instances", c3[:procs])):
+            tasks = [(q.as_dict(), budget, cpus[i % len(cpus)]) for i, q in enumerate(plist[:procs])]
+            res = pool.map(_oracle_worker, tasks)
+            out["all_core"][name] = {"processes": len(tasks),
+                                     "tile_cycles_per_s": sum(tc / dt for tc, dt in res)}
+    return out
+
+
+def timed_run_check(sim, p, rate):
+    """The timed chip's own state at the end of the timed region against the oracle's state after
+    the same number of cycles (stored by tests/golden/make_goldens.py, which runs the oracle only)."""
+    path = os.path.join(ROOT, "tests", "golden", "full_runs.json")
+    if not os.path.exists(path):
+        return {"checked": False, "reason": "no stored oracle runs"}
+    with open(path) as f:
+        run = json.load(f)["runs"].get(f"config2_{rate}")
+    if run is None or run["params"] != p.as_dict():
+        return {"checked": False, "reason": "no stored oracle run of this workload"}
+    key = str(sim.cycle)
+    if key not in run["dumps"]:
+        return {"checked": False, "reason": f"no stored oracle state after {key} cycles"}
+    import xxhash
+    h = xxhash.xxh3_128_hexdigest(memoryview(np.ascontiguousarray(sim.dump().astype("<i4"))))
+    return {"checked": True, "cycles": sim.cycle, "state_equal_oracle": h == run["dumps"][key]}
 
 
 def run_sweep(nocsim, W, torch, cycles):
@@ -297,6 +404,7 @@ def main():
     ap.add_argument("--rate", type=float, default=0.05)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-oracle-configs", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-packets", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -324,8 +432,18 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    from paper_1508_03235_amd import workload as W
+    # oracle timings in worker processes first: started before this process touches the GPU
+    oc = None
+    if not args.no_cpu and not args.no_oracle_configs:
+        try:
+            oc = oracle_configs(W)
+        except Exception as e:
+            oc = {"error": repr(e)}
+        print("# oracle timings done", file=sys.stderr, flush=True)
+
     import torch
-    from paper_1508_03235_amd import nocsim, workload as W
+    from paper_1508_03235_amd import nocsim
 
     torch.cuda.set_device(0)
     p = W.config2(args.rate)
@@ -362,6 +480,9 @@ def main():
     st = sim.stats() - st0
     cycles = args.steps * CYCLES_PER_STEP
     value = p.tiles * cycles / dt
+    # the timed run itself, checked against the oracle after the same cycles
+    timed_check = timed_run_check(sim, p, args.rate)
+    print(f"# timed run vs oracle: {timed_check}", file=sys.stderr, flush=True)
 
     # roofline of the step kernel: event-timed launches on the chip's stream
     ms_launch, launches = kernel_events_ms(sim, 2 * chunk, torch)
@@ -391,13 +512,19 @@ def main():
                    "launch": {"patch": [pw, ph], "block": block, "chunk": chunk}},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "parity": parity,
+        "parity": {"prefix_digests": parity, "timed_run": timed_check},
+        "checked": bool(timed_check.get("state_equal_oracle", False)),
         "run": {"deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
                 "avg_latency": float((st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]) / max(1, ej)),
                 "l2_hit_rate": float(st[S["l2_hit"]] / max(1, st[S["l2_hit"]] + st[S["l2_miss"]]))},
     }
     if cpu:
         out["gpu_over_oracle"] = value / cpu["value"]
+    if oc is not None:
+        if "error" not in oc:
+            oc["gpu_over_oracle_single_core"] = value / oc["single_core"]["config2_0.05"]["tile_cycles_per_s"]
+            oc["gpu_over_oracle_all_core_config2"] = value / oc["all_core"]["config2_five_rates"]["tile_cycles_per_s"]
+        out["oracle_configs"] = oc
     if not args.no_sweep:
         try:
             out["sweep"] = run_sweep(nocsim, W, torch, 5000)

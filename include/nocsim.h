@@ -135,6 +135,14 @@ typedef struct sim_group simb_t;  /* many chips advanced by one launch */
    included. */
 size_t sim_state_bytes(const sim_config* cfg);
 
+/* The reciprocal constants the kernels divide by instead of a divide instruction (host-only,
+   touches no device): out[0] = ceil(2^32 / width), so that tile / width = umulhi(tile, out[0])
+   for tile < 2^20 (0 when width = 1); out[2], out[3] = ceil(2^(32+k) / tiles) and k =
+   floor(log2 tiles) - 1, so that line / tiles = umulhi(line, out[2]) >> k for line < 2^30, which
+   gives a line's home (line mod tiles) and its L2 set ((line / tiles) mod l2_sets) (0, 0 when
+   tiles = 1); out[1] = 0.  EINVAL for width or tiles < 1. */
+int sim_div_constants(int32_t width, int32_t tiles, uint32_t* out);
+
 /* Creates one chip in `dev_mem` and initialises it (all links empty, cores idle, caches
    invalid, cycle 0).  zipf_shared / zipf_private: host arrays of zipf_k + 1 (= 65537)
    uint32 quantile boundaries (entry b = first rank whose CDF exceeds b/zipf_k; entry
@@ -178,9 +186,9 @@ int sim_stats(sim_t* h, sim_stats_t* out);
    sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);
-/* Restores a canonical state produced by sim_dump (checkpoint / resume).  EINVAL when the
-   header does not match the chip (shape, caches, reply_flits, flags) or a word is out of
-   range. */
+/* Restores a canonical state produced by sim_dump (checkpoint / resume) and clears an error
+   recorded by an earlier step (the state it belonged to is replaced).  EINVAL when the header
+   does not match the chip (shape, caches, reply_flits, flags) or a word is out of range. */
 int sim_load(sim_t* h, const int32_t* host_buf, size_t words);
 
 /* Test hooks (synchronise): make `tile` issue a memory op on `line` at its next idle cycle;
@@ -189,9 +197,18 @@ int sim_force_op(sim_t* h, int32_t tile, int32_t line);
 int sim_force_bg(sim_t* h, int32_t tile, int32_t dst);
 /* Changes the op-issue and background thresholds from the next step on (0, 0 = drain). */
 int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr);
+/* Test hook for the time-out path (the behaviour of a stuck workgroup, forced from the host):
+   patch `patch` (0 .. patches-1 of the current launch mapping; -1 = none) advances no further
+   than cycle `cycle`, and a wait for a neighbouring patch's link slot gives up after `polls`
+   polls (0 = the default, 2^25).  A wait that gives up records a hang in the chip's error word
+   and ends its workgroup's launch; waiting neighbours see the error word and stop too, so every
+   workgroup exits normally and sim_sync / sim_stats report SIM_EHANG.  The chip's state is then
+   invalid until sim_load (which clears the error; call with patch -1 first). */
+int sim_force_hang(sim_t* h, int32_t patch, int32_t cycle, int32_t polls);
 
-/* Launch mapping: patch_w x patch_h tiles per workgroup (the chip is cut into patches that
-   exchange boundary links through per-patch cycle flags), `block` threads per workgroup (64..256, a multiple of 64),
+/* Launch mapping: patch_w x patch_h tiles per workgroup (the chip is cut into patches; a tile
+   on a patch edge waits for its neighbour's link slot to carry the cycle it needs, so patches
+   synchronise with their neighbours only), `block` threads per workgroup (64..256, a multiple of 64),
    `chunk` cycles per launch.  0 keeps the current value.  EINVAL if the patch grid cannot
    be resident on the device at once.  sim_create's default: one workgroup for chips of at
    most 1,024 tiles; for chips up to 256 columns one row per workgroup of 64 or 128 threads

@@ -8,17 +8,20 @@
 // ejection and injection.
 //
 // GPU design (not the paper's three kernels per cycle): one persistent launch runs many
-// cycles.  A chip is cut into rectangular patches, one workgroup per patch; a workgroup
-// steps its tiles, then publishes the number of cycles it has completed in a per-patch flag.
-// Before cycle c it waits only for its (up to four) neighbouring patches to have completed c
-// cycles, because the only state crossing a patch edge within a cycle is a link slot.  A chip
-// that fits one workgroup needs no flags at all.  State is structure-of-arrays int32 in HBM:
+// cycles.  A chip is cut into rectangular patches, one workgroup per patch.  The only state
+// crossing a patch edge within a cycle is a link slot, so workgroups synchronise with their
+// (up to four) neighbouring patches only, through the slots themselves: every slot word
+// carries the cycle it is an input of (a stamp), and a tile on a patch edge polls its
+// neighbour's slot until it holds the cycle it needs.  A per-patch flag records the cycles a
+// patch has completed, written at the end of a launch (the next launch starts from it).  A
+// chip that fits one workgroup needs no cross-workgroup synchronisation at all.  State is structure-of-arrays int32 in HBM:
 // link slots double-buffered by cycle parity, core words, reply-queue nodes, L1/L2 tag sets
 // stored most-recently-used first (a set is one or two 16-byte vectors).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -83,6 +86,8 @@ struct ChipDev {
   int32_t mig;               // migration threshold (0 = none)
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
+  int32_t spin_limit;        // polls before a cross-workgroup wait gives up (reports a hang)
+  int32_t halt_patch, halt_cycle;  // test hook: this patch advances no further than halt_cycle
   int4* link;                // [2 parity][4 port][N]
   int4* pipe;                // [D-1][4 port][N]: raw slot words of flits waiting in the routers'
                              // pipelines; entry (a mod (D-1)) holds those arbitrated in cycle a
@@ -438,7 +443,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       const bool p0 = e0 && !slot_has_stamp(w0, (uint32_t)c), p1 = e1 && !slot_has_stamp(w1, (uint32_t)c);
       const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
       if (!(p0 | p1 | p2 | p3)) break;
-      if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
+      if ((++spins & 63) == 0 && (spins > C.spin_limit || ld_coh(C.err))) {
         note_hang(C.err);
         return false;
       }
@@ -1232,7 +1237,7 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
   if (threadIdx.x == 0) s_fail = 0;
   Acc acc = {};
   const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
-  const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
+  const int c_end = max(c0, min(min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop), patch == C.halt_patch ? C.halt_cycle : INT_MAX));
   int c_done = c0;
   __syncthreads();
 
@@ -1438,7 +1443,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   s_link[1][5][j] = EMPTY;
   Acc acc = {};
   const int c0 = ld_coh(&C.flags[patch * FLAG_STRIDE]);
-  const int c_end = min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop);
+  const int c_end = max(c0, min(min(c0 + chunk, e.stop >= 0 ? e.stop : C.stop), patch == C.halt_patch ? C.halt_cycle : INT_MAX));
   int c_done = c0;
   // pipeline entry of the current cycle (cycle mod (D-1)): the flits it holds leave this cycle,
   // and this cycle's arrivals take their place
@@ -1633,7 +1638,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           const bool p0 = e0 && !slot_has_stamp(w0, (uint32_t)c), p1 = e1 && !slot_has_stamp(w1, (uint32_t)c);
           const bool p2 = e2 && !slot_has_stamp(w2, (uint32_t)c), p3 = e3 && !slot_has_stamp(w3, (uint32_t)c);
           if (!(p0 | p1 | p2 | p3)) break;
-          if ((++spins & 63) == 0 && (spins > SPIN_LIMIT || ld_coh(C.err))) {
+          if ((++spins & 63) == 0 && (spins > C.spin_limit || ld_coh(C.err))) {
             note_hang(C.err);
             ok = false;
             break;
@@ -2294,6 +2299,23 @@ const char* sim_strerror(int code) {
 
 int sim_last_hip_error(void) { return g_last_hip; }
 
+int sim_div_constants(int32_t width, int32_t tiles, uint32_t* out) {
+  if (!out || width < 1 || tiles < 1) return SIM_EINVAL;
+  // tile / W = umulhi(tile, ceil(2^32 / W)) for tile < 2^20
+  out[0] = width > 1 ? (uint32_t)((0x100000000ull + (uint64_t)width - 1) / (uint64_t)width) : 0u;
+  out[1] = 0;
+  if (tiles > 1) {
+    // line / N = umulhi(line, ceil(2^(32+k) / N)) >> k for line < 2^30, k = floor(log2 N) - 1
+    const int k = 30 - __builtin_clz((unsigned)tiles);
+    out[2] = (uint32_t)(((1ull << (32 + k)) + (uint64_t)tiles - 1) / (uint64_t)tiles);
+    out[3] = (uint32_t)k;
+  } else {
+    out[2] = 0;
+    out[3] = 0;
+  }
+  return SIM_OK;
+}
+
 size_t sim_state_bytes(const sim_config* cfg) {
   if (!config_ok(cfg)) return 0;
   return layout(cfg).total;
@@ -2327,15 +2349,16 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   d.op_thr = cfg->op_thr;
   d.shared_thr = cfg->shared_thr;
   d.bg_thr = cfg->bg_thr;
-  d.w_magic = cfg->width > 1 ? (uint32_t)((0x100000000ull + cfg->width - 1) / cfg->width) : 0u;
-  if (N > 1) {
-    const int k = 30 - __builtin_clz((unsigned)N);  // floor(log2 N) - 1
-    d.n_shift = (uint32_t)k;
-    d.n_magic = (uint32_t)(((1ull << (32 + k)) + (uint64_t)N - 1) / (uint64_t)N);
-  } else {
-    d.n_shift = 0;
-    d.n_magic = 0;
+  {
+    uint32_t dc[4];
+    sim_div_constants(cfg->width, N, dc);
+    d.w_magic = dc[0];
+    d.n_magic = dc[2];
+    d.n_shift = dc[3];
   }
+  d.spin_limit = SPIN_LIMIT;
+  d.halt_patch = -1;
+  d.halt_cycle = 0;
   d.w1_shift = __builtin_ctz((unsigned)cfg->l1_ways);
   d.w2_shift = __builtin_ctz((unsigned)cfg->l2_ways);
   d.s1 = cfg->l1_sets;
@@ -2622,6 +2645,8 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     HIPCHECK(hipMemcpyAsync(h->hd.l2h, locw + h->hd.lines, N * h->hd.s2 * h->hd.w2 * 4, hipMemcpyHostToDevice, h->stream));
   h->cycle = cyc;
   if ((rc = launch_grid_fill_i32(h->hd.flags, (int32_t)cyc, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream))) return rc;
+  // the restored state is whole: an error recorded for the state it replaces no longer applies
+  if ((rc = launch_grid_fill_i32(h->hd.err, 0, 1, h->stream))) return rc;
   HIPCHECK(hipStreamSynchronize(h->stream));
   return SIM_OK;
 }
@@ -2644,6 +2669,14 @@ int sim_force_bg(sim_t* h, int32_t tile, int32_t dst) {
                           hipMemcpyHostToDevice, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   return SIM_OK;
+}
+
+int sim_force_hang(sim_t* h, int32_t patch, int32_t cycle, int32_t polls) {
+  if (!h || polls < 0 || patch < -1 || patch >= h->hd.n_patches || cycle < 0) return SIM_EINVAL;
+  h->hd.spin_limit = polls ? polls : SPIN_LIMIT;
+  h->hd.halt_patch = patch;
+  h->hd.halt_cycle = cycle;
+  return upload_desc(h);
 }
 
 int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr) {

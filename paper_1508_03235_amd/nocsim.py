@@ -70,6 +70,7 @@ def _lib():
         p, i32, i64, u32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_size_t
         sig = {
             "sim_state_bytes": (sz, [C.POINTER(SimConfig)]),
+            "sim_div_constants": (i32, [i32, i32, p]),
             "sim_create": (i32, [C.POINTER(SimConfig), p, p, i32, p, sz, p, C.POINTER(p)]),
             "sim_step": (i32, [p, i64, p]),
             "sim_sync": (i32, [p]),
@@ -81,6 +82,7 @@ def _lib():
             "sim_force_op": (i32, [p, i32, i32]),
             "sim_force_bg": (i32, [p, i32, i32]),
             "sim_set_rates": (i32, [p, u32, u32]),
+            "sim_force_hang": (i32, [p, i32, i32, i32]),
             "sim_set_launch": (i32, [p, i32, i32, i32, i32]),
             "sim_get_launch": (i32, [p, p, p, p, p]),
             "sim_set_kernel": (i32, [p, i32]),
@@ -108,9 +110,9 @@ def _lib():
 
 def exported_symbols():
     """Names of the functions the library must export (checked by the CPU tests)."""
-    return ["sim_state_bytes", "sim_create", "sim_step", "sim_sync", "sim_cycle", "sim_stats",
+    return ["sim_state_bytes", "sim_div_constants", "sim_create", "sim_step", "sim_sync", "sim_cycle", "sim_stats",
             "sim_dump_words", "sim_dump", "sim_load", "sim_force_op", "sim_force_bg",
-            "sim_set_rates", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
+            "sim_set_rates", "sim_force_hang", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
             "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_add", "simb_remove", "simb_slots",
             "simb_stats", "simb_set_graph", "simb_step", "simb_destroy", "simb_step_noalloc"]
 
@@ -124,6 +126,13 @@ def _stream_handle(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def div_constants(width: int, tiles: int) -> np.ndarray:
+    """The kernels' reciprocal constants for tile / width and line / tiles (sim_div_constants)."""
+    out = np.zeros(4, dtype=np.uint32)
+    _check("sim_div_constants", _lib().sim_div_constants(width, tiles, out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def state_bytes(params) -> int:
@@ -222,6 +231,9 @@ class Sim:
 
     def set_rates(self, op_thr: int, bg_thr: int):
         _check("sim_set_rates", _lib().sim_set_rates(self._h, op_thr, bg_thr))
+
+    def force_hang(self, patch: int, cycle: int, polls: int):
+        _check("sim_force_hang", _lib().sim_force_hang(self._h, patch, cycle, polls))
 
     def set_launch(self, patch_w=0, patch_h=0, block=0, chunk=0):
         _check("sim_set_launch", _lib().sim_set_launch(self._h, patch_w, patch_h, block, chunk))
