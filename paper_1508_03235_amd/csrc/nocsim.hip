@@ -243,7 +243,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     const unsigned long long p0 = (unsigned long long)0xD2511F53u * c0, p1 = (unsigned long long)0xCD9E8D57u * c2;
     const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
     const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    // three-input exclusive or in one instruction (gfx950 bitop3, truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96), n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
     c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
   }
   return make_uint4(c0, c1, c2, c3);
@@ -1291,32 +1292,42 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
 //    finishes cycle c+1, while its next writer is at least three cycles of flit traffic away.
 constexpr int FAST_MAX = 256;
 
-// Port of one flit, oldest first, without branches (the one-tile-per-thread kernel): eject if
-// destined here and free, else the first free productive port (X before Y), else the lowest
-// free port.  `key` is the flit's
-// priority key (inject cycle, then source, then its input index in the low 3 bits; all ones for
-// an empty input), `dst` its destination (negative when empty).  Records the flit's input index
-// at bits 3*port of `inv` (the flit each output port carries; 7 = none).
-template <bool DEFL_MASK>  // also record the deflected flits in `dm`
-__device__ __forceinline__ void arb_assign_sel(unsigned long long key, int dst, int t, int x, int y, const ChipDev& C,
-                                               unsigned valid, unsigned& used, uint32_t& inv, unsigned& dm, Acc& acc) {
-  const bool live = dst >= 0;
-  const unsigned idx = (unsigned)key & 7u;
-  const unsigned fr = ~used;
-  const bool ej = dst == t && (fr & 16u);
-  const int drow = C.W > 1 ? (int)__umulhi((uint32_t)dst, C.w_magic) : dst;
-  const int dx = (dst - (int)__umul24((uint32_t)drow, (uint32_t)C.W)) - x, dy = drow - y;  // both < 2^20
-  const unsigned px = dx > 0 ? 2u : 3u, py = dy > 0 ? 1u : 0u;
-  const bool okx = dx != 0 && ((fr >> px) & 1u);
-  const bool oky = dy != 0 && ((fr >> py) & 1u);
-  const unsigned dfl = (unsigned)__builtin_ctz((valid & fr & 15u) | 128u);  // 7 = none (cannot happen)
-  const unsigned port = ej ? 4u : (okx ? px : (oky ? py : dfl));
-  const bool moved = live && !ej;
-  acc.trav += moved;
-  acc.defl += moved && !okx && !oky;
-  if (DEFL_MASK) dm |= (moved && !okx && !oky) ? (1u << idx) : 0u;  // deflected: bit of its input index
+// Productive ports of a flit with destination d at the tile (x, y): bit p for each output port
+// p that brings it closer (0 north, 1 south, 2 east, 3 west), or bit 4 alone when d is the tile
+// itself.  The destination's row is d / W by the reciprocal (wm = ceil(2^32 / W)); with W = 1,
+// wm = 0 and wsel = ~0 make the row d itself.
+__device__ __forceinline__ uint32_t prod_mask(int d, int x, int y, int W, uint32_t wm, uint32_t wsel) {
+  const int drow = (int)(__umulhi((uint32_t)d, wm) | ((uint32_t)d & wsel));
+  const int dx = d - drow * W - x, dy = drow - y;
+  const int sx = min(max(dx, -1), 1), sy = min(max(dy, -1), 1);
+  // nibble tables indexed by sign + 1: west / none / east, north / none / south
+  const uint32_t mxy = ((0x408u >> (4 * (sx + 1))) | (0x201u >> (4 * (sy + 1)))) & 15u;
+  return mxy ? mxy : 16u;
+}
+
+// One step of the oldest-first assignment, for the flit with sort key q (prod_mask at bits 3-7,
+// input index i as i ^ 7 at bits 0-2; all ones when empty): the eject port if it is destined
+// here and the port is free, else its X-productive port, else its Y-productive port, if free,
+// else the lowest free valid port (a deflection; a destined flit that lost the eject port is
+// deflected too).  Marks the port in `used` (bit 4 = eject) and records the flit's input index
+// in the port's 3-bit field of `inv`, which starts as all 7s (none).  ndefl counts deflections;
+// with DEFL_MASK the deflected flits' input indices are marked in `dm`.
+template <bool DEFL_MASK>
+__device__ __forceinline__ void arb_assign_mask(unsigned long long q, unsigned valid, unsigned& used, uint32_t& inv,
+                                                unsigned& dm, int& ndefl) {
+  const uint32_t lo = (uint32_t)q;
+  const bool live = (uint32_t)(q >> 32) != 0xFFFFFFFFu;  // inject cycles stay below 2^31
+  const uint32_t a = (lo >> 3) & 31u & ~used;
+  const uint32_t ax = a & 12u, ay = a & 3u;
+  uint32_t sel = ay ? ay : (valid & ~used);
+  sel = ax ? ax : sel;
+  sel = (a & 16u) ? 16u : sel;
+  const uint32_t port = (uint32_t)__builtin_ctz(sel | 32u);  // sel != 0 for a live flit
   used |= live ? (1u << port) : 0u;
-  inv = live ? ((inv & ~(7u << (3 * port))) | (idx << (3 * port))) : inv;
+  inv ^= live ? ((lo & 7u) << (3u * port)) : 0u;
+  const bool defl = live && a == 0u;
+  ndefl += defl ? 1 : 0;
+  if (DEFL_MASK) dm |= defl ? (1u << ((lo & 7u) ^ 7u)) : 0u;
 }
 
 constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;
@@ -1414,6 +1425,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const bool aged = VARS && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
   const bool hum = VARS && (C.variants & SIM_FLAG_HIT_UNDER_MISS) != 0;  // ops drawn under a miss
   const int rd = PIPE ? C.rdelay : 1;  // router delay D: arrivals wait D-1 cycles in a pipeline
+  const uint32_t wsel = C.W > 1 ? 0u : ~0u;  // prod_mask's row when the chip is one column wide
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1768,19 +1780,21 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             acc.inj_bg++;
           }
         }
-        // sort keys: (inject cycle, source) with the input index in the low 3 bits (sources
-        // take 20 bits), all ones for an empty input; the destination rides along
+        // sort keys: (inject cycle, source), then the flit's productive ports as a 5-bit mask
+        // (prod_mask) and its input index i as i ^ 7 in the low 8 bits (sources take 20 bits;
+        // (inject cycle, source) is unique per flit, so the low bits never decide the order);
+        // all ones for an empty input, which sorts last
         typedef unsigned long long u64;
         // (with deflection counts, the source and destination words carry the count in bits
         // 20-27, masked off here; the count itself is a first key word, most deflected first)
 #define SRCW(f) (VARS ? ((uint32_t)(f).z & TILE_BITS_MASK) : (uint32_t)(f).z)
-#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)SRCW(f) << 3) | (i##ull)))
+#define DSTW(f) (VARS ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
+#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)SRCW(f) << 8) | \
+                                          ((u64)prod_mask(DSTW(f), x, y, C.W, C.w_magic, wsel) << 3) | (u64)((i) ^ 7)))
         u64 q0 = SKEY(f0, 0), q1 = SKEY(f1, 1), q2 = SKEY(f2, 2), q3 = SKEY(f3, 3), q4 = SKEY(fi, 4);
 #undef SKEY
-#undef SRCW
-#define DSTW(f) (VARS && (f).x >= 0 ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
-        int sd0 = DSTW(f0), sd1 = DSTW(f1), sd2 = DSTW(f2), sd3 = DSTW(f3), sd4 = fi.x;
 #undef DSTW
+#undef SRCW
 #define AKEY(f) ((f).x < 0 ? ~0u : (uint32_t)AGE_MAX - row_age(f))
         uint32_t ak0 = 0, ak1 = 0, ak2 = 0, ak3 = 0, ak4 = 0;
         if (aged) { ak0 = AKEY(f0); ak1 = AKEY(f1); ak2 = AKEY(f2); ak3 = AKEY(f3); ak4 = AKEY(fi); }
@@ -1789,8 +1803,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   {                                                                            \
     const bool sw = VARS ? (ak##b < ak##a || (ak##b == ak##a && q##b < q##a)) : q##b < q##a; \
     const u64 qa = sw ? q##b : q##a, qb = sw ? q##a : q##b;                    \
-    const int da = sw ? sd##b : sd##a, db = sw ? sd##a : sd##b;                \
-    q##a = qa; q##b = qb; sd##a = da; sd##b = db;                              \
+    q##a = qa; q##b = qb;                                                      \
     if (VARS) { const uint32_t xa = sw ? ak##b : ak##a, xb = sw ? ak##a : ak##b; ak##a = xa; ak##b = xb; } \
   }
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
@@ -1799,11 +1812,17 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
         unsigned used = 0, dm = 0;
         uint32_t inv = 0x7FFFu;
-        arb_assign_sel<VARS>(q0, sd0, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<VARS>(q1, sd1, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<VARS>(q2, sd2, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<VARS>(q3, sd3, t, x, y, C, valid, used, inv, dm, acc);
-        arb_assign_sel<VARS>(q4, sd4, t, x, y, C, valid, used, inv, dm, acc);
+        int ndefl = 0;
+        arb_assign_mask<VARS>(q0, valid, used, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q1, valid, used, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q2, valid, used, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q3, valid, used, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q4, valid, used, inv, dm, ndefl);
+        {  // every live flit moves over a link except the one ejected
+          const int nlive = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0) + (fi.x >= 0);
+          acc.trav += nlive - (int)((used >> 4) & 1u);
+          acc.defl += ndefl;
+        }
 
         if (PIPE && rd > 1) {  // this cycle's arrivals enter the pipeline (stamped, as on the links)
           int4* pq = &C.pipe[(size_t)pe * 4 * N + t];
