@@ -27,7 +27,9 @@ Besides the headline line the JSON carries:
                  kernel, beside the base model on that kernel, and all but the directory also on
                  the one-tile-per-thread kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
-  batched      - the 256-chip batch in one launch vs chips run one at a time (--no-batched);
+  batched      - the 256-chip batch in one launch per chunk, on the batch autotuner's patch shapes,
+                 vs the same chips run one at a time on the single-chip autotuner's mappings
+                 (--no-batched);
   serving      - Poisson-arriving simulation jobs under continuous batching: p50/p99 job
                  latency and aggregate throughput, against one job at a time (--no-serving).
 """
@@ -337,12 +339,15 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
     return out
 
 
-def run_batched(nocsim, W, torch, cycles, plain_chips):
+def run_batched(nocsim, W, torch, cycles, plain_chips=None):
+    """Config 3: the 256 uneven chips in one batch, each chip shape on the patch shape the batch
+    autotuner picked, against the same chips run one at a time, each on the best single-chip
+    mapping the single-chip autotuner found for its shape (all 256, or the first `plain_chips`)."""
+    from paper_1508_03235_amd import autotune
     params = W.config3()
+    mapping, tuned_rate, trials = autotune.tune_batch(params, block=256, cycles=1000, warmup=200)
     sims = [nocsim.Sim(p) for p in params]
-    for s, p in zip(sims, params):
-        side = min(16, p.width)
-        s.set_launch(side, side, 256, 0)  # patches of <= 256 tiles: one tile per thread
+    autotune.apply_batch_mapping(sims, mapping, block=256)
     b = nocsim.Batch(sims, block=256)
     b.step(10)
     torch.cuda.synchronize()
@@ -351,12 +356,20 @@ def run_batched(nocsim, W, torch, cycles, plain_chips):
     dt = time.perf_counter() - t0
     tiles = sum(p.tiles for p in params)
     batched = tiles * cycles / dt
+    b.close()
     del b, sims
-    # one at a time: the first `plain_chips` chips, each alone with the default single-chip
-    # mapping (patches spread over the device for the larger chips)
+    # one at a time, each chip on its shape's best single-chip mapping
+    best = {}
+    for p in params:
+        key = (p.width, p.height)
+        if key not in best:
+            best[key] = autotune.tune(p, cycles=300, warmup=50, cache_path=None)
+    sample = params if not plain_chips else params[:plain_chips]
     t_plain, tiles_plain = 0.0, 0
-    for p in params[:plain_chips]:
+    for p in sample:
         s = nocsim.Sim(p)
+        pw, ph, blk = best[(p.width, p.height)]
+        s.set_launch(pw, ph, blk, 0)
         s.step(10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -365,9 +378,12 @@ def run_batched(nocsim, W, torch, cycles, plain_chips):
         tiles_plain += p.tiles
         del s
     plain = tiles_plain * cycles / t_plain
+    fmt = lambda m: {f"{w}x{h}": list(v) for (w, h), v in sorted(m.items())}
     return {"chips": len(params), "tiles": tiles, "cycles": cycles,
             "batched_tile_cycles_per_s": batched, "plain_tile_cycles_per_s": plain,
-            "plain_sample_chips": plain_chips, "speedup": batched / plain}
+            "plain_chips": len(sample), "speedup": batched / plain,
+            "batch_mapping_patch": fmt(mapping), "batch_tuner_trials": trials,
+            "plain_mapping_patch_block": fmt(best)}
 
 
 def run_serving(W, n_jobs, one_at_a_time_jobs):
@@ -545,7 +561,7 @@ def main():
             out["variants"] = {"error": repr(e)}
     if not args.no_batched:
         try:
-            out["batched"] = run_batched(nocsim, W, torch, 2000, plain_chips=16)
+            out["batched"] = run_batched(nocsim, W, torch, 2000)
         except Exception as e:
             out["batched"] = {"error": repr(e)}
     if not args.no_serving:

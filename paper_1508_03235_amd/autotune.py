@@ -84,3 +84,82 @@ def tune(params, cycles: int = 300, warmup: int = 50, cache_path: str | None = D
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
     return best
+
+
+def batch_candidates(side_w: int, side_h: int, block: int = 256):
+    """Patch shapes for a chip inside a batch of `block`-thread workgroups (every patch at most
+    `block` tiles, so that the one-tile-per-thread kernel runs it)."""
+    out = []
+    def add(pw, ph):
+        pw, ph = min(pw, side_w), min(ph, side_h)
+        if pw * ph <= block and (pw, ph) not in out:
+            out.append((pw, ph))
+    if side_w * side_h <= block:
+        add(side_w, side_h)
+    for rows in (1, 2, 4):
+        if side_w * rows <= block:
+            add(side_w, rows)
+    for side in (8, 16):
+        add(side, side)
+    add(16, 8)
+    add(8, 16)
+    return out
+
+
+def tune_batch(params_list, block: int = 256, cycles: int = 1000, warmup: int = 200, rounds: int = 1,
+               verbose: bool = False):
+    """Patch shape per chip shape for a batch of the given chips, measured on the device: starting
+    from the largest square-ish patch of at most `block` tiles, each shape's choice is varied in
+    turn (the others fixed) and the one giving the highest tile-cycles/s of the whole batch is
+    kept.  Runs on scratch chips of the same parameters; returns {(width, height): (pw, ph)}."""
+    import torch
+    from paper_1508_03235_amd import nocsim
+    shapes = sorted({(p.width, p.height) for p in params_list})
+    choice = {s: batch_candidates(*s, block)[0] for s in shapes}
+    for s in shapes:  # start from 16x16 (or the whole chip) where it is a candidate
+        c = batch_candidates(*s, block)
+        choice[s] = (min(16, s[0]), min(16, s[1])) if (min(16, s[0]), min(16, s[1])) in c else c[0]
+    sims = [nocsim.Sim(p) for p in params_list]
+    tiles = sum(p.tiles for p in params_list)
+
+    def measure():
+        for sim, p in zip(sims, params_list):
+            pw, ph = choice[(p.width, p.height)]
+            sim.set_launch(pw, ph, block, 0)
+        b = nocsim.Batch(sims, block=block)
+        b.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(cycles)
+        dt = time.perf_counter() - t0
+        b.close()
+        return tiles * cycles / dt
+
+    best = measure()
+    trials = [(dict(choice), best)]
+    for _ in range(rounds):
+        for s in shapes:
+            keep = choice[s]
+            for cand in batch_candidates(*s, block):
+                if cand == keep:
+                    continue
+                choice[s] = cand
+                try:
+                    v = measure()
+                except nocsim.SimError:
+                    continue
+                trials.append((dict(choice), v))
+                if verbose:
+                    print(f"  {s} -> {cand}: {v:.3e} tile-cycles/s")
+                if v > best:
+                    best, keep = v, cand
+            choice[s] = keep
+    del sims
+    return dict(choice), best, len(trials)
+
+
+def apply_batch_mapping(sims, mapping, block: int = 256, chunk: int = 0):
+    """Sets every chip's launch mapping to the tuned patch shape of its chip shape."""
+    for s in sims:
+        pw, ph = mapping[(s.params.width, s.params.height)]
+        s.set_launch(pw, ph, block, chunk)

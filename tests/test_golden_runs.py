@@ -165,3 +165,22 @@ def test_config4_sampled_jobs_full_length():
     for k, s in zip(keys, sims):
         assert s.cycle == g[k]["cycles"]
         assert h128(s.dump().astype("<i4")) == g[k]["dumps"][str(g[k]["cycles"])], k
+
+
+@pytest.mark.gpu
+def test_config3_batch_full_length_on_tuned_mapping():
+    """The batch autotuner's patch shapes (as the benchmark times the batch): all 256 instances,
+    20,000 cycles, equal to their oracle runs."""
+    from paper_1508_03235_amd import autotune, nocsim
+    g = gold()["runs"]
+    params = W.config3()
+    mapping, rate, trials = autotune.tune_batch(params, block=256, cycles=300, warmup=50)
+    assert trials > 1 and rate > 0
+    assert all(pw * ph <= 256 for pw, ph in mapping.values())
+    sims = [nocsim.Sim(p) for p in params]
+    autotune.apply_batch_mapping(sims, mapping, block=256)
+    b = nocsim.Batch(sims, block=256)
+    b.step(20_000)
+    b.close()
+    bad = [i for i, s in enumerate(sims) if h128(s.dump().astype("<i4")) != g[f"config3_{i}"]["dumps"]["20000"]]
+    assert not bad, f"instances differing from the oracle: {bad[:10]}"
