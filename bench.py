@@ -428,10 +428,20 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=60)
     ap.add_argument("--launch", type=str, default="", help="patch_w,patch_h,block,chunk")
+    ap.add_argument("--maps-out", type=str, default="",
+                    help="at interpreter exit, write this process's /proc/self/maps to the given file "
+                         "(to symbolize addresses a crash report at process exit prints)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (scales the "
                          "profiler's FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.maps_out:
+        import atexit
+
+        def _dump_maps(path=args.maps_out):
+            with open("/proc/self/maps") as src, open(path, "w") as dst:
+                dst.write(src.read())
+        atexit.register(_dump_maps)
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy << 20

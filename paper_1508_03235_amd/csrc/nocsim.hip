@@ -1359,10 +1359,12 @@ __device__ __forceinline__ void draw_ahead(const ChipDev& C, int t, int c, Prefe
 // Issues every load of cycle c that does not depend on its link inputs.  The random words of c
 // and their Zipf words were drawn one cycle earlier (draw_ahead); this draws those of c+1.
 // VARS: `hline` is the op held by hit under miss (-1 for none), `hum` whether the chip has it.
-template <bool MULTI, bool VARS>
+template <bool MULTI, bool VARS, bool W48>
 __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
                                          int hline, bool hum, int* l1_base, int* l2_base, Prefetch& P) {
   const int N = C.N;
+  // way counts, fixed at compile time for 4-way L1 and 8-way L2 slices (W48)
+  const int w1 = W48 ? 4 : C.w1, w2 = W48 ? 8 : C.w2, w1s = W48 ? 2 : C.w1_shift, w2s = W48 ? 3 : C.w2_shift;
   P.r = P.r1;
   const bool svc = k1.x >= 0;
   const bool wake = k0.y == c;
@@ -1377,10 +1379,10 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const bool drawn_hum = VARS && hum && k0.x != CORE_IDLE && !fill && hline < 0 && P.r.x < C.op_thr;
   P.flags = (svc ? PF_SVC : 0u) | (local ? PF_LOCAL : 0u) | (fill ? PF_FILL : 0u) | (forced ? PF_FORCED : 0u) |
             (drawn ? PF_DRAWN : 0u) | (retry ? PF_RETRY : 0u) | (drawn_hum ? PF_HUM : 0u);
-  P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
-  P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << C.w2_shift);
-  if (svc) set_load(P.setR, C.w2, P.vR);
-  if (local) set_load(P.setL, C.w2, P.vL);
+  P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << w2s);
+  P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << w2s);
+  if (svc) set_load(P.setR, w2, P.vR);
+  if (local) set_load(P.setL, w2, P.vL);
   P.nh = make_int4(-1, -1, -1, -1);
   P.nm = make_int4(-1, -1, -1, -1);
   if ((unsigned)k1.z < (unsigned)N) P.nh = ld_node<MULTI>(&C.node[k1.z]);
@@ -1391,8 +1393,8 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const int rank = (int)(P.z_lo + (uint32_t)(((unsigned long long)(P.r.z & 0xFFFFu) * (P.z_hi - P.z_lo)) >> 16));
   const int drawn_line = (priv ? C.shared_lines + t * C.private_lines : 0) + rank;
   P.line_op = retry ? hline : forced ? k2.w : ((drawn || drawn_hum) ? drawn_line : k0.z);
-  P.set1 = l1_base + ((P.line_op & (C.s1 - 1)) << C.w1_shift);
-  if (fill || retry || forced || drawn || drawn_hum) set_load(P.set1, C.w1, P.u);
+  P.set1 = l1_base + ((P.line_op & (C.s1 - 1)) << w1s);
+  if (fill || retry || forced || drawn || drawn_hum) set_load(P.set1, w1, P.u);
   draw_ahead(C, t, c + 1, P);
 }
 
@@ -1405,13 +1407,16 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // cycle enters the network from the next one on, Sec. 6.2.1).  Without the bit they are
 // compiled out.  OPT bit 2 (FAST_PIPE): the chip may have a router delay D > 1 (arrivals wait
 // D-1 cycles in a per-tile pipeline in HBM before they are arbitrated).
-constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4;
+// OPT bit 3 (FAST_WAYS48): every chip of the launch has 4-way L1 and 8-way L2 slices, so the set
+// code is compiled for those way counts instead of reading them from the chip.
+constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
   constexpr bool PACKETS = (OPT & FAST_PACKETS) != 0;
   constexpr bool VARS = (OPT & FAST_VARIANTS) != 0;
   constexpr bool PIPE = (OPT & FAST_PIPE) != 0;
+  constexpr bool W48 = (OPT & FAST_WAYS48) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1496,12 +1501,13 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     }
   }
   // this tile's cache arrays
-  int* const l1_base = C.l1 + (size_t)(active ? t : 0) * (size_t)C.s1 * (size_t)C.w1;
-  int* const l2_base = C.l2 + (size_t)(active ? t : 0) * (size_t)C.s2 * (size_t)C.w2;
+  const int ways1 = W48 ? 4 : C.w1, ways2 = W48 ? 8 : C.w2;  // way counts (compile-time with W48)
+  int* const l1_base = C.l1 + (size_t)(active ? t : 0) * (size_t)C.s1 * (size_t)ways1;
+  int* const l2_base = C.l2 + (size_t)(active ? t : 0) * (size_t)C.s2 * (size_t)ways2;
   Prefetch P;
   if (active) {
     draw_ahead(C, t, c0, P);
-    prefetch<MULTI, VARS>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P);
+    prefetch<MULTI, VARS, W48>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P);
   }
   __syncthreads();
 
@@ -1567,7 +1573,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         // ---- phase one: home L2 service, then the core (Sec. 7.1 phase one; Sec. 3.5) -------
         if (p_svc) {
           const int rq = k1.x, line = k1.y;
-          const bool hit = set_touch(P.vR, C.w2, line, true, dirtyR);
+          const bool hit = set_touch(P.vR, ways2, line, true, dirtyR);
           acc.l2_hit += hit;
           acc.l2_miss += !hit;
           node_rq = rq;
@@ -1587,7 +1593,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k1.y = -1;
         }
         if (p_fill) {
-          set_touch(P.u, C.w1, P.line_op, true, dirty1);
+          set_touch(P.u, ways1, P.line_op, true, dirty1);
           const int lat = c - k0.w;
           acc.ops_done++;
           acc.op_lat += (unsigned long long)lat;
@@ -1599,7 +1605,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 #pragma unroll
               for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
             }
-            const bool hit = set_touch(P.vL, C.w2, k0.z, true, dirtyL);
+            const bool hit = set_touch(P.vL, ways2, k0.z, true, dirtyL);
             acc.l2_hit += hit;
             acc.l2_miss += !hit;
             k0.x = CORE_FILL;
@@ -1619,7 +1625,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           if (p_forced) k2.w = -1;
           k0.z = P.line_op;
           k0.w = issued;
-          if (set_touch(P.u, C.w1, P.line_op, false, dirty1)) {
+          if (set_touch(P.u, ways1, P.line_op, false, dirty1)) {
             acc.l1_hit++;
             acc.ops_done++;
             if (p_retry) {
@@ -1634,7 +1640,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
         if (p_hum) {  // a hit completes under the miss; a miss is held until the fill (Sec. 3.5)
           acc.ops_issued++;
-          if (set_touch(P.u, C.w1, P.line_op, false, dirty1)) {
+          if (set_touch(P.u, ways1, P.line_op, false, dirty1)) {
             acc.l1_hit++;
             acc.ops_done++;
           } else {
@@ -1866,9 +1872,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         if (i2) s_link[nxt][3][j + 1] = o2;
         if (i3) s_link[nxt][2][j - 1] = o3;
         // phase one's stores: issued before the next cycle's loads of the same sets and nodes
-        if (dirtyR) set_store(P.setR, C.w2, P.vR);
-        if (dirtyL) set_store(P.setL, C.w2, P.vL);
-        if (dirty1) set_store(P.set1, C.w1, P.u);
+        if (dirtyR) set_store(P.setR, ways2, P.vR);
+        if (dirtyL) set_store(P.setL, ways2, P.vL);
+        if (dirty1) set_store(P.set1, ways1, P.u);
         if (node_rq >= 0) {
           st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, node_w));
           if (node_tail >= 0) st_i<MULTI>(reinterpret_cast<int*>(&C.node[node_tail]), node_rq);
@@ -1903,7 +1909,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k2.z += 1;
           acc.bg_gen++;
         }
-        if (c + 1 < c_end) prefetch<MULTI, VARS>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P);
+        if (c + 1 < c_end) prefetch<MULTI, VARS, W48>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P);
 #undef out_for
       }
     }
@@ -2086,9 +2092,10 @@ int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.r
 // variants the one-tile-per-thread kernel carries, with any router delay (the directory needs
 // the general kernel)
 constexpr int32_t FAST_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
+// (FAST_WAYS48 is set only when every chip of a launch has the 4/8-way geometry: see batch_kind)
 int fast_opt(const ChipDev& d) {
   return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
-         (d.rdelay > 1 ? FAST_PIPE : 0);
+         (d.rdelay > 1 ? FAST_PIPE : 0) | ((d.w1 == 4 && d.w2 == 8) ? FAST_WAYS48 : 0);
 }
 
 int max_patches(const sim_config* c) { return (int)std::min<int64_t>(MAX_PATCHES, (int64_t)c->width * c->height); }
@@ -2163,7 +2170,7 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
-  switch (opt & 7) {
+  switch (opt & 15) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
     case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
     case 2: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 2>);
@@ -2171,7 +2178,15 @@ const void* fast_build(int opt) {
     case 4: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 4>);
     case 5: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 5>);
     case 6: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 6>);
-    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 7>);
+    case 7: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 7>);
+    case 8: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 8>);
+    case 9: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 9>);
+    case 10: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 10>);
+    case 11: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 11>);
+    case 12: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 12>);
+    case 13: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 13>);
+    case 14: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 14>);
+    default: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 15>);
   }
 }
 const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 0) {
@@ -2196,7 +2211,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 16; ++k) {
+  for (int k = 0; k < 32; ++k) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2741,13 +2756,17 @@ struct BatchKind {
 template <class ChipAt>
 BatchKind batch_kind(ChipAt chip_at, int n, int block) {
   BatchKind k{true, false, 0, 0};
+  bool w48 = true;  // every chip has the 4/8-way geometry
   for (int i = 0; i < n; ++i) {
     const sim_chip* h = chip_at(i);
     k.fast = k.fast && h->use_fast && h->hd.pw * h->hd.ph <= block;
     k.multi = k.multi || h->hd.n_patches > 1;
-    k.opt |= fast_opt(h->hd);
+    const int o = fast_opt(h->hd);
+    k.opt |= o & ~FAST_WAYS48;
+    w48 = w48 && (o & FAST_WAYS48);
     k.var = std::max(k.var, kernel_level(h->hd));
   }
+  if (w48 && n > 0) k.opt |= FAST_WAYS48;
   return k;
 }
 
