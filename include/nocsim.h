@@ -65,13 +65,15 @@ typedef struct {
   int32_t router_delay;       /* cycles per hop, 1..8 (0 counts as 1): a flit that arrives at a
                                  router waits router_delay - 1 cycles in the router's pipeline
                                  before it is arbitrated */
-  int32_t mig_threshold;      /* with LSPD: block migration (Sec. 3.3).  Each L2 way records its
-                                 last accessor and how many accesses in a row came from it; when a
-                                 remote tile's run reaches this count the owner sends it the block
-                                 (16 flits, Table 1), keeps a forwarding pointer and answers later
-                                 requests with a redirection (1 flit); the receiver claims the
-                                 directory entry (1 flit) and its op completes with the directory's
-                                 acknowledgement (1 flit).  0 = no migration, at most 4095 */
+  int32_t mig_threshold;      /* with LSPD: block migration (Sec. 3.3), 0 = none, at most 16.  Each
+                                 L2 way keeps its last mig_threshold accessors; when a remote tile
+                                 has made more than half of them, the slice sends that tile the
+                                 block (16 flits, Table 1) and keeps serving it from its own copy
+                                 until the receiver's arrival notice (1 flit) comes back; then it
+                                 drops the copy and answers later requests with a redirection
+                                 (1 flit).  The receiver claims the directory entry (1 flit) and
+                                 its op completes with the directory's acknowledgement (1 flit).
+                                 A slice sends one block at a time. */
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
@@ -166,7 +168,7 @@ int64_t sim_cycle(const sim_t* h);
 /* Statistics of the chip (synchronises). */
 int sim_stats(sim_t* h, sim_stats_t* out);
 
-/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 3, width,
+/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 4, width,
    height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, reply_flits (>= 1),
    core-record words (28), flags, router delay, LSPD mode (0 static homes, 1 interleaved
    directory, 2 central), migration threshold}, then per tile the 4 input slots of the next
@@ -175,14 +177,16 @@ int sim_stats(sim_t* h, sim_stats_t* out);
    hit_tail, miss_head, miss_tail, bg_pending, node_next, node_ready, node_line, force_line,
    force_dst, reply flits received, node flits sent, held line (-1 = none), held issue cycle,
    remote-access target, pending eviction line, directory checksum lo, hi, pending claim,
-   forwarded line, its destination, spare}, then L1 and L2 tags per tile per
+   forwarded line, its destination (| 0x40000000 while the block is on its way), the tile to
+   tell of a migrated block's arrival}, then L1 and L2 tags per tile per
    set (most recently used first, -1 invalid), then the 64 statistics as (low, high) word
    pairs, then per tile the deflection counts of the 4 input slots' flits (0 when empty or
    without AGE_DEFLECT), then, when router_delay D > 1 (header word 13 = D), the routers'
    pipelines: stages k = 1..D-1 (stage k holds the flits arbitrated k-1 cycles after the
    dump's cycle), each as per tile 4 slots of 4 words, then the stages' deflection counts,
    then with LSPD the location array (owner tile per line, -1 = not on chip), then with
-   migration the access record of every L2 way (last accessor | run << 20).
+   migration the last migration-threshold accessors of every L2 way (most recent first, -1
+   none), in the order of the L2 tags.
    sim_dump_words() gives the size in int32 words. */
 size_t sim_dump_words(const sim_t* h);
 int sim_dump(sim_t* h, int32_t* host_buf, size_t words);

@@ -56,16 +56,16 @@ enum { ST_IDLE = 0, ST_L1MISS = 1, ST_SEND = 2, ST_WAIT = 3, ST_FILL = 4, /* cor
    a negative directory answer, or an owner tile >= 0 */
 enum { CODE_ACK = -4, CODE_MIG = -3, CODE_TRAP = -2, CODE_NACK = -1 };
 #define CODE_BASE 4
-/* request types at a slice's service input (the high byte of C_L2Q) */
-enum { Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3 };
+/* request types at a slice's service input (the high byte of C_L2Q): remote access, directory
+   access, eviction notice, ownership claim, a migrated block's arrival at its new owner */
+enum { Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3, Q_ARRIVED = 4 };
 /* migration (Sec. 3.3): a block moves as 16 flits (Table 1, L2 block migration); a queued reply
-   carries this bit on its line word when it is a migration; an L2 way's access record packs the
-   last accessor (20 bits) and how many accesses in a row came from it (12 bits) */
+   carries this bit on its line word when it is a migration.  Each L2 way keeps the list of its
+   last `mig` accessors, most recent first (-1 = none yet).  While a block this slice sends away
+   is on its way, the slice's forwarding destination carries MIG_TRANSIT. */
 #define MIG_FLITS 16
 #define MIG_MARK 0x40000000
-#define REC(who, run) ((int32_t)(((uint32_t)(run) << 20) | (uint32_t)(who)))
-#define REC_WHO(r) ((int32_t)((uint32_t)(r) & 0xFFFFFu))
-#define REC_RUN(r) ((int32_t)((uint32_t)(r) >> 20))
+#define MIG_TRANSIT 0x40000000
 enum { PN = 0, PS = 1, PE = 2, PW = 3, PX = 4 };                        /* ports, 4 = eject */
 /* per-tile core record (20 words); C_NEXT, C_READY, C_NLINE and C_NSENT are the tile's queue
    node as a requester, written by its home while it waits there */
@@ -81,8 +81,10 @@ enum {
   C_EV = 21,    /* LSPD: line whose eviction notice waits for injection, -1 = none */
   C_DSUM_LO = 22, C_DSUM_HI = 23, /* LSPD: checksum of the directory entries this tile keeps */
   C_CLAIM = 24, /* migration: line whose ownership claim waits for injection, -1 = none */
-  C_FWD_LINE = 25, C_FWD_DST = 26, /* migration: the last block this slice gave away, and to whom */
-  C_PAD = 27,
+  C_FWD_LINE = 25, C_FWD_DST = 26, /* migration: the last block this slice gave away (or is giving
+                                      away: MIG_TRANSIT), and to whom */
+  C_NOTE = 27,  /* migration: the tile a block that migrated here came from, to be told of its
+                   arrival; -1 = none */
   C_WORDS = 28
 };
 /* flit record: destination, injection cycle, source, kind<<30 | line, and the number of times
@@ -104,8 +106,8 @@ struct oracle_sim {
   int32_t dir_center;    /* the central directory's tile */
   int64_t lines;         /* size of the line space (location array entries) */
   int32_t* loc;          /* LSPD location array: [lines] owner tile or -1 */
-  int32_t* l2h;          /* migration: [N][S2][W2] access record of each L2 way (REC) */
-  int32_t mig;           /* migration threshold: accesses in a row from one remote tile (0 = off) */
+  int32_t* l2h;          /* migration: [N][S2][W2][mig] the last accessors of each L2 way */
+  int32_t mig;           /* migration: length of a block's access history (0 = no migration) */
   int32_t* seen;         /* [lines] scratch of the one-copy check */
   int32_t* scratch;      /* [2N], invariant checks */
   int64_t cycle;
@@ -306,43 +308,62 @@ static void dir_evicted(oracle_sim* s, int32_t line, int32_t who) {
   s->stats[OS_DIR_EVICT]++;
 }
 
-/* L2 ways of an LSPD slice with their access records (rec = NULL without migration): find,
-   move to the front, remove, insert at the front (returns the dropped last way). */
-static int32_t* l2_rec(oracle_sim* s, int32_t t, int32_t line) {
+/* L2 ways of an LSPD slice with their access histories (hist = NULL without migration; `mig`
+   words per way, kept in the ways' order): find, move to the front, remove, insert at the front
+   (returns the dropped last way; the new way's history starts empty). */
+static int32_t* l2_hist(oracle_sim* s, int32_t t, int32_t line) {
   if (!s->mig) return NULL;
-  return s->l2h + ((size_t)t * s->cfg.l2_sets + (line & (s->cfg.l2_sets - 1))) * s->cfg.l2_ways;
+  return s->l2h + ((size_t)t * s->cfg.l2_sets + (line & (s->cfg.l2_sets - 1))) * s->cfg.l2_ways * s->mig;
 }
 static int l2_find(const int32_t* set, int ways, int32_t line) {
   for (int i = 0; i < ways; ++i)
     if (set[i] == line) return i;
   return -1;
 }
-static void l2_front(int32_t* set, int32_t* rec, int i) {
-  int32_t tag = set[i], r = rec ? rec[i] : 0;
+static void hist_copy(int32_t* dst, const int32_t* src, int mig) {
+  for (int m = 0; m < mig; ++m) dst[m] = src[m];
+}
+static void hist_clear(int32_t* h, int mig) {
+  for (int m = 0; m < mig; ++m) h[m] = -1;
+}
+static void l2_front(int32_t* set, int32_t* hist, int mig, int i) {
+  int32_t tag = set[i], h[16];
+  if (hist) hist_copy(h, hist + i * mig, mig);
   for (int j = i; j > 0; --j) {
     set[j] = set[j - 1];
-    if (rec) rec[j] = rec[j - 1];
+    if (hist) hist_copy(hist + j * mig, hist + (j - 1) * mig, mig);
   }
   set[0] = tag;
-  if (rec) rec[0] = r;
+  if (hist) hist_copy(hist, h, mig);
 }
-static void l2_remove(int32_t* set, int32_t* rec, int ways, int i) {
+static void l2_remove(int32_t* set, int32_t* hist, int mig, int ways, int i) {
   for (int j = i; j < ways - 1; ++j) {
     set[j] = set[j + 1];
-    if (rec) rec[j] = rec[j + 1];
+    if (hist) hist_copy(hist + j * mig, hist + (j + 1) * mig, mig);
   }
   set[ways - 1] = -1;
-  if (rec) rec[ways - 1] = 0;
+  if (hist) hist_clear(hist + (ways - 1) * mig, mig);
 }
-static int32_t l2_insert(int32_t* set, int32_t* rec, int ways, int32_t line, int32_t r) {
+static int32_t l2_insert(int32_t* set, int32_t* hist, int mig, int ways, int32_t line) {
   int32_t victim = set[ways - 1];
   for (int j = ways - 1; j > 0; --j) {
     set[j] = set[j - 1];
-    if (rec) rec[j] = rec[j - 1];
+    if (hist) hist_copy(hist + j * mig, hist + (j - 1) * mig, mig);
   }
   set[0] = line;
-  if (rec) rec[0] = r;
+  if (hist) hist_clear(hist, mig);
   return victim;
+}
+/* A block this slice sends away by migration is still on its way (its arrival not yet told). */
+static int sending_block(const int32_t* k) { return k[C_FWD_DST] >= 0 && (k[C_FWD_DST] & MIG_TRANSIT); }
+/* Sec. 3.3: records an access by `who` in a way's history of its last `mig` accessors and
+   returns how many of them were `who`'s. */
+static int hist_note(int32_t* h, int mig, int32_t who) {
+  for (int m = mig - 1; m > 0; --m) h[m] = h[m - 1];
+  h[0] = who;
+  int n = 0;
+  for (int m = 0; m < mig; ++m) n += h[m] == who;
+  return n;
 }
 
 /* The directory's answer to tile `rq` asking for `line`: the owner, or a negative reply, in
@@ -380,25 +401,22 @@ static void phase_memory(oracle_sim* s, int32_t t) {
     int32_t type = k[C_L2Q] >> 24, who = k[C_L2Q] & 0xFFFFFF, line = k[C_L2Q_LINE];
     if (type == Q_RA) {
       int32_t* set = l2_set(s, t, line);
-      int32_t* rec = l2_rec(s, t, line);
+      int32_t* hist = l2_hist(s, t, line);
       int i = l2_find(set, s->cfg.l2_ways, line);
       if (i >= 0) {
         s->stats[OS_L2_HIT]++;
-        int32_t run = 1;
-        if (rec) {  /* Sec. 3.3: the block's record of its latest accessors */
-          run = REC_WHO(rec[i]) == who ? REC_RUN(rec[i]) + 1 : 1;
-          if (run > 4095) run = 4095;
-          rec[i] = REC(who, run);
-        }
-        l2_front(set, rec, i);
-        /* a remote tile uses it most: the block moves there, unless it has just moved here and
-           the directory has not yet acknowledged this slice's claim (so one claim per block is
-           in flight at a time) */
+        int n = 0;
+        if (hist) n = hist_note(hist + i * s->mig, s->mig, who);  /* Sec. 3.3: the block's last accessors */
+        l2_front(set, hist, s->mig, i);
+        /* Sec. 3.3: a remote tile has made most of the block's last `mig` accesses, so the block
+           moves there.  Not while this slice still waits for the directory to acknowledge its
+           own claim of the block, and not while another block of this slice is on its way. */
         const int claiming = k[C_STATE] == ST_WAIT && k[C_LINE] == line;
-        if (s->mig && run >= s->mig && !claiming) {
-          l2_remove(set, rec, s->cfg.l2_ways, 0);
+        const int sending = sending_block(k);
+        if (s->mig && 2 * n > s->mig && !claiming && !sending) {
+          /* the block goes whole; this slice keeps serving it until it has arrived */
           k[C_FWD_LINE] = line;
-          k[C_FWD_DST] = who;
+          k[C_FWD_DST] = who | MIG_TRANSIT;
           s->stats[OS_MIGRATE]++;
           list_append(s, t, C_HIT_H, C_HIT_T, who, (int32_t)(c + delay), line | MIG_MARK);
         } else {
@@ -406,7 +424,7 @@ static void phase_memory(oracle_sim* s, int32_t t) {
         }
       } else if (s->mig && k[C_FWD_LINE] == line) {  /* Sec. 3.3: redirect to where it went */
         s->stats[OS_REDIRECT]++;
-        list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), k[C_FWD_DST]);
+        list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), k[C_FWD_DST] & ~MIG_TRANSIT);
       } else {
         s->stats[OS_TRAP]++;
         list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), CODE_TRAP);
@@ -415,6 +433,18 @@ static void phase_memory(oracle_sim* s, int32_t t) {
       list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), dir_lookup(s, line, who));
     } else if (type == Q_EV) {
       dir_evicted(s, line, who);
+    } else if (type == Q_ARRIVED) {  /* Sec. 3.3: the block reached its new owner: this slice's copy
+                                         goes (if the slice has not evicted it meanwhile) */
+      if (k[C_FWD_DST] == (who | MIG_TRANSIT)) {
+        const int32_t fl = k[C_FWD_LINE];
+        int32_t* set = l2_set(s, t, fl);
+        int i = l2_find(set, s->cfg.l2_ways, fl);
+        if (i >= 0) l2_remove(set, l2_hist(s, t, fl), s->mig, s->cfg.l2_ways, i);
+        k[C_FWD_DST] = who;
+      } else if (s->check && !s->bad) {
+        s->bad = 1;
+        snprintf(s->msg, sizeof s->msg, "arrival notice from %d at %d, which sends nothing there", who, t);
+      }
     } else {  /* Sec. 3.3: the directory is updated to the block's new owner, which is told */
       dir_set(s, line, who);
       list_append(s, t, C_MISS_H, C_MISS_T, who, (int32_t)(c + delay), CODE_ACK);
@@ -446,9 +476,12 @@ static void phase_memory(oracle_sim* s, int32_t t) {
         l1_used = 1;
         int32_t line = k[C_LINE];
         int32_t* set2 = l2_set(s, t, line);
-        int32_t victim = l2_insert(set2, l2_rec(s, t, line), s->cfg.l2_ways, line, REC(t, 0));
+        int32_t victim = l2_insert(set2, l2_hist(s, t, line), s->mig, s->cfg.l2_ways, line);
         if (s->check) check_set(s, set2, s->cfg.l2_ways, "L2", t);
-        if (victim >= 0) {                      /* the evicted block leaves the directory */
+        if (victim >= 0 && s->mig && victim == k[C_FWD_LINE] && sending_block(k)) {
+          /* the block on its way elsewhere leaves this slice; its new owner's claim updates the
+             directory, and requests still reaching here are redirected */
+        } else if (victim >= 0) {               /* the evicted block leaves the directory */
           if (dir_of(s, victim) == t) dir_evicted(s, victim, t);
           else k[C_EV] = victim;
         }
@@ -475,23 +508,30 @@ static void phase_memory(oracle_sim* s, int32_t t) {
     case ST_L1MISS:
       if (k[C_WAKE] == (int32_t)c && s->lspd) {
         /* LSPD: the core's own slice, then the directory (at once when this tile keeps the
-           entry).  A pending eviction notice goes out first, so that a core has at most one. */
+           entry).  A pending eviction notice or claim goes out first, so that a core has at most
+           one of each.  (An arrival notice goes out before the core's next directory or remote
+           access, so a second migrated block cannot come in while it is pending.) */
         int32_t line = k[C_LINE];
         int32_t* set2 = l2_set(s, t, line);
-        int32_t* rec = l2_rec(s, t, line);
+        int32_t* hist = l2_hist(s, t, line);
         int i = l2_find(set2, s->cfg.l2_ways, line);
         if (k[C_EV] >= 0 || k[C_CLAIM] >= 0) {  /* notices first */
           k[C_WAKE] = (int32_t)(c + 1);
         } else if (i >= 0) {
           s->stats[OS_L2_HIT]++;
-          if (rec) rec[i] = REC(t, REC_WHO(rec[i]) == t && REC_RUN(rec[i]) < 4095 ? REC_RUN(rec[i]) + 1 : 1);
-          l2_front(set2, rec, i);
+          if (hist) hist_note(hist + i * s->mig, s->mig, t);   /* the local core's access */
+          l2_front(set2, hist, s->mig, i);
           k[C_STATE] = ST_FILL;
+          k[C_WAKE] = (int32_t)(c + 1);
+        } else if (s->mig && k[C_FWD_LINE] == line && sending_block(k)) {
+          /* this slice sent the block away and has since evicted its copy: the core waits for
+             the arrival notice before it asks for the block again (so that the notice cannot
+             remove a copy that came back to this slice) */
           k[C_WAKE] = (int32_t)(c + 1);
         } else if (dir_of(s, line) == t) {
           int32_t o = dir_lookup(s, line, t);
           if (o == t && k[C_FWD_LINE] == line) {  /* this slice gave the block away and its new */
-            o = k[C_FWD_DST];                       /* owner's claim is still on the way */
+            o = k[C_FWD_DST] & ~MIG_TRANSIT;        /* owner's claim is still on the way */
             s->stats[OS_REDIRECT]++;
           }
           if (o == t) {                         /* stale (an older migration): look again */
@@ -686,7 +726,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
   /* (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
      eviction notice, a directory access or a remote-access request) */
   int cls = -1;
-  const int own = s->lspd ? (k[C_EV] >= 0 || k[C_CLAIM] >= 0 || ((k[C_STATE] == ST_SEND_DA || k[C_STATE] == ST_SEND_RA) &&
+  const int own = s->lspd ? (k[C_EV] >= 0 || k[C_NOTE] >= 0 || k[C_CLAIM] >= 0 || ((k[C_STATE] == ST_SEND_DA || k[C_STATE] == ST_SEND_RA) &&
                                               k[C_WAKE] <= (int32_t)c))
                           : (k[C_STATE] == ST_SEND && k[C_WAKE] + inject_delay(s) <= (int32_t)c);
   if (k[C_MISS_H] >= 0 && s->core[(size_t)k[C_MISS_H] * C_WORDS + C_READY] <= (int32_t)c) cls = 0;
@@ -716,6 +756,11 @@ static void phase_route(oracle_sim* s, int32_t t) {
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
         f[F_INFO] = (K_DIR << 30) | k[C_EV];
         k[C_EV] = -1;
+      } else if (k[C_NOTE] >= 0) {              /* Sec. 3.3: the migrated block has arrived; its */
+        f[F_DST] = k[C_NOTE];                   /* source drops its copy */
+        f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
+        f[F_INFO] = (K_REQ << 30);
+        k[C_NOTE] = -1;
       } else if (k[C_CLAIM] >= 0) {             /* a migrated block's new owner, to the directory */
         f[F_DST] = dir_of(s, k[C_CLAIM]);
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
@@ -836,7 +881,10 @@ static void phase_move(oracle_sim* s, int32_t t) {
         snprintf(s->msg, sizeof s->msg, "flit latency %lld over %lld hops at %d", (long long)lat, (long long)man, t);
       }
     }
-    if (kind == K_REQ) {                       /* request reaches its home slice (LSPD: the owner) */
+    if (kind == K_REQ && ctl) {                /* migration: the block this slice sent has arrived */
+      k[C_L2Q] = ej[F_SRC] | (Q_ARRIVED << 24);
+      k[C_L2Q_LINE] = k[C_FWD_LINE];          /* the block it sent (one at a time) */
+    } else if (kind == K_REQ) {                /* request reaches its home slice (LSPD: the owner) */
       s->stats[OS_REQ_RECV]++;
       k[C_L2Q] = ej[F_SRC];
       k[C_L2Q_LINE] = ej[F_INFO] & LINE_MASK;
@@ -851,10 +899,15 @@ static void phase_move(oracle_sim* s, int32_t t) {
       int32_t code = (ej[F_INFO] & LINE_MASK) - CODE_BASE;
       if (code != CODE_MIG) k[C_WAKE] = (int32_t)(c + 1);
       if (code == CODE_MIG) {                  /* a flit of the block migrating here; with the */
-        if (++k[C_RCV] == MIG_FLITS) {         /* last one it goes into the slice and L1 */
-          k[C_RCV] = 0;
+        if (++k[C_RCV] == MIG_FLITS) {         /* last one it goes into the slice and L1, and */
+          k[C_RCV] = 0;                        /* its source is told (Sec. 3.3) */
           k[C_STATE] = ST_FILL_MIG;
           k[C_WAKE] = (int32_t)(c + 1);
+          if (s->check && k[C_NOTE] >= 0 && !s->bad) {
+            s->bad = 1;
+            snprintf(s->msg, sizeof s->msg, "tile %d receives a block with an arrival notice pending", t);
+          }
+          k[C_NOTE] = ej[F_SRC];
         }
       } else if (code == CODE_ACK) {           /* the directory names this slice: the migrated */
         k[C_STATE] = ST_FILL;                  /* block fills L1 and the op completes */
@@ -948,7 +1001,7 @@ static void check_cycle(oracle_sim* s) {
         int kind = (int)((uint32_t)f[F_INFO] >> 30);
         const int ctl = ((uint32_t)f[F_INJ] & CTL_BIT) != 0;
         const int mig_flit = kind == K_REPLY && ctl && (f[F_INFO] & LINE_MASK) == CODE_MIG + CODE_BASE;
-        if (kind == K_REQ || (kind == K_DIR && !ctl) || (kind == K_BG && ctl)) req_fl++;  /* remote or
+        if ((kind == K_REQ && !ctl) || (kind == K_DIR && !ctl) || (kind == K_BG && ctl)) req_fl++;  /* remote or
                                                            directory access, ownership claim */
         if (kind == K_REPLY && ctl && !mig_flit) ans_fl++;       /* directory answer, trap, redirection */
         if (mig_flit) mig_to[f[F_DST]]++;
@@ -970,7 +1023,7 @@ static void check_cycle(oracle_sim* s) {
   for (int32_t t = 0; t < s->N; ++t) {
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] == ST_WAIT) waiting++;
-    if (k[C_L2Q] >= 0 && (k[C_L2Q] >> 24) != Q_EV) at_home++;
+    if (k[C_L2Q] >= 0 && (k[C_L2Q] >> 24) != Q_EV && (k[C_L2Q] >> 24) != Q_ARRIVED) at_home++;
     if (k[C_CLAIM] >= 0) at_home++;   /* a claim waiting for injection */
     for (int which = 0; which < 2; ++which) {
       int32_t r = k[which ? C_MISS_H : C_HIT_H], last = -1;
@@ -1011,7 +1064,10 @@ static void check_cycle(oracle_sim* s) {
              (long long)at_home);
   }
   /* LSPD: one copy of a block on chip, and the directory names the slice that holds it (with
-     migration: or the slice waits for the acknowledgement of its claim of it) */
+     migration: or the slice waits for the acknowledgement of its claim of it).  With migration
+     a source keeps its copy until told of the block's arrival, and the block may move on before
+     that, so besides that one copy only slices that have sent the block and wait for its
+     arrival notice may hold it. */
   if (s->lspd) {
     const int32_t S2 = s->cfg.l2_sets, W2 = s->cfg.l2_ways;
     memset(s->seen, 0, (size_t)s->lines * sizeof(int32_t));
@@ -1021,7 +1077,10 @@ static void check_cycle(oracle_sim* s) {
         const int32_t line = s->l2[(size_t)t * S2 * W2 + i];
         if (line < 0) continue;
         const int claiming = s->mig && k[C_STATE] == ST_WAIT && k[C_LINE] == line;
-        if (s->seen[line]++ || (s->loc[line] != t && !claiming)) {
+        const int sending = s->mig && k[C_FWD_LINE] == line && sending_block(k);
+        /* sources count in the high half, so that they are told apart from plain copies */
+        s->seen[line] += sending ? 0x10000 : 1;
+        if ((s->seen[line] & 0xFFFF) > 1 || (s->loc[line] != t && !claiming && !sending)) {
           s->bad = 1;
           snprintf(s->msg, sizeof s->msg, "slice %d holds line %d, directory names %d", t, line, s->loc[line]);
           break;
@@ -1073,7 +1132,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
     return ORACLE_EINVAL;
   if (cfg->router_delay < 0 || cfg->router_delay > 8) return ORACLE_EINVAL;
   if ((cfg->flags & ORACLE_FLAG_LSPD_CENTRAL) && !(cfg->flags & ORACLE_FLAG_LSPD)) return ORACLE_EINVAL;
-  if (cfg->mig_threshold < 0 || cfg->mig_threshold > 4095 || (cfg->mig_threshold && !(cfg->flags & ORACLE_FLAG_LSPD)))
+  if (cfg->mig_threshold < 0 || cfg->mig_threshold > 16 || (cfg->mig_threshold && !(cfg->flags & ORACLE_FLAG_LSPD)))
     return ORACLE_EINVAL;
   oracle_sim* s = (oracle_sim*)calloc(1, sizeof(oracle_sim));
   if (!s) return ORACLE_ENOMEM;
@@ -1103,7 +1162,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   s->pipe = (int32_t*)malloc((size_t)(s->delay - 1) * N * SLOT_WORDS * 4 + 4);
   s->loc = (int32_t*)malloc((size_t)(s->lspd ? s->lines : 0) * 4 + 4);
   s->seen = (int32_t*)malloc((size_t)(s->lspd ? s->lines : 0) * 4 + 4);
-  s->l2h = (int32_t*)calloc((size_t)(s->mig ? N * cfg->l2_sets * cfg->l2_ways : 0) + 1, 4);
+  s->l2h = (int32_t*)malloc((size_t)(s->mig ? N * cfg->l2_sets * cfg->l2_ways * s->mig : 0) * 4 + 4);
   if (!s->zs || !s->zp || !s->link[0] || !s->link[1] || !s->core || !s->l1 || !s->l2 || !s->rnd || !s->outp || !s->ej ||
       !s->oldest_ok || !s->scratch || !s->pipe || !s->loc || !s->seen || !s->l2h) {
     oracle_destroy(s);
@@ -1128,6 +1187,7 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   }
   memset(s->l1, 0xFF, (size_t)N * cfg->l1_sets * cfg->l1_ways * 4);
   memset(s->l2, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * 4);
+  if (s->mig) memset(s->l2h, 0xFF, (size_t)N * cfg->l2_sets * cfg->l2_ways * s->mig * 4);
   *out = s;
   return ORACLE_OK;
 }
@@ -1152,7 +1212,7 @@ size_t oracle_dump_words(const oracle_sim* s) {
   size_t N = (size_t)s->N;
   return DUMP_HEADER + N * 16 + N * C_WORDS + N * s->cfg.l1_sets * s->cfg.l1_ways + N * s->cfg.l2_sets * s->cfg.l2_ways +
          2 * OS_COUNT + N * 4 + (size_t)(s->delay - 1) * N * 20 + (size_t)(s->lspd ? s->lines : 0) +
-         (size_t)(s->mig ? N * s->cfg.l2_sets * s->cfg.l2_ways : 0);
+         (size_t)(s->mig ? N * s->cfg.l2_sets * s->cfg.l2_ways * s->mig : 0);
 }
 
 /* Canonical state (format version 3): header {magic, 3, W, H, cycle (low, high), L1 sets,
@@ -1168,7 +1228,7 @@ size_t oracle_dump_words(const oracle_sim* s) {
 int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
   size_t N = (size_t)s->N, o = 0;
-  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 3, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
+  int32_t hdr[DUMP_HEADER] = {DUMP_MAGIC, 4, s->W, s->H, (int32_t)(uint32_t)s->cycle, (int32_t)(s->cycle >> 32),
                               s->cfg.l1_sets, s->cfg.l1_ways, s->cfg.l2_sets, s->cfg.l2_ways, s->reply_flits,
                               C_WORDS, s->cfg.flags, s->delay, s->lspd, s->mig};
   memcpy(buf, hdr, sizeof hdr);
@@ -1202,13 +1262,13 @@ int oracle_dump(const oracle_sim* s, int32_t* buf, size_t words) {
     memcpy(buf + o, s->loc, (size_t)s->lines * 4);
     o += (size_t)s->lines;
   }
-  if (s->mig) memcpy(buf + o, s->l2h, N * s->cfg.l2_sets * s->cfg.l2_ways * 4);
+  if (s->mig) memcpy(buf + o, s->l2h, N * s->cfg.l2_sets * s->cfg.l2_ways * s->mig * 4);
   return ORACLE_OK;
 }
 
 int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
   if (!s || !buf || words < oracle_dump_words(s)) return ORACLE_EINVAL;
-  if (buf[0] != DUMP_MAGIC || buf[1] != 3 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
+  if (buf[0] != DUMP_MAGIC || buf[1] != 4 || buf[2] != s->W || buf[3] != s->H || buf[6] != s->cfg.l1_sets ||
       buf[7] != s->cfg.l1_ways || buf[8] != s->cfg.l2_sets || buf[9] != s->cfg.l2_ways || buf[10] != s->reply_flits ||
       buf[11] != C_WORDS || buf[12] != s->cfg.flags || buf[13] != s->delay || buf[14] != s->lspd ||
       buf[15] != s->mig)
@@ -1250,7 +1310,7 @@ int oracle_load(oracle_sim* s, const int32_t* buf, size_t words) {
     memcpy(s->loc, buf + o, (size_t)s->lines * 4);
     o += (size_t)s->lines;
   }
-  if (s->mig) memcpy(s->l2h, buf + o, N * s->cfg.l2_sets * s->cfg.l2_ways * 4);
+  if (s->mig) memcpy(s->l2h, buf + o, N * s->cfg.l2_sets * s->cfg.l2_ways * s->mig * 4);
   for (size_t t = 0; t < N; ++t)
     if (s->core[t * C_WORDS + C_DLINE] >= 0 && !(s->cfg.flags & ORACLE_FLAG_HIT_UNDER_MISS)) return ORACLE_EINVAL;
   return ORACLE_OK;
@@ -1284,7 +1344,8 @@ int oracle_quiescent(const oracle_sim* s) {
       if (cur[(size_t)t * SLOT_WORDS + p * F_WORDS] >= 0) return 0;
     const int32_t* k = s->core + (size_t)t * C_WORDS;
     if (k[C_STATE] != ST_IDLE || k[C_L2Q] >= 0 || k[C_HIT_H] >= 0 || k[C_MISS_H] >= 0 || k[C_BG] != 0 ||
-        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0 || k[C_EV] >= 0 || k[C_CLAIM] >= 0)
+        k[C_FLINE] >= 0 || k[C_FDST] >= 0 || k[C_RCV] != 0 || k[C_DLINE] >= 0 || k[C_EV] >= 0 || k[C_CLAIM] >= 0 ||
+        k[C_NOTE] >= 0 || sending_block(k))
       return 0;
   }
   return 1;

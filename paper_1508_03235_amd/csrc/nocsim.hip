@@ -43,12 +43,17 @@ constexpr uint32_t CTL_BIT = 0x80000000u;
 // answers (queue node line word, sent as code + CODE_BASE): claim acknowledged, a flit of a
 // migrating block, trap, negative directory answer, or an owner tile >= 0
 constexpr int CODE_ACK = -4, CODE_MIG = -3, CODE_TRAP = -2, CODE_NACK = -1, CODE_BASE = 4;
-constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3;  // message types at a slice's service input (l2q >> 24)
+// message types at a slice's service input (l2q >> 24): remote access, directory access, eviction
+// notice, ownership claim, a migrated block's arrival at its new owner
+constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3, Q_ARRIVED = 4;
 // migration (Sec. 3.3): a block moves as 16 flits (Table 1); a queued reply that is a migration
-// carries MIG_MARK on its line word; an L2 way's access record packs the last accessor (20 bits)
-// and how many accesses in a row came from it (12 bits)
+// carries MIG_MARK on its line word; each L2 way keeps its last `mig` accessors (most recent
+// first, -1 none), in the ways' order; while a block a slice sends away is on its way, the
+// slice's forwarding destination carries MIG_TRANSIT
 constexpr int MIG_FLITS = 16;
 constexpr int MIG_MARK = 0x40000000;
+constexpr int MIG_TRANSIT = 0x40000000;
+constexpr int MIG_MAX = 16;  // longest access history
 constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // words of a tile's record in the canonical dump: state, wake, line, issue, l2q, l2q_line,
 // hit head/tail, miss head/tail, bg_pending, node next/ready/line, force_line, force_dst,
@@ -56,7 +61,7 @@ constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // pending eviction line, directory checksum (low, high), pending claim, forwarded line, its
 // destination, a spare word
 constexpr int CORE_RECORD = 28;
-constexpr int DUMP_VERSION = 3;
+constexpr int DUMP_VERSION = 4;
 // model variants (sim_config.flags); the one-tile-per-thread kernel runs the base model only
 constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY | SIM_FLAG_LSPD |
                                   SIM_FLAG_LSPD_CENTRAL;
@@ -94,7 +99,7 @@ struct ChipDev {
   int4* core;                // [6][N]; group 3: force_dst, reply flits received, held line, held issue;
                              // group 4 (LSPD): remote-access target, pending eviction, directory checksum lo, hi;
                              // group 5 (migration): pending claim, forwarded line, its destination, spare
-  int32_t* l2h;              // migration: [N][s2][w2] access record of each L2 way
+  int32_t* l2h;              // migration: [N][s2][w2][mig] the last accessors of each L2 way
   int32_t* loc;              // LSPD location array [lines]: owner tile or -1; entry L belongs to L's directory tile
   int4* node;                // [N]: next, ready, line, reply flits already injected by the home
   int32_t* l1;               // [N][s1][w1]
@@ -341,45 +346,71 @@ __device__ __forceinline__ void way_put(int (&v)[8], int i, int x) {
   for (int k = 0; k < 8; ++k)
     if (i == k) v[k] = x;
 }
-__device__ __forceinline__ void way_front(int (&v)[8], int (&h)[8], int i, bool rec) {
-  const int tag = way_pick(v, i), r = way_pick(h, i);
+__device__ __forceinline__ void way_front(int (&v)[8], int i) {
+  const int tag = way_pick(v, i);
 #pragma unroll
   for (int k = 7; k >= 1; --k)
-    if (k <= i) {
-      v[k] = v[k - 1];
-      if (rec) h[k] = h[k - 1];
-    }
+    if (k <= i) v[k] = v[k - 1];
   v[0] = tag;
-  if (rec) h[0] = r;
 }
-__device__ __forceinline__ void way_remove(int (&v)[8], int (&h)[8], int ways, int i, bool rec) {
+__device__ __forceinline__ void way_remove(int (&v)[8], int ways, int i) {
   ways = __builtin_amdgcn_readfirstlane(ways);
 #pragma unroll
   for (int k = 0; k < 7; ++k)
-    if (k >= i && k < ways - 1) {
-      v[k] = v[k + 1];
-      if (rec) h[k] = h[k + 1];
-    }
+    if (k >= i && k < ways - 1) v[k] = v[k + 1];
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    if (k == ways - 1) {
-      v[k] = -1;
-      if (rec) h[k] = 0;
-    }
+    if (k == ways - 1) v[k] = -1;
 }
-// inserts `line` at the front with record r; returns the way it pushed out (or -1)
-__device__ __forceinline__ int way_insert(int (&v)[8], int (&h)[8], int ways, int line, int r, bool rec) {
+// inserts `line` at the front; returns the way it pushed out (or -1)
+__device__ __forceinline__ int way_insert(int (&v)[8], int ways, int line) {
   ways = __builtin_amdgcn_readfirstlane(ways);
   const int victim = way_pick(v, ways - 1);
 #pragma unroll
   for (int k = 7; k >= 1; --k)
-    if (k <= ways - 1) {
-      v[k] = v[k - 1];
-      if (rec) h[k] = h[k - 1];
-    }
+    if (k <= ways - 1) v[k] = v[k - 1];
   v[0] = line;
-  if (rec) h[0] = r;
   return victim;
+}
+
+// Access histories of an LSPD slice's ways (migration, Sec. 3.3), in HBM beside the tags and in
+// their order: `mig` words per way, most recent accessor first.  Only the slice's own tile
+// reads or writes them, so they are plain loads and stores, applied at once.
+__device__ __forceinline__ void hist_copy(int* dst, const int* src, int mig) {
+  for (int m = 0; m < mig; ++m) *gp(dst + m) = *gp(src + m);
+}
+__device__ __forceinline__ void hist_clear(int* h, int mig) {
+  for (int m = 0; m < mig; ++m) *gp(h + m) = -1;
+}
+// way i's history moves to the front (the ways before it move back one)
+__device__ __forceinline__ void hist_front(int* h, int mig, int i) {
+  int keep[MIG_MAX];
+  for (int m = 0; m < mig; ++m) keep[m] = *gp(h + i * mig + m);
+  for (int j = i; j > 0; --j) hist_copy(h + j * mig, h + (j - 1) * mig, mig);
+  for (int m = 0; m < mig; ++m) *gp(h + m) = keep[m];
+}
+// way i's history goes (the ways after it move up one; the last is cleared)
+__device__ __forceinline__ void hist_remove(int* h, int mig, int ways, int i) {
+  for (int j = i; j < ways - 1; ++j) hist_copy(h + j * mig, h + (j + 1) * mig, mig);
+  hist_clear(h + (ways - 1) * mig, mig);
+}
+// every way moves back one (the last is dropped); the front starts empty
+__device__ __forceinline__ void hist_insert(int* h, int mig, int ways) {
+  for (int j = ways - 1; j > 0; --j) hist_copy(h + j * mig, h + (j - 1) * mig, mig);
+  hist_clear(h, mig);
+}
+// way i was accessed by `who`: recorded first; returns how many of the way's last `mig`
+// accesses are who's
+__device__ __forceinline__ int hist_note(int* h, int mig, int i, int who) {
+  int* w = h + i * mig;
+  int n = 1;
+  for (int m = mig - 1; m > 0; --m) {
+    const int v = *gp(w + m - 1);
+    *gp(w + m) = v;
+    n += v == who;
+  }
+  *gp(w) = who;
+  return n;
 }
 
 // Queue nodes {next, ready, line, 0}: device-scope atomics when several workgroups share a chip.
@@ -554,7 +585,8 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   if (lspd && k4.x >= 0) { GUARD(k4.x) }
   if (lspd && k4.y >= 0) { GUARD_LINE(k4.y) }
   if (lspd && k5.x >= 0) { GUARD_LINE(k5.x) }
-  if (lspd && k5.z >= 0) { GUARD(k5.z) }
+  if (lspd && k5.z >= 0) { GUARD(k5.z & ~MIG_TRANSIT) }
+  if (lspd && k5.w >= 0) { GUARD(k5.w) }
   if (k1.z >= 0) { GUARD(k1.z) }
   if (k1.w >= 0) { GUARD(k1.w) }
   if (k2.x >= 0) { GUARD(k2.x) }
@@ -587,14 +619,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   int* setR = C.l2 + ((size_t)t * C.s2 + (ixR & (uint32_t)(C.s2 - 1))) * C.w2;
   int* setL = C.l2 + ((size_t)t * C.s2 + (ixL & (uint32_t)(C.s2 - 1))) * C.w2;
   int vR[8], vL[8], u[8];
-  if (svc && svc_type == Q_RA) set_load(setR, C.w2, vR);
+  if (svc && (svc_type == Q_RA || svc_type == Q_ARRIVED)) set_load(setR, C.w2, vR);
   if (local || slice_look || fill_mem) set_load(setL, C.w2, vL);
-  // migration: the access records of those two sets (same layout as the tags)
-  int* recR = mig ? C.l2h + (setR - C.l2) : nullptr;
-  int* recL = mig ? C.l2h + (setL - C.l2) : nullptr;
-  int hR[8] = {0, 0, 0, 0, 0, 0, 0, 0}, hL[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (mig && svc && svc_type == Q_RA) set_load(recR, C.w2, hR);
-  if (mig && (slice_look || fill_mem)) set_load(recL, C.w2, hL);
+  // migration: the access histories of those two sets (the ways' order, C.mig words per way)
+  const int mg = mig ? C.mig : 0;
+  int* histR = mig ? C.l2h + (size_t)(setR - C.l2) * mg : nullptr;
+  int* histL = mig ? C.l2h + (size_t)(setL - C.l2) * mg : nullptr;
   int4 nh = EMPTY, nm = EMPTY;  // nodes at the hit-queue and miss-queue heads: next, ready, line
   if (k1.z >= 0) nh = ld_node<MULTI>(&C.node[k1.z]);
   if (k2.x >= 0) nm = ld_node<MULTI>(&C.node[k2.x]);
@@ -663,21 +693,21 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       const int i = way_of(vR, line);
       if (i >= 0) {
         lds_add(L, SIM_ST_L2_HIT, 1);
-        int run = 1;
-        if (mig) {  // Sec. 3.3: the block's record of its latest accessors
-          const int hr = way_pick(hR, i);
-          run = (hr & 0xFFFFF) == who ? min(((uint32_t)hr >> 20) + 1, 4095u) : 1;
-          way_put(hR, i, (int)(((uint32_t)run << 20) | (uint32_t)who));
+        int n = 0;
+        if (mig) {  // Sec. 3.3: the block's list of its last accessors
+          n = hist_note(histR, mg, i, who);
+          hist_front(histR, mg, i);
         }
-        way_front(vR, hR, i, mig);
+        way_front(vR, i);
         dirtyR = true;
-        // a remote tile uses it most: the block moves there, unless it has just moved here and
-        // this slice still waits for the directory to acknowledge its claim
+        // a remote tile made most of the block's last accesses: the block moves there, unless it
+        // has just moved here and this slice still waits for the directory to acknowledge its
+        // claim, or another block of this slice is still on its way
         const bool claiming = k0.x == CORE_WAIT && k0.z == line;
-        if (mig && run >= C.mig && !claiming) {
-          way_remove(vR, hR, C.w2, 0, mig);
-          k5.y = line;
-          k5.z = who;
+        const bool sending = k5.z >= 0 && (k5.z & MIG_TRANSIT);
+        if (mig && 2 * n > mg && !claiming && !sending) {
+          k5.y = line;  // the block goes whole; this slice serves it until told of its arrival
+          k5.z = who | MIG_TRANSIT;
           d5 = true;
           lds_add(L, SIM_ST_MIGRATE, 1);
           enqueue(true, who, c + inj_delay, line | MIG_MARK);
@@ -686,10 +716,21 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
         }
       } else if (mig && k5.y == line) {  // Sec. 3.3: redirected to where the block went
         lds_add(L, SIM_ST_REDIRECT, 1);
-        enqueue(false, who, c + inj_delay, k5.z);
+        enqueue(false, who, c + inj_delay, k5.z & ~MIG_TRANSIT);
       } else {
         lds_add(L, SIM_ST_TRAP, 1);
         enqueue(false, who, c + inj_delay, CODE_TRAP);
+      }
+    } else if (svc_type == Q_ARRIVED) {  // Sec. 3.3: the block sent away has arrived: this copy goes
+      if (k5.z == (who | MIG_TRANSIT)) {
+        const int i = way_of(vR, line);
+        if (i >= 0) {
+          way_remove(vR, C.w2, i);
+          if (mig) hist_remove(histR, mg, C.w2, i);
+          dirtyR = true;
+        }
+        k5.z = who;
+        d5 = true;
       }
     } else if (svc_type == Q_CLAIM) {  // the directory names the block's new owner and tells it
       dir_write(line, loc_svc, who);
@@ -713,21 +754,22 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     d2 = true;
   }
   // the core's slice access below sees the service's changes when both touch one set
-  if (lspd && svc && svc_type == Q_RA && (slice_look || fill_mem) && setL == setR) {
+  if (lspd && svc && (svc_type == Q_RA || svc_type == Q_ARRIVED) && (slice_look || fill_mem) && setL == setR) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      vL[i] = vR[i];
-      hL[i] = hR[i];
-    }
+    for (int i = 0; i < 8; ++i) vL[i] = vR[i];
     dirtyL = dirtyL || dirtyR;
     dirtyR = false;
   }
   if (fill) {  // the block arrived: fill L1, the op completes
     bool claim = false;
     if (fill_mem) {  // LSPD: into the local slice too; an evicted block leaves the directory
-      const int victim = way_insert(vL, hL, C.w2, k0.z, t, mig);  // record: this tile, run 0
+      const int victim = way_insert(vL, C.w2, k0.z);
+      if (mig) hist_insert(histL, mg, C.w2);  // its history starts empty
       dirtyL = true;
-      if (victim >= 0) {
+      if (victim >= 0 && mig && victim == k5.y && k5.z >= 0 && (k5.z & MIG_TRANSIT)) {
+        // the block on its way elsewhere leaves this slice: its new owner's claim updates the
+        // directory, and requests still reaching here are redirected
+      } else if (victim >= 0) {
         GUARD_LINE(victim)
         if (dir_of(victim) == t) {
           dir_write(victim, t, -1);
@@ -760,24 +802,28 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     }
   } else if (missed && lspd) {  // LSPD: own slice, then the directory (Sec. 3.2)
     const int i = way_of(vL, k0.z);
-    if (k4.y >= 0 || k5.x >= 0) {
+    if (!slice_look) {
       k0.y = c + 1;  // a pending eviction notice or claim goes out first
     } else if (i >= 0) {
       lds_add(L, SIM_ST_L2_HIT, 1);
-      if (mig) {
-        const int hl = way_pick(hL, i);
-        const uint32_t run = (hl & 0xFFFFF) == t ? min(((uint32_t)hl >> 20) + 1, 4095u) : 1u;
-        way_put(hL, i, (int)((run << 20) | (uint32_t)t));
+      if (mig) {  // the local core's access
+        hist_note(histL, mg, i, t);
+        hist_front(histL, mg, i);
       }
-      way_front(vL, hL, i, mig);
+      way_front(vL, i);
       dirtyL = true;
       k0.x = CORE_FILL;
+      k0.y = c + 1;
+    } else if (mig && k5.y == k0.z && k5.z >= 0 && (k5.z & MIG_TRANSIT)) {
+      // this slice sent the block away and has since evicted its copy: the core waits for the
+      // arrival notice before it asks for the block again (so that the notice cannot remove a
+      // copy that came back to this slice)
       k0.y = c + 1;
     } else if (dir_core) {  // this tile keeps the entry: look it up at once
       lds_add(L, SIM_ST_DIR_ACCESS, 1);
       int o = fwd_line == k0.z ? fwd_val : loc_core;
       if (o == t && k5.y == k0.z) {  // this slice gave the block away; the new owner's claim
-        o = k5.z;                    // is still on the way
+        o = k5.z & ~MIG_TRANSIT;     // is still on the way
         lds_add(L, SIM_ST_REDIRECT, 1);
       }
       if (o == t) {  // stale (an older migration): look again next cycle
@@ -866,7 +912,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
   // (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
   // eviction notice, a directory access or a remote-access request)
-  const bool own = lspd ? (k4.y >= 0 || k5.x >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
+  const bool own = lspd ? (k4.y >= 0 || k5.w >= 0 || k5.x >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
                         : (k0.x == CORE_SEND && k0.y + inj_delay <= c);
   int cls = -1;
   if (k2.x >= 0 && nm.y <= c) cls = 0;
@@ -897,6 +943,12 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
         fi.w = (KIND_DIR << 30) | k4.y;
         k4.y = -1;
         d4 = true;
+      } else if (k5.w >= 0) {  // Sec. 3.3: the migrated block has arrived; its source drops its copy
+        fi.x = k5.w;
+        fi.y = (int)((uint32_t)c | CTL_BIT);
+        fi.w = KIND_REQ << 30;
+        k5.w = -1;
+        d5 = true;
       } else if (k5.x >= 0) {  // a migrated block's new owner, to its directory tile
         fi.x = dir_of(k5.x);
         fi.y = (int)((uint32_t)c | CTL_BIT);
@@ -1037,8 +1089,6 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   }
   if (dirtyR) set_store(setR, C.w2, vR);
   if (dirtyL) set_store(setL, C.w2, vL);
-  if (mig && dirtyR) set_store(recR, C.w2, hR);
-  if (mig && dirtyL) set_store(recL, C.w2, hL);
   if (dirty1) set_store(set1, C.w1, u);
   if (node_rq >= 0) {
     st_node<MULTI>(&C.node[node_rq], make_int4(-1, node_ready, node_line, node_w));
@@ -1092,7 +1142,11 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
     acc.lat_bg += as_bg ? ulat : 0ull;
     atomicMax(&L.v[SIM_ST_LAT_MAX], (unsigned long long)lat);
     lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
-    if (kind == KIND_REQ) {
+    if (kind == KIND_REQ && ctl) {  // migration: the block this slice sent has arrived
+      k1.x = oe.z | (Q_ARRIVED << 24);
+      k1.y = k5.y;  // the block it sent (one at a time)
+      d1 = true;
+    } else if (kind == KIND_REQ) {
       lds_add(L, SIM_ST_REQ_RECV, 1);
       k1.x = oe.z;
       k1.y = oe.w & LINE_MASK;
@@ -1110,8 +1164,10 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       if (code == CODE_MIG) {  // a flit of the block migrating here; the last one fills it in
         rcv += 1;
         d3 = true;
-        if (rcv >= MIG_FLITS) {
+        if (rcv >= MIG_FLITS) {  // the whole block is in; its source is told (Sec. 3.3)
           rcv = 0;
+          k5.w = oe.z;
+          d5 = true;
           k0.x = CORE_FILL_MIG;
           k0.y = c + 1;
         }
@@ -2074,7 +2130,7 @@ bool config_ok(const sim_config* c) {
   if (c->flags & ~VARIANT_FLAGS) return false;
   if (c->router_delay < 0 || c->router_delay > 8) return false;
   if ((c->flags & SIM_FLAG_LSPD_CENTRAL) && !(c->flags & SIM_FLAG_LSPD)) return false;
-  if (c->mig_threshold < 0 || c->mig_threshold > 4095 || (c->mig_threshold && !(c->flags & SIM_FLAG_LSPD))) return false;
+  if (c->mig_threshold < 0 || c->mig_threshold > MIG_MAX || (c->mig_threshold && !(c->flags & SIM_FLAG_LSPD))) return false;
   if ((int64_t)c->shared_lines + N * c->private_lines > (int64_t)LINE_MASK + 1) return false;
   return true;
 }
@@ -2114,7 +2170,7 @@ Layout layout(const sim_config* c) {
   L.node = take(N * sizeof(int4));
   L.l1 = take(N * c->l1_sets * c->l1_ways * sizeof(int32_t));
   L.l2 = take(N * c->l2_sets * c->l2_ways * sizeof(int32_t));
-  L.l2h = take(c->mig_threshold > 0 ? N * c->l2_sets * c->l2_ways * sizeof(int32_t) : 0);
+  L.l2h = take(c->mig_threshold > 0 ? N * c->l2_sets * c->l2_ways * c->mig_threshold * sizeof(int32_t) : 0);
   L.zs = take((ZIPF_K + 1) * sizeof(uint32_t));
   L.zp = take((ZIPF_K + 1) * sizeof(uint32_t));
   L.flags = take(maxp * FLAG_STRIDE * sizeof(int32_t));
@@ -2437,7 +2493,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if ((rc = launch_grid_fill_i32(reinterpret_cast<int32_t*>(d.pipe), -1, (size_t)(d.rdelay - 1) * 4 * N * 4, h->stream)))
     return fail(rc);
   if ((rc = launch_grid_fill_i32(d.loc, -1, lspd_lines(cfg), h->stream))) return fail(rc);
-  if ((rc = launch_grid_fill_i32(d.l2h, 0, cfg->mig_threshold > 0 ? (size_t)N * cfg->l2_sets * cfg->l2_ways : 0, h->stream)))
+  if ((rc = launch_grid_fill_i32(d.l2h, -1, cfg->mig_threshold > 0 ? (size_t)N * cfg->l2_sets * cfg->l2_ways * cfg->mig_threshold : 0, h->stream)))
     return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l1, -1, (size_t)N * cfg->l1_sets * cfg->l1_ways, h->stream))) return fail(rc);
   if ((rc = launch_grid_fill_i32(d.l2, -1, (size_t)N * cfg->l2_sets * cfg->l2_ways, h->stream))) return fail(rc);
@@ -2524,7 +2580,7 @@ size_t sim_dump_words(const sim_t* h) {
   if (!h) return 0;
   const size_t N = (size_t)h->hd.N;
   return 16 + N * 16 + N * CORE_RECORD + N * h->hd.s1 * h->hd.w1 + N * h->hd.s2 * h->hd.w2 + 2 * NSTAT + N * 4 +
-         (size_t)(h->hd.rdelay - 1) * N * 20 + (size_t)h->hd.lines + (h->hd.mig ? N * h->hd.s2 * h->hd.w2 : 0);
+         (size_t)(h->hd.rdelay - 1) * N * 20 + (size_t)h->hd.lines + (size_t)N * h->hd.s2 * h->hd.w2 * h->hd.mig;
 }
 
 int sim_dump(sim_t* h, int32_t* buf, size_t words) {
@@ -2584,8 +2640,8 @@ int sim_dump(sim_t* h, int32_t* buf, size_t words) {
     HIPCHECK(hipMemcpyAsync(buf + o, h->hd.loc, (size_t)h->hd.lines * 4, hipMemcpyDeviceToHost, h->stream));
     o += (size_t)h->hd.lines;
   }
-  if (h->hd.mig)  // migration: the access record of every L2 way
-    HIPCHECK(hipMemcpyAsync(buf + o, h->hd.l2h, N * h->hd.s2 * h->hd.w2 * 4, hipMemcpyDeviceToHost, h->stream));
+  if (h->hd.mig)  // migration: the last `mig` accessors of every L2 way, most recent first
+    HIPCHECK(hipMemcpyAsync(buf + o, h->hd.l2h, N * h->hd.s2 * h->hd.w2 * h->hd.mig * 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   return SIM_OK;
 }
@@ -2626,8 +2682,10 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
     if (r[20] < -1 || r[20] >= (int32_t)N || r[21] < -1 || r[21] >= h->hd.lines) return SIM_EINVAL;
     // migration words: a claim and a forwarding pointer only with migration
     if (!h->hd.mig && (r[24] != -1 || r[25] != -1 || r[26] != -1 || r[27] != -1)) return SIM_EINVAL;
-    if (r[24] < -1 || r[24] >= h->hd.lines || r[25] < -1 || r[25] >= h->hd.lines || r[26] < -1 ||
-        r[26] >= (int32_t)N)
+    // (a forwarding destination carries MIG_TRANSIT while its block is on the way)
+    const int32_t fwd = r[26] >= 0 ? (r[26] & ~MIG_TRANSIT) : r[26];
+    if (r[24] < -1 || r[24] >= h->hd.lines || r[25] < -1 || r[25] >= h->hd.lines || fwd < -1 ||
+        fwd >= (int32_t)N || r[27] < -1 || r[27] >= (int32_t)N)
       return SIM_EINVAL;
     core[3 * N + t] = make_int4(r[15], r[16], r[18], r[19]);
     core[4 * N + t] = make_int4(r[20], r[21], r[22], r[23]);
@@ -2676,7 +2734,7 @@ int sim_load(sim_t* h, const int32_t* buf, size_t words) {
   if (D > 1) HIPCHECK(hipMemcpyAsync(h->hd.pipe, pipe.data(), pipe.size() * sizeof(int4), hipMemcpyHostToDevice, h->stream));
   if (h->hd.lines) HIPCHECK(hipMemcpyAsync(h->hd.loc, locw, (size_t)h->hd.lines * 4, hipMemcpyHostToDevice, h->stream));
   if (h->hd.mig)
-    HIPCHECK(hipMemcpyAsync(h->hd.l2h, locw + h->hd.lines, N * h->hd.s2 * h->hd.w2 * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync(h->hd.l2h, locw + h->hd.lines, N * h->hd.s2 * h->hd.w2 * h->hd.mig * 4, hipMemcpyHostToDevice, h->stream));
   h->cycle = cyc;
   if ((rc = launch_grid_fill_i32(h->hd.flags, (int32_t)cyc, (size_t)h->hd.max_patches * FLAG_STRIDE, h->stream))) return rc;
   // the restored state is whole: an error recorded for the state it replaces no longer applies

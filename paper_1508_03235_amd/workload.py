@@ -85,7 +85,7 @@ class SimParams:
     reply_flits: int = 1      # flits per reply packet (the paper's Table 1: 4 for a remote L2 access)
     flags: int = 0            # model variants: AGE_DEFLECT | HIT_UNDER_MISS | INJECT_DELAY | LSPD [| LSPD_CENTRAL]
     router_delay: int = 1     # cycles per hop (a flit waits router_delay - 1 cycles in each router)
-    mig_threshold: int = 0    # LSPD: migrate a block to a remote tile after this many accesses in a row
+    mig_threshold: int = 0    # LSPD: history length N (<= 16); a block migrates to a tile that made most of its last N accesses
 
     @property
     def tiles(self) -> int:

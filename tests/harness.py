@@ -24,7 +24,7 @@ CORE = {"state": 0, "wake": 1, "line": 2, "issue": 3, "l2q": 4, "l2q_line": 5, "
         "hit_tail": 7, "miss_head": 8, "miss_tail": 9, "bg_pending": 10, "node_next": 11,
         "node_ready": 12, "node_line": 13, "force_line": 14, "force_dst": 15, "reply_flits_received": 16,
         "node_flits_sent": 17, "deferred_line": 18, "deferred_issue": 19, "target": 20, "pending_ev": 21,
-        "dir_sum_lo": 22, "dir_sum_hi": 23, "claim": 24, "fwd_line": 25, "fwd_dst": 26}
+        "dir_sum_lo": 22, "dir_sum_hi": 23, "claim": 24, "fwd_line": 25, "fwd_dst": 26, "note": 27}
 N_STATS = 64
 
 
@@ -51,8 +51,9 @@ def split_dump(buf, params):
     out["pipe_ages"] = buf[o:o + (D - 1) * N * 4].reshape(D - 1, N, 4); o += (D - 1) * N * 4
     lines = params.shared_lines + N * params.private_lines if int(buf[14]) else 0
     out["loc"] = buf[o:o + lines]; o += lines   # LSPD directory: owner of each line, -1 = not on chip
-    ways = N * params.l2_sets * params.l2_ways if int(buf[15]) else 0
-    out["l2rec"] = buf[o:o + ways].reshape(-1, params.l2_sets, params.l2_ways) if ways else buf[o:o]
+    mig = int(buf[15])   # migration: each L2 way's last `mig` accessors, most recent first
+    ways = N * params.l2_sets * params.l2_ways * mig
+    out["l2rec"] = buf[o:o + ways].reshape(-1, params.l2_sets, params.l2_ways * mig) if ways else buf[o:o]
     return out
 
 

@@ -85,15 +85,16 @@ def test_model_options_validation():
     assert base > 0
     for bad in [p.with_(reply_flits=17), p.with_(reply_flits=-1), p.with_(flags=32), p.with_(flags=W.LSPD_CENTRAL),
                 p.with_(router_delay=9), p.with_(router_delay=-1), p.with_(mig_threshold=2),
-                p.with_(flags=W.LSPD, mig_threshold=4096)]:
+                p.with_(flags=W.LSPD, mig_threshold=17)]:
         assert size(bad) == 0, bad
     for ok in [p.with_(reply_flits=16), p.with_(flags=W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
-               p.with_(router_delay=8), p.with_(flags=W.LSPD | W.LSPD_CENTRAL)]:
+               p.with_(router_delay=8), p.with_(flags=W.LSPD | W.LSPD_CENTRAL),
+               p.with_(flags=W.LSPD, mig_threshold=16)]:
         assert size(ok) > 0, ok
     lines = p.shared_lines + p.tiles * p.private_lines
     assert size(p.with_(flags=W.LSPD)) >= base + 4 * lines                  # location array
     ways = p.tiles * p.l2_sets * p.l2_ways
-    assert size(p.with_(flags=W.LSPD, mig_threshold=2)) >= size(p.with_(flags=W.LSPD)) + 4 * ways  # way records
+    assert size(p.with_(flags=W.LSPD, mig_threshold=3)) >= size(p.with_(flags=W.LSPD)) + 3 * 4 * ways  # way histories
     assert size(p.with_(router_delay=3)) >= base + 2 * 4 * 16 * p.tiles    # two pipeline stages
 
 

@@ -3,27 +3,56 @@ import pytest
 
 from oracle import oracle as O
 from paper_1508_03235_amd import workload as W
-from tests.harness import CORE, STAT, quiet_params, split_dump
+from tests.harness import CORE, STAT, split_dump
 from tests.test_gpu_parity import assert_same_run, gpu_sim
-from tests.test_oracle_lspd import M, _run_ops
+from tests import test_oracle_migration as OM
 
 pytestmark = pytest.mark.gpu
 
 LSPD, CENTRAL = W.LSPD, W.LSPD_CENTRAL
 
 
-def test_gpu_hand_trace_migration_and_redirection():
-    """The oracle's hand trace on the GPU: M + 4, 11, 1 + M, then the migration (30) and the
-    redirected request (15)."""
-    p = quiet_params(2, 2, l1_lat=1, mem_lat=M, flags=LSPD, mig_threshold=2, l1_sets=1, l1_ways=1)
-    sim = gpu_sim(p)
-    assert _run_ops(sim, [(0, 0, 5)]) == {0: M + 4}
-    assert _run_ops(sim, [(sim.cycle + 2, 3, 5)]) == {0: 11}
-    assert _run_ops(sim, [(sim.cycle + 2, 3, 7)]) == {0: 1 + M}
-    c0 = sim.cycle + 2
-    assert _run_ops(sim, [(c0, 3, 5), (c0 + 20, 2, 5)]) == {0: 30, 1: 15}
-    st = sim.stats()
-    assert st[STAT["migrations"]] == 1 and st[STAT["redirects"]] == 1
+def test_gpu_hand_trace_migration_then_redirection():
+    """The oracle's hand trace on the GPU: the block migrates (31) and a request that reaches
+    the source after the arrival notice is redirected (17)."""
+    OM.test_hand_trace_migration_then_redirection(make_sim=gpu_sim)
+
+
+def test_gpu_hand_trace_source_serves_during_transit():
+    """A request that reaches the source while the block is on its way is served there (14)."""
+    OM.test_hand_trace_source_serves_during_transit(make_sim=gpu_sim)
+
+
+def test_gpu_hand_trace_source_evicts_the_block_on_its_way():
+    """The source's one-way slice drops the block while it is on its way: no eviction notice."""
+    OM.test_hand_trace_source_evicts_the_block_on_its_way(make_sim=gpu_sim)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_gpu_migration_races_under_pressure(seed):
+    """The oracle's high-pressure migration runs (late arrival notices, sources evicting blocks
+    on their way, blocks moving on before the notice): every digest and the state after a
+    drain equal the oracle's."""
+    import random
+    rng = random.Random(500 + seed)
+    w, h = [(3, 3), (4, 4), (3, 2), (5, 3)][seed % 4]
+    p = OM._params(rng, w, h, LSPD | (CENTRAL if seed % 2 else 0), 1, op_thr=W.thr(0.9), shared_thr=W.thr(0.95),
+                   shared_lines=6 + seed, private_lines=2, bg_thr=0, reply_flits=1 + seed % 3, mem_lat=5,
+                   l2_sets=1, l2_ways=1 + seed % 2, l1_sets=1)
+    g, o = assert_same_run(p, 2000, step_sizes=[1, 999, 1000])
+    for s in (g, o):
+        s.set_rates(0, 0)
+        s.step(2000)
+    assert o.quiescent() and (g.dump() == o.dump()).all()
+
+
+@pytest.mark.parametrize("mig,pattern,moved", OM.MAJORITY_CASES + [(3, [8, 0, 4], 0), (16, [8] * 9, 1),
+                                                                  (16, [8] * 8, 0)])
+def test_gpu_majority_of_the_last_n_accesses(mig, pattern, moved):
+    g = OM.remote_reads(mig, pattern, make_sim=gpu_sim)
+    o = OM.remote_reads(mig, pattern)
+    assert g.stat("migrations") == o.stat("migrations") == moved
+    assert (g.dump() == o.dump()).all()   # tags, histories, forwarding words, location array
 
 
 @pytest.mark.parametrize("thr", [1, 2, 4])
