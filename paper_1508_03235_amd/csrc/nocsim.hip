@@ -1348,40 +1348,55 @@ __global__ void __launch_bounds__(256) step_kernel(const LaunchEntry* __restrict
 //    finishes cycle c+1, while its next writer is at least three cycles of flit traffic away.
 constexpr int FAST_MAX = 256;
 
-// Productive ports of a flit with destination d at the tile (x, y): bit p for each output port
-// p that brings it closer (0 north, 1 south, 2 east, 3 west), or bit 4 alone when d is the tile
-// itself.  The destination's row is d / W by the reciprocal (wm = ceil(2^32 / W)); with W = 1,
-// wm = 0 and wsel = ~0 make the row d itself.
-__device__ __forceinline__ uint32_t prod_mask(int d, int x, int y, int W, uint32_t wm, uint32_t wsel) {
+// Productive ports of a flit with destination d at the tile (x, y), as five bits in the order the
+// assignment tries them: bit 0 the eject port (d is the tile itself), bit 1 east and bit 2 west
+// (the X port), bit 3 north and bit 4 south (the Y port).  The destination's row is d / W by
+// the reciprocal (wm = ceil(2^32 / W)); with W = 1, wm = 0 and wsel = ~0 make the row d itself.
+// The offsets' signs plus one (0, 1, 2), clamped in one instruction each, index a table of
+// nine 5-bit entries; the caller passes x - 1 and y - 1 (xm1, ym1) so that the +1 is free.
+__device__ __forceinline__ uint32_t clamp02(int v) {  // max(0, min(v, 2)) in one instruction
+  int r;
+  asm("v_med3_i32 %0, %1, 0, 2" : "=v"(r) : "v"(v));
+  return (uint32_t)r;
+}
+constexpr unsigned long long PROD_TABLE =  // entry 3 (sign x + 1) + (sign y + 1), 5 bits each
+    (12ull << 0) | (4ull << 5) | (20ull << 10) |   // west: with north, alone, with south
+    (8ull << 15) | (1ull << 20) | (16ull << 25) |  // north, eject, south
+    (10ull << 30) | (2ull << 35) | (18ull << 40);  // east: with north, alone, with south
+__device__ __forceinline__ uint32_t prod_mask(int d, int xm1, int ym1, int negW, uint32_t wm, uint32_t wsel) {
   const int drow = (int)(__umulhi((uint32_t)d, wm) | ((uint32_t)d & wsel));
-  const int dx = d - drow * W - x, dy = drow - y;
-  const int sx = min(max(dx, -1), 1), sy = min(max(dy, -1), 1);
-  // nibble tables indexed by sign + 1: west / none / east, north / none / south
-  const uint32_t mxy = ((0x408u >> (4 * (sx + 1))) | (0x201u >> (4 * (sy + 1)))) & 15u;
-  return mxy ? mxy : 16u;
+  const uint32_t ux = clamp02(d - xm1 + __mul24(drow, negW)), uy = clamp02(drow - ym1);
+  return (uint32_t)(PROD_TABLE >> (__umul24(ux, 15u) + __umul24(uy, 5u))) & 31u;
 }
 
 // One step of the oldest-first assignment, for the flit with sort key q (prod_mask at bits 3-7,
 // input index i as i ^ 7 at bits 0-2; all ones when empty): the eject port if it is destined
 // here and the port is free, else its X-productive port, else its Y-productive port, if free,
 // else the lowest free valid port (a deflection; a destined flit that lost the eject port is
-// deflected too).  Marks the port in `used` (bit 4 = eject) and records the flit's input index
-// in the port's 3-bit field of `inv`, which starts as all 7s (none).  ndefl counts deflections;
-// with DEFL_MASK the deflected flits' input indices are marked in `dm`.
+// deflected too).  `taken` holds the ports in two orders at once: bits 0-4 as prod_mask orders
+// them, bits 5-8 north, south, east, west (the deflection order; ports off the mesh start out
+// taken), so the lowest free bit of (mask | 5-8) is the flit's port.  The flit's input index is
+// recorded in the port's 3-bit field of `inv` (port 4 = eject), which starts as all 7s (none).
+// ndefl counts deflections; with DEFL_MASK the deflected flits' input indices are marked in dm.
+constexpr uint32_t CODE_PORT = 4u | (2u << 3) | (3u << 6) | (0u << 9) | (1u << 12) |  // port of
+                               (0u << 15) | (1u << 18) | (2u << 21) | (3u << 24) | (7u << 27);  // each bit
+constexpr unsigned long long CODE_TWIN =  // the port's bit in the other order, 4 bits per code
+    (0ull << 0) | (7ull << 4) | (8ull << 8) | (5ull << 12) | (6ull << 16) | (3ull << 20) | (4ull << 24) |
+    (1ull << 28) | (2ull << 32) | (9ull << 36);
 template <bool DEFL_MASK>
-__device__ __forceinline__ void arb_assign_mask(unsigned long long q, unsigned valid, unsigned& used, uint32_t& inv,
-                                                unsigned& dm, int& ndefl) {
+__device__ __forceinline__ void arb_assign_mask(unsigned long long q, uint32_t& taken, uint32_t& inv, unsigned& dm,
+                                                int& ndefl) {
   const uint32_t lo = (uint32_t)q;
-  const bool live = (uint32_t)(q >> 32) != 0xFFFFFFFFu;  // inject cycles stay below 2^31
-  const uint32_t a = (lo >> 3) & 31u & ~used;
-  const uint32_t ax = a & 12u, ay = a & 3u;
-  uint32_t sel = ay ? ay : (valid & ~used);
-  sel = ax ? ax : sel;
-  sel = (a & 16u) ? 16u : sel;
-  const uint32_t port = (uint32_t)__builtin_ctz(sel | 32u);  // sel != 0 for a live flit
-  used |= live ? (1u << port) : 0u;
-  inv ^= live ? ((lo & 7u) << (3u * port)) : 0u;
-  const bool defl = live && a == 0u;
+  // all ones for a live flit (inject cycles stay below 2^31), zero for an empty one
+  const uint32_t lm = ~(uint32_t)((int)(q >> 32) >> 31);
+  // (a free port always exists for a live flit: it has at most deg - 1 rivals.  An empty one
+  // finds only bit 9, code 9, whose port field (7) and twin bit (9) nothing reads.)
+  const uint32_t code = (uint32_t)__builtin_ctz(((((lo >> 3) & 31u) | 0x1E0u) & ~taken & lm) | 0x200u);
+  const uint32_t port = (CODE_PORT >> (3u * code)) & 7u;
+  const uint32_t twin = (uint32_t)(CODE_TWIN >> (4u * code)) & 15u;
+  taken |= (1u << code) | (1u << twin);
+  inv ^= (lo & 7u) << (3u * port);
+  const bool defl = code - 5u < 4u;
   ndefl += defl ? 1 : 0;
   if (DEFL_MASK) dm |= defl ? (1u << ((lo & 7u) ^ 7u)) : 0u;
 }
@@ -1487,6 +1502,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const bool hum = VARS && (C.variants & SIM_FLAG_HIT_UNDER_MISS) != 0;  // ops drawn under a miss
   const int rd = PIPE ? C.rdelay : 1;  // router delay D: arrivals wait D-1 cycles in a pipeline
   const uint32_t wsel = C.W > 1 ? 0u : ~0u;  // prod_mask's row when the chip is one column wide
+  const int negW = -C.W;
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1614,9 +1630,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       const int dhl = hline, dhi = hissue;
       const int dfd = fdst, drcv = rcv;
       if (step) {
-        if ((k1.x >= 0 && (unsigned)k1.x >= (unsigned)N) || (k1.w >= 0 && (unsigned)k1.w >= (unsigned)N) ||
-            (k2.y >= 0 && (unsigned)k2.y >= (unsigned)N) || (k1.z >= 0 && (unsigned)k1.z >= (unsigned)N) ||
-            (k2.x >= 0 && (unsigned)k2.x >= (unsigned)N)) {
+        // (-1 = none maps to 0; a tile index to 1..N)
+        const uint32_t top = max(max(max((uint32_t)(k1.x + 1), (uint32_t)(k1.w + 1)), max((uint32_t)(k2.y + 1), (uint32_t)(k1.z + 1))),
+                                 (uint32_t)(k2.x + 1));
+        if (top > (uint32_t)N) {
           st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
           ok = false;
         }
@@ -1851,10 +1868,15 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         // 20-27, masked off here; the count itself is a first key word, most deflected first)
 #define SRCW(f) (VARS ? ((uint32_t)(f).z & TILE_BITS_MASK) : (uint32_t)(f).z)
 #define DSTW(f) (VARS ? (int)((uint32_t)(f).x & TILE_BITS_MASK) : (f).x)
-#define SKEY(f, i) ((f).x < 0 ? ~0ull : (((u64)(uint32_t)(f).y << 32) | ((u64)SRCW(f) << 8) | \
-                                          ((u64)prod_mask(DSTW(f), x, y, C.W, C.w_magic, wsel) << 3) | (u64)((i) ^ 7)))
-        u64 q0 = SKEY(f0, 0), q1 = SKEY(f1, 1), q2 = SKEY(f2, 2), q3 = SKEY(f3, 3), q4 = SKEY(fi, 4);
+#define PM(f) prod_mask(DSTW(f), x - 1, y - 1, negW, C.w_magic, wsel)
+        // (the masks are computed for every input, empty or not, so that no branch is taken here)
+        const uint32_t m0 = PM(f0), m1 = PM(f1), m2 = PM(f2), m3 = PM(f3), m4 = PM(fi);
+        // (an empty input's dst is -1: its sign makes both halves of the key all ones, no branch)
+#define SKEY(f, m, i) ((u64)((uint32_t)(f).y | (uint32_t)((f).x >> 31)) << 32 | \
+                       (u64)((SRCW(f) << 8) | ((m) << 3) | (uint32_t)((i) ^ 7) | (uint32_t)((f).x >> 31)))
+        u64 q0 = SKEY(f0, m0, 0), q1 = SKEY(f1, m1, 1), q2 = SKEY(f2, m2, 2), q3 = SKEY(f3, m3, 3), q4 = SKEY(fi, m4, 4);
 #undef SKEY
+#undef PM
 #undef DSTW
 #undef SRCW
 #define AKEY(f) ((f).x < 0 ? ~0u : (uint32_t)AGE_MAX - row_age(f))
@@ -1871,18 +1893,19 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         CSWAP(0, 1) CSWAP(3, 4) CSWAP(2, 4) CSWAP(2, 3) CSWAP(1, 4) CSWAP(0, 3) CSWAP(0, 2) CSWAP(1, 3) CSWAP(1, 2)
 #undef CSWAP
         s_link[cur][4][j] = fi;
-        const unsigned valid = (v0 ? 1u : 0u) | (v1 ? 2u : 0u) | (v2 ? 4u : 0u) | (v3 ? 8u : 0u);
-        unsigned used = 0, dm = 0;
+        // ports off the mesh start out taken (bits 5-8: north, south, east, west)
+        uint32_t taken = (v0 ? 0u : 32u) | (v1 ? 0u : 64u) | (v2 ? 0u : 128u) | (v3 ? 0u : 256u);
+        unsigned dm = 0;
         uint32_t inv = 0x7FFFu;
         int ndefl = 0;
-        arb_assign_mask<VARS>(q0, valid, used, inv, dm, ndefl);
-        arb_assign_mask<VARS>(q1, valid, used, inv, dm, ndefl);
-        arb_assign_mask<VARS>(q2, valid, used, inv, dm, ndefl);
-        arb_assign_mask<VARS>(q3, valid, used, inv, dm, ndefl);
-        arb_assign_mask<VARS>(q4, valid, used, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q0, taken, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q1, taken, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q2, taken, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q3, taken, inv, dm, ndefl);
+        arb_assign_mask<VARS>(q4, taken, inv, dm, ndefl);
         {  // every live flit moves over a link except the one ejected
           const int nlive = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0) + (fi.x >= 0);
-          acc.trav += nlive - (int)((used >> 4) & 1u);
+          acc.trav += nlive - (int)(taken & 1u);
           acc.defl += ndefl;
         }
 
