@@ -185,8 +185,9 @@ template <bool COH> __device__ __forceinline__ void st_i(int* p, int v) { if (CO
 // the "ready" signal arrive together, with no separate flag and no store drain.  A slot is
 // rewritten every second cycle, so the stamp it can hold besides the awaited cycle c is c-2.
 // Bits 20-27 of the dst word and of the src word hold the low and high byte of the flit's
-// deflection count (priority by deflection count; 0 otherwise).  An empty slot has
-// dst = src = 0xFFFFF and count 0.
+// deflection count (priority by deflection count; 0 otherwise).  An empty slot has 0xFFFFF in
+// the tile bits of its dst word; its other words are not read (slot_encode writes src 0xFFFFF,
+// count 0 and -1s, slot_encode_row leaves them as they come).
 constexpr uint32_t TILE_BITS_MASK = 0xFFFFFu;
 constexpr int AGE_SHIFT = 20;
 constexpr int STAMP_SHIFT = 28;
@@ -197,6 +198,13 @@ __device__ __forceinline__ int4 slot_encode(const int4& f, uint32_t stamp) {
   const bool empty = f.x < 0;  // selects, not a branch: every word of f is read either way
   return make_int4((int)((empty ? TILE_BITS_MASK : (uint32_t)f.x) | s), empty ? -1 : f.y,
                    (int)((empty ? TILE_BITS_MASK : (uint32_t)f.z) | s), empty ? -1 : f.w);
+}
+// The same for a flit row whose empty form has dst = -1 exactly (the other words of an empty
+// row may be anything): two instructions, the stamp put over bits 28-31 of dst and src.
+constexpr uint32_t STAMP_OFF = ~(STAMP_MASK << STAMP_SHIFT);
+__device__ __forceinline__ int4 slot_encode_row(const int4& f, uint32_t stamp) {
+  const uint32_t s = (stamp & STAMP_MASK) << STAMP_SHIFT;
+  return make_int4((int)(((uint32_t)f.x & STAMP_OFF) | s), f.y, (int)(((uint32_t)f.z & STAMP_OFF) | s), f.w);
 }
 __device__ __forceinline__ int4 slot_encode_aged(const int4& f, uint32_t stamp, uint32_t age) {
   int4 w = slot_encode(f, stamp);
@@ -217,7 +225,6 @@ __device__ __forceinline__ int4 slot_decode(const int4& w) {
 }
 // The same, keeping the deflection count in bits 20-27 of the dst and src words (the
 // one-tile-per-thread kernel's flit rows under priority by deflection count).
-constexpr uint32_t STAMP_OFF = ~(STAMP_MASK << STAMP_SHIFT);
 __device__ __forceinline__ int4 slot_decode_aged(const int4& w) {
   if (((uint32_t)w.x & TILE_BITS_MASK) == TILE_BITS_MASK) return make_int4(-1, -1, -1, -1);
   return make_int4((int)((uint32_t)w.x & STAMP_OFF), w.y, (int)((uint32_t)w.z & STAMP_OFF), w.w);
@@ -1741,11 +1748,18 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
-      // this cycle's arrivals
-      const int4 a0 = sel4(i0, l0, e0 ? (VARS ? slot_decode_aged(w0) : slot_decode(w0)) : EMPTY);
-      const int4 a1 = sel4(i1, l1, e1 ? (VARS ? slot_decode_aged(w1) : slot_decode(w1)) : EMPTY);
-      const int4 a2 = sel4(i2, l2, e2 ? (VARS ? slot_decode_aged(w2) : slot_decode(w2)) : EMPTY);
-      const int4 a3 = sel4(i3, l3, e3 ? (VARS ? slot_decode_aged(w3) : slot_decode(w3)) : EMPTY);
+      // this cycle's arrivals.  The checking build hashes them, so it decodes them whole; the
+      // timed build only makes dst -1 for an empty input: nothing reads the other words of an
+      // empty row (keys take its sign, outputs gather only assigned rows or the empty row 5)
+      auto arrival = [&](bool in, bool edge, const int4& l, const int4& w) -> int4 {
+        if (DIGEST) return sel4(in, l, edge ? (VARS ? slot_decode_aged(w) : slot_decode(w)) : EMPTY);
+        const uint32_t keep = VARS ? STAMP_OFF : TILE_BITS_MASK;  // (the count rides along)
+        const bool live = edge && ((uint32_t)w.x & TILE_BITS_MASK) != TILE_BITS_MASK;
+        return make_int4(in ? l.x : (live ? (int)((uint32_t)w.x & keep) : -1), in ? l.y : w.y,
+                         in ? l.z : (int)((uint32_t)w.z & keep), in ? l.w : w.w);
+      };
+      const int4 a0 = arrival(i0, e0, l0, w0), a1 = arrival(i1, e1, l1, w1);
+      const int4 a2 = arrival(i2, e2, l2, w2), a3 = arrival(i3, e3, l3, w3);
       // this cycle's arbitration inputs: the arrivals, or with D > 1 the flits that arrived D-1
       // cycles ago, leaving the pipeline now
       const bool piped = PIPE && rd > 1 && step;
@@ -1941,10 +1955,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           bump(o3, 3);
         }
         const uint32_t ns = (uint32_t)(c + 1);
-        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode(o0, ns), MULTI);
-        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode(o1, ns), MULTI);
-        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode(o2, ns), MULTI);
-        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode(o3, ns), MULTI);
+        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode_row(o0, ns), MULTI);
+        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode_row(o1, ns), MULTI);
+        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode_row(o2, ns), MULTI);
+        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode_row(o3, ns), MULTI);
         // inside the patch: the neighbour's input slot opp(p) in LDS
         if (i0) s_link[nxt][1][j - cols] = o0;
         if (i1) s_link[nxt][0][j + cols] = o1;
