@@ -1531,7 +1531,28 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
            ((a2 && !b2) ? 1024u : 0u) | ((a3 && !b3) ? 2048u : 0u);
   }
 #define GEO(bit) (((geo >> (bit)) & 1u) != 0u)
+#define GEO_BIT(g, bit) ((((g) >> (bit)) & 1u) != 0u)
   const int4 EMPTY = make_int4(-1, -1, -1, -1);
+  // Patch-edge slots as byte offsets inside one parity's half of the slot array (which is
+  // 4 N slots of 16 bytes): the slot each edge input is read from (0, a shared slot, where port
+  // p has no patch edge) and the neighbour's slot each edge output goes to (0 where unused).
+  // The half's base is the same for the whole launch, so it is kept in scalar registers and a
+  // slot access needs no address arithmetic of its own.
+  uint32_t ein0 = 0, ein1 = 0, ein2 = 0, ein3 = 0, eout0 = 0, eout1 = 0, eout2 = 0, eout3 = 0;
+  {
+    const uint32_t n16 = (uint32_t)N * 16u, t16 = (uint32_t)t * 16u, w16 = (uint32_t)C.W * 16u;
+    if (GEO_BIT(geo0, 8)) { ein0 = t16; eout0 = n16 + t16 - w16; }       // north: its south input
+    if (GEO_BIT(geo0, 9)) { ein1 = n16 + t16; eout1 = t16 + w16; }       // south: its north input
+    if (GEO_BIT(geo0, 10)) { ein2 = 2 * n16 + t16; eout2 = 3 * n16 + t16 + 16; }  // east: its west
+    if (GEO_BIT(geo0, 11)) { ein3 = 3 * n16 + t16; eout3 = 2 * n16 + t16 - 16; }  // west: its east
+  }
+  const unsigned long long link_u = (unsigned long long)(uintptr_t)C.link;
+  const char* const link_s = reinterpret_cast<const char*>(
+      (uintptr_t)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(link_u >> 32)) << 32) |
+                  (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)link_u)));
+  const uint32_t half16 = (uint32_t)N * 64u;  // bytes of one parity's half
+#define EDGE_IN(par, off) reinterpret_cast<const int4*>(link_s + (size_t)((par) ? half16 : 0u) + (size_t)(off))
+#define EDGE_OUT(par, off) reinterpret_cast<int4*>(const_cast<char*>(link_s) + (size_t)((par) ? half16 : 0u) + (size_t)(off))
 
   for (int i = threadIdx.x; i < NSTAT; i += blockDim.x) L.v[i] = 0;
   if (threadIdx.x == 0) s_fail = 0;
@@ -1618,11 +1639,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         if (v3) pp3 = gload4(pq + 3 * N);
       }
       if (MULTI) {
-        const int4* shared_slot = C.link;
-        w0 = ld_slot(e0 ? &C.link[(cur * 4 + 0) * N + t] : shared_slot, true);
-        w1 = ld_slot(e1 ? &C.link[(cur * 4 + 1) * N + t] : shared_slot, true);
-        w2 = ld_slot(e2 ? &C.link[(cur * 4 + 2) * N + t] : shared_slot, true);
-        w3 = ld_slot(e3 ? &C.link[(cur * 4 + 3) * N + t] : shared_slot, true);
+        w0 = ld_slot(EDGE_IN(cur, ein0), true);
+        w1 = ld_slot(EDGE_IN(cur, ein1), true);
+        w2 = ld_slot(EDGE_IN(cur, ein2), true);
+        w3 = ld_slot(EDGE_IN(cur, ein3), true);
       }
       // the four input rows of this tile, read by every lane (rows of ports without an
       // in-patch neighbour hold stale words, replaced below); their wait hides behind phase one
@@ -1741,10 +1761,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             ok = false;
             break;
           }
-          if (p0) w0 = ld_slot(&C.link[(cur * 4 + 0) * N + t], true);
-          if (p1) w1 = ld_slot(&C.link[(cur * 4 + 1) * N + t], true);
-          if (p2) w2 = ld_slot(&C.link[(cur * 4 + 2) * N + t], true);
-          if (p3) w3 = ld_slot(&C.link[(cur * 4 + 3) * N + t], true);
+          if (p0) w0 = ld_slot(EDGE_IN(cur, ein0), true);
+          if (p1) w1 = ld_slot(EDGE_IN(cur, ein1), true);
+          if (p2) w2 = ld_slot(EDGE_IN(cur, ein2), true);
+          if (p3) w3 = ld_slot(EDGE_IN(cur, ein3), true);
         }
       }
       __builtin_amdgcn_s_waitcnt(0);  // drain: every load of cycle c is in, every store of c-1 done
@@ -1955,10 +1975,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           bump(o3, 3);
         }
         const uint32_t ns = (uint32_t)(c + 1);
-        if (v0 && !i0) st_slot(&C.link[(nxt * 4 + 1) * N + t - C.W], slot_encode_row(o0, ns), MULTI);
-        if (v1 && !i1) st_slot(&C.link[(nxt * 4 + 0) * N + t + C.W], slot_encode_row(o1, ns), MULTI);
-        if (v2 && !i2) st_slot(&C.link[(nxt * 4 + 3) * N + t + 1], slot_encode_row(o2, ns), MULTI);
-        if (v3 && !i3) st_slot(&C.link[(nxt * 4 + 2) * N + t - 1], slot_encode_row(o3, ns), MULTI);
+        if (v0 && !i0) st_slot(EDGE_OUT(nxt, eout0), slot_encode_row(o0, ns), MULTI);
+        if (v1 && !i1) st_slot(EDGE_OUT(nxt, eout1), slot_encode_row(o1, ns), MULTI);
+        if (v2 && !i2) st_slot(EDGE_OUT(nxt, eout2), slot_encode_row(o2, ns), MULTI);
+        if (v3 && !i3) st_slot(EDGE_OUT(nxt, eout3), slot_encode_row(o3, ns), MULTI);
         // inside the patch: the neighbour's input slot opp(p) in LDS
         if (i0) s_link[nxt][1][j - cols] = o0;
         if (i1) s_link[nxt][0][j + cols] = o1;
@@ -2037,6 +2057,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   if (threadIdx.x == 0) st_coh(&C.flags[patch * FLAG_STRIDE], c_done);
   flush_counters(acc, L, C, patch, c0, c_done);
 #undef GEO
+#undef GEO_BIT
+#undef EDGE_IN
+#undef EDGE_OUT
 }
 
 // ---- small utility kernels (no memsets: these also record safely into graphs) -----------------
