@@ -148,7 +148,8 @@ int sim_div_constants(int32_t width, int32_t tiles, uint32_t* out);
 /* Creates one chip in `dev_mem` and initialises it (all links empty, cores idle, caches
    invalid, cycle 0).  zipf_shared / zipf_private: host arrays of zipf_k + 1 (= 65537)
    uint32 quantile boundaries (entry b = first rank whose CDF exceeds b/zipf_k; entry
-   zipf_k = region size); zipf_private may be NULL when private_lines == 0.  Copied. */
+   zipf_k = region size); zipf_private may be NULL when private_lines == 0.  Copied.  EINVAL
+   when a table decreases or its last entry exceeds its region's size. */
 int sim_create(const sim_config* cfg, const uint32_t* zipf_shared, const uint32_t* zipf_private,
                int32_t zipf_k, void* dev_mem, size_t bytes, void* stream, sim_t** out);
 

@@ -63,6 +63,8 @@ enum { Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3, Q_ARRIVED = 4 };
    carries this bit on its line word when it is a migration.  Each L2 way keeps the list of its
    last `mig` accessors, most recent first (-1 = none yet).  While a block this slice sends away
    is on its way, the slice's forwarding destination carries MIG_TRANSIT. */
+/* a flit kind in the top two bits of the info word (shifted unsigned: kind 2 reaches bit 31) */
+#define KIND_BITS(k) ((int32_t)((uint32_t)(k) << 30))
 #define MIG_FLITS 16
 #define MIG_MARK 0x40000000
 #define MIG_TRANSIT 0x40000000
@@ -747,32 +749,32 @@ static void phase_route(oracle_sim* s, int32_t t) {
       int32_t rq = list_pop(s, t, C_MISS_H, C_MISS_T);
       f[F_DST] = rq;
       f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-      f[F_INFO] = (K_REPLY << 30) | (s->core[(size_t)rq * C_WORDS + C_NLINE] + CODE_BASE);
+      f[F_INFO] = KIND_BITS(K_REPLY) | (s->core[(size_t)rq * C_WORDS + C_NLINE] + CODE_BASE);
       s->stats[OS_INJ_REPLY]++;
     } else if (cls == 2 && s->lspd) {
       const int32_t line = k[C_LINE];
       if (k[C_EV] >= 0) {                       /* eviction notice to the block's directory */
         f[F_DST] = dir_of(s, k[C_EV]);
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-        f[F_INFO] = (K_DIR << 30) | k[C_EV];
+        f[F_INFO] = KIND_BITS(K_DIR) | k[C_EV];
         k[C_EV] = -1;
       } else if (k[C_NOTE] >= 0) {              /* Sec. 3.3: the migrated block has arrived; its */
         f[F_DST] = k[C_NOTE];                   /* source drops its copy */
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-        f[F_INFO] = (K_REQ << 30);
+        f[F_INFO] = KIND_BITS(K_REQ);
         k[C_NOTE] = -1;
       } else if (k[C_CLAIM] >= 0) {             /* a migrated block's new owner, to the directory */
         f[F_DST] = dir_of(s, k[C_CLAIM]);
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-        f[F_INFO] = (K_BG << 30) | k[C_CLAIM];
+        f[F_INFO] = KIND_BITS(K_BG) | k[C_CLAIM];
         k[C_CLAIM] = -1;
       } else if (k[C_STATE] == ST_SEND_DA) {    /* directory access */
         f[F_DST] = dir_of(s, line);
-        f[F_INFO] = (K_DIR << 30) | line;
+        f[F_INFO] = KIND_BITS(K_DIR) | line;
         k[C_STATE] = ST_WAIT;
       } else {                                  /* remote access at the owner */
         f[F_DST] = k[C_TARGET];
-        f[F_INFO] = (K_REQ << 30) | line;
+        f[F_INFO] = KIND_BITS(K_REQ) | line;
         k[C_TARGET] = -1;
         k[C_STATE] = ST_WAIT;
       }
@@ -785,9 +787,9 @@ static void phase_route(oracle_sim* s, int32_t t) {
       f[F_DST] = rq;
       if (mig_pk) {
         f[F_INJ] = (int32_t)((uint32_t)c | CTL_BIT);
-        f[F_INFO] = (K_REPLY << 30) | (CODE_MIG + CODE_BASE);
+        f[F_INFO] = KIND_BITS(K_REPLY) | (CODE_MIG + CODE_BASE);
       } else {
-        f[F_INFO] = (K_REPLY << 30) | node[C_NLINE];
+        f[F_INFO] = KIND_BITS(K_REPLY) | node[C_NLINE];
       }
       s->stats[OS_INJ_REPLY]++;
       if (++node[C_NSENT] == (mig_pk ? MIG_FLITS : s->reply_flits)) {  /* the packet's last flit */
@@ -798,7 +800,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
       }
     } else if (cls == 2) {
       f[F_DST] = k[C_LINE] % s->N;
-      f[F_INFO] = (K_REQ << 30) | k[C_LINE];
+      f[F_INFO] = KIND_BITS(K_REQ) | k[C_LINE];
       k[C_STATE] = ST_WAIT;
       s->stats[OS_INJ_REQ]++;
     } else {
@@ -813,7 +815,7 @@ static void phase_route(oracle_sim* s, int32_t t) {
         f[F_DST] = d;
         k[C_BG]--;
       }
-      f[F_INFO] = K_BG << 30;
+      f[F_INFO] = KIND_BITS(K_BG);
       s->stats[OS_INJ_BG]++;
     }
   }
@@ -1126,6 +1128,11 @@ int oracle_create(const oracle_config* cfg, const uint32_t* zs, const uint32_t* 
   if (cfg->l1_lat < 1 || cfg->mem_lat < 1 || cfg->shared_lines < 1 || cfg->private_lines < 0) return ORACLE_EINVAL;
   if ((int64_t)cfg->shared_lines + N * cfg->private_lines > (int64_t)LINE_MASK + 1) return ORACLE_EINVAL;
   if (zk != 65536 || (cfg->private_lines > 0 && !zp)) return ORACLE_EINVAL;
+  /* a quantile table must not decrease and must stay inside its region */
+  for (int i = 0; i < zk; ++i)
+    if (zs[i] > zs[i + 1] || (cfg->private_lines > 0 && zp[i] > zp[i + 1])) return ORACLE_EINVAL;
+  if (zs[zk] > (uint32_t)cfg->shared_lines || (cfg->private_lines > 0 && zp[zk] > (uint32_t)cfg->private_lines))
+    return ORACLE_EINVAL;
   if (cfg->reply_flits < 0 || cfg->reply_flits > 16) return ORACLE_EINVAL;
   if (cfg->flags & ~(ORACLE_FLAG_AGE_DEFLECT | ORACLE_FLAG_HIT_UNDER_MISS | ORACLE_FLAG_INJECT_DELAY | ORACLE_FLAG_LSPD |
                      ORACLE_FLAG_LSPD_CENTRAL))

@@ -39,8 +39,9 @@ typedef struct {
   int32_t router_delay;        /* cycles a flit takes per hop, 1..8 (0 counts as 1): a flit that
                                   arrives at a router waits router_delay - 1 cycles in its
                                   pipeline before it is arbitrated */
-  int32_t mig_threshold;       /* LSPD migration (Sec. 3.3): a block moves to a remote tile whose
-                                  accesses to it, in a row, reach this count (0 = never, <= 4095) */
+  int32_t mig_threshold;       /* LSPD migration (Sec. 3.3): the length N of each L2 way's history
+                                  of its last accessors; a block moves to a remote tile that made
+                                  more than half of them (0 = never, <= 16) */
 } oracle_config;
 
 /* Model variants: each bit replaces one reading of the base model by a more literal one.
@@ -63,10 +64,11 @@ typedef struct {
      kept in a location array indexed by line; the entry of a line belongs to the line's
      directory slice, line mod N, or with LSPD_CENTRAL to the one tile at the mesh centre.
      The base model homes each line statically at slice line mod N.  With mig_threshold > 0 a
-     block migrates (Sec. 3.3): each L2 way records its last accessor and how many accesses in a
-     row came from it; when a remote tile's run reaches the threshold the owner sends it the
-     block (16 flits, Table 1) and keeps a forwarding pointer, answering a request that still
-     reaches it with a redirection (1 flit); the receiver claims the directory entry and its op
+     block migrates (Sec. 3.3): each L2 way keeps its last mig_threshold accessors; when a remote
+     tile has made more than half of them the owner sends it the block (16 flits, Table 1) and
+     keeps serving it from its own copy until the receiver's arrival notice comes back; then it
+     drops the copy and keeps a forwarding pointer, answering a request that still reaches it
+     with a redirection (1 flit).  The receiver claims the directory entry and its op
      completes with the directory's acknowledgement (a block under claim does not move on). */
 enum {
   ORACLE_FLAG_AGE_DEFLECT = 1, ORACLE_FLAG_HIT_UNDER_MISS = 2, ORACLE_FLAG_INJECT_DELAY = 4,

@@ -2476,6 +2476,13 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if (!out) return SIM_EINVAL;
   *out = nullptr;
   if (!config_ok(cfg) || !zs || zk != ZIPF_K || (cfg->private_lines > 0 && !zp) || !dev_mem) return SIM_EINVAL;
+  // a quantile table must not decrease and must stay inside its region (ranks below its size)
+  auto table_ok = [](const uint32_t* q, int32_t lines) {
+    for (int i = 0; i < ZIPF_K; ++i)
+      if (q[i] > q[i + 1]) return false;
+    return q[ZIPF_K] <= (uint32_t)lines;
+  };
+  if (!table_ok(zs, cfg->shared_lines) || (cfg->private_lines > 0 && !table_ok(zp, cfg->private_lines))) return SIM_EINVAL;
   const Layout Lo = layout(cfg);
   if (bytes < Lo.total) return SIM_ENOMEM;
   if (reinterpret_cast<uintptr_t>(dev_mem) % 256) return SIM_EINVAL;

@@ -72,6 +72,26 @@ def test_null_handles_rejected():
     assert lib.simb_create(None, -1, 64, 4, 16, C.c_void_p(256), 4096, None, C.byref(out)) == -1
 
 
+def test_zipf_tables_validated_before_any_device_work():
+    """A quantile table that decreases or runs past its region is refused (no device memory is
+    touched: the placeholder buffer below is never dereferenced)."""
+    lib = nocsim._lib()
+    p = W.config1().with_(width=4, height=4)
+    cfg = nocsim.SimConfig.from_params(p)
+    zs, zp = p.tables()
+    out = C.c_void_p()
+
+    def create(a, b):
+        return lib.sim_create(C.byref(cfg), a.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p),
+                              W.ZIPF_K, C.c_void_p(256), 1 << 30, None, C.byref(out))
+    past = zp.copy()
+    past[-1] = p.private_lines + 1
+    assert create(zs, past) == -1
+    down = zs.copy()
+    down[100] = down[101] + 1
+    assert create(down, zp) == -1
+
+
 def test_model_options_validation():
     """Host-side validation of the model options: reply packets, variant flags, router delay,
     the directory and migration; the location array and way records are sized in."""
