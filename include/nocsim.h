@@ -41,7 +41,8 @@ enum {
   SIM_EHIP = -3,       /* a HIP runtime call failed; sim_last_hip_error() has the code */
   SIM_EINVARIANT = -4, /* a state index out of range was caught on the device */
   SIM_EBUSY = -5,      /* slot in use / no free slot */
-  SIM_EHANG = -6       /* a bounded cross-workgroup wait ran out; results are invalid */
+  SIM_EHANG = -6,      /* a bounded cross-workgroup wait ran out; results are invalid */
+  SIM_ELIVELOCK = -7   /* the watchdog (sim_set_watchdog) saw a flit older than its bound */
 };
 
 /* Model parameters of one simulated chip.  Bernoulli draws are u32 and succeed when
@@ -210,6 +211,15 @@ int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr);
    workgroup exits normally and sim_sync / sim_stats report SIM_EHANG.  The chip's state is then
    invalid until sim_load (which clears the error; call with patch -1 first). */
 int sim_force_hang(sim_t* h, int32_t patch, int32_t cycle, int32_t polls);
+/* Watchdog, a debug mode (the model has no such check; the paper's oldest-first priority is
+   what makes a flit's age bounded, Sec. 4.2): with max_age > 0 every step of this chip checks,
+   for every router in every cycle, that each of its flits left by exactly one port and that no
+   flit waiting at it is older (current cycle - injection cycle) than max_age.  A violation
+   stops the chip: SIM_ELIVELOCK for the age, SIM_EINVARIANT for a lost or duplicated flit
+   (state invalid until sim_load).  The one-tile-per-thread kernel then runs its checking build
+   (slower); results are otherwise unchanged.  Applies to sim_step, not to batches.  0 = off
+   (the default). */
+int sim_set_watchdog(sim_t* h, int32_t max_age);
 
 /* Launch mapping: patch_w x patch_h tiles per workgroup (the chip is cut into patches; a tile
    on a patch edge waits for its neighbour's link slot to carry the cycle it needs, so patches

@@ -46,6 +46,11 @@ constexpr int CODE_ACK = -4, CODE_MIG = -3, CODE_TRAP = -2, CODE_NACK = -1, CODE
 // message types at a slice's service input (l2q >> 24): remote access, directory access, eviction
 // notice, ownership claim, a migrated block's arrival at its new owner
 constexpr int Q_RA = 0, Q_DA = 1, Q_EV = 2, Q_CLAIM = 3, Q_ARRIVED = 4;
+// A chip's error word: 0 none, 1 a bounded wait ran out, 2 a state index out of range, 3 an
+// interior slot from the wrong cycle, 4 a deflection count past its 16 bits, and with the
+// watchdog on, ERR_WATCHDOG a flit older than its bound and ERR_ROUTER a router whose flits
+// did not each leave by exactly one port.
+constexpr int ERR_WATCHDOG = 5, ERR_ROUTER = 6;
 // migration (Sec. 3.3): a block moves as 16 flits (Table 1); a queued reply that is a migration
 // carries MIG_MARK on its line word; each L2 way keeps its last `mig` accessors (most recent
 // first, -1 none), in the ways' order; while a block a slice sends away is on its way, the
@@ -92,6 +97,7 @@ struct ChipDev {
   int32_t pw, ph, pgx, pgy;  // patch shape and patch grid
   int32_t stop, max_patches; // cycle the chip stops at (single-chip launches); flag capacity
   int32_t spin_limit;        // polls before a cross-workgroup wait gives up (reports a hang)
+  int32_t watch_age;         // watchdog (debug): 0 off; else the oldest age a flit may reach
   int32_t halt_patch, halt_cycle;  // test hook: this patch advances no further than halt_cycle
   int4* link;                // [2 parity][4 port][N]
   int4* pipe;                // [D-1][4 port][N]: raw slot words of flits waiting in the routers'
@@ -1086,6 +1092,22 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
   assign(sd2, si2);
   assign(sd3, si3);
   assign(sd4, si4);
+  if (C.watch_age > 0) {  // watchdog (debug mode): every live flit leaves by exactly one port,
+    const int nlive = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0) + (fi.x >= 0);
+    uint32_t oldest = 0;  // and none is older than the bound (the oldest flit always advances)
+    if (f0.x >= 0) oldest = max(oldest, (uint32_t)c - ((uint32_t)f0.y & ym));
+    if (f1.x >= 0) oldest = max(oldest, (uint32_t)c - ((uint32_t)f1.y & ym));
+    if (f2.x >= 0) oldest = max(oldest, (uint32_t)c - ((uint32_t)f2.y & ym));
+    if (f3.x >= 0) oldest = max(oldest, (uint32_t)c - ((uint32_t)f3.y & ym));
+    if (__builtin_popcount(used) != nlive) {
+      st_coh(C.err, ERR_ROUTER);
+      return false;
+    }
+    if (oldest > (uint32_t)C.watch_age) {
+      st_coh(C.err, ERR_WATCHDOG);
+      return false;
+    }
+  }
 
   // ---- phase three: stores (caches, queue nodes, slots, core words) -------------------------
   if (pipe_now) {  // this cycle's arrivals enter the pipeline
@@ -1613,7 +1635,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
 
   for (int c = c0; c <= c_end; ++c) {
     const bool step = c < c_end;
-    const bool dig = DIGEST && c > c0;
+    const bool dig = DIGEST && digests != nullptr && c > c0;  // (the watchdog runs this build without)
     if (!step && !dig) break;
     const int cur = c & 1, nxt = cur ^ 1;
     unsigned long long h = 0;
@@ -1941,6 +1963,23 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           const int nlive = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0) + (fi.x >= 0);
           acc.trav += nlive - (int)(taken & 1u);
           acc.defl += ndefl;
+          if (DIGEST && C.watch_age > 0) {  // watchdog (debug mode, checking build only): every
+            // live flit took exactly one port (bits 0-4 of taken name the ports used, eject
+            // included), and none is older than the bound (the oldest flit always advances)
+            const uint32_t cu = (uint32_t)c;
+            uint32_t oldest = 0;
+            if (f0.x >= 0) oldest = max(oldest, cu - (uint32_t)f0.y);
+            if (f1.x >= 0) oldest = max(oldest, cu - (uint32_t)f1.y);
+            if (f2.x >= 0) oldest = max(oldest, cu - (uint32_t)f2.y);
+            if (f3.x >= 0) oldest = max(oldest, cu - (uint32_t)f3.y);
+            if (__builtin_popcount(taken & 31u) != nlive) {
+              st_coh(C.err, ERR_ROUTER);
+              ok = false;
+            } else if (oldest > (uint32_t)C.watch_age) {
+              st_coh(C.err, ERR_WATCHDOG);
+              ok = false;
+            }
+          }
         }
 
         if (PIPE && rd > 1) {  // this cycle's arrivals enter the pipeline (stamped, as on the links)
@@ -2409,16 +2448,18 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
 // opt: FAST_PACKETS when some chip of the table has multi-flit replies (the kernel then reads
 // each chip's count), FAST_VARIANTS when some chip has a variant the kernel carries, FAST_PIPE
 // when some chip has a router delay
+// checking: run the checking build of the one-tile-per-thread kernel even without digests (the
+// watchdog's checks live there)
 int launch_entries(const LaunchEntry* table, int64_t n, bool multi, bool fast, int block, int chunk,
-                   unsigned long long* digests, int digest_base, hipStream_t s, int opt, int var) {
+                   unsigned long long* digests, int digest_base, hipStream_t s, int opt, int var, bool checking = false) {
   if (n <= 0) return SIM_OK;
+  const bool chk = digests != nullptr || checking;
   if (multi) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, digests != nullptr, opt, var), dim3((unsigned)n), dim3(block),
-                                        args, 0, s));
+    HIPCHECK(hipLaunchCooperativeKernel(multi_kernel(fast, chk, opt, var), dim3((unsigned)n), dim3(block), args, 0, s));
   } else if (fast) {
     void* args[] = {(void*)&table, (void*)&chunk, (void*)&digests, (void*)&digest_base};
-    HIPCHECK(hipLaunchKernel(digests ? fast_build<false, true>(opt) : fast_build<false, false>(opt), dim3((unsigned)n),
+    HIPCHECK(hipLaunchKernel(chk ? fast_build<false, true>(opt) : fast_build<false, false>(opt), dim3((unsigned)n),
                              dim3(block), args, 0, s));
   } else {
     const dim3 g((unsigned)n), b(block);
@@ -2443,6 +2484,7 @@ const char* sim_strerror(int code) {
     case SIM_EINVARIANT: return "invariant violated";
     case SIM_EBUSY: return "busy";
     case SIM_EHANG: return "cross-workgroup wait timed out";
+    case SIM_ELIVELOCK: return "a flit outlived the watchdog's age bound";
     default: return "unknown error";
   }
 }
@@ -2514,6 +2556,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
     d.n_shift = dc[3];
   }
   d.spin_limit = SPIN_LIMIT;
+  d.watch_age = 0;
   d.halt_patch = -1;
   d.halt_cycle = 0;
   d.w1_shift = __builtin_ctz((unsigned)cfg->l1_ways);
@@ -2608,7 +2651,7 @@ static int check_err(sim_t* h) {
   int32_t err = 0;
   HIPCHECK(hipMemcpyAsync(&err, h->hd.err, sizeof err, hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  return err == 0 ? SIM_OK : err == 1 ? SIM_EHANG : SIM_EINVARIANT;
+  return err == 0 ? SIM_OK : err == 1 ? SIM_EHANG : err == ERR_WATCHDOG ? SIM_ELIVELOCK : SIM_EINVARIANT;
 }
 
 int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
@@ -2625,7 +2668,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
     int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
-                            fast_opt(h->hd), kernel_level(h->hd));
+                            fast_opt(h->hd), kernel_level(h->hd), h->hd.watch_age > 0);
     if (rc) return rc;
   }
   h->cycle += n;
@@ -2838,6 +2881,12 @@ int sim_force_hang(sim_t* h, int32_t patch, int32_t cycle, int32_t polls) {
   return upload_desc(h);
 }
 
+int sim_set_watchdog(sim_t* h, int32_t max_age) {
+  if (!h || max_age < 0) return SIM_EINVAL;
+  h->hd.watch_age = max_age;
+  return upload_desc(h);
+}
+
 int sim_set_rates(sim_t* h, uint32_t op_thr, uint32_t bg_thr) {
   if (!h) return SIM_EINVAL;
   h->hd.op_thr = op_thr;
@@ -2953,6 +3002,7 @@ int gather_status(int32_t* err_dev, int32_t* err_host, ChipAt chip_at, int n, hi
   int worst = SIM_OK;
   for (int i = 0; i < n; ++i) {
     if (err_host[i] == 1) worst = SIM_EHANG;
+    else if (err_host[i] == ERR_WATCHDOG && worst == SIM_OK) worst = SIM_ELIVELOCK;
     else if (err_host[i] && worst == SIM_OK) worst = SIM_EINVARIANT;
   }
   return worst;

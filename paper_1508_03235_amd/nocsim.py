@@ -24,7 +24,8 @@ STAT = {
     "bg_generated": 25, "op_lat_max": 26,
     "dir_access": 27, "dir_nack": 28, "trap": 29, "dir_evict": 30, "migrations": 48, "redirects": 49,
 }
-ERRORS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINVARIANT", -5: "EBUSY", -6: "EHANG"}
+ERRORS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EINVARIANT", -5: "EBUSY", -6: "EHANG",
+          -7: "ELIVELOCK"}
 
 
 class SimError(RuntimeError):
@@ -83,6 +84,7 @@ def _lib():
             "sim_force_bg": (i32, [p, i32, i32]),
             "sim_set_rates": (i32, [p, u32, u32]),
             "sim_force_hang": (i32, [p, i32, i32, i32]),
+            "sim_set_watchdog": (i32, [p, i32]),
             "sim_set_launch": (i32, [p, i32, i32, i32, i32]),
             "sim_get_launch": (i32, [p, p, p, p, p]),
             "sim_set_kernel": (i32, [p, i32]),
@@ -112,7 +114,7 @@ def exported_symbols():
     """Names of the functions the library must export (checked by the CPU tests)."""
     return ["sim_state_bytes", "sim_div_constants", "sim_create", "sim_step", "sim_sync", "sim_cycle", "sim_stats",
             "sim_dump_words", "sim_dump", "sim_load", "sim_force_op", "sim_force_bg",
-            "sim_set_rates", "sim_force_hang", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
+            "sim_set_rates", "sim_force_hang", "sim_set_watchdog", "sim_set_launch", "sim_get_launch", "sim_set_kernel", "sim_destroy", "sim_strerror",
             "sim_last_hip_error", "simb_state_bytes", "simb_create", "simb_add", "simb_remove", "simb_slots",
             "simb_stats", "simb_set_graph", "simb_step", "simb_destroy", "simb_step_noalloc"]
 
@@ -234,6 +236,11 @@ class Sim:
 
     def force_hang(self, patch: int, cycle: int, polls: int):
         _check("sim_force_hang", _lib().sim_force_hang(self._h, patch, cycle, polls))
+
+    def set_watchdog(self, max_age: int):
+        """Debug mode: every step checks each router's flits and that none is older than max_age
+        cycles (0 = off); a violation raises SimError (ELIVELOCK / EINVARIANT)."""
+        _check("sim_set_watchdog", _lib().sim_set_watchdog(self._h, max_age))
 
     def set_launch(self, patch_w=0, patch_h=0, block=0, chunk=0):
         _check("sim_set_launch", _lib().sim_set_launch(self._h, patch_w, patch_h, block, chunk))

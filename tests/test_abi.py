@@ -61,6 +61,7 @@ def test_null_handles_rejected():
     assert lib.simb_step(None, None) == -1
     assert lib.simb_stats(None, 0, None) == -1
     assert lib.simb_remove(None, 0) == -1
+    assert lib.sim_set_watchdog(None, 5) == -1
     assert lib.simb_set_graph(None, 1) == -1
     assert lib.simb_slots(None) == -1
     slot = C.c_int32()
