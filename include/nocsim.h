@@ -167,10 +167,14 @@ int sim_sync(sim_t* h);
 /* Cycles run so far (counting steps already enqueued). */
 int64_t sim_cycle(const sim_t* h);
 
-/* Statistics of the chip (synchronises). */
+/* Statistics of the chip (synchronises): the counts the paper's simulator reports (Sec. 6.2.2;
+   requests made and received, replies sent and received, traps, as in Table 3) together with
+   the latency, traffic and cache counters listed above. */
 int sim_stats(sim_t* h, sim_stats_t* out);
 
-/* Canonical state (synchronises): 16-word header {magic 0x4E4F4353, version 4, width,
+/* Canonical state (synchronises): everything the cycle loop of Sec. 7.1 carries from one cycle
+   to the next (the paper keeps no checkpoint; this one is for checkpoint / resume and for
+   comparing simulators word by word).  16-word header {magic 0x4E4F4353, version 4, width,
    height, cycle lo, cycle hi, l1_sets, l1_ways, l2_sets, l2_ways, reply_flits (>= 1),
    core-record words (28), flags, router delay, LSPD mode (0 static homes, 1 interleaved
    directory, 2 central), migration threshold}, then per tile the 4 input slots of the next
