@@ -67,7 +67,7 @@ constexpr int32_t LINE_MASK = 0x3FFFFFFF;
 // destination, a spare word
 constexpr int CORE_RECORD = 28;
 constexpr int DUMP_VERSION = 4;
-// model variants (sim_config.flags); the one-tile-per-thread kernel runs the base model only
+// model variants (sim_config.flags)
 constexpr int32_t VARIANT_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY | SIM_FLAG_LSPD |
                                   SIM_FLAG_LSPD_CENTRAL;
 constexpr int AGE_MAX = 0xFFFF;  // deflections a flit may take; one more stops the run (livelock)
@@ -1432,6 +1432,9 @@ __device__ __forceinline__ void arb_assign_mask(unsigned long long q, uint32_t& 
 
 constexpr uint32_t PF_SVC = 1, PF_LOCAL = 2, PF_FILL = 4, PF_FORCED = 8, PF_DRAWN = 16;
 constexpr uint32_t PF_RETRY = 32, PF_HUM = 64;  // hit under miss: the held op again; an op drawn under a miss
+// LSPD: a block from memory goes into the own slice; the own slice is looked up after an L1 miss;
+// this tile keeps that line's directory entry; a line read from state was out of range
+constexpr uint32_t PF_FILLMEM = 128, PF_SLICE = 256, PF_DIRCORE = 512, PF_BAD = 1024;
 
 struct Prefetch {            // loads of one cycle issued ahead of it
   uint4 r;                   // the tile's random words of the cycle
@@ -1444,6 +1447,8 @@ struct Prefetch {            // loads of one cycle issued ahead of it
   int* setL;
   int u[8], vR[8], vL[8];    // L1 set of the op; L2 sets of the served request and of a local miss
   int4 nh, nm;               // hit-queue and miss-queue head nodes
+  int loc_svc, loc_core;     // LSPD: the directory entries of a served directory access and of
+                             // the core's own line when this tile keeps it (-1 otherwise)
 };
 
 // Random words of cycle c and the Zipf table words their op draw would use (issued, not waited).
@@ -1459,18 +1464,33 @@ __device__ __forceinline__ void draw_ahead(const ChipDev& C, int t, int c, Prefe
 // Issues every load of cycle c that does not depend on its link inputs.  The random words of c
 // and their Zipf words were drawn one cycle earlier (draw_ahead); this draws those of c+1.
 // VARS: `hline` is the op held by hit under miss (-1 for none), `hum` whether the chip has it.
-template <bool MULTI, bool VARS, bool W48>
+template <bool MULTI, bool VARS, bool W48, bool LSPDB = false>
 __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
-                                         int hline, bool hum, int* l1_base, int* l2_base, Prefetch& P) {
+                                         int hline, bool hum, int* l1_base, int* l2_base, Prefetch& P,
+                                         const int4& k4 = make_int4(-1, -1, 0, 0)) {
   const int N = C.N;
   // way counts, fixed at compile time for 4-way L1 and 8-way L2 slices (W48)
   const int w1 = W48 ? 4 : C.w1, w2 = W48 ? 8 : C.w2, w1s = W48 ? 2 : C.w1_shift, w2s = W48 ? 3 : C.w2_shift;
   P.r = P.r1;
+  const bool lspd = LSPDB && C.lspd != 0;
   const bool svc = k1.x >= 0;
   const bool wake = k0.y == c;
-  const bool fill = k0.x == CORE_FILL && wake;
+  // LSPD (Sec. 3.2): a block from memory goes into the own slice as it fills L1
+  const bool fill_mem = lspd && k0.x == CORE_FILL_MEM && wake;
+  const bool fill = (k0.x == CORE_FILL && wake) || fill_mem;
   const bool missed = k0.x == CORE_L1MISS && wake;
-  const bool local = missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  const bool local = !lspd && missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
+  // LSPD: the served message's kind, the own slice look-up (not while an eviction notice is
+  // pending) and the directory entries read this cycle; a line read from state is checked
+  // before it addresses the location array
+  const int svc_type = lspd ? (k1.x >> 24) : Q_RA;
+  const bool slice_look = lspd && missed && k4.y < 0;
+  const bool bad = lspd && ((svc && (unsigned)k1.y >= (unsigned)C.lines) ||
+                            ((slice_look || fill_mem) && (unsigned)k0.z >= (unsigned)C.lines));
+  const int dir_of_op = C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)k0.z);
+  const bool dir_core = slice_look && !bad && dir_of_op == t;
+  P.loc_svc = lspd && svc && svc_type == Q_DA && !bad ? *gp(&C.loc[k1.y]) : -1;
+  P.loc_core = dir_core ? *gp(&C.loc[k0.z]) : -1;
   const bool retry = VARS && k0.x == CORE_IDLE && hline >= 0;
   const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
   const bool drawn = k0.x == CORE_IDLE && !retry && !forced && P.r.x < C.op_thr;
@@ -1479,10 +1499,14 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const bool drawn_hum = VARS && hum && k0.x != CORE_IDLE && !fill && hline < 0 && P.r.x < C.op_thr;
   P.flags = (svc ? PF_SVC : 0u) | (local ? PF_LOCAL : 0u) | (fill ? PF_FILL : 0u) | (forced ? PF_FORCED : 0u) |
             (drawn ? PF_DRAWN : 0u) | (retry ? PF_RETRY : 0u) | (drawn_hum ? PF_HUM : 0u);
-  P.setR = l2_base + ((div_n(C, (uint32_t)k1.y) & (uint32_t)(C.s2 - 1)) << w2s);
-  P.setL = l2_base + ((div_n(C, (uint32_t)k0.z) & (uint32_t)(C.s2 - 1)) << w2s);
-  if (svc) set_load(P.setR, w2, P.vR);
-  if (local) set_load(P.setL, w2, P.vL);
+  if (LSPDB)
+    P.flags |= (fill_mem ? PF_FILLMEM : 0u) | (slice_look ? PF_SLICE : 0u) | (dir_core ? PF_DIRCORE : 0u) | (bad ? PF_BAD : 0u);
+  // L2 set: a static home holds only its own lines (index line / N); an LSPD slice any line
+  const uint32_t ixR = lspd ? (uint32_t)k1.y : div_n(C, (uint32_t)k1.y), ixL = lspd ? (uint32_t)k0.z : div_n(C, (uint32_t)k0.z);
+  P.setR = l2_base + ((ixR & (uint32_t)(C.s2 - 1)) << w2s);
+  P.setL = l2_base + ((ixL & (uint32_t)(C.s2 - 1)) << w2s);
+  if (svc && svc_type == Q_RA) set_load(P.setR, w2, P.vR);
+  if (local || ((slice_look || fill_mem) && !bad)) set_load(P.setL, w2, P.vL);
   P.nh = make_int4(-1, -1, -1, -1);
   P.nm = make_int4(-1, -1, -1, -1);
   if ((unsigned)k1.z < (unsigned)N) P.nh = ld_node<MULTI>(&C.node[k1.z]);
@@ -1509,7 +1533,9 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // D-1 cycles in a per-tile pipeline in HBM before they are arbitrated).
 // OPT bit 3 (FAST_WAYS48): every chip of the launch has 4-way L1 and 8-way L2 slices, so the set
 // code is compiled for those way counts instead of reading them from the chip.
-constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8;
+// OPT bit 4 (FAST_LSPD): the chip may have the LSPD directory (Sec. 3.2, Sec. 6.2.2) without
+// migration; it is built with the three other options on and the way counts read at run time.
+constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
@@ -1517,6 +1543,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   constexpr bool VARS = (OPT & FAST_VARIANTS) != 0;
   constexpr bool PIPE = (OPT & FAST_PIPE) != 0;
   constexpr bool W48 = (OPT & FAST_WAYS48) != 0;
+  constexpr bool LSPDB = (OPT & FAST_LSPD) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1532,6 +1559,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const int rd = PIPE ? C.rdelay : 1;  // router delay D: arrivals wait D-1 cycles in a pipeline
   const uint32_t wsel = C.W > 1 ? 0u : ~0u;  // prod_mask's row when the chip is one column wide
   const int negW = -C.W;
+  const bool lspd = LSPDB && C.lspd != 0;  // the directory model (Sec. 3.2)
+  const uint32_t ym = LSPDB ? ~CTL_BIT : ~0u;  // an inject cycle without the LSPD control bit
+  // the tile that keeps a line's directory entry
+  auto dir_of = [&](int line) -> int { return C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)line); };
   const int patch = e.patch;
   const int pxi = patch % C.pgx, pyi = patch / C.pgx;
   const int x0 = pxi * C.pw, y0 = pyi * C.ph;
@@ -1591,6 +1622,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   int4 k0 = EMPTY, k1 = EMPTY, k2 = EMPTY;
   int fdst = -1, rcv = 0;  // forced background destination; flits of the awaited reply received
   int hline = -1, hissue = 0;  // hit under miss: the held op's line and issue cycle (none: -1, 0)
+  // LSPD core words: remote-access target, pending eviction notice, directory checksum lo, hi
+  int4 k4 = make_int4(-1, -1, 0, 0);
   uint32_t geo = geo0;
   const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
   if (active) {
@@ -1604,6 +1637,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       hline = k3.z;
       hissue = k3.w;
     }
+    if (lspd) k4 = gload4(&C.core[4 * N + t]);
     const int par = c0 & 1;
     if (i0) {
       const int4 w = gload4(&C.link[(par * 4 + 0) * N + t]);
@@ -1629,7 +1663,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   Prefetch P;
   if (active) {
     draw_ahead(C, t, c0, P);
-    prefetch<MULTI, VARS, W48>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P);
+    prefetch<MULTI, VARS, W48, LSPDB>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4);
   }
   __syncthreads();
 
@@ -1678,11 +1712,14 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       const int4 d0 = k0, d1 = k1, d2 = k2;
       const int dhl = hline, dhi = hissue;
       const int dfd = fdst, drcv = rcv;
+      const int4 dk4 = k4;
       if (step) {
-        // (-1 = none maps to 0; a tile index to 1..N)
-        const uint32_t top = max(max(max((uint32_t)(k1.x + 1), (uint32_t)(k1.w + 1)), max((uint32_t)(k2.y + 1), (uint32_t)(k1.z + 1))),
-                                 (uint32_t)(k2.x + 1));
-        if (top > (uint32_t)N) {
+        // (-1 = none maps to 0; a tile index to 1..N; LSPD: the served requester without its
+        // message kind, the remote-access target, and the lines the prefetch checked)
+        const int who1 = LSPDB && k1.x >= 0 ? (k1.x & 0xFFFFFF) : k1.x;
+        const uint32_t top = max(max(max((uint32_t)(who1 + 1), (uint32_t)(k1.w + 1)), max((uint32_t)(k2.y + 1), (uint32_t)(k1.z + 1))),
+                                 max((uint32_t)(k2.x + 1), (uint32_t)(k4.x + 1)));
+        if (top > (uint32_t)N || (LSPDB && ((P.flags & PF_BAD) || (k4.y >= 0 && k4.y >= C.lines)))) {
           st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
           ok = false;
         }
@@ -1693,16 +1730,15 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       if (step && ok) {
         // phase one reads no link input: it runs while this cycle's patch-edge reads are in flight
         // ---- phase one: home L2 service, then the core (Sec. 7.1 phase one; Sec. 3.5) -------
-        if (p_svc) {
-          const int rq = k1.x, line = k1.y;
-          const bool hit = set_touch(P.vR, ways2, line, true, dirtyR);
-          acc.l2_hit += hit;
-          acc.l2_miss += !hit;
+        // appends requester rq to the hit queue (replies with the block) or the miss queue (a
+        // static home's memory misses; the directory's one-flit answers); its node is stored in
+        // phase three
+        auto enqueue = [&](bool hitq, int rq, int ready, int word) {
           node_rq = rq;
-          node_ready = (hit ? c : c + C.mem_lat) + idl;
-          node_line = line;
-          const int4 fresh = make_int4(-1, node_ready, line, 0);
-          if (hit) {
+          node_ready = ready;
+          node_line = word;
+          const int4 fresh = make_int4(-1, ready, word, 0);
+          if (hitq) {
             if (k1.w >= 0) { node_tail = k1.w; if (k1.w == k1.z) nh.x = rq; }
             else { k1.z = rq; nh = fresh; }
             k1.w = rq;
@@ -1711,10 +1747,80 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             else { k2.x = rq; nm = fresh; }
             k2.y = rq;
           }
+        };
+        // LSPD (Sec. 3.2): a write of one of this tile's directory entries, which also moves the
+        // tile's checksum of them (k4.z, k4.w)
+        int fwd_line = -1, fwd_val = 0;  // the entry the service wrote, read again by the core
+        auto dir_write = [&](int line, int old_owner, int owner) {
+          typedef unsigned long long u64;
+          u64 sum = (u64)(uint32_t)k4.z | ((u64)(uint32_t)k4.w << 32);
+          if (old_owner >= 0) sum -= mix64(((u64)(uint32_t)line << 32) | (uint32_t)old_owner);
+          if (owner >= 0) sum += mix64(((u64)(uint32_t)line << 32) | (uint32_t)owner);
+          k4.z = (int)(uint32_t)sum;
+          k4.w = (int)(uint32_t)(sum >> 32);
+          *gp(&C.loc[line]) = owner;
+          fwd_line = line;
+          fwd_val = owner;
+        };
+        const int svc_type = k1.x >> 24;  // LSPD: the served message's kind (Q_*)
+        if (p_svc && !lspd) {
+          const int rq = k1.x, line = k1.y;
+          const bool hit = set_touch(P.vR, ways2, line, true, dirtyR);
+          acc.l2_hit += hit;
+          acc.l2_miss += !hit;
+          enqueue(hit, rq, (hit ? c : c + C.mem_lat) + idl, line);
+          k1.x = -1;
+          k1.y = -1;
+        } else if (LSPDB && p_svc) {  // remote access, directory access, eviction notice (Sec. 3.2)
+          const int who = k1.x & 0xFFFFFF, line = k1.y;
+          if (svc_type == Q_RA) {  // the block is here: reply with it; gone: a trap
+            const int i = way_of(P.vR, line);
+            if (i >= 0) {
+              acc.l2_hit++;
+              way_front(P.vR, i);
+              dirtyR = true;
+              enqueue(true, who, c + idl, line);
+            } else {
+              lds_add(L, SIM_ST_TRAP, 1);
+              enqueue(false, who, c + idl, CODE_TRAP);
+            }
+          } else if (svc_type == Q_DA) {  // the owner, or (not on chip) the asker brings it from memory
+            lds_add(L, SIM_ST_DIR_ACCESS, 1);
+            int code = P.loc_svc;
+            if (code < 0) {
+              dir_write(line, -1, who);
+              lds_add(L, SIM_ST_DIR_NACK, 1);
+              code = CODE_NACK;
+            }
+            enqueue(false, who, c + idl, code);
+          } else {  // the entry names the evicting slice until its notice arrives
+            dir_write(line, who, -1);
+            lds_add(L, SIM_ST_DIR_EVICT, 1);
+          }
           k1.x = -1;
           k1.y = -1;
         }
+        // the core's slice access below sees the service's changes when both touch one set
+        if (LSPDB && (pf & PF_SVC) && (pf & (PF_SLICE | PF_FILLMEM)) && svc_type == Q_RA && P.setL == P.setR) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
+          dirtyL = dirtyL || dirtyR;
+          dirtyR = false;
+        }
         if (p_fill) {
+          if (LSPDB && (pf & PF_FILLMEM)) {  // from memory into the local slice too; an evicted
+            const int victim = way_insert(P.vL, ways2, k0.z);  // block leaves the directory
+            dirtyL = true;
+            if (victim >= 0 && (unsigned)victim >= (unsigned)C.lines) {
+              st_coh(C.err, 2);  // a corrupt slice word: stop rather than address memory with it
+              ok = false;
+            } else if (victim >= 0 && dir_of(victim) == t) {
+              dir_write(victim, t, -1);
+              lds_add(L, SIM_ST_DIR_EVICT, 1);
+            } else if (victim >= 0) {
+              k4.y = victim;  // the eviction notice goes out before the next directory access
+            }
+          }
           set_touch(P.u, ways1, P.line_op, true, dirty1);
           const int lat = c - k0.w;
           acc.ops_done++;
@@ -1722,7 +1828,42 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           acc.op_lat_max = max(acc.op_lat_max, lat);
           k0.x = CORE_IDLE;
         } else if (k0.x == CORE_L1MISS && k0.y == c) {
-          if (p_local) {
+          if (LSPDB && lspd) {  // own slice, then the directory (Sec. 3.2)
+            const int i = way_of(P.vL, k0.z);
+            if (!(pf & PF_SLICE)) {
+              k0.y = c + 1;  // a pending eviction notice goes out first
+            } else if (i >= 0) {
+              acc.l2_hit++;
+              way_front(P.vL, i);
+              dirtyL = true;
+              k0.x = CORE_FILL;
+              k0.y = c + 1;
+            } else if (pf & PF_DIRCORE) {  // this tile keeps the entry: look it up at once
+              lds_add(L, SIM_ST_DIR_ACCESS, 1);
+              const int o = fwd_line == k0.z ? fwd_val : P.loc_core;
+              if (o == t) {  // this slice's own eviction is still on its way: look again
+                lds_add(L, SIM_ST_TRAP, 1);
+                k0.y = c + 1;
+              } else {
+                acc.l2_miss++;
+                if (o < 0) {
+                  dir_write(k0.z, -1, t);
+                  lds_add(L, SIM_ST_DIR_NACK, 1);
+                  k0.x = CORE_FILL_MEM;
+                  k0.y = c + C.mem_lat;
+                } else {
+                  k0.x = CORE_SEND_RA;
+                  k4.x = o;
+                  k0.y = c + idl;
+                  acc.req_made++;
+                }
+              }
+            } else {
+              acc.l2_miss++;
+              k0.x = CORE_SEND_DA;
+              k0.y = c + idl;
+            }
+          } else if (p_local) {
             if (p_svc && P.setL == P.setR) {
 #pragma unroll
               for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
@@ -1833,8 +1974,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, d2.w, dfd);
         h = mix_pair(h, drcv, 0);
         h = mix_pair(h, dhl, dhi);  // the op held by hit under miss (-1, 0: none)
-        h = mix_pair(h, -1, -1);  // nor a remote-access target or eviction notice,
-        h = mix_pair(h, 0, 0);    // no directory entry,
+        h = mix_pair(h, dk4.x, dk4.y);  // LSPD: remote-access target, pending eviction notice
+        h = mix_pair(h, dk4.z, dk4.w);  // and the directory checksum (without LSPD: -1, -1, 0, 0)
         h = mix_pair(h, -1, -1);  // no claim, forwarded block
         h = mix_pair(h, -1, -1);  // or its destination
         if (aged)  // the arrivals' deflection counts
@@ -1865,9 +2006,13 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         const int arrivals = (f0.x >= 0) + (f1.x >= 0) + (f2.x >= 0) + (f3.x >= 0);
         const int deg = (int)v0 + (int)v1 + (int)v2 + (int)v3;
         int cls = -1;
+        // (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
+        // eviction notice, a directory access or a remote access)
+        const bool own = LSPDB && lspd ? (k4.y >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
+                                       : (k0.x == CORE_SEND && (!VARS || k0.y + idl <= c));
         if (k2.x >= 0 && nm.y <= c) cls = 0;
         else if (k1.z >= 0 && (!VARS || nh.y <= c)) cls = 1;
-        else if (k0.x == CORE_SEND && (!VARS || k0.y + idl <= c)) cls = 2;
+        else if (own) cls = 2;
         else if (fdst >= 0) cls = 3;
         else if (k2.z > 0) cls = 4;
         if (cls >= 0 && arrivals >= deg) {
@@ -1878,7 +2023,31 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         if (cls >= 0) {
           fi.y = c;
           fi.z = t;
-          if (cls <= 1) {  // a flit of the head's reply; the head is popped with the last one
+          if (LSPDB && lspd && cls == 0) {  // the directory's answer or a trap: one flit, control bit
+            fi.x = k2.x;
+            fi.y = (int)((uint32_t)c | CTL_BIT);
+            fi.w = (KIND_REPLY << 30) | (nm.z + CODE_BASE);
+            k2.x = nm.x;
+            if (nm.x < 0) k2.y = -1;
+            acc.inj_reply++;
+          } else if (LSPDB && lspd && cls == 2) {
+            if (k4.y >= 0) {  // eviction notice to the block's directory tile
+              fi.x = dir_of(k4.y);
+              fi.y = (int)((uint32_t)c | CTL_BIT);
+              fi.w = (KIND_DIR << 30) | k4.y;
+              k4.y = -1;
+            } else if (k0.x == CORE_SEND_DA) {  // directory access
+              fi.x = dir_of(k0.z);
+              fi.w = (KIND_DIR << 30) | k0.z;
+              k0.x = CORE_WAIT;
+            } else {  // remote access at the owner
+              fi.x = k4.x;
+              fi.w = (KIND_REQ << 30) | k0.z;
+              k4.x = -1;
+              k0.x = CORE_WAIT;
+            }
+            acc.inj_req++;
+          } else if (cls <= 1) {  // a flit of the head's reply; the head is popped with the last one
             const int4 hd = cls == 0 ? nm : nh;
             fi.x = cls == 0 ? k2.x : k1.z;
             const int sent = hd.w + 1;
@@ -1928,7 +2097,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         // (the masks are computed for every input, empty or not, so that no branch is taken here)
         const uint32_t m0 = PM(f0), m1 = PM(f1), m2 = PM(f2), m3 = PM(f3), m4 = PM(fi);
         // (an empty input's dst is -1: its sign makes both halves of the key all ones, no branch)
-#define SKEY(f, m, i) ((u64)((uint32_t)(f).y | (uint32_t)((f).x >> 31)) << 32 | \
+#define SKEY(f, m, i) ((u64)(((uint32_t)(f).y & ym) | (uint32_t)((f).x >> 31)) << 32 | \
                        (u64)((SRCW(f) << 8) | ((m) << 3) | (uint32_t)((i) ^ 7) | (uint32_t)((f).x >> 31)))
         u64 q0 = SKEY(f0, m0, 0), q1 = SKEY(f1, m1, 1), q2 = SKEY(f2, m2, 2), q3 = SKEY(f3, m3, 3), q4 = SKEY(fi, m4, 4);
 #undef SKEY
@@ -1968,10 +2137,10 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             // included), and none is older than the bound (the oldest flit always advances)
             const uint32_t cu = (uint32_t)c;
             uint32_t oldest = 0;
-            if (f0.x >= 0) oldest = max(oldest, cu - (uint32_t)f0.y);
-            if (f1.x >= 0) oldest = max(oldest, cu - (uint32_t)f1.y);
-            if (f2.x >= 0) oldest = max(oldest, cu - (uint32_t)f2.y);
-            if (f3.x >= 0) oldest = max(oldest, cu - (uint32_t)f3.y);
+            if (f0.x >= 0) oldest = max(oldest, cu - ((uint32_t)f0.y & ym));
+            if (f1.x >= 0) oldest = max(oldest, cu - ((uint32_t)f1.y & ym));
+            if (f2.x >= 0) oldest = max(oldest, cu - ((uint32_t)f2.y & ym));
+            if (f3.x >= 0) oldest = max(oldest, cu - ((uint32_t)f3.y & ym));
             if (__builtin_popcount(taken & 31u) != nlive) {
               st_coh(C.err, ERR_ROUTER);
               ok = false;
@@ -2033,12 +2202,14 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         }
         if (oe.x >= 0) {
           const int kind = (int)((uint32_t)oe.w >> 30);
-          const int lat = c - oe.y;
+          const bool ctl = LSPDB && ((uint32_t)oe.y & CTL_BIT);
+          const int lat = c - (int)((uint32_t)oe.y & ym);
           const unsigned long long ulat = (unsigned long long)lat;
-          acc.ej_req += kind == KIND_REQ;
+          const bool as_req = kind == KIND_REQ || (LSPDB && kind == KIND_DIR);  // directory messages count as requests
+          acc.ej_req += as_req;
           acc.ej_reply += kind == KIND_REPLY;
           acc.ej_bg += kind == KIND_BG;
-          acc.lat_req += kind == KIND_REQ ? ulat : 0ull;
+          acc.lat_req += as_req ? ulat : 0ull;
           acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
           acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
           acc.lat_max = max(acc.lat_max, lat);
@@ -2047,6 +2218,24 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             acc.req_recv++;
             k1.x = VARS ? (int)((uint32_t)oe.z & TILE_BITS_MASK) : oe.z;
             k1.y = oe.w & LINE_MASK;
+          } else if (LSPDB && kind == KIND_DIR) {  // directory access or (control bit) eviction notice
+            k1.x = (int)((uint32_t)oe.z & TILE_BITS_MASK) | ((ctl ? Q_EV : Q_DA) << 24);
+            k1.y = oe.w & LINE_MASK;
+          } else if (LSPDB && kind == KIND_REPLY && ctl) {  // the directory's answer or a trap
+            const int code = (oe.w & LINE_MASK) - CODE_BASE;
+            if (code == CODE_NACK) {  // not on chip: from memory into the local slice
+              k0.x = CORE_FILL_MEM;
+              k0.y = c + C.mem_lat;
+            } else if (code == CODE_TRAP || code == t) {  // stale entry: ask the directory again
+              if (code == t) lds_add(L, SIM_ST_TRAP, 1);
+              k0.x = CORE_SEND_DA;
+              k0.y = c + 1;
+            } else {  // the owner: a remote access to it
+              k0.x = CORE_SEND_RA;
+              k0.y = c + 1;
+              k4.x = code;
+              acc.req_made++;
+            }
           } else if (kind == KIND_REPLY) {  // a flit of the block; the last one completes it
             rcv += PACKETS ? 1 : 0;
             if (!PACKETS || rcv >= C.reply_flits) {
@@ -2061,7 +2250,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k2.z += 1;
           acc.bg_gen++;
         }
-        if (c + 1 < c_end) prefetch<MULTI, VARS, W48>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P);
+        if (c + 1 < c_end) prefetch<MULTI, VARS, W48, LSPDB>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4);
 #undef out_for
       }
     }
@@ -2087,6 +2276,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     gstore4(&C.core[N + t], k1);
     gstore4(&C.core[2 * N + t], k2);
     gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, hline, hissue));
+    if (lspd) gstore4(&C.core[4 * N + t], k4);
     const int par = c_done & 1;
     if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
     if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
@@ -2244,11 +2434,17 @@ int router_delay(const sim_config* c) { return c->router_delay > 0 ? c->router_d
 // which build of the general kernel a chip needs: 0 base model, 1 variants / router delay, 2 directory
 int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.rdelay > 1) ? 1 : 0; }
 // OPT bits of the one-tile-per-thread kernel a chip needs
-// variants the one-tile-per-thread kernel carries, with any router delay (the directory needs
-// the general kernel)
+// variants the one-tile-per-thread kernel carries, with any router delay
 constexpr int32_t FAST_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
+// whether a chip may run on the one-tile-per-thread kernel: any of those variants, and the LSPD
+// directory without migration (a migrating chip needs the general kernel)
+bool fast_model(const sim_config* c) {
+  const int32_t carried = FAST_FLAGS | SIM_FLAG_LSPD | SIM_FLAG_LSPD_CENTRAL;
+  return (c->flags & VARIANT_FLAGS & ~carried) == 0 && c->mig_threshold == 0;
+}
 // (FAST_WAYS48 is set only when every chip of a launch has the 4/8-way geometry: see batch_kind)
 int fast_opt(const ChipDev& d) {
+  if (d.lspd) return FAST_LSPD | FAST_PACKETS | FAST_VARIANTS | FAST_PIPE;  // (one build carries it)
   return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
          (d.rdelay > 1 ? FAST_PIPE : 0) | ((d.w1 == 4 && d.w2 == 8) ? FAST_WAYS48 : 0);
 }
@@ -2325,6 +2521,7 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
+  if (opt & FAST_LSPD) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | 7>);
   switch (opt & 15) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
     case 1: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 1>);
@@ -2354,6 +2551,12 @@ const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 
 int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
   int per_cu = 0, per_cu_var = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
+  if (fast) {  // (the directory's build of the one-tile-per-thread kernel too)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(true, false, FAST_LSPD), block, 0) !=
+        hipSuccess)
+      return 0;
+    per_cu = std::min(per_cu, per_cu_var);
+  }
   for (int v = 1; !fast && v <= 2; ++v) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(false, false, false, v), block, 0) !=
         hipSuccess)
@@ -2366,7 +2569,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 32; ++k) {
+  for (int k = 0; k < 34; ++k) {  // (OPT 16: the directory's build)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2536,8 +2739,8 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  // the directory: general kernel
-  h->use_fast = (cfg->flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0;
+  // migration: general kernel
+  h->use_fast = fast_model(cfg);
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;
   d.W = cfg->width;
@@ -2631,7 +2834,7 @@ int sim_set_launch(sim_t* h, int32_t pw, int32_t ph, int32_t block, int32_t chun
 
 int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
-  const bool use_fast = !generic_only && (h->cfg.flags & VARIANT_FLAGS & ~FAST_FLAGS) == 0;
+  const bool use_fast = !generic_only && fast_model(&h->cfg);
   const int np = h->hd.n_patches;
   if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
   h->use_fast = use_fast;

@@ -1,7 +1,9 @@
 """Parity of the LSPD directory model (SimParams.flags LSPD) on the GPU with the serial oracle.
 
 Bit-exact, as for the base model: per-cycle digests (which carry each directory tile's
-checksum of its entries) and the final canonical dump, location array included.
+checksum of its entries) and the final canonical dump, location array included.  Without
+migration a chip runs on the one-tile-per-thread kernel by default; the main cases run on both
+that kernel and the general one.
 """
 import pytest
 
@@ -35,38 +37,42 @@ def test_gpu_hand_traces():
     assert sim.stats()[STAT["trap"]] == 1
 
 
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
 @pytest.mark.parametrize("flags", MODES, ids=IDS)
-def test_lspd_config0_full_run(flags):
+def test_lspd_config0_full_run(flags, generic):
     """4x4, 10,000 cycles of config 0 with the directory (small slices, so blocks are evicted
     and entries go stale)."""
     p = W.config0().with_(flags=flags, op_thr=W.thr(0.5), l2_sets=16, l2_ways=2, shared_lines=2048, reply_flits=4)
-    assert_same_run(p, 10_000, step_sizes=[1, 999, 4000, 5000])
+    assert_same_run(p, 10_000, step_sizes=[1, 999, 4000, 5000], generic=generic)
 
 
 @pytest.mark.parametrize("flags", MODES + [LSPD | W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY],
                          ids=IDS + ["with_variants"])
 @pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (5, 5), (13, 7)])
-def test_lspd_small_shapes(w, h, flags):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_lspd_small_shapes(w, h, flags, generic):
     p = W.config1().with_(width=w, height=h, seed=w * 100 + h + flags, bg_thr=W.thr(0.1) if w * h > 1 else 0,
                           op_thr=W.thr(0.6), l1_sets=8, l2_sets=8, l2_ways=2, shared_lines=512, private_lines=64,
                           flags=flags, reply_flits=2)
-    assert_same_run(p, 3000)
+    assert_same_run(p, 3000, generic=generic)
 
 
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
-def test_lspd_patch_mappings(launch):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_lspd_patch_mappings(launch, generic):
     """Directory accesses, answers, traps and eviction notices cross patch edges and launch
     boundaries exactly; entries are only touched by their directory tile."""
     p = W.config1().with_(width=20, height=13, seed=10, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l2_sets=8, l2_ways=2,
                           shared_lines=1024, private_lines=64, flags=LSPD)
-    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800], generic=generic)
 
 
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
 @pytest.mark.parametrize("flags", MODES, ids=IDS)
-def test_lspd_208x208_prefix(flags):
+def test_lspd_208x208_prefix(flags, generic):
     """The 208x208 chip (43,264 tiles) with the directory, 2^10 private lines per tile."""
     p = W.config2(0.05).with_(flags=flags, private_lines=2**10)
-    assert_same_run(p, 80, step_sizes=[30, 50])
+    assert_same_run(p, 80, step_sizes=[30, 50], generic=generic)
 
 
 @pytest.mark.parametrize("flags", MODES, ids=IDS)
