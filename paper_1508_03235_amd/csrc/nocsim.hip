@@ -347,17 +347,13 @@ __device__ __forceinline__ int way_of(const int (&v)[8], int line) {
     if (v[i] == line) pos = i;
   return pos;
 }
+// (way i, 0 <= i < 8, as an OR of masked words: a chain of selects between the ways would be
+// folded into one load at a computed offset, which takes the array out of registers)
 __device__ __forceinline__ int way_pick(const int (&v)[8], int i) {
-  int x = v[0];
+  int x = 0;
 #pragma unroll
-  for (int k = 1; k < 8; ++k)
-    if (i == k) x = v[k];
+  for (int k = 0; k < 8; ++k) x |= v[k] & -(int)(i == k);
   return x;
-}
-__device__ __forceinline__ void way_put(int (&v)[8], int i, int x) {
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (i == k) v[k] = x;
 }
 __device__ __forceinline__ void way_front(int (&v)[8], int i) {
   const int tag = way_pick(v, i);
