@@ -1530,7 +1530,8 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // OPT bit 3 (FAST_WAYS48): every chip of the launch has 4-way L1 and 8-way L2 slices, so the set
 // code is compiled for those way counts instead of reading them from the chip.
 // OPT bit 4 (FAST_LSPD): the chip may have the LSPD directory (Sec. 3.2, Sec. 6.2.2) without
-// migration; it is built with the three other options on and the way counts read at run time.
+// migration.  It has two builds: for single-flit chips without variants or router delay and with
+// 4/8-way caches (bit 3 alone beside it), and with bits 0-2 on and the way counts read at run time.
 constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
@@ -2440,8 +2441,7 @@ bool fast_model(const sim_config* c) {
 }
 // (FAST_WAYS48 is set only when every chip of a launch has the 4/8-way geometry: see batch_kind)
 int fast_opt(const ChipDev& d) {
-  if (d.lspd) return FAST_LSPD | FAST_PACKETS | FAST_VARIANTS | FAST_PIPE;  // (one build carries it)
-  return (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
+  return (d.lspd ? FAST_LSPD : 0) | (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
          (d.rdelay > 1 ? FAST_PIPE : 0) | ((d.w1 == 4 && d.w2 == 8) ? FAST_WAYS48 : 0);
 }
 
@@ -2517,6 +2517,8 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
+  if ((opt & (FAST_LSPD | 7)) == FAST_LSPD && (opt & FAST_WAYS48))
+    return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | FAST_WAYS48>);
   if (opt & FAST_LSPD) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | 7>);
   switch (opt & 15) {
     case 0: return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, 0>);
@@ -2547,9 +2549,8 @@ const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 
 int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
   int per_cu = 0, per_cu_var = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
-  if (fast) {  // (the directory's build of the one-tile-per-thread kernel too)
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(true, false, FAST_LSPD), block, 0) !=
-        hipSuccess)
+  for (int o = FAST_LSPD; fast && o <= (FAST_LSPD | FAST_WAYS48); o += FAST_WAYS48) {  // (the directory's builds)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(true, false, o), block, 0) != hipSuccess)
       return 0;
     per_cu = std::min(per_cu, per_cu_var);
   }
@@ -2565,7 +2566,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 34; ++k) {  // (OPT 16: the directory's build)
+  for (int k = 0; k < 64; ++k) {  // (OPT 16-31 map to the directory's two builds)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;

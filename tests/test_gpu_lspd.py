@@ -57,6 +57,17 @@ def test_lspd_small_shapes(w, h, flags, generic):
     assert_same_run(p, 3000, generic=generic)
 
 
+@pytest.mark.parametrize("w,h,launch", [(13, 7, None), (20, 13, (5, 5, 64, 0)), (20, 13, (20, 1, 64, 37))])
+@pytest.mark.parametrize("flags", MODES, ids=IDS)
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_lspd_ways48_single_flit(w, h, launch, flags, generic):
+    """4-way L1, 8-way slices of 4 sets (blocks are evicted from the slices all the time),
+    single-flit replies, no variants: the directory build compiled for those way counts."""
+    p = W.config1().with_(width=w, height=h, seed=w * 31 + h, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l1_sets=8, l2_sets=4,
+                          shared_lines=2048, private_lines=64, flags=flags)
+    assert_same_run(p, 3000, launch=launch, step_sizes=[1000, 2000], generic=generic)
+
+
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
 @pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
 def test_lspd_patch_mappings(launch, generic):
