@@ -24,8 +24,8 @@ Besides the headline line the JSON carries:
   variants     - the same chip under each model variant (priority by deflection count, hit
                  under miss, injection register, all three; router delay 2; the LSPD directory,
                  interleaved and central, and migrating a block on every remote access) on the general
-                 kernel, beside the base model on that kernel, and all but migration also on
-                 the one-tile-per-thread kernel: throughput, deflection rate, latencies, ops per
+                 kernel, beside the base model on that kernel, and each again on the
+                 one-tile-per-thread kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
   batched      - the 256-chip batch in one launch per chunk, on the batch autotuner's patch shapes,
                  vs the same chips run one at a time on the single-chip autotuner's mappings
@@ -293,8 +293,8 @@ def run_packets(nocsim, W, torch, O, cycles, parity_cycles=200, flits=4):
 
 
 def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
-    """The 208x208 chip at background 0.05 under each model variant (general kernel; all but
-    migration also on the one-tile-per-thread kernel)."""
+    """The 208x208 chip at background 0.05 under each model variant, on the general kernel and
+    on the one-tile-per-thread kernel."""
     out = {}
     cases = [("base", 0), ("age_deflect", W.AGE_DEFLECT), ("hit_under_miss", W.HIT_UNDER_MISS),
              ("inject_delay", W.INJECT_DELAY), ("all", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
@@ -302,12 +302,12 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
              ("lspd_migration_1", W.LSPD), ("age_deflect_fast", W.AGE_DEFLECT),
              ("hit_under_miss_fast", W.HIT_UNDER_MISS), ("inject_delay_fast", W.INJECT_DELAY),
              ("all_fast", W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY), ("router_delay_2_fast", 0),
-             ("lspd_fast", W.LSPD), ("lspd_central_fast", W.LSPD | W.LSPD_CENTRAL)]
+             ("lspd_fast", W.LSPD), ("lspd_central_fast", W.LSPD | W.LSPD_CENTRAL), ("lspd_migration_1_fast", W.LSPD)]
     S = nocsim.STAT
     for name, flags in cases:
         generic = not name.endswith("_fast")
         p = W.config2(0.05).with_(flags=flags, router_delay=2 if name.startswith("router_delay_2") else 1,
-                                  mig_threshold=1 if name == "lspd_migration_1" else 0)
+                                  mig_threshold=1 if name.startswith("lspd_migration_1") else 0)
         sim = nocsim.Sim(p)
         sim.set_kernel(generic)
         sim.step(300)

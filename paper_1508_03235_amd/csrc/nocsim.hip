@@ -1460,10 +1460,11 @@ __device__ __forceinline__ void draw_ahead(const ChipDev& C, int t, int c, Prefe
 // Issues every load of cycle c that does not depend on its link inputs.  The random words of c
 // and their Zipf words were drawn one cycle earlier (draw_ahead); this draws those of c+1.
 // VARS: `hline` is the op held by hit under miss (-1 for none), `hum` whether the chip has it.
-template <bool MULTI, bool VARS, bool W48, bool LSPDB = false>
+template <bool MULTI, bool VARS, bool W48, bool LSPDB = false, bool MIGB = false>
 __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const int4& k0, const int4& k1, const int4& k2,
                                          int hline, bool hum, int* l1_base, int* l2_base, Prefetch& P,
-                                         const int4& k4 = make_int4(-1, -1, 0, 0)) {
+                                         const int4& k4 = make_int4(-1, -1, 0, 0),
+                                         const int4& k5 = make_int4(-1, -1, -1, -1)) {
   const int N = C.N;
   // way counts, fixed at compile time for 4-way L1 and 8-way L2 slices (W48)
   const int w1 = W48 ? 4 : C.w1, w2 = W48 ? 8 : C.w2, w1s = W48 ? 2 : C.w1_shift, w2s = W48 ? 3 : C.w2_shift;
@@ -1471,21 +1472,23 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const bool lspd = LSPDB && C.lspd != 0;
   const bool svc = k1.x >= 0;
   const bool wake = k0.y == c;
-  // LSPD (Sec. 3.2): a block from memory goes into the own slice as it fills L1
-  const bool fill_mem = lspd && k0.x == CORE_FILL_MEM && wake;
+  // LSPD (Sec. 3.2): a block from memory, or one that migrated here (Sec. 3.3), goes into the
+  // own slice as it fills L1
+  const bool fill_mig = MIGB && lspd && k0.x == CORE_FILL_MIG && wake;
+  const bool fill_mem = (lspd && k0.x == CORE_FILL_MEM && wake) || fill_mig;
   const bool fill = (k0.x == CORE_FILL && wake) || fill_mem;
   const bool missed = k0.x == CORE_L1MISS && wake;
   const bool local = !lspd && missed && mod_n(C, (uint32_t)k0.z) == (uint32_t)t;
-  // LSPD: the served message's kind, the own slice look-up (not while an eviction notice is
-  // pending) and the directory entries read this cycle; a line read from state is checked
-  // before it addresses the location array
+  // LSPD: the served message's kind, the own slice look-up (not while an eviction notice or a
+  // claim is pending) and the directory entries read this cycle; a line read from state is
+  // checked before it addresses the location array
   const int svc_type = lspd ? (k1.x >> 24) : Q_RA;
-  const bool slice_look = lspd && missed && k4.y < 0;
+  const bool slice_look = lspd && missed && k4.y < 0 && (!MIGB || k5.x < 0);
   const bool bad = lspd && ((svc && (unsigned)k1.y >= (unsigned)C.lines) ||
                             ((slice_look || fill_mem) && (unsigned)k0.z >= (unsigned)C.lines));
   const int dir_of_op = C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)k0.z);
-  const bool dir_core = slice_look && !bad && dir_of_op == t;
-  P.loc_svc = lspd && svc && svc_type == Q_DA && !bad ? *gp(&C.loc[k1.y]) : -1;
+  const bool dir_core = (slice_look || fill_mig) && !bad && dir_of_op == t;
+  P.loc_svc = lspd && svc && (svc_type == Q_DA || (MIGB && svc_type == Q_CLAIM)) && !bad ? *gp(&C.loc[k1.y]) : -1;
   P.loc_core = dir_core ? *gp(&C.loc[k0.z]) : -1;
   const bool retry = VARS && k0.x == CORE_IDLE && hline >= 0;
   const bool forced = k0.x == CORE_IDLE && !retry && k2.w >= 0;
@@ -1501,7 +1504,7 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
   const uint32_t ixR = lspd ? (uint32_t)k1.y : div_n(C, (uint32_t)k1.y), ixL = lspd ? (uint32_t)k0.z : div_n(C, (uint32_t)k0.z);
   P.setR = l2_base + ((ixR & (uint32_t)(C.s2 - 1)) << w2s);
   P.setL = l2_base + ((ixL & (uint32_t)(C.s2 - 1)) << w2s);
-  if (svc && svc_type == Q_RA) set_load(P.setR, w2, P.vR);
+  if (svc && (svc_type == Q_RA || (MIGB && svc_type == Q_ARRIVED))) set_load(P.setR, w2, P.vR);
   if (local || ((slice_look || fill_mem) && !bad)) set_load(P.setL, w2, P.vL);
   P.nh = make_int4(-1, -1, -1, -1);
   P.nm = make_int4(-1, -1, -1, -1);
@@ -1529,10 +1532,11 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // D-1 cycles in a per-tile pipeline in HBM before they are arbitrated).
 // OPT bit 3 (FAST_WAYS48): every chip of the launch has 4-way L1 and 8-way L2 slices, so the set
 // code is compiled for those way counts instead of reading them from the chip.
-// OPT bit 4 (FAST_LSPD): the chip may have the LSPD directory (Sec. 3.2, Sec. 6.2.2) without
-// migration.  It has two builds: for single-flit chips without variants or router delay and with
+// OPT bit 4 (FAST_LSPD): the chip may have the LSPD directory (Sec. 3.2, Sec. 6.2.2).  Without
+// migration it has two builds: for single-flit chips without variants or router delay and with
 // 4/8-way caches (bit 3 alone beside it), and with bits 0-2 on and the way counts read at run time.
-constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16;
+// OPT bit 5 (FAST_MIG): the directory with migration (Sec. 3.3), built with bits 0-2 and 4 on.
+constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16, FAST_MIG = 32;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
@@ -1541,6 +1545,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   constexpr bool PIPE = (OPT & FAST_PIPE) != 0;
   constexpr bool W48 = (OPT & FAST_WAYS48) != 0;
   constexpr bool LSPDB = (OPT & FAST_LSPD) != 0;
+  constexpr bool MIGB = LSPDB && (OPT & FAST_MIG) != 0;
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
@@ -1557,6 +1562,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   const uint32_t wsel = C.W > 1 ? 0u : ~0u;  // prod_mask's row when the chip is one column wide
   const int negW = -C.W;
   const bool lspd = LSPDB && C.lspd != 0;  // the directory model (Sec. 3.2)
+  const bool mig = MIGB && lspd && C.mig > 0;  // with migration (Sec. 3.3): N accessors per way
+  const int mg = mig ? C.mig : 0;
   const uint32_t ym = LSPDB ? ~CTL_BIT : ~0u;  // an inject cycle without the LSPD control bit
   // the tile that keeps a line's directory entry
   auto dir_of = [&](int line) -> int { return C.lspd == 2 ? C.dir_center : (int)mod_n(C, (uint32_t)line); };
@@ -1621,6 +1628,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   int hline = -1, hissue = 0;  // hit under miss: the held op's line and issue cycle (none: -1, 0)
   // LSPD core words: remote-access target, pending eviction notice, directory checksum lo, hi
   int4 k4 = make_int4(-1, -1, 0, 0);
+  // migration core words: pending claim (line), the block sent away, its destination (with the
+  // in-transit bit until its arrival notice is served), a pending arrival notice (its source)
+  int4 k5 = EMPTY;
   uint32_t geo = geo0;
   const bool i0 = GEO(4), i1 = GEO(5), i2 = GEO(6), i3 = GEO(7);
   if (active) {
@@ -1635,6 +1645,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       hissue = k3.w;
     }
     if (lspd) k4 = gload4(&C.core[4 * N + t]);
+    if (mig) k5 = gload4(&C.core[5 * N + t]);
     const int par = c0 & 1;
     if (i0) {
       const int4 w = gload4(&C.link[(par * 4 + 0) * N + t]);
@@ -1660,7 +1671,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   Prefetch P;
   if (active) {
     draw_ahead(C, t, c0, P);
-    prefetch<MULTI, VARS, W48, LSPDB>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4);
+    prefetch<MULTI, VARS, W48, LSPDB, MIGB>(C, t, c0, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4, k5);
   }
   __syncthreads();
 
@@ -1709,14 +1720,18 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
       const int4 d0 = k0, d1 = k1, d2 = k2;
       const int dhl = hline, dhi = hissue;
       const int dfd = fdst, drcv = rcv;
-      const int4 dk4 = k4;
+      const int4 dk4 = k4, dk5 = k5;
       if (step) {
         // (-1 = none maps to 0; a tile index to 1..N; LSPD: the served requester without its
         // message kind, the remote-access target, and the lines the prefetch checked)
         const int who1 = LSPDB && k1.x >= 0 ? (k1.x & 0xFFFFFF) : k1.x;
         const uint32_t top = max(max(max((uint32_t)(who1 + 1), (uint32_t)(k1.w + 1)), max((uint32_t)(k2.y + 1), (uint32_t)(k1.z + 1))),
                                  max((uint32_t)(k2.x + 1), (uint32_t)(k4.x + 1)));
-        if (top > (uint32_t)N || (LSPDB && ((P.flags & PF_BAD) || (k4.y >= 0 && k4.y >= C.lines)))) {
+        // (migration: the pending claim's line, the forwarded block's destination, the notice's
+        // target)
+        const uint32_t top5 = MIGB ? max(k5.z >= 0 ? (uint32_t)((k5.z & ~MIG_TRANSIT) + 1) : 0u, (uint32_t)(k5.w + 1)) : 0u;
+        if (top > (uint32_t)N || (LSPDB && ((P.flags & PF_BAD) || (k4.y >= 0 && k4.y >= C.lines))) ||
+            (MIGB && (top5 > (uint32_t)N || (k5.x >= 0 && k5.x >= C.lines)))) {
           st_coh(C.err, 2);  // a corrupt queue index: stop rather than address memory with it
           ok = false;
         }
@@ -1759,6 +1774,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           fwd_line = line;
           fwd_val = owner;
         };
+        // migration: the access histories of the two slice sets (the ways' order, mg words a way)
+        int* const histR = MIGB ? C.l2h + (size_t)(P.setR - C.l2) * mg : nullptr;
+        int* const histL = MIGB ? C.l2h + (size_t)(P.setL - C.l2) * mg : nullptr;
         const int svc_type = k1.x >> 24;  // LSPD: the served message's kind (Q_*)
         if (p_svc && !lspd) {
           const int rq = k1.x, line = k1.y;
@@ -1774,13 +1792,46 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             const int i = way_of(P.vR, line);
             if (i >= 0) {
               acc.l2_hit++;
+              int n = 0;
+              if (mig) {  // Sec. 3.3: the block's list of its last accessors
+                n = hist_note(histR, mg, i, who);
+                hist_front(histR, mg, i);
+              }
               way_front(P.vR, i);
               dirtyR = true;
-              enqueue(true, who, c + idl, line);
+              // a remote tile made most of the block's last accesses: the block moves there,
+              // unless it has just moved here and this slice still waits for the directory to
+              // acknowledge its claim, or another block of this slice is still on its way
+              const bool claiming = k0.x == CORE_WAIT && k0.z == line;
+              const bool sending = k5.z >= 0 && (k5.z & MIG_TRANSIT);
+              if (mig && 2 * n > mg && !claiming && !sending) {
+                k5.y = line;  // sent whole; this slice serves it until told of its arrival
+                k5.z = who | MIG_TRANSIT;
+                lds_add(L, SIM_ST_MIGRATE, 1);
+                enqueue(true, who, c + idl, line | MIG_MARK);
+              } else {
+                enqueue(true, who, c + idl, line);
+              }
+            } else if (mig && k5.y == line) {  // Sec. 3.3: redirected to where the block went
+              lds_add(L, SIM_ST_REDIRECT, 1);
+              enqueue(false, who, c + idl, k5.z & ~MIG_TRANSIT);
             } else {
               lds_add(L, SIM_ST_TRAP, 1);
               enqueue(false, who, c + idl, CODE_TRAP);
             }
+          } else if (MIGB && svc_type == Q_ARRIVED) {  // the block sent away has arrived: this copy goes
+            if (k5.z == (who | MIG_TRANSIT)) {
+              const int i = way_of(P.vR, line);
+              if (i >= 0) {
+                way_remove(P.vR, ways2, i);
+                if (mig) hist_remove(histR, mg, ways2, i);
+                dirtyR = true;
+              }
+              k5.z = who;
+            }
+          } else if (MIGB && svc_type == Q_CLAIM) {  // the directory names the block's new owner and tells it
+            dir_write(line, P.loc_svc, who);
+            enqueue(false, who, c + idl, CODE_ACK);
           } else if (svc_type == Q_DA) {  // the owner, or (not on chip) the asker brings it from memory
             lds_add(L, SIM_ST_DIR_ACCESS, 1);
             int code = P.loc_svc;
@@ -1798,47 +1849,77 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k1.y = -1;
         }
         // the core's slice access below sees the service's changes when both touch one set
-        if (LSPDB && (pf & PF_SVC) && (pf & (PF_SLICE | PF_FILLMEM)) && svc_type == Q_RA && P.setL == P.setR) {
+        if (LSPDB && (pf & PF_SVC) && (pf & (PF_SLICE | PF_FILLMEM)) && (svc_type == Q_RA || (MIGB && svc_type == Q_ARRIVED)) &&
+            P.setL == P.setR) {
 #pragma unroll
           for (int i = 0; i < 8; ++i) P.vL[i] = P.vR[i];
           dirtyL = dirtyL || dirtyR;
           dirtyR = false;
         }
         if (p_fill) {
-          if (LSPDB && (pf & PF_FILLMEM)) {  // from memory into the local slice too; an evicted
-            const int victim = way_insert(P.vL, ways2, k0.z);  // block leaves the directory
+          bool claim = false;  // migration: the op completes when the directory has the new owner
+          if (LSPDB && (pf & PF_FILLMEM)) {  // from memory (or migrated) into the local slice too;
+            const int victim = way_insert(P.vL, ways2, k0.z);  // an evicted block leaves the directory
+            if (mig) hist_insert(histL, mg, ways2);  // its history starts empty
             dirtyL = true;
             if (victim >= 0 && (unsigned)victim >= (unsigned)C.lines) {
               st_coh(C.err, 2);  // a corrupt slice word: stop rather than address memory with it
               ok = false;
+            } else if (victim >= 0 && mig && victim == k5.y && k5.z >= 0 && (k5.z & MIG_TRANSIT)) {
+              // the block on its way elsewhere leaves this slice: its new owner's claim updates
+              // the directory, and requests still reaching here are redirected
             } else if (victim >= 0 && dir_of(victim) == t) {
               dir_write(victim, t, -1);
               lds_add(L, SIM_ST_DIR_EVICT, 1);
             } else if (victim >= 0) {
               k4.y = victim;  // the eviction notice goes out before the next directory access
             }
+            if (MIGB && k0.x == CORE_FILL_MIG) {  // Sec. 3.3: the directory learns the new owner
+              if (dir_of(k0.z) == t) {
+                dir_write(k0.z, fwd_line == k0.z ? fwd_val : P.loc_core, t);
+              } else {
+                claim = true;
+                k5.x = k0.z;
+                k0.x = CORE_WAIT;
+              }
+            }
           }
-          set_touch(P.u, ways1, P.line_op, true, dirty1);
-          const int lat = c - k0.w;
-          acc.ops_done++;
-          acc.op_lat += (unsigned long long)lat;
-          acc.op_lat_max = max(acc.op_lat_max, lat);
-          k0.x = CORE_IDLE;
+          if (!MIGB || !claim) {
+            set_touch(P.u, ways1, P.line_op, true, dirty1);
+            const int lat = c - k0.w;
+            acc.ops_done++;
+            acc.op_lat += (unsigned long long)lat;
+            acc.op_lat_max = max(acc.op_lat_max, lat);
+            k0.x = CORE_IDLE;
+          }
         } else if (k0.x == CORE_L1MISS && k0.y == c) {
           if (LSPDB && lspd) {  // own slice, then the directory (Sec. 3.2)
             const int i = way_of(P.vL, k0.z);
             if (!(pf & PF_SLICE)) {
-              k0.y = c + 1;  // a pending eviction notice goes out first
+              k0.y = c + 1;  // a pending eviction notice or claim goes out first
             } else if (i >= 0) {
               acc.l2_hit++;
+              if (mig) {  // the local core's access
+                hist_note(histL, mg, i, t);
+                hist_front(histL, mg, i);
+              }
               way_front(P.vL, i);
               dirtyL = true;
               k0.x = CORE_FILL;
               k0.y = c + 1;
+            } else if (mig && k5.y == k0.z && k5.z >= 0 && (k5.z & MIG_TRANSIT)) {
+              // this slice sent the block away and has since evicted its copy: the core waits
+              // for the arrival notice before it asks for the block again (so that the notice
+              // cannot remove a copy that came back to this slice)
+              k0.y = c + 1;
             } else if (pf & PF_DIRCORE) {  // this tile keeps the entry: look it up at once
               lds_add(L, SIM_ST_DIR_ACCESS, 1);
-              const int o = fwd_line == k0.z ? fwd_val : P.loc_core;
-              if (o == t) {  // this slice's own eviction is still on its way: look again
+              int o = fwd_line == k0.z ? fwd_val : P.loc_core;
+              if (MIGB && o == t && k5.y == k0.z) {  // this slice gave the block away; the new
+                o = k5.z & ~MIG_TRANSIT;             // owner's claim is still on the way
+                lds_add(L, SIM_ST_REDIRECT, 1);
+              }
+              if (o == t) {  // this slice's own eviction (or an older migration) is still on its way: look again
                 lds_add(L, SIM_ST_TRAP, 1);
                 k0.y = c + 1;
               } else {
@@ -1973,8 +2054,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         h = mix_pair(h, dhl, dhi);  // the op held by hit under miss (-1, 0: none)
         h = mix_pair(h, dk4.x, dk4.y);  // LSPD: remote-access target, pending eviction notice
         h = mix_pair(h, dk4.z, dk4.w);  // and the directory checksum (without LSPD: -1, -1, 0, 0)
-        h = mix_pair(h, -1, -1);  // no claim, forwarded block
-        h = mix_pair(h, -1, -1);  // or its destination
+        h = mix_pair(h, dk5.x, dk5.y);  // migration: claim, forwarded block,
+        h = mix_pair(h, dk5.z, dk5.w);  // its destination, arrival notice (all -1 without)
         if (aged)  // the arrivals' deflection counts
           h = mix_pair(h, (int)(row_age(a0) | (row_age(a1) << 16)), (int)(row_age(a2) | (row_age(a3) << 16)));
         if (PIPE && rd > 1) {  // stage st: the flits that leave the pipeline in cycle c-1+st
@@ -2005,7 +2086,9 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
         int cls = -1;
         // (LSPD: the miss queue holds one-flit answers, and the core's own flit is a pending
         // eviction notice, a directory access or a remote access)
-        const bool own = LSPDB && lspd ? (k4.y >= 0 || ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
+        // (migration: an arrival notice or a claim as well)
+        const bool own = LSPDB && lspd ? (k4.y >= 0 || (MIGB && (k5.w >= 0 || k5.x >= 0)) ||
+                                          ((k0.x == CORE_SEND_DA || k0.x == CORE_SEND_RA) && k0.y <= c))
                                        : (k0.x == CORE_SEND && (!VARS || k0.y + idl <= c));
         if (k2.x >= 0 && nm.y <= c) cls = 0;
         else if (k1.z >= 0 && (!VARS || nh.y <= c)) cls = 1;
@@ -2033,6 +2116,16 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
               fi.y = (int)((uint32_t)c | CTL_BIT);
               fi.w = (KIND_DIR << 30) | k4.y;
               k4.y = -1;
+            } else if (MIGB && k5.w >= 0) {  // Sec. 3.3: the migrated block has arrived; its source drops its copy
+              fi.x = k5.w;
+              fi.y = (int)((uint32_t)c | CTL_BIT);
+              fi.w = KIND_REQ << 30;
+              k5.w = -1;
+            } else if (MIGB && k5.x >= 0) {  // a migrated block's new owner, to its directory tile
+              fi.x = dir_of(k5.x);
+              fi.y = (int)((uint32_t)c | CTL_BIT);
+              fi.w = (KIND_BG << 30) | k5.x;
+              k5.x = -1;
             } else if (k0.x == CORE_SEND_DA) {  // directory access
               fi.x = dir_of(k0.z);
               fi.w = (KIND_DIR << 30) | k0.z;
@@ -2048,19 +2141,26 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             const int4 hd = cls == 0 ? nm : nh;
             fi.x = cls == 0 ? k2.x : k1.z;
             const int sent = hd.w + 1;
-            const bool last = !PACKETS || sent >= C.reply_flits;
+            // a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits
+            const bool mig_pk = MIGB && lspd && (hd.z & MIG_MARK);
+            const int len = mig_pk ? MIG_FLITS : C.reply_flits;
+            const bool last = !PACKETS || sent >= len;
             if (last) {
               if (cls == 0) { k2.x = hd.x; if (hd.x < 0) k2.y = -1; }
               else { k1.z = hd.x; if (hd.x < 0) k1.w = -1; }
             }
             // the sent count goes to the head's node; a node appended this cycle is written
             // whole with phase one's stores, so its count rides with that store
-            if (PACKETS && C.reply_flits > 1) {
+            if (PACKETS && len > 1) {
               if (fi.x == node_rq) node_w = last ? 0 : sent;
               else st_i<MULTI>(reinterpret_cast<int*>(&C.node[fi.x]) + 3, last ? 0 : sent);
             }
             fi.w = (KIND_REPLY << 30) | hd.z;
-            acc.reply_sent += last;
+            if (mig_pk) {
+              fi.w = (KIND_REPLY << 30) | (CODE_MIG + CODE_BASE);
+              fi.y = (int)((uint32_t)c | CTL_BIT);
+            }
+            acc.reply_sent += last && !mig_pk;
             acc.inj_reply++;
           } else if (cls == 2) {
             fi.x = (int)mod_n(C, (uint32_t)k0.z);
@@ -2202,25 +2302,44 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           const bool ctl = LSPDB && ((uint32_t)oe.y & CTL_BIT);
           const int lat = c - (int)((uint32_t)oe.y & ym);
           const unsigned long long ulat = (unsigned long long)lat;
-          const bool as_req = kind == KIND_REQ || (LSPDB && kind == KIND_DIR);  // directory messages count as requests
+          // directory messages and ownership claims count as requests
+          const bool as_req = kind == KIND_REQ || (LSPDB && kind == KIND_DIR) || (MIGB && kind == KIND_BG && ctl);
+          const bool as_bg = kind == KIND_BG && !(MIGB && ctl);
           acc.ej_req += as_req;
           acc.ej_reply += kind == KIND_REPLY;
-          acc.ej_bg += kind == KIND_BG;
+          acc.ej_bg += as_bg;
           acc.lat_req += as_req ? ulat : 0ull;
           acc.lat_reply += kind == KIND_REPLY ? ulat : 0ull;
-          acc.lat_bg += kind == KIND_BG ? ulat : 0ull;
+          acc.lat_bg += as_bg ? ulat : 0ull;
           acc.lat_max = max(acc.lat_max, lat);
           lds_add(L, SIM_ST_HIST + min(15, 31 - __builtin_clz((unsigned)max(lat, 1))), 1);
-          if (kind == KIND_REQ) {
+          if (MIGB && kind == KIND_REQ && ctl) {  // migration: the block this slice sent has arrived
+            k1.x = (int)((uint32_t)oe.z & TILE_BITS_MASK) | (Q_ARRIVED << 24);
+            k1.y = k5.y;  // the block it sent (one at a time)
+          } else if (kind == KIND_REQ) {
             acc.req_recv++;
             k1.x = VARS ? (int)((uint32_t)oe.z & TILE_BITS_MASK) : oe.z;
+            k1.y = oe.w & LINE_MASK;
+          } else if (MIGB && kind == KIND_BG && ctl) {  // migration: the new owner's claim
+            k1.x = (int)((uint32_t)oe.z & TILE_BITS_MASK) | (Q_CLAIM << 24);
             k1.y = oe.w & LINE_MASK;
           } else if (LSPDB && kind == KIND_DIR) {  // directory access or (control bit) eviction notice
             k1.x = (int)((uint32_t)oe.z & TILE_BITS_MASK) | ((ctl ? Q_EV : Q_DA) << 24);
             k1.y = oe.w & LINE_MASK;
           } else if (LSPDB && kind == KIND_REPLY && ctl) {  // the directory's answer or a trap
             const int code = (oe.w & LINE_MASK) - CODE_BASE;
-            if (code == CODE_NACK) {  // not on chip: from memory into the local slice
+            if (MIGB && code == CODE_MIG) {  // a flit of the block migrating here; the last one fills it in
+              rcv += 1;
+              if (rcv >= MIG_FLITS) {  // the whole block is in; its source is told (Sec. 3.3)
+                rcv = 0;
+                k5.w = (int)((uint32_t)oe.z & TILE_BITS_MASK);
+                k0.x = CORE_FILL_MIG;
+                k0.y = c + 1;
+              }
+            } else if (MIGB && code == CODE_ACK) {  // the directory names this slice: L1 fill, op complete
+              k0.x = CORE_FILL;
+              k0.y = c + 1;
+            } else if (code == CODE_NACK) {  // not on chip: from memory into the local slice
               k0.x = CORE_FILL_MEM;
               k0.y = c + C.mem_lat;
             } else if (code == CODE_TRAP || code == t) {  // stale entry: ask the directory again
@@ -2247,7 +2366,8 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
           k2.z += 1;
           acc.bg_gen++;
         }
-        if (c + 1 < c_end) prefetch<MULTI, VARS, W48, LSPDB>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4);
+        if (c + 1 < c_end)
+          prefetch<MULTI, VARS, W48, LSPDB, MIGB>(C, t, c + 1, k0, k1, k2, hline, hum, l1_base, l2_base, P, k4, k5);
 #undef out_for
       }
     }
@@ -2274,6 +2394,7 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
     gstore4(&C.core[2 * N + t], k2);
     gstore4(&C.core[3 * N + t], make_int4(fdst, rcv, hline, hissue));
     if (lspd) gstore4(&C.core[4 * N + t], k4);
+    if (mig) gstore4(&C.core[5 * N + t], k5);
     const int par = c_done & 1;
     if (i0) gstore4(&C.link[(par * 4 + 0) * N + t], slot_encode(s_link[par][0][j], (uint32_t)c_done));
     if (i1) gstore4(&C.link[(par * 4 + 1) * N + t], slot_encode(s_link[par][1][j], (uint32_t)c_done));
@@ -2434,14 +2555,14 @@ int kernel_level(const ChipDev& d) { return d.lspd ? 2 : (d.variants != 0 || d.r
 // variants the one-tile-per-thread kernel carries, with any router delay
 constexpr int32_t FAST_FLAGS = SIM_FLAG_AGE_DEFLECT | SIM_FLAG_HIT_UNDER_MISS | SIM_FLAG_INJECT_DELAY;
 // whether a chip may run on the one-tile-per-thread kernel: any of those variants, and the LSPD
-// directory without migration (a migrating chip needs the general kernel)
+// directory with or without migration
 bool fast_model(const sim_config* c) {
   const int32_t carried = FAST_FLAGS | SIM_FLAG_LSPD | SIM_FLAG_LSPD_CENTRAL;
-  return (c->flags & VARIANT_FLAGS & ~carried) == 0 && c->mig_threshold == 0;
+  return (c->flags & VARIANT_FLAGS & ~carried) == 0;
 }
 // (FAST_WAYS48 is set only when every chip of a launch has the 4/8-way geometry: see batch_kind)
 int fast_opt(const ChipDev& d) {
-  return (d.lspd ? FAST_LSPD : 0) | (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
+  return (d.lspd ? FAST_LSPD : 0) | (d.mig ? FAST_MIG : 0) | (d.reply_flits > 1 ? FAST_PACKETS : 0) | ((d.variants & FAST_FLAGS) ? FAST_VARIANTS : 0) |
          (d.rdelay > 1 ? FAST_PIPE : 0) | ((d.w1 == 4 && d.w2 == 8) ? FAST_WAYS48 : 0);
 }
 
@@ -2517,6 +2638,7 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
+  if (opt & FAST_MIG) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_MIG | FAST_LSPD | 7>);
   if ((opt & (FAST_LSPD | 7)) == FAST_LSPD && (opt & FAST_WAYS48))
     return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | FAST_WAYS48>);
   if (opt & FAST_LSPD) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | 7>);
@@ -2549,7 +2671,7 @@ const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 
 int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
   int per_cu = 0, per_cu_var = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
-  for (int o = FAST_LSPD; fast && o <= (FAST_LSPD | FAST_WAYS48); o += FAST_WAYS48) {  // (the directory's builds)
+  for (int o = FAST_LSPD; fast && o <= (FAST_MIG | FAST_LSPD); o += FAST_WAYS48) {  // (the directory's builds)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(true, false, o), block, 0) != hipSuccess)
       return 0;
     per_cu = std::min(per_cu, per_cu_var);
@@ -2566,7 +2688,7 @@ int resident_limit(int block, bool fast) {  // the general kernel: the lower of 
 // OPT bits, or on the general kernel)
 int resident_limit_any(int block) {
   int lo = resident_limit(block, false);
-  for (int k = 0; k < 64; ++k) {  // (OPT 16-31 map to the directory's two builds)
+  for (int k = 0; k < 128; ++k) {  // (OPT 16-63 map to the directory's three builds)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
       return 0;
@@ -2736,7 +2858,6 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   h->stream = static_cast<hipStream_t>(stream);
   h->cycle = 0;
   h->chunk = 1000;
-  // migration: general kernel
   h->use_fast = fast_model(cfg);
   const int N = cfg->width * cfg->height;
   ChipDev& d = h->hd;

@@ -1,4 +1,9 @@
-"""Parity of block migration and redirection (Sec. 3.3) on the GPU with the serial oracle."""
+"""Parity of block migration and redirection (Sec. 3.3) on the GPU with the serial oracle.
+
+A migrating chip runs on the one-tile-per-thread kernel by default; the main cases run on both
+that kernel and the general one."""
+from functools import partial
+
 import pytest
 
 from oracle import oracle as O
@@ -12,24 +17,28 @@ pytestmark = pytest.mark.gpu
 LSPD, CENTRAL = W.LSPD, W.LSPD_CENTRAL
 
 
-def test_gpu_hand_trace_migration_then_redirection():
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_gpu_hand_trace_migration_then_redirection(generic):
     """The oracle's hand trace on the GPU: the block migrates (31) and a request that reaches
     the source after the arrival notice is redirected (17)."""
-    OM.test_hand_trace_migration_then_redirection(make_sim=gpu_sim)
+    OM.test_hand_trace_migration_then_redirection(make_sim=partial(gpu_sim, generic=generic))
 
 
-def test_gpu_hand_trace_source_serves_during_transit():
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_gpu_hand_trace_source_serves_during_transit(generic):
     """A request that reaches the source while the block is on its way is served there (14)."""
-    OM.test_hand_trace_source_serves_during_transit(make_sim=gpu_sim)
+    OM.test_hand_trace_source_serves_during_transit(make_sim=partial(gpu_sim, generic=generic))
 
 
-def test_gpu_hand_trace_source_evicts_the_block_on_its_way():
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_gpu_hand_trace_source_evicts_the_block_on_its_way(generic):
     """The source's one-way slice drops the block while it is on its way: no eviction notice."""
-    OM.test_hand_trace_source_evicts_the_block_on_its_way(make_sim=gpu_sim)
+    OM.test_hand_trace_source_evicts_the_block_on_its_way(make_sim=partial(gpu_sim, generic=generic))
 
 
 @pytest.mark.parametrize("seed", range(8))
-def test_gpu_migration_races_under_pressure(seed):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_gpu_migration_races_under_pressure(seed, generic):
     """The oracle's high-pressure migration runs (late arrival notices, sources evicting blocks
     on their way, blocks moving on before the notice): every digest and the state after a
     drain equal the oracle's."""
@@ -39,7 +48,7 @@ def test_gpu_migration_races_under_pressure(seed):
     p = OM._params(rng, w, h, LSPD | (CENTRAL if seed % 2 else 0), 1, op_thr=W.thr(0.9), shared_thr=W.thr(0.95),
                    shared_lines=6 + seed, private_lines=2, bg_thr=0, reply_flits=1 + seed % 3, mem_lat=5,
                    l2_sets=1, l2_ways=1 + seed % 2, l1_sets=1)
-    g, o = assert_same_run(p, 2000, step_sizes=[1, 999, 1000])
+    g, o = assert_same_run(p, 2000, step_sizes=[1, 999, 1000], generic=generic)
     for s in (g, o):
         s.set_rates(0, 0)
         s.step(2000)
@@ -48,8 +57,9 @@ def test_gpu_migration_races_under_pressure(seed):
 
 @pytest.mark.parametrize("mig,pattern,moved", OM.MAJORITY_CASES + [(3, [8, 0, 4], 0), (16, [8] * 9, 1),
                                                                   (16, [8] * 8, 0)])
-def test_gpu_majority_of_the_last_n_accesses(mig, pattern, moved):
-    g = OM.remote_reads(mig, pattern, make_sim=gpu_sim)
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_gpu_majority_of_the_last_n_accesses(mig, pattern, moved, generic):
+    g = OM.remote_reads(mig, pattern, make_sim=partial(gpu_sim, generic=generic))
     o = OM.remote_reads(mig, pattern)
     assert g.stat("migrations") == o.stat("migrations") == moved
     assert (g.dump() == o.dump()).all()   # tags, histories, forwarding words, location array
@@ -57,32 +67,36 @@ def test_gpu_majority_of_the_last_n_accesses(mig, pattern, moved):
 
 @pytest.mark.parametrize("thr", [1, 2, 4])
 @pytest.mark.parametrize("flags", [LSPD, LSPD | CENTRAL], ids=["interleaved", "central"])
-def test_migration_config0_run(flags, thr):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_migration_config0_run(flags, thr, generic):
     p = W.config0().with_(flags=flags, mig_threshold=thr, op_thr=W.thr(0.5), l1_sets=2, l1_ways=1, l2_sets=8,
                           l2_ways=2, shared_lines=256, reply_flits=4)
-    assert_same_run(p, 6000, step_sizes=[1, 999, 5000])
+    assert_same_run(p, 6000, step_sizes=[1, 999, 5000], generic=generic)
 
 
 @pytest.mark.parametrize("w,h", [(1, 1), (1, 7), (5, 5), (13, 7)])
 @pytest.mark.parametrize("flags", [LSPD, LSPD | W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY],
                          ids=["lspd", "with_variants"])
-def test_migration_small_shapes(w, h, flags):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_migration_small_shapes(w, h, flags, generic):
     p = W.config1().with_(width=w, height=h, seed=w * 100 + h + flags, bg_thr=W.thr(0.1) if w * h > 1 else 0,
                           op_thr=W.thr(0.6), l1_sets=2, l1_ways=1, l2_sets=8, l2_ways=2, shared_lines=256,
                           private_lines=32, flags=flags, mig_threshold=1, reply_flits=2, router_delay=2)
-    assert_same_run(p, 3000)
+    assert_same_run(p, 3000, generic=generic)
 
 
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
-def test_migration_patch_mappings(launch):
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_migration_patch_mappings(launch, generic):
     p = W.config1().with_(width=20, height=13, seed=12, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l1_sets=2, l1_ways=1,
                           l2_sets=8, l2_ways=2, shared_lines=512, private_lines=32, flags=LSPD, mig_threshold=2)
-    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800])
+    assert_same_run(p, 1500, launch=launch, step_sizes=[700, 800], generic=generic)
 
 
-def test_migration_208x208_prefix():
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_migration_208x208_prefix(generic):
     p = W.config2(0.05).with_(flags=LSPD, private_lines=2**10, mig_threshold=2)
-    assert_same_run(p, 80, step_sizes=[30, 50])
+    assert_same_run(p, 80, step_sizes=[30, 50], generic=generic)
 
 
 def test_migration_checkpoint_mid_claim_and_drain():
