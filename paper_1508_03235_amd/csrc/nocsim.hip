@@ -2667,33 +2667,26 @@ const void* multi_kernel(bool fast, bool digest = false, int opt = 0, int var = 
                                : reinterpret_cast<const void*>(step_kernel<true, 0>);
   return digest ? fast_build<true, true>(opt) : fast_build<true, false>(opt);
 }
-// how many workgroups of `block` threads of the multi-patch kernel can be resident at once
-int resident_limit(int block, bool fast) {  // the general kernel: the lower of its two builds
-  int per_cu = 0, per_cu_var = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast), block, 0) != hipSuccess) return 0;
-  for (int o = FAST_LSPD; fast && o <= (FAST_MIG | FAST_LSPD); o += FAST_WAYS48) {  // (the directory's builds)
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(true, false, o), block, 0) != hipSuccess)
-      return 0;
-    per_cu = std::min(per_cu, per_cu_var);
-  }
-  for (int v = 1; !fast && v <= 2; ++v) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_var, multi_kernel(false, false, false, v), block, 0) !=
+// how many workgroups of `block` threads of the multi-patch kernel of one kind (the general
+// kernel's build `var`, or the one-tile-per-thread build for OPT bits `opt`) the device holds at
+// once; with `digests`, the lower of its builds with and without them, as a single chip may
+// ask for either (batches launch the build without); 0 if the runtime cannot tell
+int resident_limit(int block, bool fast, int opt, int var, bool digests) {
+  int lo = INT_MAX;
+  for (int dig = 0; dig < (fast && digests ? 2 : 1); ++dig) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(fast, dig != 0, opt, var), block, 0) !=
         hipSuccess)
       return 0;
-    per_cu = std::min(per_cu, per_cu_var);
+    lo = std::min(lo, per_cu);
   }
-  return per_cu * device_cus();
+  return lo * device_cus();
 }
-// the same over every build a chip may be launched with (with or without digests, with any
-// OPT bits, or on the general kernel)
+// the same over every build a chip may be launched with (any OPT bits, or the general kernel)
 int resident_limit_any(int block) {
-  int lo = resident_limit(block, false);
-  for (int k = 0; k < 128; ++k) {  // (OPT 16-63 map to the directory's three builds)
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_kernel(true, k & 1, k >> 1), block, 0) != hipSuccess)
-      return 0;
-    lo = std::min(lo, per_cu * device_cus());
-  }
+  int lo = INT_MAX;
+  for (int v = 0; v <= 2; ++v) lo = std::min(lo, resident_limit(block, false, 0, v, true));
+  for (int o = 0; o < 64; ++o) lo = std::min(lo, resident_limit(block, true, o, 0, true));  // (16-63: the directory's)
   return lo;
 }
 
@@ -2743,7 +2736,8 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   const int pgx = (h->cfg.width + pw - 1) / pw, pgy = (h->cfg.height + ph - 1) / ph;
   const int np = pgx * pgy;
   if (np > h->hd.max_patches) return SIM_EINVAL;
-  if (np > 1 && np > resident_limit(block, pw * ph <= block && h->use_fast)) return SIM_EINVAL;
+  if (np > 1 && np > resident_limit(block, pw * ph <= block && h->use_fast, fast_opt(h->hd), kernel_level(h->hd), true))
+    return SIM_EINVAL;
   h->hd.pw = pw;
   h->hd.ph = ph;
   h->hd.pgx = pgx;
@@ -2954,7 +2948,8 @@ int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
   const bool use_fast = !generic_only && fast_model(&h->cfg);
   const int np = h->hd.n_patches;
-  if (np > 1 && np > resident_limit(h->block, h->fast && use_fast)) return SIM_EINVAL;
+  if (np > 1 && np > resident_limit(h->block, h->fast && use_fast, fast_opt(h->hd), kernel_level(h->hd), true))
+    return SIM_EINVAL;
   h->use_fast = use_fast;
   return SIM_OK;
 }
@@ -3350,7 +3345,7 @@ int rebuild(sim_group* g) {
   g->fast = k.fast;
   g->opt = k.opt;
   g->var = k.var;
-  const int limit = k.multi ? resident_limit(g->block, k.fast) : 0;
+  const int limit = k.multi ? resident_limit(g->block, k.fast, k.opt, k.var, false) : 0;
   int64_t e = 0;
   for (int i = 0; i < n; ++i) {
     g->first_entry.push_back((int32_t)e);
@@ -3492,10 +3487,11 @@ int simb_add(simb_t* g, sim_t* chip, int32_t* slot) {
   if (members + 1 > g->max_chips || entries > g->max_entries) return SIM_EBUSY;
   // a chip of several patches must fit the device at once under the batch's kernel
   if (chip->hd.n_patches > 1) {
-    bool fast = chip->use_fast && chip->hd.pw * chip->hd.ph <= g->block;
+    std::vector<sim_chip*> all(1, chip);
     for (sim_chip* h : g->slots)
-      if (h) fast = fast && h->use_fast && h->hd.pw * h->hd.ph <= g->block;
-    if (chip->hd.n_patches > resident_limit(g->block, fast)) return SIM_EINVAL;
+      if (h) all.push_back(h);
+    const BatchKind k = batch_kind([&all](int i) { return all[i]; }, (int)all.size(), g->block);
+    if (chip->hd.n_patches > resident_limit(g->block, k.fast, k.opt, k.var, false)) return SIM_EINVAL;
   }
   if (free_slot < 0) {
     free_slot = (int)g->slots.size();
@@ -3612,7 +3608,7 @@ int simb_step_noalloc(sim_t* const* chips, int32_t n, int32_t block, const int64
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto chip_at = [chips](int k) { return chips[k]; };
   const BatchKind k = batch_kind(chip_at, n, blk);
-  const int limit = k.multi ? resident_limit(blk, k.fast) : 0;
+  const int limit = k.multi ? resident_limit(blk, k.fast, k.opt, k.var, false) : 0;
   // a chip too large to be resident is refused before anything is launched
   rc = plan_groups(chip_at, n, limit, [](const sim_launch_group&) {});
   if (rc) return rc;
