@@ -9,8 +9,9 @@ from paper_1508_03235_amd import workload as W
 pytestmark = pytest.mark.gpu
 
 
-def chips(sides, base_seed):
-    return [W.config1().with_(width=s, height=s, seed=base_seed + i, bg_thr=W.thr(0.03 + 0.04 * (i % 4)))
+def chips(sides, base_seed, flags=0, mig=0):
+    return [W.config1().with_(width=s, height=s, seed=base_seed + i, bg_thr=W.thr(0.03 + 0.04 * (i % 4)), flags=flags,
+                              mig_threshold=mig, l2_sets=16 if flags else 512)
             for i, s in enumerate(sides)]
 
 
@@ -23,9 +24,10 @@ def make(params, patch):
 
 
 @pytest.mark.parametrize("patch", [64, 16])
-def test_noalloc_equals_workspace_batch(patch):
+@pytest.mark.parametrize("flags,mig", [(0, 0), (W.LSPD, 0), (W.LSPD, 2)], ids=["base", "directory", "migration"])
+def test_noalloc_equals_workspace_batch(patch, flags, mig):
     from paper_1508_03235_amd import nocsim
-    first = chips([8, 24, 16, 32, 8, 48], 9100)
+    first = chips([8, 24, 16, 32, 8, 48], 9100, flags, mig)
     second_idx = [1, 4]            # the second call: fewer chips, one of them small
     c1 = [700, 1234, 999, 1500, 1, 333]
     c2 = [0, 257, 0, 0, 911, 0]
