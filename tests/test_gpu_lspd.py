@@ -57,6 +57,17 @@ def test_lspd_small_shapes(w, h, flags, generic):
     assert_same_run(p, 3000, generic=generic)
 
 
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("flags", MODES + [LSPD | W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY],
+                         ids=IDS + ["with_variants"])
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_lspd_router_delay(D, flags, generic):
+    """The directory with a router delay of D cycles per hop and 3-flit replies."""
+    p = W.config1().with_(width=9, height=6, seed=77 + D, bg_thr=W.thr(0.1), op_thr=W.thr(0.6), l1_sets=8, l2_sets=8,
+                          l2_ways=2, shared_lines=512, private_lines=64, flags=flags, reply_flits=3, router_delay=D)
+    assert_same_run(p, 2500, step_sizes=[1000, 1500], generic=generic)
+
+
 @pytest.mark.parametrize("w,h,launch", [(13, 7, None), (20, 13, (5, 5, 64, 0)), (20, 13, (20, 1, 64, 37))])
 @pytest.mark.parametrize("flags", MODES, ids=IDS)
 @pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
