@@ -78,8 +78,8 @@ typedef struct {
 } sim_config;
 
 /* Model variants (bits of sim_config.flags).  Each replaces one reading of the base model by a
-   more literal reading of the paper.  Chips with the directory run on the general kernel; the
-   other variants, and a router delay above 1, also run on the one-tile-per-thread kernel.
+   more literal reading of the paper.  Every variant, the directory and migration included, and
+   a router delay above 1 run on both the one-tile-per-thread kernel and the general one.
    AGE_DEFLECT: a flit's priority is the number of times it has been deflected (more first,
      0 at injection; Sec. 4.2, Sec. 6.2.1, Sec. 7.1 phase two), ties by (injection cycle,
      source).  The base model ranks by (injection cycle, source) alone.  A flit deflected

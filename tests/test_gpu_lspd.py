@@ -97,6 +97,20 @@ def test_lspd_208x208_prefix(flags, generic):
     assert_same_run(p, 80, step_sizes=[30, 50], generic=generic)
 
 
+@pytest.mark.parametrize("mig", [0, 1], ids=["directory", "migration"])
+def test_lspd_208x208_past_memory_latency_timed_build(mig):
+    """The 208x208 chip with the directory (and with migration at a history of 1) for 1,200
+    cycles, past the 200-cycle memory latency, on the build the benchmark times (no digests):
+    the whole state, location array and histories included, equals the oracle's."""
+    p = W.config2(0.05).with_(flags=LSPD, mig_threshold=mig, private_lines=2**10)
+    g = gpu_sim(p)
+    g.step(1200)
+    o = O.OracleSim(p)
+    o.step(1200)
+    assert (g.dump() == o.dump()).all()
+    assert g.stat("dir_nack") > 0 and g.stat("l2_hit") > 0
+
+
 @pytest.mark.parametrize("flags", MODES, ids=IDS)
 def test_lspd_checkpoint_and_drain_on_gpu(flags):
     p = W.config1().with_(width=6, height=6, seed=51, bg_thr=W.thr(0.1), op_thr=W.thr(0.5), l2_sets=8, l2_ways=2,
