@@ -248,6 +248,13 @@ __device__ __forceinline__ int4 row_clean(const int4& f) {
 __device__ __forceinline__ int4 sel4(bool p, const int4& a, const int4& b) {  // p ? a : b, per word
   return make_int4(p ? a.x : b.x, p ? a.y : b.y, p ? a.z : b.z, p ? a.w : b.w);
 }
+// The same through a mask the optimizer cannot see through: selects between two records would
+// otherwise be folded into one load from a selected address, which takes both out of registers.
+__device__ __forceinline__ int4 pick4(bool p, const int4& a, const int4& b) {
+  int m = -(int)p;
+  asm volatile("" : "+v"(m));
+  return make_int4((a.x & m) | (b.x & ~m), (a.y & m) | (b.y & ~m), (a.z & m) | (b.z & ~m), (a.w & m) | (b.w & ~m));
+}
 __device__ __forceinline__ bool slot_has_stamp(const int4& w, uint32_t stamp) {
   return ((uint32_t)w.x >> STAMP_SHIFT) == (stamp & STAMP_MASK) && ((uint32_t)w.z >> STAMP_SHIFT) == (stamp & STAMP_MASK);
 }
@@ -979,7 +986,7 @@ __device__ __forceinline__ bool tile_step(const ChipDev& C, int t, int x, int y,
       }
       acc.inj_req++;
     } else if (cls <= 1) {  // a flit of the head's reply; the head is popped with the packet's last flit
-      const int4 hd = sel4(cls == 0, nm, nh);  // word by word (a struct select can go through scratch)
+      const int4 hd = pick4(cls == 0, nm, nh);
       const int rq = cls == 0 ? k2.x : k1.z;
       const int sent = hd.w + 1;
       // a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits
