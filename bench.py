@@ -91,16 +91,9 @@ def event_bytes(p, st_delta, cycles):
     return b
 
 
-def kernel_events_ms(sim, n_cycles, torch):
-    """Average duration of one step-kernel launch, timed with events on the chip's stream."""
-    s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    sim.step(n_cycles, sync=False)
-    e1.record(s)
-    e1.synchronize()
-    _, _, _, chunk = sim.get_launch()
+def kernel_events_ms(e0, e1, n_cycles, chunk):
+    """Average duration of one step-kernel launch over a region bracketed by events e0, e1 on
+    the chip's stream (n_cycles cycles in launches of `chunk` cycles)."""
     launches = -(-n_cycles // chunk)
     return e0.elapsed_time(e1) / launches, launches
 
@@ -497,10 +490,16 @@ def main():
         sim.step(CYCLES_PER_STEP)
     torch.cuda.synchronize()
     st0 = sim.stats()
+    # events on the chip's stream around the timed launches (the roofline's launch duration)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for _ in range(args.steps):
         sim.step(CYCLES_PER_STEP, sync=False)
+    ev1.record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     sim.sync()
@@ -511,8 +510,8 @@ def main():
     timed_check = timed_run_check(sim, p, args.rate)
     print(f"# timed run vs oracle: {timed_check}", file=sys.stderr, flush=True)
 
-    # roofline of the step kernel: event-timed launches on the chip's stream
-    ms_launch, launches = kernel_events_ms(sim, 2 * chunk, torch)
+    # roofline of the step kernel: its launches in the timed region, event-timed on the chip's stream
+    ms_launch, launches = kernel_events_ms(ev0, ev1, cycles, chunk)
     abytes_per_launch = algorithmic_bytes(p, st, cycles) / cycles * chunk
     achieved = abytes_per_launch / (ms_launch * 1e-3) / 1e9
     fast = pw * ph <= block
