@@ -285,7 +285,7 @@ def run_packets(nocsim, W, torch, O, cycles, parity_cycles=200, flits=4):
     return out
 
 
-def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
+def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100, only=None):
     """The 208x208 chip at background 0.05 under each model variant, on the general kernel and
     on the one-tile-per-thread kernel."""
     out = {}
@@ -298,6 +298,8 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100):
              ("lspd_fast", W.LSPD), ("lspd_central_fast", W.LSPD | W.LSPD_CENTRAL), ("lspd_migration_1_fast", W.LSPD)]
     S = nocsim.STAT
     for name, flags in cases:
+        if only and name not in only:
+            continue
         generic = not name.endswith("_fast")
         p = W.config2(0.05).with_(flags=flags, router_delay=2 if name.startswith("router_delay_2") else 1,
                                   mig_threshold=1 if name.startswith("lspd_migration_1") else 0)
@@ -418,6 +420,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-packets", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant", action="append", default=None, metavar="NAME",
+                    help="run only the named variant (repeatable), e.g. lspd_fast")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=60)
@@ -566,7 +570,7 @@ def main():
             out["packets"] = {"error": repr(e)}
     if not args.no_variants:
         try:
-            out["variants"] = run_variants(nocsim, W, torch, O, 3000)
+            out["variants"] = run_variants(nocsim, W, torch, O, 3000, only=args.variant)
         except Exception as e:
             out["variants"] = {"error": repr(e)}
     if not args.no_batched:
