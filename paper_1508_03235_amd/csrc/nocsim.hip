@@ -1542,7 +1542,8 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // OPT bit 4 (FAST_LSPD): the chip may have the LSPD directory (Sec. 3.2, Sec. 6.2.2).  Without
 // migration it has two builds: for single-flit chips without variants or router delay and with
 // 4/8-way caches (bit 3 alone beside it), and with bits 0-2 on and the way counts read at run time.
-// OPT bit 5 (FAST_MIG): the directory with migration (Sec. 3.3), built with bits 0-2 and 4 on.
+// OPT bit 5 (FAST_MIG): the directory with migration (Sec. 3.3), in the same two builds (bit 3
+// alone beside bits 4-5, or bits 0-2 on).
 constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16, FAST_MIG = 32;
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
@@ -2151,14 +2152,14 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
             // a migrating block (Sec. 3.3, Table 1) goes as MIG_FLITS answer flits
             const bool mig_pk = MIGB && lspd && (hd.z & MIG_MARK);
             const int len = mig_pk ? MIG_FLITS : C.reply_flits;
-            const bool last = !PACKETS || sent >= len;
+            const bool last = (!PACKETS && !mig_pk) || sent >= len;  // (a single-flit build still sends a block whole)
             if (last) {
               if (cls == 0) { k2.x = hd.x; if (hd.x < 0) k2.y = -1; }
               else { k1.z = hd.x; if (hd.x < 0) k1.w = -1; }
             }
             // the sent count goes to the head's node; a node appended this cycle is written
             // whole with phase one's stores, so its count rides with that store
-            if (PACKETS && len > 1) {
+            if ((PACKETS || mig_pk) && len > 1) {
               if (fi.x == node_rq) node_w = last ? 0 : sent;
               else st_i<MULTI>(reinterpret_cast<int*>(&C.node[fi.x]) + 3, last ? 0 : sent);
             }
@@ -2645,6 +2646,8 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
+  if ((opt & (FAST_MIG | 7)) == FAST_MIG && (opt & FAST_WAYS48))
+    return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_MIG | FAST_LSPD | FAST_WAYS48>);
   if (opt & FAST_MIG) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_MIG | FAST_LSPD | 7>);
   if ((opt & (FAST_LSPD | 7)) == FAST_LSPD && (opt & FAST_WAYS48))
     return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_LSPD | FAST_WAYS48>);
@@ -2693,7 +2696,7 @@ int resident_limit(int block, bool fast, int opt, int var, bool digests) {
 int resident_limit_any(int block) {
   int lo = INT_MAX;
   for (int v = 0; v <= 2; ++v) lo = std::min(lo, resident_limit(block, false, 0, v, true));
-  for (int o = 0; o < 64; ++o) lo = std::min(lo, resident_limit(block, true, o, 0, true));  // (16-63: the directory's)
+  for (int o = 0; o < 64; ++o) lo = std::min(lo, resident_limit(block, true, o, 0, true));  // (16-63: the directory's four)
   return lo;
 }
 

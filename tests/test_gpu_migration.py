@@ -85,6 +85,21 @@ def test_migration_small_shapes(w, h, flags, generic):
     assert_same_run(p, 3000, generic=generic)
 
 
+@pytest.mark.parametrize("w,h,launch", [(13, 7, None), (20, 13, (5, 5, 64, 0)), (20, 13, (20, 1, 64, 37))])
+@pytest.mark.parametrize("mig", [1, 2])
+@pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
+def test_migration_ways48_single_flit(w, h, launch, mig, generic):
+    """4-way L1, 8-way slices of 4 sets, single-flit replies, no variants: the migration build
+    compiled for those way counts; with a history of one, blocks move, are evicted and are
+    redirected all the time."""
+    p = W.config1().with_(width=w, height=h, seed=w * 37 + h + mig, bg_thr=W.thr(0.1), op_thr=W.thr(0.6), l1_sets=8,
+                          l2_sets=4, shared_lines=256, shared_thr=W.thr(0.8), private_lines=32, flags=LSPD,
+                          mig_threshold=mig)
+    g, o = assert_same_run(p, 3000, launch=launch, step_sizes=[1000, 2000], generic=generic)
+    if mig == 1:  # (a remote majority of the last two accesses is rare under this sharing)
+        assert g.stat("migrations") > 0 and g.stat("redirects") > 0
+
+
 @pytest.mark.parametrize("launch", [(4, 4, 64, 0), (7, 2, 64, 0), (20, 1, 64, 0), (5, 5, 64, 37), (20, 13, 64, 0)])
 @pytest.mark.parametrize("generic", [False, True], ids=["fast", "generic"])
 def test_migration_patch_mappings(launch, generic):
