@@ -10,6 +10,9 @@ state dump at the end (and, for the benchmark's 208x208 chip at background 0.05,
   config2   208x208 at each background rate, 50,000 cycles
   config3   each of the 256 batch instances, 20,000 cycles
   config4   a sample of the served jobs (the first ones whose tiles x cycles stay below a bound)
+  variants  the 208x208 chip at background 0.05 under the paper-literal variants, 10,000 cycles:
+            the LSPD directory (interleaved and central), with migration at a history of 1,
+            the three router variants together, and a router delay of 2
 
 Hashes are xxh3-128 of the little-endian bytes: the uint64 digests of a block of cycles, or
 the int32 dump words.  Nothing here reads a GPU result.  Run:
@@ -34,6 +37,21 @@ BLOCK = 1000
 CONFIG4_JOBS = 60            # the served job list the benchmark runs
 CONFIG4_MAX_WORK = 3.0e8     # tile-cycles per sampled job
 CONFIG4_SAMPLE = 8
+VARIANT_CYCLES = 10_000
+
+
+def variant_runs():
+    """key -> parameters of the 208x208 variant runs (the benchmark's variants leg)."""
+    sys.path.insert(0, ROOT)
+    from paper_1508_03235_amd import workload as W
+    base = W.config2(0.05)
+    return {
+        "config2_0.05_lspd": base.with_(flags=W.LSPD),
+        "config2_0.05_lspd_central": base.with_(flags=W.LSPD | W.LSPD_CENTRAL),
+        "config2_0.05_lspd_mig1": base.with_(flags=W.LSPD, mig_threshold=1),
+        "config2_0.05_variants": base.with_(flags=W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
+        "config2_0.05_rdelay2": base.with_(router_delay=2),
+    }
 
 
 def _hash(a: np.ndarray) -> str:
@@ -86,6 +104,8 @@ def tasks():
         t.append((f"config3_{i}", p.as_dict(), 20_000, 0))
     for j in config4_sample():
         t.append((f"config4_{j.index}", j.params.as_dict(), j.cycles, 0))
+    for key, p in variant_runs().items():
+        t.append((key, p.as_dict(), VARIANT_CYCLES, 0))
     # longest first, so the pool's tail is short
     t.sort(key=lambda x: -x[1]["width"] * x[1]["height"] * x[2])
     return t

@@ -31,6 +31,18 @@ def params_of(run):
     return W.SimParams(**run["params"])
 
 
+def variant_params():
+    """The 208x208 variant runs (the benchmark's variants leg at background 0.05)."""
+    base = W.config2(0.05)
+    return {
+        "config2_0.05_lspd": base.with_(flags=W.LSPD),
+        "config2_0.05_lspd_central": base.with_(flags=W.LSPD | W.LSPD_CENTRAL),
+        "config2_0.05_lspd_mig1": base.with_(flags=W.LSPD, mig_threshold=1),
+        "config2_0.05_variants": base.with_(flags=W.AGE_DEFLECT | W.HIT_UNDER_MISS | W.INJECT_DELAY),
+        "config2_0.05_rdelay2": base.with_(router_delay=2),
+    }
+
+
 # ---- CPU: the stored runs are the workloads of today -------------------------------------------
 
 def test_golden_runs_match_workloads():
@@ -51,6 +63,8 @@ def test_golden_runs_match_workloads():
     for k in keys:
         j = jobs[int(k.split("_")[1])]
         assert params_of(g[k]) == j.params and g[k]["cycles"] == j.cycles
+    for k, p in variant_params().items():
+        assert params_of(g[k]) == p and g[k]["cycles"] == 10_000 and len(g[k]["digest_blocks"]) == 10
 
 
 def test_golden_hashes_are_xxh3_of_dump_bytes():
@@ -104,6 +118,22 @@ def test_config1_full_length():
 @pytest.mark.parametrize("rate", W.CONFIG2_RATES)
 def test_config2_full_length(rate):
     run = gold()["runs"][f"config2_{rate}"]
+    p = params_of(run)
+    s = gpu_run(p, run["cycles"])
+    assert h128(s.dump().astype("<i4")) == run["dumps"][str(run["cycles"])]
+    del s
+    blocks = digest_blocks(p, run["cycles"], 1000)
+    bad = [i for i, (a, b) in enumerate(zip(blocks, run["digest_blocks"])) if a != b]
+    assert not bad, f"first differing block of 1,000 cycles: {bad[0]}"
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("key", list(variant_params()))
+def test_config2_variants_full_length(key):
+    """The 208x208 chip under each variant (directory, central directory, migration, the router
+    variants, router delay 2) for 10,000 cycles, on the kernel each runs on by default: final
+    state in the timed build, per-cycle digests in the checking build."""
+    run = gold()["runs"][key]
     p = params_of(run)
     s = gpu_run(p, run["cycles"])
     assert h128(s.dump().astype("<i4")) == run["dumps"][str(run["cycles"])]
