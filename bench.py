@@ -315,6 +315,7 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100, only=None):
         ej = st[S["ej_req"]] + st[S["ej_reply"]] + st[S["ej_bg"]]
         lat = st[S["lat_req"]] + st[S["lat_reply"]] + st[S["lat_bg"]]
         r = {"flags": flags, "router_delay": p.router_delay, "kernel": "general" if generic else "one tile per thread",
+             "state_gb": nocsim.state_bytes(p) / 1e9,  # the chip's device state (the model's memory cost)
              "tile_cycles_per_s": p.tiles * cycles / dt,
              "deflection_rate": float(st[S["deflections"]] / max(1, st[S["traversals"]])),
              "avg_flit_latency": float(lat / max(1, ej)),
