@@ -27,6 +27,8 @@ Besides the headline line the JSON carries:
                  kernel, beside the base model on that kernel, and each again on the
                  one-tile-per-thread kernel: throughput, deflection rate, latencies, ops per
                  tile-cycle, and per-cycle digests of a prefix against the oracle (--no-variants);
+  meshes       - square meshes from 208x208 to 832x832 tiles on their default mapping:
+                 throughput, kernel and device state (--no-meshes);
   batched      - the 256-chip batch in one launch per chunk, on the batch autotuner's patch shapes,
                  vs the same chips run one at a time on the single-chip autotuner's mappings
                  (--no-batched);
@@ -336,6 +338,28 @@ def run_variants(nocsim, W, torch, O, cycles, parity_cycles=100, only=None):
     return out
 
 
+def run_meshes(nocsim, W, torch, cycles, sides=(208, 256, 320, 416, 624, 832)):
+    """Square meshes of growing size (the config-2 model at background 0.05, 2^10 private lines
+    per tile so that every line stays below 2^30) on the default mapping: throughput, the
+    kernel it runs on and the device state."""
+    out = {}
+    for side in sides:
+        p = W.config2(0.05).with_(width=side, height=side, private_lines=2**10)
+        sim = nocsim.Sim(p)
+        pw, ph, block, chunk = sim.get_launch()
+        sim.step(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(cycles)
+        dt = time.perf_counter() - t0
+        out[f"{side}x{side}"] = {"tiles": p.tiles, "patch": [pw, ph], "block": block,
+                                 "kernel": "one tile per thread" if pw * ph <= block else "general",
+                                 "tile_cycles_per_s": p.tiles * cycles / dt, "us_per_cycle": dt / cycles * 1e6,
+                                 "state_gb": nocsim.state_bytes(p) / 1e9}
+        del sim
+    return out
+
+
 def run_batched(nocsim, W, torch, cycles, plain_chips=None):
     """Config 3: the 256 uneven chips in one batch, each chip shape on the patch shape the batch
     autotuner picked, against the same chips run one at a time, each on the best single-chip
@@ -425,6 +449,7 @@ def main():
                     help="run only the named variant (repeatable), e.g. lspd_fast")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-meshes", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=60)
     ap.add_argument("--launch", type=str, default="", help="patch_w,patch_h,block,chunk")
     ap.add_argument("--maps-out", type=str, default="",
@@ -574,6 +599,11 @@ def main():
             out["variants"] = run_variants(nocsim, W, torch, O, 3000, only=args.variant)
         except Exception as e:
             out["variants"] = {"error": repr(e)}
+    if not args.no_meshes:
+        try:
+            out["meshes"] = run_meshes(nocsim, W, torch, 500)
+        except Exception as e:
+            out["meshes"] = {"error": repr(e)}
     if not args.no_batched:
         try:
             out["batched"] = run_batched(nocsim, W, torch, 2000)
