@@ -1544,7 +1544,23 @@ __device__ __forceinline__ void prefetch(const ChipDev& C, int t, int c, const i
 // 4/8-way caches (bit 3 alone beside it), and with bits 0-2 on and the way counts read at run time.
 // OPT bit 5 (FAST_MIG): the directory with migration (Sec. 3.3), in the same two builds (bit 3
 // alone beside bits 4-5, or bits 0-2 on).
+// OPT bit 6 (FAST_NARROW): workgroups of at most 128 threads, with the LDS rows sized for them,
+// so that four workgroups of two waves share a compute unit (base model only).
 constexpr int FAST_PACKETS = 1, FAST_VARIANTS = 2, FAST_PIPE = 4, FAST_WAYS48 = 8, FAST_LSPD = 16, FAST_MIG = 32;
+constexpr int FAST_NARROW = 64;
+// The chip descriptor read through the constant address space from a pointer made uniform: the
+// descriptor does not change while a launch runs.
+__device__ __forceinline__ ChipDev desc_const(const ChipDev* p) {
+  const unsigned long long u = (unsigned long long)(uintptr_t)p;
+  const unsigned long long s = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32)) << 32) |
+                               (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+  static_assert(sizeof(ChipDev) % 4 == 0, "descriptor copied in 4-byte words");
+  union Words { ChipDev d; uint32_t w[sizeof(ChipDev) / 4]; } out;
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)(uintptr_t)s;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ChipDev) / 4); ++i) out.w[i] = src[i];
+  return out.d;
+}
 template <bool MULTI, bool DIGEST, int OPT>
 __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restrict__ table, int chunk,
                                                       unsigned long long* digests, int digest_base) {
@@ -1554,14 +1570,22 @@ __global__ void __launch_bounds__(FAST_MAX) step_fast(const LaunchEntry* __restr
   constexpr bool W48 = (OPT & FAST_WAYS48) != 0;
   constexpr bool LSPDB = (OPT & FAST_LSPD) != 0;
   constexpr bool MIGB = LSPDB && (OPT & FAST_MIG) != 0;
+  constexpr int LW = (OPT & FAST_NARROW) ? 128 : FAST_MAX;  // threads the LDS rows are sized for
   __shared__ LdsStats L;
   __shared__ int s_fail;
   // [parity][row][local tile]: rows 0-3 are the input slots of ports 0-3 (written by the
   // neighbour inside the patch, or by the tile itself from a patch-edge slot), row 4 the flit
   // the tile injects, row 5 an empty flit; each output port copies the row of the flit it carries
-  __shared__ int4 s_link[2][6][FAST_MAX];
+  __shared__ int4 s_link[2][6][LW];
   const LaunchEntry e = table[blockIdx.x];
-  const ChipDev C = *e.chip;
+  // the checking build reads the chip descriptor as constant memory (scalar loads: the compiler
+  // then keeps its fields out of vector registers, which lets two waves share a SIMD; the timed
+  // build keeps the vector copy, whose arithmetic issues faster at one wave per SIMD)
+  auto load_desc = [&]() -> ChipDev {
+    if constexpr (DIGEST) return desc_const(e.chip);
+    else return *e.chip;
+  };
+  const ChipDev C = load_desc();
   const int N = C.N;
   const int idl = VARS ? C.inj_delay : 0;  // 1: a reply or request made in cycle c enters from c+1
   const bool aged = VARS && (C.variants & SIM_FLAG_AGE_DEFLECT) != 0;  // counts kept and ranked
@@ -2484,6 +2508,7 @@ struct sim_chip {
   int32_t block, chunk;
   bool fast;               // every patch fits its workgroup: one tile per thread (step_fast)
   bool use_fast;           // allow step_fast (tests compare both kernels)
+  bool narrow;             // step_fast's build for workgroups of at most 128 threads (FAST_NARROW)
   LaunchEntry* table_dev;  // max_patches entries
 };
 
@@ -2646,6 +2671,9 @@ int device_cus() {
 // the one-tile-per-thread kernel's build for the given OPT bits (FAST_*)
 template <bool MULTI, bool DIGEST>
 const void* fast_build(int opt) {
+  if ((opt & FAST_NARROW) && (opt & ~(FAST_NARROW | FAST_WAYS48)) == 0)
+    return (opt & FAST_WAYS48) ? reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_NARROW | FAST_WAYS48>)
+                               : reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_NARROW>);
   if ((opt & (FAST_MIG | 7)) == FAST_MIG && (opt & FAST_WAYS48))
     return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_MIG | FAST_LSPD | FAST_WAYS48>);
   if (opt & FAST_MIG) return reinterpret_cast<const void*>(step_fast<MULTI, DIGEST, FAST_MIG | FAST_LSPD | 7>);
@@ -2692,12 +2720,19 @@ int resident_limit(int block, bool fast, int opt, int var, bool digests) {
   }
   return lo * device_cus();
 }
-// the same over every build a chip may be launched with (any OPT bits, or the general kernel)
-int resident_limit_any(int block) {
-  int lo = INT_MAX;
-  for (int v = 0; v <= 2; ++v) lo = std::min(lo, resident_limit(block, false, 0, v, true));
-  for (int o = 0; o < 64; ++o) lo = std::min(lo, resident_limit(block, true, o, 0, true));  // (16-63: the directory's four)
-  return lo;
+// Whether a chip cut into np patches of `block` threads can be resident at once on the kernel it
+// would run (fast: one tile per thread); when the usual build cannot hold them, a base-model
+// chip of workgroups of at most 128 threads may use the narrow build (*narrow), which can.
+int fit_mapping(const sim_chip* h, int np, int block, bool fast, bool* narrow) {
+  *narrow = false;
+  if (np <= 1) return SIM_OK;
+  const int opt = fast_opt(h->hd), var = kernel_level(h->hd);
+  if (np <= resident_limit(block, fast, opt, var, true)) return SIM_OK;
+  if (fast && block <= 128 && (opt & ~FAST_WAYS48) == 0 && np <= resident_limit(block, true, opt | FAST_NARROW, var, true)) {
+    *narrow = true;
+    return SIM_OK;
+  }
+  return SIM_EINVAL;
 }
 
 int upload_desc(sim_chip* h) {
@@ -2708,11 +2743,12 @@ int upload_desc(sim_chip* h) {
 
 static int block_for(int tiles) { return tiles <= 64 ? 64 : tiles <= 128 ? 128 : tiles <= 192 ? 192 : 256; }
 
-// Default mapping: one workgroup for small chips; for chips up to 256 columns, one tile per
-// thread in strips of one row per workgroup of one or two waves (half a row above 128 columns;
-// up to 256 tiles of whole rows below 64 columns), as long as every strip can be resident at
-// once; otherwise square-ish patches, about one per compute unit.
-void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* block) {
+// Default mapping: one workgroup for small chips; otherwise one tile per thread in strips of one
+// row per workgroup of one or two waves (a row cut into equal strips of at most 128 tiles; up to
+// 256 tiles of whole rows below 64 columns), as long as every strip can be resident at once on
+// the chip's own build; otherwise square-ish patches, about one per compute unit.
+void default_mapping(const sim_chip* hc, int32_t* pw, int32_t* ph, int32_t* block) {
+  const sim_config* c = &hc->cfg;
   const int N = c->width * c->height;
   if (N <= 1024) {
     *pw = c->width;
@@ -2720,11 +2756,13 @@ void default_mapping(const sim_config* c, int32_t* pw, int32_t* ph, int32_t* blo
     *block = N <= 64 ? 64 : 256;
     return;
   }
-  if (c->width <= 256) {
-    const int w = c->width > 128 ? (c->width + 1) / 2 : c->width;
+  {
+    const int k = (c->width + 127) / 128;  // strips per row
+    const int w = (c->width + k - 1) / k;
     const int h = c->width < 64 ? std::min(c->height, 256 / c->width) : 1;
     const int np = ((c->width + w - 1) / w) * ((c->height + h - 1) / h);
-    if (np <= resident_limit_any(block_for(w * h))) {
+    bool narrow = false;
+    if (np <= hc->hd.max_patches && fit_mapping(hc, np, block_for(w * h), hc->use_fast, &narrow) == SIM_OK) {
       *pw = w;
       *ph = h;
       *block = block_for(w * h);
@@ -2746,8 +2784,9 @@ int apply_mapping(sim_chip* h, int32_t pw, int32_t ph, int32_t block) {
   const int pgx = (h->cfg.width + pw - 1) / pw, pgy = (h->cfg.height + ph - 1) / ph;
   const int np = pgx * pgy;
   if (np > h->hd.max_patches) return SIM_EINVAL;
-  if (np > 1 && np > resident_limit(block, pw * ph <= block && h->use_fast, fast_opt(h->hd), kernel_level(h->hd), true))
-    return SIM_EINVAL;
+  bool narrow = false;
+  if (fit_mapping(h, np, block, pw * ph <= block && h->use_fast, &narrow)) return SIM_EINVAL;
+  h->narrow = narrow;
   h->hd.pw = pw;
   h->hd.ph = ph;
   h->hd.pgx = pgx;
@@ -2939,7 +2978,7 @@ int sim_create(const sim_config* cfg, const uint32_t* zs, const uint32_t* zp, in
   if (hipMemcpyAsync(const_cast<uint32_t*>(d.zp), zp ? zp : zs, (ZIPF_K + 1) * 4, hipMemcpyHostToDevice, h->stream) != hipSuccess)
     return fail(SIM_EHIP);
   int32_t pw, ph, block;
-  default_mapping(cfg, &pw, &ph, &block);
+  default_mapping(h, &pw, &ph, &block);
   if ((rc = apply_mapping(h, pw, ph, block))) return fail(rc);
   *out = h;
   return SIM_OK;
@@ -2958,9 +2997,10 @@ int sim_set_kernel(sim_t* h, int32_t generic_only) {
   if (!h) return SIM_EINVAL;
   const bool use_fast = !generic_only && fast_model(&h->cfg);
   const int np = h->hd.n_patches;
-  if (np > 1 && np > resident_limit(h->block, h->fast && use_fast, fast_opt(h->hd), kernel_level(h->hd), true))
-    return SIM_EINVAL;
+  bool narrow = false;
+  if (fit_mapping(h, np, h->block, h->fast && use_fast, &narrow)) return SIM_EINVAL;
   h->use_fast = use_fast;
+  h->narrow = narrow;
   return SIM_OK;
 }
 
@@ -2994,7 +3034,7 @@ int sim_step(sim_t* h, int64_t n, uint64_t* dev_digests) {
   const int launches = (int)((n + h->chunk - 1) / h->chunk);
   for (int i = 0; i < launches; ++i) {
     int rc = launch_entries(h->table_dev, np, np > 1, h->fast && h->use_fast, h->block, h->chunk, dig, (int)h->cycle, h->stream,
-                            fast_opt(h->hd), kernel_level(h->hd), h->hd.watch_age > 0);
+                            fast_opt(h->hd) | (h->narrow ? FAST_NARROW : 0), kernel_level(h->hd), h->hd.watch_age > 0);
     if (rc) return rc;
   }
   h->cycle += n;

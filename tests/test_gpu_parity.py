@@ -168,21 +168,27 @@ def test_batch_split_into_resident_groups():
 
 @pytest.mark.parametrize("w,h", [(700, 3), (3, 700), (1, 1500), (300, 17)])
 def test_wide_and_tall_chips(w, h):
-    """Chips wider than 256 columns (square patches) and very tall or one-column chips."""
+    """Chips wider than 256 columns (rows cut into three or more strips) and very tall or
+    one-column chips."""
     p = W.config0().with_(width=w, height=h, seed=w + 7 * h, bg_thr=W.thr(0.1), op_thr=W.thr(0.3),
                           l1_sets=16, l2_sets=32)
     assert_same_run(p, 150, step_sizes=[60, 90])
 
 
-@pytest.mark.parametrize("w,h", [(100, 2048), (256, 300)])
-def test_default_mapping_of_tall_chips(w, h):
-    """Strips of one row per workgroup would outnumber the workgroups some build of the kernel
-    can hold at once on these chips: the default mapping falls back to square-ish patches."""
+@pytest.mark.parametrize("w,h,strips", [(100, 2048, False), (256, 300, True)])
+def test_default_mapping_of_tall_chips(w, h, strips):
+    """A 256x300 chip's 600 row strips are all resident with four two-wave workgroups per
+    compute unit (the narrow build of the one-tile-per-thread kernel); a 100x2048 chip's 2,048
+    strips are not, and the default mapping falls back to square-ish patches, about one per
+    compute unit."""
     p = W.config0().with_(width=w, height=h, seed=w + h, bg_thr=W.thr(0.1), op_thr=W.thr(0.3),
                           l1_sets=16, l2_sets=32)
     g = gpu_sim(p)
     pw, ph, block, _ = g.get_launch()
-    assert -(-w // pw) * -(-h // ph) <= 512
+    if strips:
+        assert (pw, ph, block) == (128, 1, 128)
+    else:
+        assert -(-w // pw) * -(-h // ph) <= 256 and pw * ph > block
     del g
     assert_same_run(p, 40, step_sizes=[15, 25])
 
