@@ -230,10 +230,10 @@ int sim_set_watchdog(sim_t* h, int32_t max_age);
    synchronise with their neighbours only), `block` threads per workgroup (64..256, a multiple of 64),
    `chunk` cycles per launch.  0 keeps the current value.  EINVAL if the patch grid cannot
    be resident on the device at once.  sim_create's default: one workgroup for chips of at
-   most 1,024 tiles; for chips up to 256 columns one row per workgroup of 64 or 128 threads
-   (half a row above 128 columns, whole rows up to 256 tiles below 64 columns) when every
-   build of the step kernel can hold all of them at once; otherwise square-ish patches, about
-   one per compute unit; chunk 1,000. */
+   most 1,024 tiles; otherwise one row per workgroup of 64 or 128 threads (a row cut into
+   equal strips of at most 128 tiles; whole rows up to 256 tiles below 64 columns) when the
+   chip's own builds of the step kernel can hold all of them at once; otherwise square-ish
+   patches, about one per compute unit; chunk 1,000. */
 int sim_set_launch(sim_t* h, int32_t patch_w, int32_t patch_h, int32_t block, int32_t chunk);
 int sim_get_launch(const sim_t* h, int32_t* patch_w, int32_t* patch_h, int32_t* block, int32_t* chunk);
 /* Kernel choice: when every patch has at most `block` tiles the library runs a kernel that keeps
